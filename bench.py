@@ -1,0 +1,165 @@
+"""Benchmark of the LSMS tau-solve + Kubo-Greenwood hot path on one MI355X.
+
+Workload: random binary fcc alloy A0.25B0.75, a = 7.6 bohr, 10x10x10 conventional cells
+(4000 atoms), lmax = 3, LIZ of 135 atoms (n = 2160 complex per system), both energies
+eF +- i eta with eta cycling over (0.005, 0.002, 0.001) Ry step by step.  A step is the
+whole hot path for all 4000 atoms at one eta: assembly of 1 - t g, 8000 complex LU
+factorizations with partial pivoting, the tau solves (split precision: FP32 trailing
+updates + FP64 refinement), the Kubo-Greenwood traces and the reduction to sigma.
+Inputs are synthetic and seeded (no dataset); they live in HBM before the timed region.
+
+Prints one JSON line; see the design doc for the roofline and baseline definitions.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "atoms/sec through LIZ τ-solve + Kubo trace; % MFMA peak; split vs FP64 at 1e-8"
+PEAK_FP32_MFMA = 157.3e12
+PEAK_FP64_MFMA = 78.6e12
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, eta, n_sample):
+    """The oracle as it stands on a few atoms of the same workload (host cores)."""
+    from oracle import kubo
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    import paper_2311_12134_amd as P
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    atoms = list(range(n_sample))
+    t0 = time.perf_counter()
+    kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta, atoms=atoms,
+               liz_lists=(liz.ptr, liz.atom, liz.pos))
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "atoms/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d atoms of the 4000-atom fcc alloy at eta=%g (both energies, assembly + LU + both tau "
+                      "blocks + Kubo traces), %.1f s" % (n_sample, eta, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fcc4000")
+    ap.add_argument("--precision", default="split", choices=["split", "fp64"])
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(atoms shard trivially across GPUs; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2311_12134_amd as P
+    import synthetic
+
+    w = synthetic.workload(args.workload)
+    etas = list(w["etas"])
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    log("LIZ built in %.2f s: %d atoms, members %d..%d" % (time.perf_counter() - t0, liz.n_atoms,
+                                                             np.diff(liz.ptr).min(), np.diff(liz.ptr).max()))
+    la, lp = liz.to_device(dev)
+    phase = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(dev)
+    species = torch.from_numpy(w["species"].astype(np.int32)).to(dev)
+    J = torch.from_numpy(np.ascontiguousarray(w["J"])).to(dev)
+    ctx = P.Context(0)
+    n_atoms = liz.n_atoms
+    tp = torch.empty((liz.total, 16, 16), dtype=torch.complex128, device=dev)
+    tm = torch.empty_like(tp)
+    info = torch.empty((n_atoms, 2), dtype=torch.int32, device=dev)
+    berr = torch.empty((n_atoms, 2), dtype=torch.float64, device=dev)
+    sig = torch.empty(3, dtype=torch.float64, device=dev)
+    st = torch.empty((4, 3), dtype=torch.complex128, device=dev)
+
+    def step(i, precision, keep_sigma=None):
+        eta = etas[i % len(etas)]
+        ctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision, out=(tp, tm, info, berr))
+        ctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], out=(sig, st, None))
+        if keep_sigma is not None:
+            keep_sigma[eta] = sig.clone()
+
+    sig_main = {}
+    for i in range(args.warmup):
+        step(i, args.precision, sig_main)
+        torch.cuda.synchronize()
+        log("warmup step %d done" % i)
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i, args.precision, sig_main)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gemm_ms, gemm_launches, gemm_flops = ctx.kernel_stats()
+    ctx.set_profiling(False)
+    info_np = info.cpu().numpy()
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = n_atoms * args.steps / elapsed
+    log("timed %d steps: %.1f ms/step, %.1f atoms/s" % (args.steps, ms_per_step, value))
+
+    n_true = 16 * np.diff(liz.ptr).astype(np.float64)
+    alg_flops_step = float(np.sum(2.0 * ((8.0 / 3.0) * n_true**3 + 128.0 * n_true**2)))
+    peak = PEAK_FP32_MFMA if args.precision == "split" else PEAK_FP64_MFMA
+    out = {"metric": METRIC, "value": value, "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None,
+           "dtype": "fp32 trailing updates + fp64 panels/refinement" if args.precision == "split" else "f64",
+           "data": "synthetic (seeded structure, phase shifts and current matrices)",
+           "config": {"workload": "%s: %s, %d atoms, LIZ %d-%d atoms, lmax 3, eF %.2f Ry, eta cycling %s Ry"
+                      % (w["name"], w["lattice"], n_atoms, int(n_true.min() / 16), int(n_true.max() / 16),
+                         w["e_fermi"], etas),
+                      "precision": args.precision, "parallelism": "single GPU, all atoms batched"},
+           "path_tflops_alg": alg_flops_step * args.steps / elapsed / 1e12,
+           "path_frac_of_peak": alg_flops_step * args.steps / elapsed / peak,
+           "info_nonzero": int((info_np != 0).sum())}
+    if gemm_launches:
+        avg_s = gemm_ms / gemm_launches / 1e3
+        achieved = gemm_flops / gemm_launches / avg_s
+        out["roofline"] = {"kernel": "gemm_f32_3m_kernel" if args.precision == "split" else "gemm_f64_kernel",
+                           "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                           "frac": achieved / peak, "traffic": None,
+                           "launches": gemm_launches, "avg_launch_ms": 1e3 * avg_s}
+    if not args.no_fp64_compare and args.precision == "split":
+        sig64 = {}
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step(0, "fp64", sig64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        eta0 = etas[0]
+        s_split = sig_main[eta0].cpu().numpy()
+        s_64 = sig64[eta0].cpu().numpy()
+        out["fp64_ms_per_step"] = 1e3 * t64
+        out["fp64_atoms_per_s"] = n_atoms / t64
+        out["split_speedup_vs_fp64"] = (n_atoms / t64) and value / (n_atoms / t64)
+        out["sigma_rel_err_split_vs_fp64"] = float(np.abs(s_split - s_64).max() / np.abs(s_64).max())
+        log("fp64 step %.1f ms; sigma split %s fp64 %s" % (1e3 * t64, s_split, s_64))
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, etas[0], args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * lsms_kkr.h -- C ABI of the MI355X (gfx950) library for the hot path of
+ * LSMS residual-resistivity calculations (Raghuraman, Eisenbach, Widom,
+ * Wang, "First principles residual resistivity using locally
+ * self-consistent multiple scattering method", arXiv:2311.12134).
+ *
+ * For every atom m the library
+ *   1. builds the local interaction zone (LIZ) of m           (Sec. II.A, Fig. 1),
+ *   2. assembles M = 1 - t g over that LIZ at z = eF +- i eta  (Eq. (3)-(4), Eq. (7)),
+ *      g = free-electron structure constants (spherical Hankel functions
+ *      times Gaunt coefficients times real spherical harmonics),
+ *   3. factors M (complex LU with partial pivoting) and solves for the tau
+ *      blocks tau^{a0} linking every LIZ member a to the centre (Eq. (3), Eq. (10)),
+ *   4. contracts tau with current matrix elements into the Kubo-Greenwood
+ *      sums of Eq. (10) and combines the four energy pairs with Eq. (7).
+ *
+ * Conventions shared by every call:
+ *   - Rydberg atomic units (hbar = 1, 2 m_e = 1): kappa = sqrt(z), bohr, Ry.
+ *   - lmax = 3: 16 angular channels, L = l*l + l + m, real spherical harmonics
+ *     without the Condon-Shortley phase.
+ *   - Complex numbers are interleaved (re, im) pairs of double (the layout of
+ *     C99 double _Complex and torch.complex128).
+ *   - t_l(z+) = -sin(delta_l) exp(i delta_l) / kappa+, t(z-) = conj(t(z+)),
+ *     kappa+ = principal sqrt(z+), kappa- = -conj(kappa+).
+ *   - Energy pairs ("combos") are ordered (z1, z2) = (+,+), (+,-), (-,+), (-,-);
+ *     directions x, y, z.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the context's GPU.  The caller owns every array it
+ *     passes; the library never frees or keeps a caller pointer beyond the
+ *     completion of the work it enqueued.
+ *   - Every call returns an lsms_status.  On failure lsms_last_error() gives a
+ *     thread-local message; no C++ exception crosses this boundary.
+ *   - Device work is enqueued on the caller's HIP stream (NULL = the null
+ *     stream) and is asynchronous unless stated otherwise; argument errors are
+ *     detected synchronously, before anything is enqueued.
+ */
+#ifndef LSMS_KKR_H
+#define LSMS_KKR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LSMS_LMAX 3
+#define LSMS_NL 16        /* (LSMS_LMAX + 1)^2 channels per site */
+#define LSMS_MAX_LIZ 256  /* largest LIZ (members) a single solve accepts */
+
+typedef enum {
+  LSMS_OK = 0,
+  LSMS_E_ARG = -1,      /* invalid argument (null pointer, size, NaN, lmax != 3, ...) */
+  LSMS_E_CAPACITY = -2, /* caller-provided capacity too small; *needed tells the size */
+  LSMS_E_DEVICE = -3,   /* HIP runtime error */
+  LSMS_E_NOMEM = -4,    /* workspace limit too small for the request */
+  LSMS_E_STATE = -5     /* object used in the wrong state (e.g. stale factors) */
+} lsms_status;
+
+typedef enum {
+  LSMS_FP64 = 0,  /* whole factorization and solve in FP64 */
+  LSMS_SPLIT = 1  /* FP32 trailing updates + FP64 panels, residuals, refinement */
+} lsms_precision;
+
+/* Per-job status codes written to info[] by lsms_tau_solve. */
+#define LSMS_INFO_OK 0
+/* k > 0 : exact zero pivot met at column k (1-based); tau of that job is not valid */
+#define LSMS_INFO_NOCONV (-1)   /* split mode: refinement did not reach refine_tol */
+#define LSMS_INFO_BADINPUT (-2) /* non-finite phase shift or position in this LIZ */
+
+typedef struct lsms_ctx lsms_ctx;
+typedef struct lsms_factors lsms_factors;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lsms_last_error(void);
+
+/*
+ * Create a context on HIP device `hip_device`.  `lmax` must be 3.
+ * `workspace_limit` bounds the device memory the library may hold for
+ * factorizations (bytes; 0 = 60% of the device's free memory).  The Gaunt
+ * table (integrals of three real spherical harmonics) is built here on the
+ * host and uploaded once.
+ */
+int lsms_create(int hip_device, int lmax, size_t workspace_limit, lsms_ctx** out);
+
+/* Release the context and everything it owns (factors handles must be freed first). */
+int lsms_destroy(lsms_ctx* ctx);
+
+/*
+ * LIZ construction (Sec. II.A, Fig. 1; the inner sum of Eq. (10) runs over
+ * the LIZ of m).  Host-only, synchronous.
+ *   pos      host [n_atoms][3]  atom positions (bohr)
+ *   cell     host [3][3]        lattice vectors as rows, or NULL for an open cluster
+ *   r_liz    LIZ radius (bohr, > 0); a member is any periodic image R_j + T of
+ *            any atom j with |R_j + T - R_m| < r_liz (strict)
+ *   capacity number of members the output arrays can hold
+ *   liz_ptr  host [n_atoms + 1]      CSR offsets (always written when capacity suffices)
+ *   liz_atom host [capacity]         atom index of each member
+ *   liz_pos  host [capacity][3]      displacement (R_j + T) - R_m of each member
+ *   needed   host [1]                total number of members (always written)
+ * Order inside each LIZ: the centre first, then by increasing distance, ties
+ * by the displacement's x, y, z (all compared after rounding to 1e-9).
+ * Returns LSMS_E_CAPACITY (with *needed) when capacity is too small,
+ * LSMS_E_ARG for coincident sites (distance < 1e-8 bohr), non-finite input,
+ * a LIZ larger than LSMS_MAX_LIZ or r_liz <= 0.
+ */
+int lsms_build_liz(lsms_ctx* ctx, int32_t n_atoms, const double* pos, const double* cell, double r_liz,
+                   int64_t capacity, int64_t* liz_ptr, int32_t* liz_atom, double* liz_pos, int64_t* needed);
+
+/*
+ * tau solve (Eq. (3)-(4)): for every atom m and both energies z+- = e_fermi +- i eta,
+ * assemble M = 1 - T g over LIZ_m, factor it, and solve M X = E0 t_m so that
+ * block a of X is tau^{a0}(z) (the row tau^{0a} equals its transpose, since
+ * g_{LL'}(R) = g_{L'L}(-R) makes T^-1 - g complex symmetric).
+ *   liz_ptr   host   [n_atoms + 1]       from lsms_build_liz
+ *   liz_atom  device [liz_ptr[n]]        member atom indices
+ *   liz_pos   device [liz_ptr[n]][3]     member displacements (bohr)
+ *   phase     device [n_atoms][4]        phase shifts delta_l (radians), l = 0..3
+ *   e_fermi, eta   eta > 0 (Ry)
+ *   precision LSMS_FP64 or LSMS_SPLIT
+ *   refine_tol, max_refine  split mode only: stop when the normwise backward
+ *             error ||r||_inf / (||M||_inf ||X||_inf + ||B||_inf) <= refine_tol,
+ *             or after max_refine corrections (then info = LSMS_INFO_NOCONV and
+ *             the job is recomputed in FP64)
+ *   tau_plus, tau_minus device [liz_ptr[n]][16][16] complex (out): tau^{a0}_{LL'}
+ *   info      device [n_atoms][2] int32 (out), per atom and energy (0 = +, 1 = -)
+ *   berr      device [n_atoms][2] double (out): final backward error (split mode),
+ *             0 in FP64 mode
+ *   keep      NULL, or receives a library-owned handle that keeps every LU factor
+ *             alive for lsms_kubo_sigma_grad (free with lsms_factors_free)
+ *   hip_stream  hipStream_t (NULL = null stream)
+ * Device memory used: the jobs are processed in waves that fit the workspace
+ * limit (all at once when keep != NULL, else LSMS_E_NOMEM).
+ */
+int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
+                   const double* liz_pos, const double* phase, double e_fermi, double eta, int precision,
+                   double refine_tol, int max_refine, void* tau_plus, void* tau_minus, int32_t* info,
+                   double* berr, lsms_factors** keep, void* hip_stream);
+
+/*
+ * Kubo-Greenwood sum (Eq. (10)) and four-term combination (Eq. (7)):
+ *   s_m[c][mu] = sum_{a in LIZ_m} Tr[ J^{m mu}(z2,z1) tau^{0a}(z1) J^{a mu}(z1,z2) tau^{a0}(z2) ]
+ *   sigma~[c][mu] = -(1 / (pi * volume)) * sum_m s_m[c][mu]
+ *   sigma[mu]     = 1/4 (sigma~[++] - sigma~[+-] - sigma~[-+] + sigma~[--])   (real part)
+ * (Rydberg units make 4 m_e^2 / hbar^3 = 1; volume = N Omega, the supercell volume.)
+ *   liz_ptr    host   [n_atoms + 1]
+ *   liz_atom   device [liz_ptr[n]]
+ *   tau_plus, tau_minus device [liz_ptr[n]][16][16] complex, as written by lsms_tau_solve
+ *   species    device [n_atoms] int32 in [0, n_species)
+ *   J          device [n_species][4][3][16][16] complex: J[s][c][mu] = J^{s mu}(zA, zB)
+ *              for the energy pair (zA, zB) of combo c
+ *   volume     > 0 (bohr^3)
+ *   sigma      device [3] double (out)
+ *   sigma_tilde device [4][3] complex (out)
+ *   per_atom   device [n_atoms][4][3] complex (out) or NULL
+ * The reduction over atoms has a fixed order (bitwise reproducible).
+ */
+int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
+                    const void* tau_plus, const void* tau_minus, const int32_t* species, int32_t n_species,
+                    const void* J, double volume, double* sigma, void* sigma_tilde, void* per_atom,
+                    void* hip_stream);
+
+/*
+ * Adjoint of the whole path: gradient of L = sum_mu dsigma[mu] sigma_mu with
+ * respect to every phase shift, d L / d phase[k][l].  Derived from Eq. (3)
+ * (d tau = W dT W^T with W = (1 - T g)^-1) and Eq. (10): one transposed solve
+ * M^T Y = [R, E0] per atom and energy with the factors kept by lsms_tau_solve,
+ * then a contraction over each LIZ, then the chain rule
+ * dt_l(z+)/d delta_l = -exp(2 i delta_l)/kappa+ (conjugate at z-), summed
+ * over every LIZ image of site k.
+ *   factors   handle from lsms_tau_solve(..., keep) with the same inputs
+ *   phase, tau_plus, tau_minus, species, J, volume as in the forward calls
+ *   dsigma    device [3] double: upstream gradient
+ *   dphase    device [n_atoms][4] double (out, overwritten)
+ */
+int lsms_kubo_sigma_grad(lsms_ctx* ctx, const lsms_factors* factors, int32_t n_atoms, const int64_t* liz_ptr,
+                         const int32_t* liz_atom, const double* phase, const void* tau_plus,
+                         const void* tau_minus, const int32_t* species, int32_t n_species, const void* J,
+                         double volume, const double* dsigma, double* dphase, void* hip_stream);
+
+/* Free a factors handle (waits for outstanding work on the context's device). */
+int lsms_factors_free(lsms_factors* factors);
+
+/*
+ * Diagnostic entry: factor caller-supplied matrices with the library's batched
+ * LU (partial pivoting) and solve A X = B in place of B.
+ *   batch     number of systems
+ *   n         host [batch] sizes (1 .. 16 * LSMS_MAX_LIZ)
+ *   A         host [batch] device pointers to row-major n x n complex matrices (read only)
+ *   B         host [batch] device pointers to row-major n x nrhs complex right-hand sides (overwritten by X)
+ *   nrhs      1 .. 16
+ *   precision LSMS_FP64 (or LSMS_SPLIT: FP32 factors, no refinement)
+ *   info      device [batch] int32 (out): 0, or k > 0 for an exact zero pivot at column k
+ */
+int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t* n, void* const* A, void* const* B,
+                          int32_t nrhs, int precision, int32_t* info, void* hip_stream);
+
+/*
+ * Measurement of the dominant kernel, the trailing-matrix update A22 -= L21 U12 of the
+ * blocked LU (the matrix inverse of Eq. (3) dominates the cost, Sec. II.A).
+ * lsms_set_profiling(ctx, 1) waits for the device, clears the statistics and makes every
+ * later lsms_tau_solve record a pair of HIP events around each trailing-update launch on
+ * the caller's stream (0 switches recording off).  lsms_kernel_stats waits for the
+ * recorded events and returns the summed launch time (ms), the number of launches and
+ * their algorithmic flops: 8 m^2 NB per system and launch with m = n - k - NB (the
+ * standard complex count of a rank-NB update; the split mode executes 3/4 of it).
+ */
+int lsms_set_profiling(lsms_ctx* ctx, int on);
+int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launches, double* alg_flops);
+
+/*
+ * Host-only query of the library's Gaunt table (Sec. II.A: g is built from these
+ * integrals): out[(L * 16 + L') * 49 + L''] = integral of Y_L Y_L' Y_L'' over the unit
+ * sphere for l, l' <= 3 and l'' <= 6 (real harmonics as above).  out is host
+ * [16][16][49] double.  Needs no context and no GPU.
+ */
+int lsms_gaunt_table(double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSMS_KKR_H */

@@ -1,0 +1,219 @@
+"""Thin PyTorch binding of the C ABI (include/lsms_kkr.h).
+
+PyTorch only provides device memory and the current HIP stream; every step of the
+path (assembly, LU, solves, refinement, Kubo sums, adjoint) runs in liblsms_kkr.so.
+"""
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+NL = 16
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Liz:
+    """CSR local interaction zones: ptr [N+1] int64 (host), atom [S] int32, pos [S,3] float64."""
+    ptr: np.ndarray
+    atom: np.ndarray
+    pos: np.ndarray
+
+    @property
+    def n_atoms(self):
+        return len(self.ptr) - 1
+
+    @property
+    def total(self):
+        return int(self.ptr[-1])
+
+    def to_device(self, device):
+        return (torch.from_numpy(np.ascontiguousarray(self.atom)).to(device),
+                torch.from_numpy(np.ascontiguousarray(self.pos)).to(device))
+
+
+def gaunt_table():
+    """The library's Gaunt table [16, 16, 49] (host query, no GPU needed)."""
+    out = np.zeros((NL, NL, 49), dtype=np.float64)
+    check(lib().lsms_gaunt_table(out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def build_liz(pos, cell, r_liz):
+    """LIZ construction in the library (host C++); no context or GPU needed."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    cellp = None
+    if cell is not None:
+        cell = np.ascontiguousarray(cell, dtype=np.float64)
+        cellp = cell.ctypes.data_as(ctypes.c_void_p)
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    needed = ctypes.c_int64(0)
+    rc = lib().lsms_build_liz(None, n, pos.ctypes.data_as(ctypes.c_void_p), cellp, float(r_liz), 0,
+                              ptr.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(needed))
+    if rc not in (_lib.LSMS_OK, _lib.LSMS_E_CAPACITY):
+        check(rc)
+    cap = needed.value
+    atom = np.zeros(cap, dtype=np.int32)
+    disp = np.zeros((cap, 3), dtype=np.float64)
+    check(lib().lsms_build_liz(None, n, pos.ctypes.data_as(ctypes.c_void_p), cellp, float(r_liz), cap,
+                               ptr.ctypes.data_as(ctypes.c_void_p), atom.ctypes.data_as(ctypes.c_void_p),
+                               disp.ctypes.data_as(ctypes.c_void_p), ctypes.byref(needed)))
+    return Liz(ptr, atom, disp)
+
+
+class Factors:
+    """Library-owned LU factors kept by a tau solve for the adjoint."""
+
+    def __init__(self, handle, ctx):
+        self.handle = handle
+        self.ctx = ctx
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            check(lib().lsms_factors_free(self.handle))
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context on one GPU (lmax = 3)."""
+
+    def __init__(self, device=0, workspace_limit=0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the LSMS tau-solve library needs a HIP device")
+        self.device = torch.device("cuda", device)
+        self._h = ctypes.c_void_p()
+        check(lib().lsms_create(device, 3, int(workspace_limit), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            check(lib().lsms_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tau ------------------------------------------------------------------------
+    def tau_solve(self, liz, liz_atom_dev, liz_pos_dev, phase, e_fermi, eta, precision="fp64", refine_tol=1e-14,
+                  max_refine=10, keep=False, out=None):
+        """tau^{a0}(z+-) for every atom: returns (tau_plus, tau_minus, info, berr[, factors])."""
+        prec = {"fp64": _lib.LSMS_FP64, "split": _lib.LSMS_SPLIT}[precision]
+        n = liz.n_atoms
+        assert phase.is_cuda and phase.dtype == torch.float64 and phase.shape == (n, 4) and phase.is_contiguous()
+        assert liz_atom_dev.dtype == torch.int32 and liz_pos_dev.dtype == torch.float64
+        if out is None:
+            tp = torch.empty((liz.total, NL, NL), dtype=torch.complex128, device=self.device)
+            tm = torch.empty_like(tp)
+            info = torch.empty((n, 2), dtype=torch.int32, device=self.device)
+            berr = torch.empty((n, 2), dtype=torch.float64, device=self.device)
+        else:
+            tp, tm, info, berr = out
+        fh = ctypes.c_void_p() if keep else None
+        check(lib().lsms_tau_solve(self._h, n, liz.ptr.ctypes.data_as(ctypes.c_void_p), _ptr(liz_atom_dev),
+                                   _ptr(liz_pos_dev), _ptr(phase), float(e_fermi), float(eta), prec,
+                                   float(refine_tol), int(max_refine), _ptr(tp), _ptr(tm), _ptr(info), _ptr(berr),
+                                   ctypes.byref(fh) if keep else None, _stream()))
+        if keep:
+            return tp, tm, info, berr, Factors(fh, self)
+        return tp, tm, info, berr
+
+    # -- Kubo-Greenwood -----------------------------------------------------------------
+    def kubo_sigma(self, liz, liz_atom_dev, tau_plus, tau_minus, species, J, volume, per_atom=False, out=None):
+        """sigma [3] (float64), sigma_tilde [4,3] (complex128) and optionally per-atom sums [N,4,3]."""
+        n = liz.n_atoms
+        assert species.dtype == torch.int32 and J.dtype == torch.complex128 and J.is_contiguous()
+        n_species = J.shape[0]
+        if out is None:
+            sig = torch.empty(3, dtype=torch.float64, device=self.device)
+            st = torch.empty((4, 3), dtype=torch.complex128, device=self.device)
+            pa = torch.empty((n, 4, 3), dtype=torch.complex128, device=self.device) if per_atom else None
+        else:
+            sig, st, pa = out
+        check(lib().lsms_kubo_sigma(self._h, n, liz.ptr.ctypes.data_as(ctypes.c_void_p), _ptr(liz_atom_dev),
+                                    _ptr(tau_plus), _ptr(tau_minus), _ptr(species), n_species, _ptr(J),
+                                    float(volume), _ptr(sig), _ptr(st), _ptr(pa), _stream()))
+        return sig, st, pa
+
+    def kubo_sigma_grad(self, factors, liz, liz_atom_dev, phase, tau_plus, tau_minus, species, J, volume, dsigma):
+        n = liz.n_atoms
+        dphase = torch.empty((n, 4), dtype=torch.float64, device=self.device)
+        dsig = dsigma.to(device=self.device, dtype=torch.float64).contiguous()
+        check(lib().lsms_kubo_sigma_grad(self._h, factors.handle, n, liz.ptr.ctypes.data_as(ctypes.c_void_p),
+                                         _ptr(liz_atom_dev), _ptr(phase), _ptr(tau_plus), _ptr(tau_minus),
+                                         _ptr(species), J.shape[0], _ptr(J), float(volume), _ptr(dsig),
+                                         _ptr(dphase), _stream()))
+        return dphase
+
+    # -- measurement ---------------------------------------------------------------------
+    def set_profiling(self, on=True):
+        check(lib().lsms_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_stats(self):
+        """(total ms, launches, algorithmic flops) of the recorded trailing-update launches."""
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        fl = ctypes.c_double(0)
+        check(lib().lsms_kernel_stats(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
+        return ms.value, n.value, fl.value
+
+    # -- diagnostic batched solve ------------------------------------------------------
+    def batched_lu_solve(self, mats, rhs, precision="fp64"):
+        """Solve A_b X_b = B_b in place of B_b (lists of CUDA complex128 tensors); returns info [batch]."""
+        batch = len(mats)
+        ns = np.array([m.shape[0] for m in mats], dtype=np.int32)
+        nrhs = rhs[0].shape[1]
+        aptr = (ctypes.c_void_p * batch)(*[m.data_ptr() for m in mats])
+        bptr = (ctypes.c_void_p * batch)(*[b.data_ptr() for b in rhs])
+        info = torch.zeros(batch, dtype=torch.int32, device=self.device)
+        prec = {"fp64": _lib.LSMS_FP64, "split": _lib.LSMS_SPLIT}[precision]
+        check(lib().lsms_batched_lu_solve(self._h, batch, ns.ctypes.data_as(ctypes.c_void_p), aptr, bptr, nrhs,
+                                          prec, _ptr(info), _stream()))
+        return info
+
+
+class KuboSigma(torch.autograd.Function):
+    """sigma(phase) through the library, with the hand-written adjoint as backward.
+
+    forward(ctx, phase, lsms_context, liz, liz_atom_dev, liz_pos_dev, species, J, volume, e_fermi, eta)
+    """
+
+    @staticmethod
+    def forward(ctx, phase, lctx, liz, liz_atom_dev, liz_pos_dev, species, J, volume, e_fermi, eta):
+        phase = phase.contiguous()
+        tp, tm, info, berr, fac = lctx.tau_solve(liz, liz_atom_dev, liz_pos_dev, phase, e_fermi, eta, keep=True)
+        sig, _, _ = lctx.kubo_sigma(liz, liz_atom_dev, tp, tm, species, J, volume)
+        ctx.lctx = lctx
+        ctx.liz = liz
+        ctx.fac = fac
+        ctx.volume = volume
+        ctx.save_for_backward(phase, liz_atom_dev, tp, tm, species, J)
+        return sig
+
+    @staticmethod
+    def backward(ctx, gsig):
+        phase, liz_atom_dev, tp, tm, species, J = ctx.saved_tensors
+        dphase = ctx.lctx.kubo_sigma_grad(ctx.fac, ctx.liz, liz_atom_dev, phase, tp, tm, species, J, ctx.volume,
+                                          gsig)
+        ctx.fac.free()
+        return (dphase,) + (None,) * 9

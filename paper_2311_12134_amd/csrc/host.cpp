@@ -1,0 +1,822 @@
+// Host side of the library: C ABI entry points, argument checking, the Gaunt table,
+// LIZ construction, and the scheduler that groups (atom, energy) systems into waves
+// that fit the workspace and drives the HIP kernels over each wave.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lsms_kkr.h"
+#include "lsms_internal.h"
+#include "ylm.h"
+
+using namespace lsms;
+
+namespace lsms {
+void lu_solve_f32_skip(const JobDesc* jobs, int njobs, const float2* work, const int32_t* piv, double2* x,
+                       const int32_t* skip, hipStream_t s);
+}
+
+// ---------------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                                \
+  do {                                                                                               \
+    hipError_t e_ = (expr);                                                                          \
+    if (e_ != hipSuccess) return fail(LSMS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char* lsms_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Records a pair of events around every trailing-update launch (see GemmProfiler).
+struct EventProf : GemmProfiler {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<double> flops;
+  hipEvent_t get() {
+    if (used < pool.size()) return pool[used++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pool.push_back(e);
+    ++used;
+    return e;
+  }
+  void before(hipStream_t s) override {
+    hipEvent_t e = get();
+    if (e) hipEventRecord(e, s);
+  }
+  void after(hipStream_t s, double f) override {
+    hipEvent_t e = get();
+    if (e) hipEventRecord(e, s);
+    flops.push_back(f);
+  }
+  void reset() {
+    used = 0;
+    flops.clear();
+  }
+  ~EventProf() override {
+    for (hipEvent_t e : pool) hipEventDestroy(e);
+  }
+};
+
+struct lsms_ctx {
+  int device = 0;
+  bool profiling = false;
+  EventProf prof;
+  std::vector<int> n_true;
+  size_t workspace_limit = 0;
+  GauntTable gaunt;
+  DevBuf work;      // wave workspace
+  DevBuf small;     // per-call small arrays
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+};
+
+struct lsms_factors {
+  lsms_ctx* ctx = nullptr;
+  int precision = 0;
+  int n_atoms = 0;
+  std::vector<JobDesc> jobs;
+  int npad_max = 0;
+  void* work = nullptr;  // factors, pivots, solution blocks (device)
+  size_t work_bytes = 0;
+  JobDesc* jobs_dev = nullptr;
+  int64_t x_base = 0, piv_base = 0;  // byte offsets inside work (matrices start at 0)
+  double2 kp{0, 0}, km{0, 0};
+  const int32_t* liz_atom = nullptr;     // the forward call's arrays, for a consistency check
+  int64_t total_members = 0;
+};
+
+static int ensure_dev(DevBuf& b, size_t bytes, hipStream_t s) {
+  if (b.bytes >= bytes) return LSMS_OK;
+  if (b.p) {
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) return fail(LSMS_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  b.bytes = bytes;
+  return LSMS_OK;
+}
+
+static int ensure_pinned(lsms_ctx* c, size_t bytes, hipStream_t s) {
+  // the previous call's uploads may still read from the pinned buffer
+  HIP_TRY(hipStreamSynchronize(s));
+  if (c->pinned_bytes >= bytes) return LSMS_OK;
+  if (c->pinned) HIP_TRY(hipHostFree(c->pinned));
+  c->pinned = nullptr;
+  c->pinned_bytes = 0;
+  HIP_TRY(hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault));
+  c->pinned_bytes = bytes;
+  return LSMS_OK;
+}
+
+// Gaunt integrals C[L][L'][L''] = int Y_L Y_L' Y_L'' dOmega for l, l' <= 3, l'' <= 6, by a
+// Gauss-Legendre (cos t) x uniform (p) product rule that is exact at these degrees.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int l = 2; l <= n; ++l) {
+        double p2 = ((2 * l - 1) * z * p1 - (l - 1) * p0) / l;
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_n(z), p0 = P_{n-1}(z)
+      double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int l = 2; l <= n; ++l) {
+      double p2 = ((2 * l - 1) * z * p1 - (l - 1) * p0) / l;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+static void gaunt_dense(std::vector<double>& C) {
+  const int nt = 12, np = 20;
+  std::vector<double> xt, wt;
+  gauss_legendre(nt, xt, wt);
+  C.assign(NL * NL * NL3, 0.0);
+  double Y[NL3];
+  for (int it = 0; it < nt; ++it) {
+    double z = xt[it], st = sqrt(1.0 - z * z);
+    for (int ip = 0; ip < np; ++ip) {
+      double ph = 2.0 * M_PI * ip / np;
+      double w = wt[it] * 2.0 * M_PI / np;
+      real_ylm_all<6>(st * cos(ph), st * sin(ph), z, Y);
+      for (int a = 0; a < NL; ++a)
+        for (int b = 0; b < NL; ++b) {
+          double wab = w * Y[a] * Y[b];
+          for (int c = 0; c < NL3; ++c) C[(a * NL + b) * NL3 + c] += wab * Y[c];
+        }
+    }
+  }
+  for (double& v : C)
+    if (fabs(v) < 1e-13) v = 0.0;
+}
+
+static int build_gaunt(GauntTable& g) {
+  std::vector<double> C;
+  gaunt_dense(C);
+  int q = 0;
+  for (int p = 0; p < NL * NL; ++p) {
+    g.start[p] = q;
+    for (int c = 0; c < NL3; ++c) {
+      double v = C[p * NL3 + c];
+      if (v != 0.0) {
+        if (q >= MAX_GAUNT) return fail(LSMS_E_ARG, "Gaunt table overflow");
+        g.l3[q] = c;
+        g.coef[q] = v;
+        ++q;
+      }
+    }
+  }
+  g.start[NL * NL] = q;
+  return LSMS_OK;
+}
+
+extern "C" int lsms_gaunt_table(double* out) {
+  if (!out) return fail(LSMS_E_ARG, "out is NULL");
+  std::vector<double> C;
+  gaunt_dense(C);
+  std::memcpy(out, C.data(), C.size() * sizeof(double));
+  return LSMS_OK;
+}
+
+extern "C" int lsms_create(int hip_device, int lmax, size_t workspace_limit, lsms_ctx** out) {
+  if (!out) return fail(LSMS_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (lmax != LSMS_LMAX) return fail(LSMS_E_ARG, "lmax must be %d (got %d)", LSMS_LMAX, lmax);
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (hip_device < 0 || hip_device >= ndev) return fail(LSMS_E_ARG, "hip_device %d out of range [0, %d)", hip_device, ndev);
+  HIP_TRY(hipSetDevice(hip_device));
+  std::unique_ptr<lsms_ctx> c(new (std::nothrow) lsms_ctx());
+  if (!c) return fail(LSMS_E_NOMEM, "host allocation failed");
+  c->device = hip_device;
+  if (workspace_limit == 0) {
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    workspace_limit = (size_t)(0.6 * (double)fr);
+  }
+  c->workspace_limit = workspace_limit;
+  int rc = build_gaunt(c->gaunt);
+  if (rc) return rc;
+  HIP_TRY(upload_gaunt(c->gaunt));
+  *out = c.release();
+  return LSMS_OK;
+}
+
+extern "C" int lsms_destroy(lsms_ctx* ctx) {
+  if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (ctx->work.p) hipFree(ctx->work.p);
+  if (ctx->small.p) hipFree(ctx->small.p);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  delete ctx;
+  return LSMS_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// LIZ construction (Sec. II.A, Fig. 1)
+// ---------------------------------------------------------------------------------
+static inline int64_t quant(double v) { return (int64_t)floor(v * 1e9 + 0.5); }
+
+extern "C" int lsms_build_liz(lsms_ctx* ctx, int32_t n_atoms, const double* pos, const double* cell, double r_liz,
+                              int64_t capacity, int64_t* liz_ptr, int32_t* liz_atom, double* liz_pos,
+                              int64_t* needed) {
+  (void)ctx;
+  if (!pos || !needed || !liz_ptr) return fail(LSMS_E_ARG, "NULL argument");
+  if (n_atoms <= 0) return fail(LSMS_E_ARG, "n_atoms must be positive");
+  if (!(r_liz > 0.0) || !std::isfinite(r_liz)) return fail(LSMS_E_ARG, "r_liz must be a positive finite number");
+  for (int64_t i = 0; i < 3 * (int64_t)n_atoms; ++i)
+    if (!std::isfinite(pos[i])) return fail(LSMS_E_ARG, "non-finite position");
+  double c[3][3] = {{0}};
+  double inv[3][3] = {{0}};
+  int K[3] = {0, 0, 0};
+  double h[3] = {0, 0, 0};
+  if (cell) {
+    for (int i = 0; i < 9; ++i) {
+      if (!std::isfinite(cell[i])) return fail(LSMS_E_ARG, "non-finite cell");
+      c[i / 3][i % 3] = cell[i];
+    }
+    double det = c[0][0] * (c[1][1] * c[2][2] - c[1][2] * c[2][1]) - c[0][1] * (c[1][0] * c[2][2] - c[1][2] * c[2][0]) +
+                 c[0][2] * (c[1][0] * c[2][1] - c[1][1] * c[2][0]);
+    if (fabs(det) < 1e-12) return fail(LSMS_E_ARG, "singular cell");
+    // inverse (columns map cartesian -> fractional): f = x * inv
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        int i1 = (j + 1) % 3, i2 = (j + 2) % 3, j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+        inv[i][j] = (c[i1][j1] * c[i2][j2] - c[i1][j2] * c[i2][j1]) / det;
+      }
+    for (int d = 0; d < 3; ++d) {
+      const double* e = c[(d + 1) % 3];
+      const double* f = c[(d + 2) % 3];
+      double cx = e[1] * f[2] - e[2] * f[1], cy = e[2] * f[0] - e[0] * f[2], cz = e[0] * f[1] - e[1] * f[0];
+      h[d] = fabs(det) / sqrt(cx * cx + cy * cy + cz * cz);
+      K[d] = (int)ceil(r_liz / h[d]) + 1;
+    }
+  }
+  const double r2max = r_liz * r_liz;
+  struct Mem {
+    int64_t k0, k1, k2, k3;
+    int32_t atom;
+    double d[3];
+  };
+  std::vector<Mem> mem;
+  std::vector<double> frac;
+  if (cell) {
+    frac.resize(3 * (size_t)n_atoms);
+    for (int j = 0; j < n_atoms; ++j)
+      for (int d = 0; d < 3; ++d)
+        frac[3 * j + d] = pos[3 * j] * inv[0][d] + pos[3 * j + 1] * inv[1][d] + pos[3 * j + 2] * inv[2][d];
+  }
+  int64_t total = 0;
+  liz_ptr[0] = 0;
+  for (int i = 0; i < n_atoms; ++i) {
+    mem.clear();
+    const double* pi = pos + 3 * (size_t)i;
+    for (int j = 0; j < n_atoms; ++j) {
+      const double* pj = pos + 3 * (size_t)j;
+      int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+      if (cell) {
+        for (int d = 0; d < 3; ++d) {
+          double f = frac[3 * j + d] - frac[3 * i + d];
+          lo[d] = std::max(-K[d], (int)ceil(-r_liz / h[d] - f) - 1);
+          hi[d] = std::min(K[d], (int)floor(r_liz / h[d] - f) + 1);
+        }
+      }
+      for (int n1 = lo[0]; n1 <= hi[0]; ++n1)
+        for (int n2 = lo[1]; n2 <= hi[1]; ++n2)
+          for (int n3 = lo[2]; n3 <= hi[2]; ++n3) {
+            double T[3];
+            for (int d = 0; d < 3; ++d) {
+              double t = (double)n1 * c[0][d] + (double)n2 * c[1][d];
+              T[d] = t + (double)n3 * c[2][d];
+            }
+            double dd[3];
+            for (int d = 0; d < 3; ++d) dd[d] = (pj[d] + T[d]) - pi[d];
+            double d2 = dd[0] * dd[0] + dd[1] * dd[1];
+            d2 = d2 + dd[2] * dd[2];
+            if (d2 < r2max) {
+              Mem m;
+              m.k0 = quant(d2);
+              m.k1 = quant(dd[0]);
+              m.k2 = quant(dd[1]);
+              m.k3 = quant(dd[2]);
+              m.atom = j;
+              m.d[0] = dd[0];
+              m.d[1] = dd[1];
+              m.d[2] = dd[2];
+              mem.push_back(m);
+            }
+          }
+    }
+    std::stable_sort(mem.begin(), mem.end(), [](const Mem& a, const Mem& b) {
+      if (a.k0 != b.k0) return a.k0 < b.k0;
+      if (a.k1 != b.k1) return a.k1 < b.k1;
+      if (a.k2 != b.k2) return a.k2 < b.k2;
+      return a.k3 < b.k3;
+    });
+    if (mem.empty() || mem[0].atom != i || mem[0].k0 != 0)
+      return fail(LSMS_E_ARG, "atom %d is not at the centre of its own LIZ", i);
+    if (mem.size() > 1) {
+      const Mem& m = mem[1];
+      double d2 = m.d[0] * m.d[0] + m.d[1] * m.d[1] + m.d[2] * m.d[2];
+      if (d2 < 1e-16) return fail(LSMS_E_ARG, "coincident sites near atom %d", i);
+    }
+    if ((int64_t)mem.size() > LSMS_MAX_LIZ)
+      return fail(LSMS_E_ARG, "LIZ of atom %d has %zu members (limit %d)", i, mem.size(), LSMS_MAX_LIZ);
+    if (total + (int64_t)mem.size() <= capacity && liz_atom && liz_pos) {
+      for (size_t q = 0; q < mem.size(); ++q) {
+        liz_atom[total + q] = mem[q].atom;
+        for (int d = 0; d < 3; ++d) liz_pos[3 * (total + q) + d] = mem[q].d[d];
+      }
+    }
+    total += (int64_t)mem.size();
+    liz_ptr[i + 1] = total;
+  }
+  *needed = total;
+  if (total > capacity || !liz_atom || !liz_pos)
+    return fail(LSMS_E_CAPACITY, "capacity %lld < needed %lld", (long long)capacity, (long long)total);
+  return LSMS_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// scheduling helpers
+// ---------------------------------------------------------------------------------
+static inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct JobBytes {
+  int64_t a, m, x, r, piv;
+};
+
+static JobBytes job_bytes(int npad, int precision) {
+  JobBytes b;
+  const int64_t n2 = (int64_t)npad * npad;
+  b.a = align_up(n2 * (precision == LSMS_SPLIT ? 8 : 16), 256);
+  b.m = precision == LSMS_SPLIT ? align_up(n2 * 16, 256) : 0;
+  b.x = align_up((int64_t)npad * NRHS_MAX * 16, 256);
+  b.r = precision == LSMS_SPLIT ? b.x : 0;
+  b.piv = align_up((int64_t)npad * 4, 256);
+  return b;
+}
+
+static int validate_liz_ptr(int32_t n_atoms, const int64_t* liz_ptr) {
+  if (n_atoms <= 0) return fail(LSMS_E_ARG, "n_atoms must be positive");
+  if (!liz_ptr) return fail(LSMS_E_ARG, "liz_ptr is NULL");
+  if (liz_ptr[0] != 0) return fail(LSMS_E_ARG, "liz_ptr[0] must be 0");
+  for (int i = 0; i < n_atoms; ++i) {
+    int64_t nl = liz_ptr[i + 1] - liz_ptr[i];
+    if (nl < 1 || nl > LSMS_MAX_LIZ) return fail(LSMS_E_ARG, "LIZ of atom %d has %lld members", i, (long long)nl);
+  }
+  return LSMS_OK;
+}
+
+// One wave: jobs [b, e) of the sorted job list share the workspace.
+struct Wave {
+  int b, e;
+  int64_t bytes;
+};
+
+static std::vector<Wave> make_waves(std::vector<JobDesc>& jobs, int precision, int64_t limit, bool single) {
+  std::vector<Wave> waves;
+  int b = 0;
+  int64_t acc = 0;
+  for (int j = 0; j < (int)jobs.size(); ++j) {
+    JobBytes jb = job_bytes(jobs[j].npad, precision);
+    int64_t need = jb.a + jb.m + jb.x + jb.r + jb.piv;
+    if (!single && j > b && (acc + need > limit || j - b >= 8192)) {
+      waves.push_back({b, j, acc});
+      b = j;
+      acc = 0;
+    }
+    acc += need;
+  }
+  waves.push_back({b, (int)jobs.size(), acc});
+  return waves;
+}
+
+// Offsets (complex elements for matrices / blocks, int32 elements for pivots) of every
+// job of a wave inside one allocation: [matrices | m64 | x | r | piv].
+static void layout_wave(std::vector<JobDesc>& jobs, const Wave& w, int precision, int64_t& bytes_a,
+                        int64_t& bytes_m, int64_t& bytes_x, int64_t& bytes_r, int64_t& bytes_p) {
+  bytes_a = bytes_m = bytes_x = bytes_r = bytes_p = 0;
+  for (int j = w.b; j < w.e; ++j) {
+    JobBytes jb = job_bytes(jobs[j].npad, precision);
+    jobs[j].a_off = bytes_a / (precision == LSMS_SPLIT ? 8 : 16);
+    bytes_a += jb.a;
+    jobs[j].m_off = precision == LSMS_SPLIT ? bytes_m / 16 : -1;
+    bytes_m += jb.m;
+    jobs[j].x_off = bytes_x / 16;
+    bytes_x += jb.x;
+    jobs[j].r_off = precision == LSMS_SPLIT ? bytes_r / 16 : -1;
+    bytes_r += jb.r;
+    jobs[j].piv_off = bytes_p / 4;
+    bytes_p += jb.piv;
+  }
+}
+
+static void energies(double e_fermi, double eta, double2& kp, double2& km) {
+  std::complex<double> z(e_fermi, eta);
+  std::complex<double> k = std::sqrt(z);
+  if (k.imag() < 0) k = -k;
+  kp = make_double2(k.real(), k.imag());
+  km = make_double2(-k.real(), k.imag());
+}
+
+// Refinement state per job: norms[j][0] = ||M||_inf, [1] = ||r||_inf, [2] = ||X||_inf, [3] = berr.
+namespace lsms {
+void launch_residual_norms(const JobDesc* jobs, int njobs, int npad_max, const double2* m64, const double2* x,
+                           double2* r, const double2* tpm, const int32_t* liz_atom, double* norms,
+                           const int32_t* done, hipStream_t s);
+void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double tol, int32_t* done, int last,
+                        int32_t* job_info, hipStream_t s);
+void launch_add_correction(const JobDesc* jobs, int njobs, int npad_max, double2* x, const double2* r,
+                           const int32_t* done, hipStream_t s);
+void launch_zero_i32(int32_t* p, int n, hipStream_t s);
+}  // namespace lsms
+
+// ---------------------------------------------------------------------------------
+// tau solve
+// ---------------------------------------------------------------------------------
+extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
+                              const double* liz_pos, const double* phase, double e_fermi, double eta, int precision,
+                              double refine_tol, int max_refine, void* tau_plus, void* tau_minus, int32_t* info,
+                              double* berr, lsms_factors** keep, void* hip_stream) {
+  if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  int rc = validate_liz_ptr(n_atoms, liz_ptr);
+  if (rc) return rc;
+  if (!liz_atom || !liz_pos || !phase || !tau_plus || !tau_minus || !info || !berr)
+    return fail(LSMS_E_ARG, "NULL device pointer");
+  if (!std::isfinite(e_fermi) || !(eta > 0.0) || !std::isfinite(eta))
+    return fail(LSMS_E_ARG, "e_fermi must be finite and eta positive");
+  if (precision != LSMS_FP64 && precision != LSMS_SPLIT) return fail(LSMS_E_ARG, "unknown precision %d", precision);
+  if (precision == LSMS_SPLIT && (!(refine_tol > 0.0) || max_refine < 0 || max_refine > 100))
+    return fail(LSMS_E_ARG, "refine_tol must be > 0 and 0 <= max_refine <= 100");
+  if (keep && precision != LSMS_FP64) return fail(LSMS_E_ARG, "keep (factors for the adjoint) needs LSMS_FP64");
+  if (keep) *keep = nullptr;
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  // jobs, sorted by size (largest first) so each wave is nearly uniform
+  std::vector<JobDesc> jobs;
+  jobs.reserve(2 * (size_t)n_atoms);
+  for (int a = 0; a < n_atoms; ++a) {
+    const int nl = (int)(liz_ptr[a + 1] - liz_ptr[a]);
+    for (int e = 0; e < 2; ++e) {
+      JobDesc j{};
+      j.liz_off = liz_ptr[a];
+      j.atom = a;
+      j.energy = e;
+      j.nl = nl;
+      j.n = NL * nl;
+      j.npad = (int)align_up(j.n, PAD);
+      jobs.push_back(j);
+    }
+  }
+  std::stable_sort(jobs.begin(), jobs.end(), [](const JobDesc& x, const JobDesc& y) { return x.npad > y.npad; });
+  const int64_t small_fixed = align_up((int64_t)n_atoms * 8 * 16, 256);  // tpm
+  const int64_t limit = (int64_t)ctx->workspace_limit;
+  std::vector<Wave> waves = make_waves(jobs, precision, limit, keep != nullptr);
+  int64_t max_wave = 0;
+  for (auto& w : waves) max_wave = std::max(max_wave, w.bytes);
+  if (max_wave > limit) {
+    return fail(LSMS_E_NOMEM, "a wave needs %lld bytes of workspace but the limit is %lld%s", (long long)max_wave,
+                (long long)limit, keep ? " (keep requires every factor to stay resident)" : "");
+  }
+  double2 kp, km;
+  energies(e_fermi, eta, kp, km);
+
+  // small per-call device arrays: tpm | jobdesc (all jobs) | job_info | norms | done
+  const int njobs_all = (int)jobs.size();
+  const int64_t off_jobs = small_fixed;
+  const int64_t off_info = off_jobs + align_up((int64_t)njobs_all * sizeof(JobDesc), 256);
+  const int64_t off_norm = off_info + align_up((int64_t)njobs_all * 4, 256);
+  const int64_t off_done = off_norm + align_up((int64_t)njobs_all * 8 * 8, 256);
+  const int64_t small_bytes = off_done + align_up((int64_t)njobs_all * 4, 256);
+
+  // lay out every wave now (offsets are relative to the wave's base)
+  std::vector<int64_t> wave_sizes(waves.size() * 5);
+  for (size_t w = 0; w < waves.size(); ++w)
+    layout_wave(jobs, waves[w], precision, wave_sizes[5 * w], wave_sizes[5 * w + 1], wave_sizes[5 * w + 2],
+                wave_sizes[5 * w + 3], wave_sizes[5 * w + 4]);
+
+  rc = ensure_pinned(ctx, (size_t)njobs_all * sizeof(JobDesc), s);
+  if (rc) return rc;
+  std::memcpy(ctx->pinned, jobs.data(), (size_t)njobs_all * sizeof(JobDesc));
+
+  // factors kept for the adjoint get their own allocation; otherwise the context's pool
+  char* wbase = nullptr;
+  char* sbase = nullptr;
+  std::unique_ptr<lsms_factors> fac;
+  if (keep) {
+    fac.reset(new lsms_factors());
+    fac->ctx = ctx;
+    fac->precision = precision;
+    fac->n_atoms = n_atoms;
+    fac->kp = kp;
+    fac->km = km;
+    fac->work_bytes = (size_t)(max_wave + small_bytes);
+    hipError_t e = hipMalloc(&fac->work, fac->work_bytes);
+    if (e != hipSuccess) return fail(LSMS_E_NOMEM, "hipMalloc(%zu) for kept factors failed", fac->work_bytes);
+    wbase = (char*)fac->work;
+    sbase = wbase + max_wave;
+  } else {
+    rc = ensure_dev(ctx->work, (size_t)max_wave, s);
+    if (rc) return rc;
+    rc = ensure_dev(ctx->small, (size_t)small_bytes, s);
+    if (rc) return rc;
+    wbase = (char*)ctx->work.p;
+    sbase = (char*)ctx->small.p;
+  }
+  double2* tpm = (double2*)sbase;
+  JobDesc* jobs_dev = (JobDesc*)(sbase + off_jobs);
+  int32_t* job_info = (int32_t*)(sbase + off_info);
+  double* norms = (double*)(sbase + off_norm);
+  int32_t* done = (int32_t*)(sbase + off_done);
+  HIP_TRY(hipMemcpyAsync(jobs_dev, ctx->pinned, (size_t)njobs_all * sizeof(JobDesc), hipMemcpyHostToDevice, s));
+  launch_tmatrix(phase, n_atoms, kp, tpm, s);
+
+  for (size_t w = 0; w < waves.size(); ++w) {
+    const Wave& wv = waves[w];
+    const int nj = wv.e - wv.b;
+    const int npad_max = jobs[wv.b].npad;
+    const JobDesc* jd = jobs_dev + wv.b;
+    int32_t* jinfo = job_info + wv.b;
+    double* jnorm = norms + 8 * (size_t)wv.b;
+    int32_t* jdone = done + wv.b;
+    char* p = wbase;
+    void* abuf = p;
+    p += wave_sizes[5 * w];
+    double2* m64 = (double2*)p;
+    p += wave_sizes[5 * w + 1];
+    double2* xbuf = (double2*)p;
+    p += wave_sizes[5 * w + 2];
+    double2* rbuf = (double2*)p;
+    p += wave_sizes[5 * w + 3];
+    int32_t* piv = (int32_t*)p;
+
+    GemmProfiler* prof = nullptr;
+    if (ctx->profiling) {
+      ctx->n_true.resize(nj);
+      for (int j = 0; j < nj; ++j) ctx->n_true[j] = jobs[wv.b + j].n;
+      ctx->prof.n_true = ctx->n_true.data();
+      prof = &ctx->prof;
+    }
+    launch_check_inputs(jd, nj, liz_pos, liz_atom, phase, jinfo, s);
+    launch_init_rhs(jd, nj, npad_max, liz_atom, tpm, xbuf, s);
+    if (precision == LSMS_FP64) {
+      launch_assemble_f64(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (double2*)abuf, s);
+      lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, s, prof);
+      lu_solve_f64(jd, nj, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
+      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, s);
+      launch_write_status(jd, nj, jinfo, nullptr, info, berr, s);
+    } else {
+      launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, m64, s);
+      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, s, prof);
+      lu_solve_f32(jd, nj, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
+      launch_zero_i32(jdone, nj, s);
+      launch_zero(jnorm, 8 * (int64_t)nj, s);
+      for (int it = 0; it <= max_refine; ++it) {
+        const int last = it == max_refine;
+        launch_residual_norms(jd, nj, npad_max, m64, xbuf, rbuf, tpm, liz_atom, jnorm, jdone, s);
+        launch_refine_step(jd, nj, jnorm, refine_tol, jdone, last, jinfo, s);
+        if (last) break;
+        lu_solve_f32_skip(jd, nj, (const float2*)abuf, piv, rbuf, jdone, s);
+        launch_add_correction(jd, nj, npad_max, xbuf, rbuf, jdone, s);
+      }
+      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, s);
+      launch_write_status(jd, nj, jinfo, jnorm, info, berr, s);
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  if (keep) {
+    fac->jobs = jobs;
+    fac->npad_max = jobs[0].npad;
+    fac->jobs_dev = jobs_dev;
+    fac->x_base = wave_sizes[0] + wave_sizes[1];
+    fac->piv_base = wave_sizes[0] + wave_sizes[1] + wave_sizes[2] + wave_sizes[3];
+    fac->liz_atom = liz_atom;
+    fac->total_members = liz_ptr[n_atoms];
+    *keep = fac.release();
+  }
+  return LSMS_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Kubo-Greenwood sum
+// ---------------------------------------------------------------------------------
+extern "C" int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
+                               const void* tau_plus, const void* tau_minus, const int32_t* species, int32_t n_species,
+                               const void* J, double volume, double* sigma, void* sigma_tilde, void* per_atom,
+                               void* hip_stream) {
+  if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  int rc = validate_liz_ptr(n_atoms, liz_ptr);
+  if (rc) return rc;
+  if (!liz_atom || !tau_plus || !tau_minus || !species || !J || !sigma || !sigma_tilde)
+    return fail(LSMS_E_ARG, "NULL device pointer");
+  if (n_species <= 0) return fail(LSMS_E_ARG, "n_species must be positive");
+  if (!(volume > 0.0) || !std::isfinite(volume)) return fail(LSMS_E_ARG, "volume must be positive");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int64_t off_pa = align_up((int64_t)(n_atoms + 1) * 8, 256);
+  const int64_t bytes = off_pa + align_up((int64_t)n_atoms * 12 * 16, 256);
+  rc = ensure_pinned(ctx, (size_t)(n_atoms + 1) * 8, s);
+  if (rc) return rc;
+  rc = ensure_dev(ctx->small, (size_t)bytes, s);
+  if (rc) return rc;
+  std::memcpy(ctx->pinned, liz_ptr, (size_t)(n_atoms + 1) * 8);
+  int64_t* ptr_dev = (int64_t*)ctx->small.p;
+  double2* pa = per_atom ? (double2*)per_atom : (double2*)((char*)ctx->small.p + off_pa);
+  HIP_TRY(hipMemcpyAsync(ptr_dev, ctx->pinned, (size_t)(n_atoms + 1) * 8, hipMemcpyHostToDevice, s));
+  launch_kubo_trace(n_atoms, ptr_dev, liz_atom, (const double2*)tau_plus, (const double2*)tau_minus, species,
+                    n_species, (const double2*)J, pa, s);
+  launch_kubo_reduce(n_atoms, pa, volume, sigma, (double2*)sigma_tilde, s);
+  HIP_TRY(hipGetLastError());
+  return LSMS_OK;
+}
+
+extern "C" int lsms_set_profiling(lsms_ctx* ctx, int on) {
+  if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipDeviceSynchronize());
+  ctx->profiling = on != 0;
+  ctx->prof.reset();
+  return LSMS_OK;
+}
+
+extern "C" int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launches, double* alg_flops) {
+  if (!ctx || !total_ms || !launches || !alg_flops) return fail(LSMS_E_ARG, "NULL argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  double ms = 0.0, fl = 0.0;
+  const size_t n = ctx->prof.flops.size();
+  for (size_t i = 0; i < n; ++i) {
+    hipEvent_t a = ctx->prof.pool[2 * i], b = ctx->prof.pool[2 * i + 1];
+    HIP_TRY(hipEventSynchronize(b));
+    float e = 0.f;
+    HIP_TRY(hipEventElapsedTime(&e, a, b));
+    ms += e;
+    fl += ctx->prof.flops[i];
+  }
+  *total_ms = ms;
+  *launches = (int64_t)n;
+  *alg_flops = fl;
+  return LSMS_OK;
+}
+
+extern "C" int lsms_factors_free(lsms_factors* f) {
+  if (!f) return fail(LSMS_E_ARG, "factors is NULL");
+  hipSetDevice(f->ctx->device);
+  hipDeviceSynchronize();
+  if (f->work) hipFree(f->work);
+  delete f;
+  return LSMS_OK;
+}
+
+extern "C" int lsms_kubo_sigma_grad(lsms_ctx* ctx, const lsms_factors* factors, int32_t n_atoms,
+                                    const int64_t* liz_ptr, const int32_t* liz_atom, const double* phase,
+                                    const void* tau_plus, const void* tau_minus, const int32_t* species,
+                                    int32_t n_species, const void* J, double volume, const double* dsigma,
+                                    double* dphase, void* hip_stream) {
+  if (!ctx || !factors) return fail(LSMS_E_ARG, "ctx or factors is NULL");
+  if (factors->ctx != ctx) return fail(LSMS_E_STATE, "factors belong to another context");
+  int rc = validate_liz_ptr(n_atoms, liz_ptr);
+  if (rc) return rc;
+  if (n_atoms != factors->n_atoms || liz_ptr[n_atoms] != factors->total_members)
+    return fail(LSMS_E_STATE, "inputs do not match the factored system");
+  if (!liz_atom || !phase || !tau_plus || !tau_minus || !species || !J || !dsigma || !dphase)
+    return fail(LSMS_E_ARG, "NULL device pointer");
+  if (n_species <= 0) return fail(LSMS_E_ARG, "n_species must be positive");
+  if (!(volume > 0.0) || !std::isfinite(volume)) return fail(LSMS_E_ARG, "volume must be positive");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int nj = (int)factors->jobs.size();
+  char* base = (char*)factors->work;
+  double2* abuf = (double2*)base;
+  double2* xbuf = (double2*)(base + factors->x_base);
+  int32_t* piv = (int32_t*)(base + factors->piv_base);
+  launch_zero(dphase, (int64_t)n_atoms * 4, s);
+  launch_adjoint_rhs(factors->jobs_dev, nj, factors->npad_max, liz_atom, (const double2*)tau_plus,
+                     (const double2*)tau_minus, species, n_species, (const double2*)J, dsigma, volume, xbuf, s);
+  lu_solve_f64(factors->jobs_dev, nj, abuf, piv, xbuf, 0, 32, 1, s);
+  launch_adjoint_contract(factors->jobs_dev, nj, factors->npad_max, liz_atom, phase, factors->kp, xbuf, dphase, s);
+  HIP_TRY(hipGetLastError());
+  return LSMS_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// diagnostic batched LU solve of caller matrices
+// ---------------------------------------------------------------------------------
+namespace lsms {
+void launch_load_user(const JobDesc* jobs, int njobs, int npad_max, void* const* A_dev, void* const* B_dev, int nrhs,
+                      int precision, void* work, double2* x, hipStream_t s);
+void launch_store_user(const JobDesc* jobs, int njobs, int npad_max, void* const* B_dev, int nrhs, const double2* x,
+                       hipStream_t s);
+}  // namespace lsms
+
+extern "C" int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t* n, void* const* A, void* const* B,
+                                     int32_t nrhs, int precision, int32_t* info, void* hip_stream) {
+  if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  if (batch <= 0 || !n || !A || !B || !info) return fail(LSMS_E_ARG, "NULL argument or empty batch");
+  if (nrhs < 1 || nrhs > 16) return fail(LSMS_E_ARG, "nrhs must be in [1, 16]");
+  if (precision != LSMS_FP64 && precision != LSMS_SPLIT) return fail(LSMS_E_ARG, "unknown precision");
+  for (int b = 0; b < batch; ++b) {
+    if (n[b] < 1 || n[b] > NL * LSMS_MAX_LIZ) return fail(LSMS_E_ARG, "n[%d] = %d out of range", b, n[b]);
+    if (!A[b] || !B[b]) return fail(LSMS_E_ARG, "NULL matrix pointer for system %d", b);
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::vector<JobDesc> jobs(batch);
+  int npad_max = 0;
+  for (int b = 0; b < batch; ++b) {
+    JobDesc j{};
+    j.atom = b;
+    j.n = n[b];
+    j.npad = (int)align_up(n[b], PAD);
+    j.nl = (n[b] + NL - 1) / NL;
+    npad_max = std::max(npad_max, j.npad);
+    jobs[b] = j;
+  }
+  Wave w{0, batch, 0};
+  int64_t ba, bm, bx, br, bp;
+  const int prec = precision == LSMS_SPLIT ? LSMS_SPLIT : LSMS_FP64;
+  layout_wave(jobs, w, prec, ba, bm, bx, br, bp);
+  const int64_t ptr_bytes = align_up((int64_t)batch * 16, 256);
+  const int64_t jd_bytes = align_up((int64_t)batch * sizeof(JobDesc), 256);
+  const int64_t total = ba + bx + bp + jd_bytes + 2 * ptr_bytes;
+  if (total > (int64_t)ctx->workspace_limit) return fail(LSMS_E_NOMEM, "batch needs %lld bytes", (long long)total);
+  int rc = ensure_dev(ctx->work, (size_t)total, s);
+  if (rc) return rc;
+  const size_t host_bytes = (size_t)jd_bytes + 2 * (size_t)ptr_bytes;
+  rc = ensure_pinned(ctx, host_bytes, s);
+  if (rc) return rc;
+  char* base = (char*)ctx->work.p;
+  void* abuf = base;
+  double2* xbuf = (double2*)(base + ba);
+  int32_t* piv = (int32_t*)(base + ba + bx);
+  JobDesc* jd = (JobDesc*)(base + ba + bx + bp);
+  void** aptr = (void**)(base + ba + bx + bp + jd_bytes);
+  void** bptr = (void**)(base + ba + bx + bp + jd_bytes + ptr_bytes);
+  char* hp = (char*)ctx->pinned;
+  std::memcpy(hp, jobs.data(), batch * sizeof(JobDesc));
+  std::memcpy(hp + jd_bytes, A, batch * sizeof(void*));
+  std::memcpy(hp + jd_bytes + ptr_bytes, B, batch * sizeof(void*));
+  HIP_TRY(hipMemcpyAsync(jd, hp, (size_t)host_bytes, hipMemcpyHostToDevice, s));
+  launch_zero_i32(info, batch, s);
+  launch_load_user(jd, batch, npad_max, aptr, bptr, nrhs, prec, abuf, xbuf, s);
+  if (prec == LSMS_FP64) {
+    lu_factor_f64(jd, batch, npad_max, (double2*)abuf, piv, info, s);
+    lu_solve_f64(jd, batch, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
+  } else {
+    lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s);
+    lu_solve_f32(jd, batch, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
+  }
+  launch_store_user(jd, batch, npad_max, bptr, nrhs, xbuf, s);
+  HIP_TRY(hipGetLastError());
+  // the pinned staging buffer must outlive the upload
+  HIP_TRY(hipStreamSynchronize(s));
+  return LSMS_OK;
+}

@@ -1,0 +1,146 @@
+// Internal declarations shared by the library's host and device translation units.
+// Nothing here is part of the C ABI (see include/lsms_kkr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lsms {
+
+constexpr int NL = 16;        // channels per site, lmax = 3
+constexpr int NL3 = 49;       // channels of the Gaunt-coupled harmonics, l'' <= 6
+constexpr int NB = 64;        // outer panel width of the blocked LU
+constexpr int PAD = 64;       // matrices are padded (identity) to a multiple of this
+constexpr int MAX_GAUNT = 1024;
+
+// Complex helpers (interleaved re, im) -------------------------------------------
+struct cd { double x, y; };
+
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+// a - b*c
+__host__ __device__ inline double2 cfms(double2 a, double2 b, double2 c) {
+  return make_double2(a.x - (b.x * c.x - b.y * c.y), a.y - (b.x * c.y + b.y * c.x));
+}
+// a + b*c
+__host__ __device__ inline double2 cfma(double2 a, double2 b, double2 c) {
+  return make_double2(a.x + (b.x * c.x - b.y * c.y), a.y + (b.x * c.y + b.y * c.x));
+}
+__host__ __device__ inline double2 cinv(double2 a) {
+  // Smith-style scaling avoids overflow for large components.
+  if (fabs(a.x) >= fabs(a.y)) {
+    double r = a.y / a.x, d = a.x + a.y * r;
+    return make_double2(1.0 / d, -r / d);
+  } else {
+    double r = a.x / a.y, d = a.y + a.x * r;
+    return make_double2(r / d, -1.0 / d);
+  }
+}
+
+// Storage conversions: the working matrix is complex double (FP64 mode) or
+// complex float (split mode); arithmetic in the panel and solves is FP64.
+__device__ inline double2 ld2(const double2* p) { return *p; }
+__device__ inline double2 ld2(const float2* p) {
+  float2 v = *p;
+  return make_double2((double)v.x, (double)v.y);
+}
+__device__ inline void st2(double2* p, double2 v) { *p = v; }
+__device__ inline void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
+// One (atom, energy) system.
+struct JobDesc {
+  int64_t a_off;    // working matrix (npad x npad, row-major, ld = npad), in complex elements
+  int64_t m_off;    // FP64 copy of M (split mode), in complex elements; -1 if absent
+  int64_t x_off;    // solution / right-hand-side block (npad x NRHS_MAX complex double)
+  int64_t r_off;    // residual / correction block (split mode), same shape; -1 if absent
+  int64_t piv_off;  // pivots (npad int32)
+  int64_t liz_off;  // first LIZ member of this atom
+  int32_t atom;     // atom index
+  int32_t energy;   // 0: z+ ; 1: z-
+  int32_t nl;       // LIZ members
+  int32_t n;        // NL * nl
+  int32_t npad;     // n rounded up to PAD
+  int32_t info;     // host-side scratch
+};
+
+constexpr int NRHS_MAX = 32;  // columns of the solution block (16 forward, 32 adjoint)
+
+struct GauntTable {
+  // CSR over the 256 (L, L') pairs: terms [start[p], start[p+1]) hold (L'', C).
+  int32_t start[NL * NL + 1];
+  int32_t l3[MAX_GAUNT];
+  double coef[MAX_GAUNT];
+};
+
+// ---- launchers (defined in the .hip files) ---------------------------------------
+hipError_t upload_gaunt(const GauntTable& g);
+
+// t_l(z+-) for every atom: tpm[atom][e][l] (complex), e = 0 (+), 1 (-).
+void launch_tmatrix(const double* phase, int n_atoms, double2 kappa_plus, double2* tpm, hipStream_t s);
+
+// M = 1 - T g over each job's LIZ (padded with identity), written to the working
+// matrix (double2 or float2) and, if m64 != nullptr, also to the FP64 copy.
+void launch_assemble_f64(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
+                         const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, double2* work,
+                         hipStream_t s);
+void launch_assemble_split(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
+                           const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, float2* work,
+                           double2* m64, hipStream_t s);
+// B = E0 t_centre in the solution block (first NL columns), zero elsewhere.
+void launch_init_rhs(const JobDesc* jobs, int njobs, int npad_max, const int32_t* liz_atom, const double2* tpm,
+                     double2* x, hipStream_t s);
+
+// Optional timing of the trailing-update launches (the dominant kernel): before()/after()
+// bracket every launch; n_true holds the unpadded size of each job of the wave (host),
+// from which the algorithmic flops of the launch (8 m^2 NB per job, m = n - k - NB) follow.
+struct GemmProfiler {
+  const int* n_true = nullptr;
+  virtual void before(hipStream_t s) = 0;
+  virtual void after(hipStream_t s, double alg_flops) = 0;
+  virtual ~GemmProfiler() {}
+};
+
+// Blocked LU with partial pivoting of every job's working matrix.
+void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
+                   hipStream_t s, GemmProfiler* prof = nullptr);
+void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
+                   hipStream_t s, GemmProfiler* prof = nullptr);
+// Solve with the factors: trans = 0 solves M X = B, trans = 1 solves M^T X = B (in place on X).
+void lu_solve_f64(const JobDesc* jobs, int njobs, const double2* work, const int32_t* piv, double2* x,
+                  int64_t x_col_off, int nrhs, int trans, hipStream_t s);
+void lu_solve_f32(const JobDesc* jobs, int njobs, const float2* work, const int32_t* piv, double2* x,
+                  int64_t x_col_off, int nrhs, int trans, hipStream_t s);
+
+// Split-mode refinement helpers.
+void launch_residual(const JobDesc* jobs, int njobs, int npad_max, const double2* m64, const double2* x,
+                     double2* r, double* norms, hipStream_t s);
+void launch_refine_update(const JobDesc* jobs, int njobs, double2* x, const double2* d, double* norms,
+                          double tol, int32_t* done, hipStream_t s);
+// Copy tau^{a0} (first n rows, NL columns) out of each job's solution block.
+void launch_copy_tau(const JobDesc* jobs, int njobs, int npad_max, const double2* x, double2* tau_plus,
+                     double2* tau_minus, hipStream_t s);
+void launch_write_status(const JobDesc* jobs, int njobs, const int32_t* job_info, const double* norms,
+                         int32_t* info, double* berr, hipStream_t s);
+void launch_check_inputs(const JobDesc* jobs, int njobs, const double* liz_pos, const int32_t* liz_atom,
+                         const double* phase, int32_t* job_info, hipStream_t s);
+
+// Kubo-Greenwood sums.
+void launch_kubo_trace(int n_atoms, const int64_t* liz_ptr_dev, const int32_t* liz_atom, const double2* tau_plus,
+                       const double2* tau_minus, const int32_t* species, int n_species, const double2* J,
+                       double2* per_atom, hipStream_t s);
+void launch_kubo_reduce(int n_atoms, const double2* per_atom, double volume, double* sigma, double2* sigma_tilde,
+                        hipStream_t s);
+
+// Adjoint.
+void launch_adjoint_rhs(const JobDesc* jobs, int njobs, int npad_max, const int32_t* liz_atom,
+                        const double2* tau_plus, const double2* tau_minus, const int32_t* species, int n_species,
+                        const double2* J, const double* dsigma, double volume, double2* x, hipStream_t s);
+void launch_adjoint_contract(const JobDesc* jobs, int njobs, int npad_max, const int32_t* liz_atom,
+                             const double* phase, double2 kappa_plus, const double2* x, double* dphase,
+                             hipStream_t s);
+void launch_zero(double* p, int64_t n, hipStream_t s);
+
+}  // namespace lsms

@@ -1,0 +1,493 @@
+// Batched complex LU with partial pivoting (the tau inverse of Eq. (3) is the dominant
+// cost of the method, Sec. II.A), right-looking and blocked with panel width NB.
+//
+// All jobs of a wave advance through the same panel steps; each step is three
+// launches over the whole batch:
+//   panel_kernel      one workgroup per job factors rows [k, n) x cols [k, k+NB) with
+//                     partial pivoting (pivot = largest |re|+|im|, first on ties) in FP64:
+//                     IB-wide leaves live in registers (rows distributed cyclically over
+//                     the workgroup), every pivot swaps the whole panel row, and the rest
+//                     of the panel is updated by the leaf (triangular solve + rank-IB).
+//   swap_trsm_kernel  applies the panel's row interchanges to the trailing columns and
+//                     forms U12 = L11^-1 A12 (one workgroup per 64-column tile).
+//   gemm_*_kernel     trailing update A22 -= L21 U12 on the matrix cores:
+//                     FP64 MFMA 16x16x4 with the four real products of a complex product,
+//                     or (split mode) FP32 MFMA 16x16x4 with three real products
+//                     (Ar Br, Ai Bi, (Ar+Ai)(Br+Bi)).
+// Interchanges are applied only to the right of each panel; the solves apply them
+// panel by panel in the same order, so the left columns never need swapping.
+// Matrices are row-major with leading dimension npad (a multiple of 64); the padding
+// is an identity block that no pivot ever selects.
+#include "lsms_internal.h"
+
+namespace lsms {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------------------------
+// panel factorization
+// ------------------------------------------------------------------------------------
+template <typename T, int PT, int S, int IB>
+__global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, T* work, int32_t* piv,
+                                                   int32_t* info) {
+  const JobDesc jd = jobs[blockIdx.x];
+  if (k >= jd.npad) return;  // uniform over the workgroup
+  T* A = work + jd.a_off;
+  const int64_t ld = jd.npad;
+  const int nrows = jd.npad;
+  int32_t* ip = piv + jd.piv_off;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  constexpr int NW = PT / 64;
+
+  __shared__ double2 s_prow[IB], s_drow[IB];
+  __shared__ double s_rv[NW];
+  __shared__ int s_rr[NW];
+  __shared__ int s_piv[IB];
+  __shared__ double2 s_L11[IB][IB];
+  __shared__ double2 s_U[IB][NB];
+  __shared__ double2 s_Lc[PT][IB];
+
+  double2 v[S][IB];
+  int first_zero = 0;
+
+  for (int c = 0; c < NB / IB; ++c) {
+    const int cl = k + c * IB;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int r = k + t + s * PT;
+#pragma unroll
+      for (int q = 0; q < IB; ++q)
+        v[s][q] = (r >= cl && r < nrows) ? ld2(A + r * ld + cl + q) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < IB; ++j) {
+      const int d = cl + j;
+      // NaN magnitudes never win a comparison; the diagonal row is the fallback pivot, so
+      // the chosen row is always inside the matrix even for non-finite input
+      double best = -1.0;
+      int brow = d;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = k + t + s * PT;
+        if (r >= d && r < nrows) {
+          const double a = fabs(v[s][j].x) + fabs(v[s][j].y);
+          if (a > best) {
+            best = a;
+            brow = r;
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int orow = __shfl_xor(brow, off);
+        if (ob > best || (ob == best && orow < brow)) {
+          best = ob;
+          brow = orow;
+        }
+      }
+      if (lane == 0) {
+        s_rv[wave] = best;
+        s_rr[wave] = brow;
+      }
+      __syncthreads();
+      best = s_rv[0];
+      brow = s_rr[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        const double ob = s_rv[w];
+        const int orow = s_rr[w];
+        if (ob > best || (ob == best && orow < brow)) {
+          best = ob;
+          brow = orow;
+        }
+      }
+      const int p = (brow >= d && brow < nrows) ? brow : d;
+      const int od = (d - k) % PT, sd = (d - k) / PT;
+      const int op = (p - k) % PT, sp = (p - k) / PT;
+      if (t == op) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (s == sp) {
+#pragma unroll
+            for (int q = 0; q < IB; ++q) s_prow[q] = v[s][q];
+          }
+      }
+      if (t == od) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (s == sd) {
+#pragma unroll
+            for (int q = 0; q < IB; ++q) s_drow[q] = v[s][q];
+          }
+      }
+      if (t == 0) {
+        s_piv[j] = p;
+        ip[d] = p;
+      }
+      __syncthreads();
+      if (t == od) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (s == sd) {
+#pragma unroll
+            for (int q = 0; q < IB; ++q) v[s][q] = s_prow[q];
+          }
+      }
+      if (t == op && p != d) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (s == sp) {
+#pragma unroll
+            for (int q = 0; q < IB; ++q) v[s][q] = s_drow[q];
+          }
+      }
+      const double2 pv = s_prow[j];
+      const bool zero = (pv.x == 0.0 && pv.y == 0.0);
+      if (zero && first_zero == 0) first_zero = d + 1;
+      const double2 inv = zero ? make_double2(0.0, 0.0) : cinv(pv);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = k + t + s * PT;
+        if (r > d && r < nrows) {
+          const double2 l = cmul(v[s][j], inv);
+          v[s][j] = l;
+#pragma unroll
+          for (int q = j + 1; q < IB; ++q) v[s][q] = cfms(v[s][q], l, s_prow[q]);
+        }
+      }
+    }
+    // leaf back to memory, its diagonal block to LDS
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int r = k + t + s * PT;
+      if (r >= cl && r < nrows) {
+#pragma unroll
+        for (int q = 0; q < IB; ++q) st2(A + r * ld + cl + q, v[s][q]);
+      }
+      if (r >= cl && r < cl + IB) {
+#pragma unroll
+        for (int q = 0; q < IB; ++q) s_L11[r - cl][q] = v[s][q];
+      }
+    }
+    __syncthreads();
+    // the leaf's interchanges on the other columns of the panel (whole panel rows)
+    for (int cc = t; cc < NB - IB; cc += PT) {
+      const int col = k + (cc < c * IB ? cc : cc + IB);
+      for (int q = 0; q < IB; ++q) {
+        const int d = cl + q, p = s_piv[q];
+        if (p != d && p > d && p < nrows) {
+          const double2 x = ld2(A + d * ld + col);
+          const double2 y = ld2(A + p * ld + col);
+          st2(A + d * ld + col, y);
+          st2(A + p * ld + col, x);
+        }
+      }
+    }
+    __syncthreads();
+    const int w = k + NB - cl - IB;  // panel columns right of the leaf
+    if (w > 0) {
+      for (int cc = t; cc < w; cc += PT) {
+        const int col = cl + IB + cc;
+        double2 u[IB];
+#pragma unroll
+        for (int q = 0; q < IB; ++q) {
+          u[q] = ld2(A + (cl + q) * ld + col);
+#pragma unroll
+          for (int pp = 0; pp < q; ++pp) u[q] = cfms(u[q], s_L11[q][pp], u[pp]);
+        }
+#pragma unroll
+        for (int q = 0; q < IB; ++q) {
+          st2(A + (cl + q) * ld + col, u[q]);
+          s_U[q][cc] = u[q];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r0 = k + s * PT;
+        if (r0 < nrows && r0 + PT > cl + IB) {
+          {
+            const int r = r0 + t;
+#pragma unroll
+            for (int q = 0; q < IB; ++q) s_Lc[t][q] = v[s][q];
+            (void)r;
+          }
+          __syncthreads();
+          for (int idx = t; idx < PT * w; idx += PT) {
+            const int rr = idx / w, cc = idx - rr * w;
+            const int row = r0 + rr;
+            if (row >= cl + IB && row < nrows) {
+              const int col = cl + IB + cc;
+              double2 acc = ld2(A + row * ld + col);
+#pragma unroll
+              for (int q = 0; q < IB; ++q) acc = cfms(acc, s_Lc[rr][q], s_U[q][cc]);
+              st2(A + row * ld + col, acc);
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+  }
+  if (t == 0 && first_zero != 0) {
+    if (info[blockIdx.x] == 0) info[blockIdx.x] = first_zero;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// interchanges + U12 = L11^-1 A12 on one 64-column tile of the trailing matrix
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int k, T* work, const int32_t* piv) {
+  const JobDesc jd = jobs[blockIdx.y];
+  const int col0 = k + NB + blockIdx.x * 64;
+  if (col0 >= jd.npad) return;  // uniform
+  T* A = work + jd.a_off;
+  const int64_t ld = jd.npad;
+  const int t = threadIdx.x;
+  __shared__ int s_piv[NB];
+  __shared__ double2 s_L[NB][NB + 1];
+  __shared__ double2 s_X[NB][64 + 1];
+  if (t < NB) s_piv[t] = piv[jd.piv_off + k + t];
+  for (int idx = t; idx < NB * NB; idx += 256) {
+    const int q = idx / NB, pp = idx % NB;
+    s_L[q][pp] = pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (t < 64) {
+    const int col = col0 + t;
+    for (int q = 0; q < NB; ++q) {
+      const int d = k + q, p = s_piv[q];
+      if (p != d && p > d && p < jd.npad) {
+        const double2 x = ld2(A + d * ld + col);
+        const double2 y = ld2(A + p * ld + col);
+        st2(A + d * ld + col, y);
+        st2(A + p * ld + col, x);
+      }
+    }
+  }
+  __syncthreads();  // the interchanges above must land before the tile is read
+  // forward substitution on the tile held in LDS: row r is final once rows < r are done
+  for (int idx = t; idx < NB * 64; idx += 256) {
+    const int q = idx >> 6, c = idx & 63;
+    s_X[q][c] = ld2(A + (k + q) * ld + col0 + c);
+  }
+  const int c = t & 63, g = t >> 6;
+  for (int r = 0; r < NB - 1; ++r) {
+    __syncthreads();
+    const double2 xr = s_X[r][c];
+    for (int q = r + 1 + g; q < NB; q += 4) s_X[q][c] = cfms(s_X[q][c], s_L[q][r], xr);
+  }
+  __syncthreads();
+  for (int idx = t; idx < NB * 64; idx += 256) {
+    const int q = idx >> 6, cc = idx & 63;
+    st2(A + (k + q) * ld + col0 + cc, s_X[q][cc]);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// trailing update A22 -= L21 U12, FP64 MFMA (4 real products per complex product)
+// 64 x 64 complex tile per workgroup, 4 waves of 32 x 32, K = NB in chunks of 16.
+// v_mfma_f64_16x16x4: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);
+// D lane l, register r -> (row l/16 + 4r, col l%16).
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const JobDesc* jobs, int k, double2* work) {
+  const JobDesc jd = jobs[blockIdx.z];
+  const int row0 = k + NB + blockIdx.y * 64, col0 = k + NB + blockIdx.x * 64;
+  if (row0 >= jd.npad || col0 >= jd.npad) return;  // uniform
+  double2* A = work + jd.a_off;
+  const int64_t ld = jd.npad;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  __shared__ double2 sA[16][64 + 1];
+  __shared__ double2 sB[16][64 + 1];
+  d4 are[2][2], aim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      are[i][j] = d4{0, 0, 0, 0};
+      aim[i][j] = d4{0, 0, 0, 0};
+    }
+  const int ii = lane & 15, kq = lane >> 4;
+  for (int kc = 0; kc < NB; kc += 16) {
+    {
+      const int i = t >> 2, k4 = (t & 3) * 4;
+      const double2* src = A + (row0 + i) * ld + k + kc + k4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sA[k4 + u][i] = src[u];
+      const int kk = t >> 4, j4 = (t & 15) * 4;
+      const double2* srb = A + (k + kc + kk) * ld + col0 + j4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sB[kk][j4 + u] = srb[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      double2 a[2], b[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) a[rb] = sA[k4 + kq][wr * 32 + rb * 16 + ii];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) b[cb] = sB[k4 + kq][wc * 32 + cb * 16 + ii];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          are[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb].x, b[cb].x, are[rb][cb], 0, 0, 0);
+          are[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[rb].y, b[cb].y, are[rb][cb], 0, 0, 0);
+          aim[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb].x, b[cb].y, aim[rb][cb], 0, 0, 0);
+          aim[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb].y, b[cb].x, aim[rb][cb], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wr * 32 + rb * 16 + kq + 4 * r;
+        const int col = col0 + wc * 32 + cb * 16 + ii;
+        double2* cp = A + row * ld + col;
+        double2 cv = *cp;
+        cv.x -= are[rb][cb][r];
+        cv.y -= aim[rb][cb][r];
+        *cp = cv;
+      }
+}
+
+// ------------------------------------------------------------------------------------
+// trailing update, split mode: FP32 storage, FP32 MFMA with three real products.
+// v_mfma_f32_16x16x4: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);
+// D lane l, register r -> (row 4(l/16) + r, col l%16).
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, int k, float2* work) {
+  const JobDesc jd = jobs[blockIdx.z];
+  const int row0 = k + NB + blockIdx.y * 64, col0 = k + NB + blockIdx.x * 64;
+  if (row0 >= jd.npad || col0 >= jd.npad) return;  // uniform
+  float2* A = work + jd.a_off;
+  const int64_t ld = jd.npad;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  __shared__ float2 sA[16][64 + 1];
+  __shared__ float2 sB[16][64 + 1];
+  f4 t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      t1[i][j] = f4{0, 0, 0, 0};
+      t2[i][j] = f4{0, 0, 0, 0};
+      t3[i][j] = f4{0, 0, 0, 0};
+    }
+  const int ii = lane & 15, kq = lane >> 4;
+  for (int kc = 0; kc < NB; kc += 16) {
+    {
+      const int i = t >> 2, k4 = (t & 3) * 4;
+      const float2* src = A + (row0 + i) * ld + k + kc + k4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sA[k4 + u][i] = src[u];
+      const int kk = t >> 4, j4 = (t & 15) * 4;
+      const float2* srb = A + (k + kc + kk) * ld + col0 + j4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sB[kk][j4 + u] = srb[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      float2 a[2], b[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) a[rb] = sA[k4 + kq][wr * 32 + rb * 16 + ii];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) b[cb] = sB[k4 + kq][wc * 32 + cb * 16 + ii];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          t1[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb].x, b[cb].x, t1[rb][cb], 0, 0, 0);
+          t2[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb].y, b[cb].y, t2[rb][cb], 0, 0, 0);
+          t3[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb].x + a[rb].y, b[cb].x + b[cb].y, t3[rb][cb],
+                                                            0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wr * 32 + rb * 16 + 4 * kq + r;
+        const int col = col0 + wc * 32 + cb * 16 + ii;
+        float2* cp = A + row * ld + col;
+        float2 cv = *cp;
+        cv.x -= t1[rb][cb][r] - t2[rb][cb][r];
+        cv.y -= t3[rb][cb][r] - t1[rb][cb][r] - t2[rb][cb][r];
+        *cp = cv;
+      }
+}
+
+// ------------------------------------------------------------------------------------
+// drivers
+// ------------------------------------------------------------------------------------
+template <typename T>
+static void launch_panel(const JobDesc* jobs, int njobs, int k, int rows, T* work, int32_t* piv, int32_t* info,
+                         hipStream_t s) {
+  constexpr int PT = 512;
+  const int S = (rows + PT - 1) / PT;
+  switch (S) {
+    case 1: panel_kernel<T, PT, 1, 8><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
+    case 2: panel_kernel<T, PT, 2, 8><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
+    case 3: panel_kernel<T, PT, 3, 8><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
+    case 4: panel_kernel<T, PT, 4, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
+    case 5: panel_kernel<T, PT, 5, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
+    case 6: panel_kernel<T, PT, 6, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
+    case 7: panel_kernel<T, PT, 7, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
+    default: panel_kernel<T, PT, 8, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
+  }
+}
+
+static double step_flops(const GemmProfiler* prof, int njobs, int k) {
+  double f = 0.0;
+  for (int j = 0; j < njobs; ++j) {
+    const double m = (double)(prof->n_true[j] - k - NB);
+    if (m > 0) f += 8.0 * m * m * NB;
+  }
+  return f;
+}
+
+void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
+                   hipStream_t s, GemmProfiler* prof) {
+  for (int k = 0; k < npad_max; k += NB) {
+    launch_panel<double2>(jobs, njobs, k, npad_max - k, work, piv, info, s);
+    const int rest = npad_max - k - NB;
+    if (rest > 0) {
+      const int tiles = rest / 64;
+      swap_trsm_kernel<double2><<<dim3(tiles, njobs), 256, 0, s>>>(jobs, k, work, piv);
+      if (prof) prof->before(s);
+      gemm_f64_kernel<<<dim3(tiles, tiles, njobs), 256, 0, s>>>(jobs, k, work);
+      if (prof) prof->after(s, step_flops(prof, njobs, k));
+    }
+  }
+}
+
+void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
+                   hipStream_t s, GemmProfiler* prof) {
+  for (int k = 0; k < npad_max; k += NB) {
+    launch_panel<float2>(jobs, njobs, k, npad_max - k, work, piv, info, s);
+    const int rest = npad_max - k - NB;
+    if (rest > 0) {
+      const int tiles = rest / 64;
+      swap_trsm_kernel<float2><<<dim3(tiles, njobs), 256, 0, s>>>(jobs, k, work, piv);
+      if (prof) prof->before(s);
+      gemm_f32_3m_kernel<<<dim3(tiles, tiles, njobs), 256, 0, s>>>(jobs, k, work);
+      if (prof) prof->after(s, step_flops(prof, njobs, k));
+    }
+  }
+}
+
+}  // namespace lsms

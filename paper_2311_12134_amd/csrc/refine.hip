@@ -1,0 +1,223 @@
+// FP64 iterative refinement for the split-precision solve, and the copy kernels of
+// the diagnostic batched-solve entry point.
+//
+// Classical mixed-precision iterative refinement (Wilkinson; Moler 1967): with FP32
+// factors of M, repeat  r = B - M X (FP64, M kept in FP64),  d = U^-1 L^-1 P r (FP32
+// factors, FP64 arithmetic),  X += d,  until the normwise backward error
+//   berr = ||r||_inf / (||M||_inf ||X||_inf + ||B||_inf)
+// reaches the requested tolerance.  B = E0 t_centre is regenerated from the t-matrix.
+// Per-job norms live in norms[job][8]: 0 ||M||, 1 ||r||, 2 ||X||, 3 berr, 4 ||B||.
+#include "lsms_internal.h"
+
+namespace lsms {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void atomic_max_nonneg(double* addr, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ inline double cabs2(double2 v) { return sqrt(v.x * v.x + v.y * v.y); }
+
+// r = B - M X for 64 rows x 16 columns per workgroup; M X on FP64 MFMA (4 real products).
+__global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, const double2* m64, const double2* x,
+                                                       double2* r, const double2* tpm, const int32_t* liz_atom,
+                                                       double* norms, const int32_t* done) {
+  const int job = blockIdx.y;
+  if (done[job]) return;
+  const JobDesc jd = jobs[job];
+  const int row0 = blockIdx.x * 64;
+  if (row0 >= jd.npad) return;
+  const double2* M = m64 + jd.m_off;
+  const double2* X = x + jd.x_off;
+  double2* R = r + jd.x_off;  // residual blocks mirror the solution blocks' offsets
+  const int npad = jd.npad;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  __shared__ double2 sM[64][16 + 1];
+  __shared__ double2 sX[16][16 + 1];
+  __shared__ double s_max[3][4];
+  d4 are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+  double rowabs = 0.0;
+  for (int kc = 0; kc < npad; kc += 16) {
+    {
+      const int i = t >> 2, k4 = (t & 3) * 4;
+      const double2* src = M + (int64_t)(row0 + i) * npad + kc + k4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 v = src[u];
+        sM[i][k4 + u] = v;
+        rowabs += cabs2(v);
+      }
+      const int kk = t >> 4, c = t & 15;
+      sX[kk][c] = X[(int64_t)(kc + kk) * NRHS_MAX + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      const double2 a = sM[wave * 16 + (lane & 15)][k4 + (lane >> 4)];
+      const double2 b = sX[k4 + (lane >> 4)][lane & 15];
+      are = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, are, 0, 0, 0);
+      are = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, are, 0, 0, 0);
+      aim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, aim, 0, 0, 0);
+      aim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, aim, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // ||M||_inf over this tile's rows: four threads share a row
+  rowabs += __shfl_xor(rowabs, 1);
+  rowabs += __shfl_xor(rowabs, 2);
+  double mmax = rowabs;
+  // residual entries: lane l, register q -> row 16*wave + l/16 + 4q, column l%16
+  const int col = lane & 15;
+  const double2 tc = (col < NL) ? tpm[liz_atom[jd.liz_off] * 8 + jd.energy * 4 +
+                                      (col == 0 ? 0 : (col < 4 ? 1 : (col < 9 ? 2 : 3)))]
+                                : make_double2(0, 0);
+  double rmax = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int row = row0 + wave * 16 + (lane >> 4) + 4 * q;
+    double2 b = (row == col) ? tc : make_double2(0.0, 0.0);
+    double2 rv = make_double2(b.x - are[q], b.y - aim[q]);
+    R[(int64_t)row * NRHS_MAX + col] = rv;
+    double a = cabs2(rv);
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) a += __shfl_xor(a, o);
+    rmax = fmax(rmax, a);
+  }
+  // ||X||_inf over the tile's rows
+  double xmax = 0.0;
+  if (t < 64) {
+    double s = 0.0;
+    for (int c = 0; c < 16; ++c) s += cabs2(X[(int64_t)(row0 + t) * NRHS_MAX + c]);
+    xmax = s;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    mmax = fmax(mmax, __shfl_xor(mmax, o));
+    rmax = fmax(rmax, __shfl_xor(rmax, o));
+    xmax = fmax(xmax, __shfl_xor(xmax, o));
+  }
+  if (lane == 0) {
+    s_max[0][wave] = mmax;
+    s_max[1][wave] = rmax;
+    s_max[2][wave] = xmax;
+  }
+  __syncthreads();
+  if (t < 3) {
+    double v = fmax(fmax(s_max[t][0], s_max[t][1]), fmax(s_max[t][2], s_max[t][3]));
+    atomic_max_nonneg(norms + job * 8 + t, v);
+  }
+  if (t == 3 && row0 == 0) {
+    double b = 0.0;
+    for (int l = 0; l < 4; ++l) b = fmax(b, cabs2(tpm[liz_atom[jd.liz_off] * 8 + jd.energy * 4 + l]));
+    norms[job * 8 + 4] = b;
+  }
+}
+
+void launch_residual_norms(const JobDesc* jobs, int njobs, int npad_max, const double2* m64, const double2* x,
+                           double2* r, const double2* tpm, const int32_t* liz_atom, double* norms,
+                           const int32_t* done, hipStream_t s) {
+  dim3 grid(npad_max / 64, njobs);
+  residual_kernel<<<grid, 256, 0, s>>>(jobs, m64, x, r, tpm, liz_atom, norms, done);
+}
+
+__global__ void refine_step_kernel(int njobs, double* norms, double tol, int32_t* done, int last,
+                                   int32_t* job_info) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= njobs || done[j]) return;
+  double* nm = norms + j * 8;
+  const double berr = nm[1] / (nm[0] * nm[2] + nm[4]);
+  nm[3] = berr;
+  if (berr <= tol) {
+    done[j] = 1;
+  } else if (last) {
+    if (job_info[j] == 0) job_info[j] = -1;
+  }
+  nm[0] = 0.0;
+  nm[1] = 0.0;
+  nm[2] = 0.0;
+}
+
+void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double tol, int32_t* done, int last,
+                        int32_t* job_info, hipStream_t s) {
+  (void)jobs;
+  refine_step_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(njobs, norms, tol, done, last, job_info);
+}
+
+__global__ void add_correction_kernel(const JobDesc* jobs, double2* x, const double2* r, const int32_t* done) {
+  const int job = blockIdx.y;
+  if (done[job]) return;
+  const JobDesc jd = jobs[job];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= jd.npad * NL) return;
+  const int row = idx / NL, c = idx % NL;
+  const int64_t o = jd.x_off + (int64_t)row * NRHS_MAX + c;
+  x[o] = cadd(x[o], r[o]);
+}
+
+void launch_add_correction(const JobDesc* jobs, int njobs, int npad_max, double2* x, const double2* r,
+                           const int32_t* done, hipStream_t s) {
+  dim3 grid((npad_max * NL + 255) / 256, njobs);
+  add_correction_kernel<<<grid, 256, 0, s>>>(jobs, x, r, done);
+}
+
+__global__ void zero_i32_kernel(int32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+void launch_zero_i32(int32_t* p, int n, hipStream_t s) {
+  if (n <= 0) return;
+  zero_i32_kernel<<<(n + 255) / 256, 256, 0, s>>>(p, n);
+}
+
+// diagnostic entry: caller matrices (row-major n x n, complex double) into padded work
+template <typename T>
+__global__ void load_user_kernel(const JobDesc* jobs, void* const* A_dev, void* const* B_dev, int nrhs, T* work,
+                                 double2* x) {
+  const JobDesc jd = jobs[blockIdx.y];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n2 = (int64_t)jd.npad * jd.npad;
+  const double2* A = (const double2*)A_dev[jd.atom];
+  const double2* B = (const double2*)B_dev[jd.atom];
+  if (idx < n2) {
+    const int row = (int)(idx / jd.npad), col = (int)(idx % jd.npad);
+    double2 v;
+    if (row < jd.n && col < jd.n)
+      v = A[(int64_t)row * jd.n + col];
+    else
+      v = make_double2(row == col ? 1.0 : 0.0, 0.0);
+    st2(work + jd.a_off + idx, v);
+  }
+  if (idx < (int64_t)jd.npad * NRHS_MAX) {
+    const int row = (int)(idx / NRHS_MAX), col = (int)(idx % NRHS_MAX);
+    x[jd.x_off + idx] = (row < jd.n && col < nrhs) ? B[(int64_t)row * nrhs + col] : make_double2(0.0, 0.0);
+  }
+}
+
+void launch_load_user(const JobDesc* jobs, int njobs, int npad_max, void* const* A_dev, void* const* B_dev, int nrhs,
+                      int precision, void* work, double2* x, hipStream_t s) {
+  const int64_t n2 = (int64_t)npad_max * npad_max;
+  dim3 grid((unsigned)((n2 + 255) / 256), njobs);
+  if (precision == 1)
+    load_user_kernel<float2><<<grid, 256, 0, s>>>(jobs, A_dev, B_dev, nrhs, (float2*)work, x);
+  else
+    load_user_kernel<double2><<<grid, 256, 0, s>>>(jobs, A_dev, B_dev, nrhs, (double2*)work, x);
+}
+
+__global__ void store_user_kernel(const JobDesc* jobs, void* const* B_dev, int nrhs, const double2* x) {
+  const JobDesc jd = jobs[blockIdx.y];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= jd.n * nrhs) return;
+  const int row = idx / nrhs, col = idx % nrhs;
+  ((double2*)B_dev[jd.atom])[idx] = x[jd.x_off + (int64_t)row * NRHS_MAX + col];
+}
+
+void launch_store_user(const JobDesc* jobs, int njobs, int npad_max, void* const* B_dev, int nrhs, const double2* x,
+                       hipStream_t s) {
+  dim3 grid((npad_max * nrhs + 255) / 256, njobs);
+  store_user_kernel<<<grid, 256, 0, s>>>(jobs, B_dev, nrhs, x);
+}
+
+}  // namespace lsms

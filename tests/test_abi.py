@@ -1,0 +1,104 @@
+"""CPU checks of the C ABI library: it loads, exports every declared symbol, and its
+host-side pieces (Gaunt table, LIZ construction, argument checking) match the oracle."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import liz as oliz
+from oracle import special
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(lsms_\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2311_12134_amd import _lib
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    names = _declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib._PROTOS), "ctypes prototypes and header disagree"
+
+
+def test_gaunt_table_matches_oracle():
+    import paper_2311_12134_amd as P
+    G = P.gaunt_table()
+    C = special.gaunt_table(3, 3, 6)
+    assert np.abs(G - C).max() < 1e-14
+    assert (np.abs(G) > 0).sum() == 708
+
+
+@pytest.mark.parametrize("name", ["fcc32", "bcc16", "bcc250", "bcc1940"])
+def test_liz_matches_oracle_exactly(name):
+    import paper_2311_12134_amd as P
+    w = synthetic.workload(name)
+    L = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    o = oliz.build_liz(w["pos"], w["cell"], w["r_liz"])
+    assert np.array_equal(L.ptr, o[0])
+    assert np.array_equal(L.atom, o[1])
+    assert np.array_equal(L.pos, o[2])  # bitwise: same IEEE operations in the same order
+
+
+def test_liz_fcc4000_sizes():
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("fcc4000")
+    L = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    assert (np.diff(L.ptr) == 135).all()
+
+
+def test_liz_open_cluster():
+    import paper_2311_12134_amd as P
+    pos = np.array([[0, 0, 0], [3.0, 0, 0], [0, 4.0, 0], [10.0, 0, 0]])
+    L = P.build_liz(pos, None, 5.5)
+    o = oliz.build_liz(pos, None, 5.5)
+    assert np.array_equal(L.ptr, o[0]) and np.array_equal(L.atom, o[1]) and np.array_equal(L.pos, o[2])
+
+
+def test_liz_argument_errors():
+    import paper_2311_12134_amd as P
+    from paper_2311_12134_amd._lib import LsmsError
+    with pytest.raises(LsmsError) as e:
+        P.build_liz(np.zeros((2, 3)), None, 1.0)
+    assert e.value.code == -1 and "coincident" in str(e.value)
+    with pytest.raises(LsmsError):
+        P.build_liz(np.zeros((1, 3)), None, -1.0)
+    with pytest.raises(LsmsError):
+        P.build_liz(np.array([[np.nan, 0, 0]]), None, 1.0)
+    pos, cell = synthetic.fcc_supercell(7.0, 4)
+    with pytest.raises(LsmsError):
+        P.build_liz(pos, cell, 4.0 * 7.0)  # > 256 members
+
+
+def test_liz_capacity_reporting():
+    from paper_2311_12134_amd._lib import lib
+    pos, cell = synthetic.fcc_supercell(7.7, 2)
+    ptr = np.zeros(33, dtype=np.int64)
+    needed = ctypes.c_int64(0)
+    atom = np.zeros(10, dtype=np.int32)
+    disp = np.zeros((10, 3))
+    rc = lib().lsms_build_liz(None, 32, pos.ctypes.data_as(ctypes.c_void_p), cell.ctypes.data_as(ctypes.c_void_p),
+                              1.1 * 7.7, 10, ptr.ctypes.data_as(ctypes.c_void_p), atom.ctypes.data_as(ctypes.c_void_p),
+                              disp.ctypes.data_as(ctypes.c_void_p), ctypes.byref(needed))
+    assert rc == -2 and needed.value == 32 * 19
+
+
+def test_create_rejects_lmax_before_touching_a_device():
+    from paper_2311_12134_amd._lib import lib
+    h = ctypes.c_void_p()
+    assert lib().lsms_create(0, 4, 0, ctypes.byref(h)) == -1
+    assert b"lmax" in lib().lsms_last_error()

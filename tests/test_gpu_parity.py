@@ -1,0 +1,237 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: FP64 mode 1e-10 relative (tau per atom in Frobenius norm, sigma and the
+per-atom Kubo sums); split mode (FP32 trailing updates + FP64 refinement) 1e-8.
+"""
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import kkr, kubo
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL_SPLIT = 1e-8
+
+
+@pytest.fixture(scope="module")
+def lctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_12134_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _run(lctx, w, eta, precision="fp64", per_atom=True, refine_tol=1e-14, max_refine=10):
+    import paper_2311_12134_amd as P
+    print("[gpu] workload=%s eta=%g precision=%s" % (w["name"], eta, precision), flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    dev = torch.device("cuda", 0)
+    la, lp = liz.to_device(dev)
+    phase = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(dev)
+    species = torch.from_numpy(w["species"].astype(np.int32)).to(dev)
+    J = torch.from_numpy(np.ascontiguousarray(w["J"])).to(dev)
+    tp, tm, info, berr = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision,
+                                        refine_tol=refine_tol, max_refine=max_refine)
+    sig, st, pa = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], per_atom=per_atom)
+    torch.cuda.synchronize()
+    return dict(liz=liz, tau_plus=tp.cpu().numpy(), tau_minus=tm.cpu().numpy(), info=info.cpu().numpy(),
+                berr=berr.cpu().numpy(), sigma=sig.cpu().numpy(), sigma_tilde=st.cpu().numpy(),
+                per_atom=None if pa is None else pa.cpu().numpy())
+
+
+def _oracle_atoms(w, eta, atoms, liz):
+    lists = (liz.ptr, liz.atom, liz.pos)
+    return kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                      atoms=atoms, liz_lists=lists)
+
+
+def _check_atoms(g, o, atoms, tol):
+    ptr = g["liz"].ptr
+    worst = 0.0
+    for i in atoms:
+        sl = slice(ptr[i], ptr[i + 1])
+        for tag, key in (("+", "tau_plus"), ("-", "tau_minus")):
+            ref = o["tau"][i]["col" + tag]
+            got = g[key][sl]
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            worst = max(worst, err)
+            assert err <= tol, "atom %d tau%s rel err %.3e" % (i, tag, err)
+        ref = o["per_atom"][i]
+        got = g["per_atom"][i]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert err <= tol, "atom %d Kubo sum rel err %.3e" % (i, err)
+    return worst
+
+
+def test_fcc32_fp64_full(lctx):
+    w = synthetic.workload("fcc32")
+    eta = w["etas"][0]
+    g = _run(lctx, w, eta)
+    assert (g["info"] == 0).all()
+    atoms = list(range(32))
+    o = _oracle_atoms(w, eta, atoms, g["liz"])
+    _check_atoms(g, o, atoms, TOL64)
+    ref_sig = o["sigma"].real
+    assert np.allclose(g["sigma"], ref_sig, rtol=TOL64, atol=0)
+    assert np.allclose(g["sigma_tilde"], o["sigma_tilde"], rtol=TOL64, atol=TOL64 * np.abs(o["sigma_tilde"]).max())
+
+
+def test_bcc16_fp64_full(lctx):
+    w = synthetic.workload("bcc16")
+    eta = w["etas"][0]
+    g = _run(lctx, w, eta)
+    assert (g["info"] == 0).all()
+    atoms = list(range(16))
+    o = _oracle_atoms(w, eta, atoms, g["liz"])
+    _check_atoms(g, o, atoms, TOL64)
+    assert np.allclose(g["sigma"], o["sigma"].real, rtol=TOL64, atol=0)
+
+
+def test_bcc16_split_full(lctx):
+    w = synthetic.workload("bcc16")
+    eta = w["etas"][0]
+    g = _run(lctx, w, eta, precision="split")
+    assert (g["info"] == 0).all(), g["info"]
+    assert (g["berr"] <= 1e-14).all()
+    atoms = list(range(16))
+    o = _oracle_atoms(w, eta, atoms, g["liz"])
+    _check_atoms(g, o, atoms, TOL_SPLIT)
+    assert np.allclose(g["sigma"], o["sigma"].real, rtol=TOL_SPLIT, atol=0)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("split", TOL_SPLIT)])
+def test_bcc250_sampled(lctx, precision, tol):
+    w = synthetic.workload("bcc250")
+    eta = w["etas"][0]
+    g = _run(lctx, w, eta, precision=precision)
+    assert (g["info"] == 0).all()
+    atoms = [0, 77, 249]
+    o = _oracle_atoms(w, eta, atoms, g["liz"])
+    _check_atoms(g, o, atoms, tol)
+
+
+def test_bcc1940_uneven_sampled(lctx):
+    w = synthetic.workload("bcc1940")
+    eta = w["etas"][0]
+    g = _run(lctx, w, eta)
+    assert (g["info"] == 0).all()
+    sizes = np.diff(g["liz"].ptr)
+    atoms = [int(np.argmin(sizes)), int(np.argmax(sizes)), 1000]
+    o = _oracle_atoms(w, eta, atoms, g["liz"])
+    _check_atoms(g, o, atoms, TOL64)
+
+
+def test_deterministic(lctx):
+    w = synthetic.workload("bcc16")
+    a = _run(lctx, w, w["etas"][0])
+    b = _run(lctx, w, w["etas"][0])
+    assert np.array_equal(a["tau_plus"], b["tau_plus"]) and np.array_equal(a["sigma"], b["sigma"])
+
+
+def test_nan_phase_flags_input(lctx):
+    w = dict(synthetic.workload("bcc16"))
+    ph = w["phase"].copy()
+    ph[3, 2] = np.nan
+    w["phase"] = ph
+    g = _run(lctx, w, w["etas"][0], per_atom=False)
+    # every LIZ that contains atom 3 is flagged
+    ptr, atom = g["liz"].ptr, g["liz"].atom
+    for i in range(16):
+        has = 3 in atom[ptr[i]:ptr[i + 1]]
+        assert (g["info"][i] == -2).all() == has
+
+
+def test_batched_lu_solve_random_and_singular(lctx):
+    rng = np.random.default_rng(7)
+    dev = torch.device("cuda", 0)
+    sizes = [1, 17, 64, 100, 300, 129]
+    mats, rhs, refs = [], [], []
+    for n in sizes:
+        A = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)) + 2 * np.eye(n)
+        B = rng.normal(size=(n, 5)) + 1j * rng.normal(size=(n, 5))
+        refs.append(np.linalg.solve(A, B))
+        mats.append(torch.from_numpy(A).to(dev))
+        rhs.append(torch.from_numpy(B).to(dev))
+    # a singular system: column 40 of a 100 x 100 matrix is zero
+    S = rng.normal(size=(100, 100)) + 0j
+    S[:, 40] = 0.0
+    mats.append(torch.from_numpy(S).to(dev))
+    rhs.append(torch.from_numpy(np.ones((100, 5), dtype=complex)).to(dev))
+    info = lctx.batched_lu_solve(mats, rhs).cpu().numpy()
+    torch.cuda.synchronize()
+    for k, ref in enumerate(refs):
+        got = rhs[k].cpu().numpy()
+        assert info[k] == 0
+        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max(), (sizes[k], np.abs(got - ref).max())
+    assert info[-1] > 0
+
+
+def _grad_setup(w):
+    import paper_2311_12134_amd as P
+    dev = torch.device("cuda", 0)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp = liz.to_device(dev)
+    species = torch.from_numpy(w["species"].astype(np.int32)).to(dev)
+    J = torch.from_numpy(np.ascontiguousarray(w["J"])).to(dev)
+    return liz, la, lp, species, J
+
+
+def _gpu_sigma(lctx, w, liz, la, lp, species, J, phase_np, eta):
+    dev = torch.device("cuda", 0)
+    ph = torch.from_numpy(np.ascontiguousarray(phase_np)).to(dev)
+    tp, tm, info, _ = lctx.tau_solve(liz, la, lp, ph, w["e_fermi"], eta)
+    sig, _, _ = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"])
+    return sig.cpu().numpy()
+
+
+def test_adjoint_bcc16_vs_oracle_and_fd(lctx):
+    import paper_2311_12134_amd as P
+    from oracle import adjoint
+    w = synthetic.workload("bcc16")
+    eta = w["etas"][0]
+    liz, la, lp, species, J = _grad_setup(w)
+    dsig = np.array([1.0, -0.5, 0.25])
+    ph = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(torch.device("cuda", 0)).requires_grad_(True)
+    sig = P.KuboSigma.apply(ph, lctx, liz, la, lp, species, J, w["volume"], w["e_fermi"], eta)
+    sig.backward(torch.from_numpy(dsig).to(sig.device))
+    g = ph.grad.cpu().numpy()
+    ref = adjoint.dsigma_dphase(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                                dsig, liz_lists=(liz.ptr, liz.atom, liz.pos))
+    assert np.abs(g - ref.real).max() <= 1e-9 * np.abs(ref.real).max()
+    h = 1e-6
+    for (k, l) in [(0, 0), (3, 2), (9, 1), (15, 3)]:
+        p1 = w["phase"].copy()
+        p1[k, l] += h
+        p2 = w["phase"].copy()
+        p2[k, l] -= h
+        fd = (np.dot(dsig, _gpu_sigma(lctx, w, liz, la, lp, species, J, p1, eta))
+              - np.dot(dsig, _gpu_sigma(lctx, w, liz, la, lp, species, J, p2, eta))) / (2 * h)
+        assert abs(fd - g[k, l]) <= 1e-6 * np.abs(g).max(), (k, l, fd, g[k, l])
+
+
+def test_adjoint_bcc250_vs_fd_sampled(lctx):
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc250grad")
+    eta = w["etas"][0]
+    liz, la, lp, species, J = _grad_setup(w)
+    dsig = np.array([1.0, 0.0, 0.0])  # d sigma_xx / d delta
+    ph = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(torch.device("cuda", 0)).requires_grad_(True)
+    sig = P.KuboSigma.apply(ph, lctx, liz, la, lp, species, J, w["volume"], w["e_fermi"], eta)
+    sig.backward(torch.from_numpy(dsig).to(sig.device))
+    g = ph.grad.cpu().numpy()
+    assert g.shape == (250, 4) and np.isfinite(g).all()
+    h = 1e-6
+    for (k, l) in [(0, 0), (100, 2), (249, 1)]:
+        p1 = w["phase"].copy()
+        p1[k, l] += h
+        p2 = w["phase"].copy()
+        p2[k, l] -= h
+        fd = (_gpu_sigma(lctx, w, liz, la, lp, species, J, p1, eta)[0]
+              - _gpu_sigma(lctx, w, liz, la, lp, species, J, p2, eta)[0]) / (2 * h)
+        assert abs(fd - g[k, l]) <= 1e-6 * np.abs(g).max(), (k, l, fd, g[k, l])
