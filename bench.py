@@ -60,7 +60,7 @@ def main():
     ap.add_argument("--workload", default="fcc4000")
     ap.add_argument("--precision", default="split", choices=["split", "fp64"])
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4)
+    ap.add_argument("--cpu-sample", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -400,7 +400,7 @@ static JobBytes job_bytes(int npad, int precision) {
   b.m = precision == LSMS_SPLIT ? align_up(n2 * 16, 256) : 0;
   b.x = align_up((int64_t)npad * NRHS_MAX * 16, 256);
   b.r = precision == LSMS_SPLIT ? b.x : 0;
-  b.piv = align_up((int64_t)npad * 4, 256);
+  b.piv = align_up(piv_ints(npad) * 4, 256);
   return b;
 }
 

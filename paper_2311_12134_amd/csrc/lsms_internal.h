@@ -68,6 +68,16 @@ struct JobDesc {
 
 constexpr int NRHS_MAX = 32;  // columns of the solution block (16 forward, 32 adjoint)
 
+// The NB interchanges of one panel permute at most 2 NB rows.  The panel kernel stores
+// that permutation once per panel as (destination row, source row) pairs so that the
+// trailing update and the solves apply it as one parallel gather instead of NB
+// dependent swaps.  Per job, after the npad pivots: (npad / NB) lists of PERM_STRIDE ints
+// laid out as [count, unused, dst[PERM_MAX], src[PERM_MAX]].
+constexpr int PERM_MAX = 2 * NB;
+constexpr int PERM_STRIDE = 2 + 2 * PERM_MAX;
+__host__ __device__ inline int64_t piv_ints(int npad) { return (int64_t)npad + (int64_t)(npad / NB) * PERM_STRIDE; }
+__host__ __device__ inline int64_t perm_off(int npad, int k) { return (int64_t)npad + (int64_t)(k / NB) * PERM_STRIDE; }
+
 struct GauntTable {
   // CSR over the 256 (L, L') pairs: terms [start[p], start[p+1]) hold (L'', C).
   int32_t start[NL * NL + 1];

@@ -19,6 +19,7 @@
 // Matrices are row-major with leading dimension npad (a multiple of 64); the padding
 // is an identity block that no pivot ever selects.
 #include "lsms_internal.h"
+#include "tri.h"
 
 namespace lsms {
 
@@ -47,6 +48,8 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, T
   __shared__ double2 s_L11[IB][IB];
   __shared__ double2 s_U[IB][NB];
   __shared__ double2 s_Lc[PT][IB];
+  __shared__ int s_pivall[NB];
+  __shared__ int s_pos[PERM_MAX], s_org[PERM_MAX];
 
   double2 v[S][IB];
   int first_zero = 0;
@@ -124,6 +127,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, T
       }
       if (t == 0) {
         s_piv[j] = p;
+        s_pivall[c * IB + j] = p;
         ip[d] = p;
       }
       __syncthreads();
@@ -231,6 +235,48 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, T
       }
     }
   }
+  // The panel's NB interchanges as one permutation of at most 2 NB rows: entries
+  // 0..NB-1 are the positions k..k+NB-1, further entries the pivot rows below the panel;
+  // s_org[e] is the original row that ends up at position s_pos[e].
+  __syncthreads();
+  if (wave == 0) {
+    for (int i = lane; i < NB; i += 64) {
+      s_pos[i] = k + i;
+      s_org[i] = k + i;
+    }
+    int cnt = NB;
+    for (int q = 0; q < NB; ++q) {
+      const int d = k + q, p = s_pivall[q];
+      if (p == d) continue;
+      int e;
+      if (p < k + NB) {
+        e = p - k;
+      } else {
+        const unsigned long long m = __ballot(NB + lane < cnt && s_pos[NB + lane] == p);
+        if (m) {
+          e = NB + __ffsll((long long)m) - 1;
+        } else {
+          e = cnt;
+          if (lane == 0) {
+            s_pos[cnt] = p;
+            s_org[cnt] = p;
+          }
+          ++cnt;
+        }
+      }
+      if (lane == 0) {
+        const int tmp = s_org[q];
+        s_org[q] = s_org[e];
+        s_org[e] = tmp;
+      }
+    }
+    int32_t* lst = ip + perm_off(nrows, k);
+    if (lane == 0) lst[0] = cnt;
+    for (int i = lane; i < cnt; i += 64) {
+      lst[2 + i] = s_pos[i];
+      lst[2 + PERM_MAX + i] = s_org[i];
+    }
+  }
   if (t == 0 && first_zero != 0) {
     if (info[blockIdx.x] == 0) info[blockIdx.x] = first_zero;
   }
@@ -246,40 +292,46 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   if (col0 >= jd.npad) return;  // uniform
   T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
-  const int t = threadIdx.x;
-  __shared__ int s_piv[NB];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   __shared__ double2 s_L[NB][NB + 1];
   __shared__ double2 s_X[NB][64 + 1];
-  if (t < NB) s_piv[t] = piv[jd.piv_off + k + t];
+  __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
+  const int32_t* lst = piv + jd.piv_off + perm_off(jd.npad, k);
+  const int cnt = lst[0];
+  for (int i = t; i < cnt; i += 256) {
+    s_dst[i] = lst[2 + i];
+    s_src[i] = lst[2 + PERM_MAX + i];
+  }
   for (int idx = t; idx < NB * NB; idx += 256) {
     const int q = idx / NB, pp = idx % NB;
     s_L[q][pp] = pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  if (t < 64) {
-    const int col = col0 + t;
-    for (int q = 0; q < NB; ++q) {
-      const int d = k + q, p = s_piv[q];
-      if (p != d && p > d && p < jd.npad) {
-        const double2 x = ld2(A + d * ld + col);
-        const double2 y = ld2(A + p * ld + col);
-        st2(A + d * ld + col, y);
-        st2(A + p * ld + col, x);
-      }
+  // the panel's permutation as a gather on this tile: entry i = wave + 4 s, column = lane
+  double2 held[PERM_MAX / 4];
+#pragma unroll
+  for (int s = 0; s < PERM_MAX / 4; ++s) {
+    const int i = wave + 4 * s;
+    if (i < cnt) {
+      const int dst = s_dst[i];
+      const double2 v = ld2(A + s_src[i] * ld + col0 + lane);
+      if (dst < k + NB)
+        s_X[dst - k][lane] = v;
+      else
+        held[s] = v;
     }
   }
-  __syncthreads();  // the interchanges above must land before the tile is read
-  // forward substitution on the tile held in LDS: row r is final once rows < r are done
-  for (int idx = t; idx < NB * 64; idx += 256) {
-    const int q = idx >> 6, c = idx & 63;
-    s_X[q][c] = ld2(A + (k + q) * ld + col0 + c);
+  __syncthreads();  // every source row is read before any destination row is written
+#pragma unroll
+  for (int s = 0; s < PERM_MAX / 4; ++s) {
+    const int i = wave + 4 * s;
+    if (i < cnt) {
+      const int dst = s_dst[i];
+      if (dst >= k + NB) st2(A + dst * ld + col0 + lane, held[s]);
+    }
   }
-  const int c = t & 63, g = t >> 6;
-  for (int r = 0; r < NB - 1; ++r) {
-    __syncthreads();
-    const double2 xr = s_X[r][c];
-    for (int q = r + 1 + g; q < NB; q += 4) s_X[q][c] = cfms(s_X[q][c], s_L[q][r], xr);
-  }
+  // U12 = L11^-1 A12: each wavefront solves 16 of the tile's columns
+  tri_unit_lower<16>(&s_L[0][0], NB + 1, &s_X[0][0], 64 + 1, wave * 16, lane);
   __syncthreads();
   for (int idx = t; idx < NB * 64; idx += 256) {
     const int q = idx >> 6, cc = idx & 63;

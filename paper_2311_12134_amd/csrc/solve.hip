@@ -6,129 +6,22 @@
 // never re-permuted by later panels).  Hence
 //   M X = B   :  X = U^-1 L_K^-1 P_K ... L_1^-1 P_1 B          (trans = 0)
 //   M^T X = B :  X = P_1^T L_1^-T ... P_K^T L_K^-T U^-T B      (trans = 1)
-// One workgroup per job walks the panels.  The diagonal NB x NB triangles are solved by
-// one wavefront holding the right-hand sides in registers (lane = column + NRHS * group)
-// and broadcasting each finished row with cross-lane shuffles; the off-diagonal blocks
-// are applied by the whole workgroup.  Arithmetic is FP64 for both storage types.
+// One workgroup per job walks the panels.  Each panel's interchanges are applied as one
+// gather of at most 2 NB rows (the permutation list written by the panel kernel), the
+// diagonal NB x NB triangle is solved by one wavefront with cross-lane shuffles (tri.h),
+// and the off-diagonal blocks stream through LDS one coalesced NB x NB tile at a time.
+// Arithmetic is FP64 for both storage types.
 #include "lsms_internal.h"
+#include "tri.h"
 
 namespace lsms {
 
+// Per-thread share of an NB x NRHS block: entry u of thread t is idx = t + 256 u,
+// row idx / NRHS, column idx % NRHS.
 template <int NRHS>
-struct SolveShape {
-  static constexpr int G = 64 / NRHS;   // row groups per wavefront
-  static constexpr int RPL = NB / G;    // rows per lane
+struct Blk {
+  static constexpr int PER = NB * NRHS / 256;
 };
-
-// Forward substitution with a unit lower triangle (s_T strictly lower) on s_X, by wave 0.
-template <int NRHS>
-__device__ inline void diag_unit_lower(double2 (*s_T)[NB + 1], double2 (*s_X)[NRHS], int lane) {
-  constexpr int G = SolveShape<NRHS>::G, RPL = SolveShape<NRHS>::RPL;
-  const int c = lane % NRHS, g = lane / NRHS;
-  double2 xr[RPL];
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) xr[s] = s_X[g + G * s][c];
-#pragma unroll
-  for (int sr = 0; sr < RPL; ++sr) {
-    for (int gr = 0; gr < G; ++gr) {
-      const int r = G * sr + gr;
-      const int src = c + NRHS * gr;
-      double2 xv;
-      xv.x = __shfl(xr[sr].x, src);
-      xv.y = __shfl(xr[sr].y, src);
-#pragma unroll
-      for (int s = sr; s < RPL; ++s) {
-        const int q = g + G * s;
-        if (q > r) xr[s] = cfms(xr[s], s_T[q][r], xv);
-      }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) s_X[g + G * s][c] = xr[s];
-}
-
-// Backward substitution with a non-unit upper triangle (s_T upper incl. diagonal), by wave 0.
-template <int NRHS>
-__device__ inline void diag_upper(double2 (*s_T)[NB + 1], double2 (*s_X)[NRHS], int lane) {
-  constexpr int G = SolveShape<NRHS>::G, RPL = SolveShape<NRHS>::RPL;
-  const int c = lane % NRHS, g = lane / NRHS;
-  double2 xr[RPL];
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) xr[s] = s_X[g + G * s][c];
-#pragma unroll
-  for (int sr = RPL - 1; sr >= 0; --sr) {
-    for (int gr = G - 1; gr >= 0; --gr) {
-      const int r = G * sr + gr;
-      if (g == gr) xr[sr] = cmul(xr[sr], cinv(s_T[r][r]));
-      const int src = c + NRHS * gr;
-      double2 xv;
-      xv.x = __shfl(xr[sr].x, src);
-      xv.y = __shfl(xr[sr].y, src);
-#pragma unroll
-      for (int s = 0; s <= sr; ++s) {
-        const int q = g + G * s;
-        if (q < r) xr[s] = cfms(xr[s], s_T[q][r], xv);
-      }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) s_X[g + G * s][c] = xr[s];
-}
-
-// Forward substitution with U^T (lower, non-unit): x_r /= U[r][r]; x_q -= U[r][q] x_r (q > r).
-template <int NRHS>
-__device__ inline void diag_upper_trans(double2 (*s_T)[NB + 1], double2 (*s_X)[NRHS], int lane) {
-  constexpr int G = SolveShape<NRHS>::G, RPL = SolveShape<NRHS>::RPL;
-  const int c = lane % NRHS, g = lane / NRHS;
-  double2 xr[RPL];
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) xr[s] = s_X[g + G * s][c];
-#pragma unroll
-  for (int sr = 0; sr < RPL; ++sr) {
-    for (int gr = 0; gr < G; ++gr) {
-      const int r = G * sr + gr;
-      if (g == gr) xr[sr] = cmul(xr[sr], cinv(s_T[r][r]));
-      const int src = c + NRHS * gr;
-      double2 xv;
-      xv.x = __shfl(xr[sr].x, src);
-      xv.y = __shfl(xr[sr].y, src);
-#pragma unroll
-      for (int s = sr; s < RPL; ++s) {
-        const int q = g + G * s;
-        if (q > r) xr[s] = cfms(xr[s], s_T[r][q], xv);
-      }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) s_X[g + G * s][c] = xr[s];
-}
-
-// Backward substitution with L^T (unit upper): x_q -= L[r][q] x_r (q < r).
-template <int NRHS>
-__device__ inline void diag_unit_lower_trans(double2 (*s_T)[NB + 1], double2 (*s_X)[NRHS], int lane) {
-  constexpr int G = SolveShape<NRHS>::G, RPL = SolveShape<NRHS>::RPL;
-  const int c = lane % NRHS, g = lane / NRHS;
-  double2 xr[RPL];
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) xr[s] = s_X[g + G * s][c];
-#pragma unroll
-  for (int sr = RPL - 1; sr >= 0; --sr) {
-    for (int gr = G - 1; gr >= 0; --gr) {
-      const int r = G * sr + gr;
-      const int src = c + NRHS * gr;
-      double2 xv;
-      xv.x = __shfl(xr[sr].x, src);
-      xv.y = __shfl(xr[sr].y, src);
-#pragma unroll
-      for (int s = 0; s <= sr; ++s) {
-        const int q = g + G * s;
-        if (q < r) xr[s] = cfms(xr[s], s_T[r][q], xv);
-      }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) s_X[g + G * s][c] = xr[s];
-}
 
 template <typename T, int NRHS, int TRANS>
 __global__ __launch_bounds__(256) void solve_kernel(const JobDesc* jobs, const T* work, const int32_t* piv,
@@ -139,130 +32,175 @@ __global__ __launch_bounds__(256) void solve_kernel(const JobDesc* jobs, const T
   const T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
   const int npad = jd.npad;
-  const int32_t* ip = piv + jd.piv_off;
+  const int32_t* pv = piv + jd.piv_off;
   double2* X = xbuf + jd.x_off + col_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  __shared__ double2 s_T[NB][NB + 1];
-  __shared__ double2 s_X[NB][NRHS];
+  constexpr int PER = Blk<NRHS>::PER;
+  constexpr int HELD = PERM_MAX * NRHS / 256;
+  __shared__ double2 s_T[NB][NB + 1];  // diagonal block, or one NB x NB tile of L / U
+  __shared__ double2 s_X[NB][NRHS];    // right-hand sides of the current panel rows
+  __shared__ double2 s_C[NB][NRHS];    // a chunk of other right-hand-side rows
+  __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
+  auto xrow = [&](int r) { return X + (int64_t)r * NRHS_MAX; };
 
-  auto swap_rows = [&](int k, bool reverse) {
-    if (t < NRHS) {
-      for (int qq = 0; qq < NB; ++qq) {
-        const int q = reverse ? NB - 1 - qq : qq;
-        const int d = k + q, p = ip[d];
-        if (p != d && p > d && p < npad) {
-          const double2 a = X[(int64_t)d * NRHS_MAX + t];
-          const double2 b = X[(int64_t)p * NRHS_MAX + t];
-          X[(int64_t)d * NRHS_MAX + t] = b;
-          X[(int64_t)p * NRHS_MAX + t] = a;
-        }
-      }
+  // apply the permutation of panel k to X (gather dst <- src), or its inverse
+  auto permute = [&](int k, bool inverse) {
+    const int32_t* lst = pv + perm_off(npad, k);
+    const int cnt = lst[0];
+    for (int i = t; i < cnt; i += 256) {
+      s_dst[i] = lst[2 + i];
+      s_src[i] = lst[2 + PERM_MAX + i];
     }
+    __syncthreads();
+    double2 held[HELD];
+#pragma unroll
+    for (int u = 0; u < HELD; ++u) {
+      const int idx = t + 256 * u, i = idx / NRHS, c = idx % NRHS;
+      if (i < cnt) held[u] = xrow(inverse ? s_dst[i] : s_src[i])[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < HELD; ++u) {
+      const int idx = t + 256 * u, i = idx / NRHS, c = idx % NRHS;
+      if (i < cnt) xrow(inverse ? s_src[i] : s_dst[i])[c] = held[u];
+    }
+    __syncthreads();
+  };
+  auto load_diag = [&](int k, int which) {  // 0: strict lower (L), 1: upper with diagonal (U)
+    for (int idx = t; idx < NB * NB; idx += 256) {
+      const int q = idx / NB, pp = idx % NB;
+      const bool keep = which ? (pp >= q) : (pp < q);
+      s_T[q][pp] = keep ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+    }
+  };
+  auto load_tile = [&](int r0, int c0) {  // s_T = A[r0 .. r0+NB, c0 .. c0+NB)
+    for (int idx = t; idx < NB * NB; idx += 256) {
+      const int q = idx / NB, pp = idx % NB;
+      s_T[q][pp] = ld2(A + (int64_t)(r0 + q) * ld + c0 + pp);
+    }
+  };
+  auto load_rows = [&](double2 (*dst)[NRHS], int r0) {
+    for (int idx = t; idx < NB * NRHS; idx += 256) dst[idx / NRHS][idx % NRHS] = xrow(r0 + idx / NRHS)[idx % NRHS];
+  };
+  auto store_rows = [&](double2 (*src)[NRHS], int r0) {
+    for (int idx = t; idx < NB * NRHS; idx += 256) xrow(r0 + idx / NRHS)[idx % NRHS] = src[idx / NRHS][idx % NRHS];
   };
 
   if (TRANS == 0) {
-    // L phase
+    // X <- L_K^-1 P_K ... L_1^-1 P_1 X
     for (int k = 0; k < npad; k += NB) {
-      swap_rows(k, false);
+      permute(k, false);
+      load_diag(k, 0);
+      load_rows(s_X, k);
       __syncthreads();
-      for (int idx = t; idx < NB * NB; idx += 256) {
-        const int q = idx / NB, pp = idx % NB;
-        s_T[q][pp] = pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
-      }
-      for (int idx = t; idx < NB * NRHS; idx += 256) {
-        const int q = idx / NRHS, c = idx % NRHS;
-        s_X[q][c] = X[(int64_t)(k + q) * NRHS_MAX + c];
-      }
+      if (wave == 0) tri_unit_lower<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
       __syncthreads();
-      if (wave == 0) diag_unit_lower<NRHS>(s_T, s_X, lane);
+      store_rows(s_X, k);
       __syncthreads();
-      for (int idx = t; idx < NB * NRHS; idx += 256) {
-        const int q = idx / NRHS, c = idx % NRHS;
-        X[(int64_t)(k + q) * NRHS_MAX + c] = s_X[q][c];
-      }
-      const int rows = npad - k - NB;
-      for (int idx = t; idx < rows * NRHS; idx += 256) {
-        const int r = k + NB + idx / NRHS, c = idx % NRHS;
-        double2 acc = X[(int64_t)r * NRHS_MAX + c];
-        const T* lrow = A + r * ld + k;
+      for (int r0 = k + NB; r0 < npad; r0 += NB) {  // rows below: X -= L21 X_p
+        load_tile(r0, k);
+        load_rows(s_C, r0);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int idx = t + 256 * u, rr = idx / NRHS, c = idx % NRHS;
+          double2 acc = s_C[rr][c];
 #pragma unroll 8
-        for (int q = 0; q < NB; ++q) acc = cfms(acc, ld2(lrow + q), s_X[q][c]);
-        X[(int64_t)r * NRHS_MAX + c] = acc;
+          for (int q = 0; q < NB; ++q) acc = cfms(acc, s_T[rr][q], s_X[q][c]);
+          xrow(r0 + rr)[c] = acc;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
-    // U phase
+    // X <- U^-1 X
     for (int k = npad - NB; k >= 0; k -= NB) {
-      for (int idx = t; idx < NB * NRHS; idx += 256) {
-        const int q = idx / NRHS, c = idx % NRHS;
-        double2 acc = X[(int64_t)(k + q) * NRHS_MAX + c];
-        const T* urow = A + (k + q) * ld;
-        for (int col = k + NB; col < npad; ++col) acc = cfms(acc, ld2(urow + col), X[(int64_t)col * NRHS_MAX + c]);
-        s_X[q][c] = acc;
+      double2 acc[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = t + 256 * u;
+        acc[u] = xrow(k + idx / NRHS)[idx % NRHS];
       }
-      for (int idx = t; idx < NB * NB; idx += 256) {
-        const int q = idx / NB, pp = idx % NB;
-        s_T[q][pp] = pp >= q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+      for (int c0 = k + NB; c0 < npad; c0 += NB) {  // X_p -= U12 X_right
+        load_tile(k, c0);
+        load_rows(s_C, c0);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int idx = t + 256 * u, q = idx / NRHS, c = idx % NRHS;
+#pragma unroll 8
+          for (int cc = 0; cc < NB; ++cc) acc[u] = cfms(acc[u], s_T[q][cc], s_C[cc][c]);
+        }
+        __syncthreads();
       }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = t + 256 * u;
+        s_X[idx / NRHS][idx % NRHS] = acc[u];
+      }
+      load_diag(k, 1);
       __syncthreads();
-      if (wave == 0) diag_upper<NRHS>(s_T, s_X, lane);
+      if (wave == 0) tri_upper<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
       __syncthreads();
-      for (int idx = t; idx < NB * NRHS; idx += 256) {
-        const int q = idx / NRHS, c = idx % NRHS;
-        X[(int64_t)(k + q) * NRHS_MAX + c] = s_X[q][c];
-      }
+      store_rows(s_X, k);
       __syncthreads();
     }
   } else {
-    // U^T phase (forward)
+    // X <- U^-T X (forward over panels)
     for (int k = 0; k < npad; k += NB) {
-      for (int idx = t; idx < NB * NB; idx += 256) {
-        const int q = idx / NB, pp = idx % NB;
-        s_T[q][pp] = pp >= q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
-      }
-      for (int idx = t; idx < NB * NRHS; idx += 256) {
-        const int q = idx / NRHS, c = idx % NRHS;
-        s_X[q][c] = X[(int64_t)(k + q) * NRHS_MAX + c];
-      }
+      load_diag(k, 1);
+      load_rows(s_X, k);
       __syncthreads();
-      if (wave == 0) diag_upper_trans<NRHS>(s_T, s_X, lane);
+      if (wave == 0) tri_upper_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
       __syncthreads();
-      for (int idx = t; idx < NB * NRHS; idx += 256) {
-        const int q = idx / NRHS, c = idx % NRHS;
-        X[(int64_t)(k + q) * NRHS_MAX + c] = s_X[q][c];
-      }
-      const int rows = npad - k - NB;
-      for (int idx = t; idx < rows * NRHS; idx += 256) {
-        const int r = k + NB + idx / NRHS, c = idx % NRHS;
-        double2 acc = X[(int64_t)r * NRHS_MAX + c];
+      store_rows(s_X, k);
+      __syncthreads();
+      for (int r0 = k + NB; r0 < npad; r0 += NB) {  // X_r -= U12^T X_p
+        load_tile(k, r0);
+        load_rows(s_C, r0);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int idx = t + 256 * u, rr = idx / NRHS, c = idx % NRHS;
+          double2 a = s_C[rr][c];
 #pragma unroll 8
-        for (int q = 0; q < NB; ++q) acc = cfms(acc, ld2(A + (k + q) * ld + r), s_X[q][c]);
-        X[(int64_t)r * NRHS_MAX + c] = acc;
+          for (int q = 0; q < NB; ++q) a = cfms(a, s_T[q][rr], s_X[q][c]);
+          xrow(r0 + rr)[c] = a;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
-    // L^T phase (backward) with the panel interchanges undone in reverse order
+    // X <- P_1^T L_1^-T ... P_K^T L_K^-T X (backward over panels)
     for (int k = npad - NB; k >= 0; k -= NB) {
-      for (int idx = t; idx < NB * NRHS; idx += 256) {
-        const int q = idx % NB, c = idx / NB;
-        double2 acc = X[(int64_t)(k + q) * NRHS_MAX + c];
-        for (int r = k + NB; r < npad; ++r) acc = cfms(acc, ld2(A + r * ld + k + q), X[(int64_t)r * NRHS_MAX + c]);
-        s_X[q][c] = acc;
+      double2 acc[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = t + 256 * u;
+        acc[u] = xrow(k + idx / NRHS)[idx % NRHS];
       }
-      for (int idx = t; idx < NB * NB; idx += 256) {
-        const int q = idx / NB, pp = idx % NB;
-        s_T[q][pp] = pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+      for (int r0 = k + NB; r0 < npad; r0 += NB) {  // X_p -= L21^T X_below
+        load_tile(r0, k);
+        load_rows(s_C, r0);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int idx = t + 256 * u, q = idx / NRHS, c = idx % NRHS;
+#pragma unroll 8
+          for (int rr = 0; rr < NB; ++rr) acc[u] = cfms(acc[u], s_T[rr][q], s_C[rr][c]);
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      if (wave == 0) diag_unit_lower_trans<NRHS>(s_T, s_X, lane);
-      __syncthreads();
-      for (int idx = t; idx < NB * NRHS; idx += 256) {
-        const int q = idx / NRHS, c = idx % NRHS;
-        X[(int64_t)(k + q) * NRHS_MAX + c] = s_X[q][c];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = t + 256 * u;
+        s_X[idx / NRHS][idx % NRHS] = acc[u];
       }
+      load_diag(k, 0);
       __syncthreads();
-      swap_rows(k, true);
+      if (wave == 0) tri_unit_lower_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
       __syncthreads();
+      store_rows(s_X, k);
+      __syncthreads();
+      permute(k, true);
     }
   }
 }
