@@ -142,6 +142,7 @@ def main():
                            "launches": gemm_launches, "avg_launch_ms": 1e3 * avg_s}
     if not args.no_fp64_compare and args.precision == "split":
         sig64 = {}
+        step(0, "fp64", sig64)  # warm-up of the FP64 path (workspace layout differs)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         step(0, "fp64", sig64)

@@ -20,10 +20,6 @@
 
 using namespace lsms;
 
-namespace lsms {
-void lu_solve_f32_skip(const JobDesc* jobs, int njobs, const float2* work, const int32_t* piv, double2* x,
-                       const int32_t* skip, hipStream_t s);
-}
 
 // ---------------------------------------------------------------------------------
 // errors
@@ -98,6 +94,8 @@ struct lsms_ctx {
   DevBuf small;     // per-call small arrays
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  int32_t* pinned_flag = nullptr;  // host-visible counter read back between refinement sweeps
+  DevBuf fallback;                 // job list of the FP64 fallback
 };
 
 struct lsms_factors {
@@ -244,6 +242,7 @@ extern "C" int lsms_create(int hip_device, int lmax, size_t workspace_limit, lsm
   int rc = build_gaunt(c->gaunt);
   if (rc) return rc;
   HIP_TRY(upload_gaunt(c->gaunt));
+  HIP_TRY(hipHostMalloc((void**)&c->pinned_flag, 256, hipHostMallocDefault));
   *out = c.release();
   return LSMS_OK;
 }
@@ -255,6 +254,8 @@ extern "C" int lsms_destroy(lsms_ctx* ctx) {
   if (ctx->work.p) hipFree(ctx->work.p);
   if (ctx->small.p) hipFree(ctx->small.p);
   if (ctx->pinned) hipHostFree(ctx->pinned);
+  if (ctx->pinned_flag) hipHostFree(ctx->pinned_flag);
+  if (ctx->fallback.p) hipFree(ctx->fallback.p);
   delete ctx;
   return LSMS_OK;
 }
@@ -473,7 +474,7 @@ void launch_residual_norms(const JobDesc* jobs, int njobs, int npad_max, const d
                            double2* r, const double2* tpm, const int32_t* liz_atom, double* norms,
                            const int32_t* done, hipStream_t s);
 void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double tol, int32_t* done, int last,
-                        int32_t* job_info, hipStream_t s);
+                        int32_t* job_info, int32_t* pending, hipStream_t s);
 void launch_add_correction(const JobDesc* jobs, int njobs, int npad_max, double2* x, const double2* r,
                            const int32_t* done, hipStream_t s);
 void launch_zero_i32(int32_t* p, int n, hipStream_t s);
@@ -536,7 +537,8 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
   const int64_t off_info = off_jobs + align_up((int64_t)njobs_all * sizeof(JobDesc), 256);
   const int64_t off_norm = off_info + align_up((int64_t)njobs_all * 4, 256);
   const int64_t off_done = off_norm + align_up((int64_t)njobs_all * 8 * 8, 256);
-  const int64_t small_bytes = off_done + align_up((int64_t)njobs_all * 4, 256);
+  const int64_t off_pend = off_done + align_up((int64_t)njobs_all * 4, 256);
+  const int64_t small_bytes = off_pend + 256;
 
   // lay out every wave now (offsets are relative to the wave's base)
   std::vector<int64_t> wave_sizes(waves.size() * 5);
@@ -565,8 +567,14 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     wbase = (char*)fac->work;
     sbase = wbase + max_wave;
   } else {
-    rc = ensure_dev(ctx->work, (size_t)max_wave, s);
-    if (rc) return rc;
+    if (ctx->work.bytes < (size_t)max_wave) {
+      // grow with slack, so alternating precisions or slightly larger waves do not
+      // reallocate (and re-map) tens of GB on every call
+      const size_t want = std::min((size_t)limit, std::max((size_t)max_wave + ((size_t)max_wave >> 2),
+                                                           2 * ctx->work.bytes));
+      rc = ensure_dev(ctx->work, std::max(want, (size_t)max_wave), s);
+      if (rc) return rc;
+    }
     rc = ensure_dev(ctx->small, (size_t)small_bytes, s);
     if (rc) return rc;
     wbase = (char*)ctx->work.p;
@@ -577,6 +585,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
   int32_t* job_info = (int32_t*)(sbase + off_info);
   double* norms = (double*)(sbase + off_norm);
   int32_t* done = (int32_t*)(sbase + off_done);
+  int32_t* pending = (int32_t*)(sbase + off_pend);
   HIP_TRY(hipMemcpyAsync(jobs_dev, ctx->pinned, (size_t)njobs_all * sizeof(JobDesc), hipMemcpyHostToDevice, s));
   launch_tmatrix(phase, n_atoms, kp, tpm, s);
 
@@ -611,22 +620,55 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     if (precision == LSMS_FP64) {
       launch_assemble_f64(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (double2*)abuf, s);
       lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, s, prof);
-      lu_solve_f64(jd, nj, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
+      lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
       launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, s);
       launch_write_status(jd, nj, jinfo, nullptr, info, berr, s);
     } else {
       launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, m64, s);
       lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, s, prof);
-      lu_solve_f32(jd, nj, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
+      lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
       launch_zero_i32(jdone, nj, s);
       launch_zero(jnorm, 8 * (int64_t)nj, s);
+      int left = nj;
       for (int it = 0; it <= max_refine; ++it) {
         const int last = it == max_refine;
         launch_residual_norms(jd, nj, npad_max, m64, xbuf, rbuf, tpm, liz_atom, jnorm, jdone, s);
-        launch_refine_step(jd, nj, jnorm, refine_tol, jdone, last, jinfo, s);
-        if (last) break;
-        lu_solve_f32_skip(jd, nj, (const float2*)abuf, piv, rbuf, jdone, s);
+        launch_zero_i32(pending, 1, s);
+        launch_refine_step(jd, nj, jnorm, refine_tol, jdone, last, jinfo, pending, s);
+        // read back how many jobs still miss the tolerance: stop as soon as none does
+        HIP_TRY(hipMemcpyAsync(ctx->pinned_flag, pending, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        left = ctx->pinned_flag[0];
+        if (last || left == 0) break;
+        lu_solve_f32_skip(jd, nj, npad_max, (const float2*)abuf, piv, rbuf, jdone, s);
         launch_add_correction(jd, nj, npad_max, xbuf, rbuf, jdone, s);
+      }
+      if (left > 0) {
+        // Jobs whose refinement did not converge (info = NOCONV) are recomputed in FP64:
+        // the FP64 copy of M is factored in place and solved directly.
+        std::vector<int32_t> hinfo(nj);
+        HIP_TRY(hipMemcpy(hinfo.data(), jinfo, nj * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::vector<JobDesc> fb;
+        for (int j = 0; j < nj; ++j)
+          if (hinfo[j] == LSMS_INFO_NOCONV) {
+            JobDesc d = jobs[wv.b + j];
+            d.a_off = d.m_off;
+            d.info = j;
+            fb.push_back(d);
+          }
+        if (!fb.empty()) {
+          const int nf = (int)fb.size();
+          rc = ensure_dev(ctx->fallback, fb.size() * sizeof(JobDesc) + align_up(4 * (int64_t)nf, 256) + 256, s);
+          if (rc) return rc;
+          JobDesc* fjd = (JobDesc*)ctx->fallback.p;
+          int32_t* finfo = (int32_t*)((char*)ctx->fallback.p + align_up(fb.size() * sizeof(JobDesc), 256));
+          HIP_TRY(hipMemcpy(fjd, fb.data(), fb.size() * sizeof(JobDesc), hipMemcpyHostToDevice));
+          launch_zero_i32(finfo, nf, s);
+          const int fpad = fb[0].npad;
+          launch_init_rhs(fjd, nf, fpad, liz_atom, tpm, xbuf, s);
+          lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s);
+          lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, s);
+        }
       }
       launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, s);
       launch_write_status(jd, nj, jinfo, jnorm, info, berr, s);
@@ -741,7 +783,7 @@ extern "C" int lsms_kubo_sigma_grad(lsms_ctx* ctx, const lsms_factors* factors, 
   launch_zero(dphase, (int64_t)n_atoms * 4, s);
   launch_adjoint_rhs(factors->jobs_dev, nj, factors->npad_max, liz_atom, (const double2*)tau_plus,
                      (const double2*)tau_minus, species, n_species, (const double2*)J, dsigma, volume, xbuf, s);
-  lu_solve_f64(factors->jobs_dev, nj, abuf, piv, xbuf, 0, 32, 1, s);
+  lu_solve_f64(factors->jobs_dev, nj, factors->npad_max, abuf, piv, xbuf, 0, 32, 1, s);
   launch_adjoint_contract(factors->jobs_dev, nj, factors->npad_max, liz_atom, phase, factors->kp, xbuf, dphase, s);
   HIP_TRY(hipGetLastError());
   return LSMS_OK;
@@ -809,10 +851,10 @@ extern "C" int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t
   launch_load_user(jd, batch, npad_max, aptr, bptr, nrhs, prec, abuf, xbuf, s);
   if (prec == LSMS_FP64) {
     lu_factor_f64(jd, batch, npad_max, (double2*)abuf, piv, info, s);
-    lu_solve_f64(jd, batch, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
+    lu_solve_f64(jd, batch, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
   } else {
     lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s);
-    lu_solve_f32(jd, batch, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
+    lu_solve_f32(jd, batch, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
   }
   launch_store_user(jd, batch, npad_max, bptr, nrhs, xbuf, s);
   HIP_TRY(hipGetLastError());

@@ -119,10 +119,13 @@ void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, 
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
                    hipStream_t s, GemmProfiler* prof = nullptr);
 // Solve with the factors: trans = 0 solves M X = B, trans = 1 solves M^T X = B (in place on X).
-void lu_solve_f64(const JobDesc* jobs, int njobs, const double2* work, const int32_t* piv, double2* x,
-                  int64_t x_col_off, int nrhs, int trans, hipStream_t s);
-void lu_solve_f32(const JobDesc* jobs, int njobs, const float2* work, const int32_t* piv, double2* x,
-                  int64_t x_col_off, int nrhs, int trans, hipStream_t s);
+void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
+                  double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);
+void lu_solve_f32(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
+                  double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);
+// Correction solve of the refinement (16 columns) that skips the jobs flagged in skip[].
+void lu_solve_f32_skip(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
+                       double2* x, const int32_t* skip, hipStream_t s);
 
 // Split-mode refinement helpers.
 void launch_residual(const JobDesc* jobs, int njobs, int npad_max, const double2* m64, const double2* x,

@@ -1,8 +1,8 @@
 // Batched complex LU with partial pivoting (the tau inverse of Eq. (3) is the dominant
 // cost of the method, Sec. II.A), right-looking and blocked with panel width NB.
 //
-// All jobs of a wave advance through the same panel steps; each step is three
-// launches over the whole batch:
+// All jobs of a wave advance through the same panel steps; every panel is a few
+// launches over the whole batch (panels come in look-ahead pairs, see lu_factor_any):
 //   panel_kernel      one workgroup per job factors rows [k, n) x cols [k, k+NB) with
 //                     partial pivoting (pivot = largest |re|+|im|, first on ties) in FP64:
 //                     IB-wide leaves live in registers (rows distributed cyclically over
@@ -14,10 +14,13 @@
 //                     FP64 MFMA 16x16x4 with the four real products of a complex product,
 //                     or (split mode) FP32 MFMA 16x16x4 with three real products
 //                     (Ar Br, Ai Bi, (Ar+Ai)(Br+Bi)).
-// Interchanges are applied only to the right of each panel; the solves apply them
-// panel by panel in the same order, so the left columns never need swapping.
+// Interchanges are applied only to the right of each panel (and, for the second panel
+// of a pair, to the first panel's columns); the solves apply them panel by panel in the
+// same order, so older columns never need swapping.
 // Matrices are row-major with leading dimension npad (a multiple of 64); the padding
 // is an identity block that no pivot ever selects.
+#include <algorithm>
+
 #include "lsms_internal.h"
 #include "tri.h"
 
@@ -30,7 +33,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // panel factorization
 // ------------------------------------------------------------------------------------
 template <typename T, int PT, int S, int IB>
-__global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, T* work, int32_t* piv,
+__global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, int left, T* work, int32_t* piv,
                                                    int32_t* info) {
   const JobDesc jd = jobs[blockIdx.x];
   if (k >= jd.npad) return;  // uniform over the workgroup
@@ -176,9 +179,11 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, T
       }
     }
     __syncthreads();
-    // the leaf's interchanges on the other columns of the panel (whole panel rows)
-    for (int cc = t; cc < NB - IB; cc += PT) {
-      const int col = k + (cc < c * IB ? cc : cc + IB);
+    // the leaf's interchanges on the other columns of the panel (whole panel rows), and on
+    // the `left` columns before it (the first panel of a pair, see lu_factor)
+    for (int cc = t; cc < left + NB - IB; cc += PT) {
+      const int cr = cc - left;
+      const int col = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
       for (int q = 0; q < IB; ++q) {
         const int d = cl + q, p = s_piv[q];
         if (p != d && p > d && p < nrows) {
@@ -285,11 +290,14 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, T
 // ------------------------------------------------------------------------------------
 // interchanges + U12 = L11^-1 A12 on one 64-column tile of the trailing matrix
 // ------------------------------------------------------------------------------------
-template <typename T>
+// SECOND: k is the second panel of a pair whose first panel starts at k - NB.  Its
+// trailing columns have not yet received the first panel's update, so after the gather
+// the panel rows get  A12 -= L[k.., k-NB..k) U12_first  (FP64 MFMA) before the solve.
+template <typename T, bool SECOND>
 __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int k, T* work, const int32_t* piv) {
   const JobDesc jd = jobs[blockIdx.y];
   const int col0 = k + NB + blockIdx.x * 64;
-  if (col0 >= jd.npad) return;  // uniform
+  if (k >= jd.npad || col0 >= jd.npad) return;  // uniform
   T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -302,9 +310,16 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
     s_dst[i] = lst[2 + i];
     s_src[i] = lst[2 + PERM_MAX + i];
   }
-  for (int idx = t; idx < NB * NB; idx += 256) {
-    const int q = idx / NB, pp = idx % NB;
-    s_L[q][pp] = pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+  if (SECOND) {  // the first panel's L rows that face this panel
+    for (int idx = t; idx < NB * NB; idx += 256) {
+      const int q = idx / NB, pp = idx % NB;
+      s_L[q][pp] = ld2(A + (k + q) * ld + (k - NB) + pp);
+    }
+  } else {
+    for (int idx = t; idx < NB * NB; idx += 256) {
+      const int q = idx / NB, pp = idx % NB;
+      s_L[q][pp] = pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+    }
   }
   __syncthreads();
   // the panel's permutation as a gather on this tile: entry i = wave + 4 s, column = lane
@@ -330,6 +345,44 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
       if (dst >= k + NB) st2(A + dst * ld + col0 + lane, held[s]);
     }
   }
+  if (SECOND) {
+    __syncthreads();  // the gathered panel rows are complete in s_X
+    // s_X -= L[k.., k-NB..k) (in s_L) * U[k-NB.., col0..] : wave w owns rows 16w..16w+16
+    typedef double d4_ __attribute__((ext_vector_type(4)));
+    d4_ are[4], aim[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      are[cb] = d4_{0, 0, 0, 0};
+      aim[cb] = d4_{0, 0, 0, 0};
+    }
+    const int ii = lane & 15, kq = lane >> 4;
+    for (int k4 = 0; k4 < NB; k4 += 4) {
+      const double2 a = s_L[wave * 16 + ii][k4 + kq];
+      const T* urow = A + (int64_t)(k - NB + k4 + kq) * ld + col0;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const double2 b = ld2(urow + cb * 16 + ii);
+        are[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, are[cb], 0, 0, 0);
+        are[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, are[cb], 0, 0, 0);
+        aim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, aim[cb], 0, 0, 0);
+        aim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, aim[cb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double2& xv = s_X[wave * 16 + kq + 4 * r][cb * 16 + ii];
+        xv.x -= are[cb][r];
+        xv.y -= aim[cb][r];
+      }
+    __syncthreads();
+    for (int idx = t; idx < NB * NB; idx += 256) {  // now the panel's own unit lower triangle
+      const int q = idx / NB, pp = idx % NB;
+      s_L[q][pp] = pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+  }
   // U12 = L11^-1 A12: each wavefront solves 16 of the tile's columns
   tri_unit_lower<16>(&s_L[0][0], NB + 1, &s_X[0][0], 64 + 1, wave * 16, lane);
   __syncthreads();
@@ -345,10 +398,11 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
 // v_mfma_f64_16x16x4: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);
 // D lane l, register r -> (row l/16 + 4r, col l%16).
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const JobDesc* jobs, int k, double2* work) {
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const JobDesc* jobs, int k, int kd, int r_begin, int c_begin,
+                                                   int c_end, double2* work) {
   const JobDesc jd = jobs[blockIdx.z];
-  const int row0 = k + NB + blockIdx.y * 64, col0 = k + NB + blockIdx.x * 64;
-  if (row0 >= jd.npad || col0 >= jd.npad) return;  // uniform
+  const int row0 = r_begin + blockIdx.y * 64, col0 = c_begin + blockIdx.x * 64;
+  if (row0 >= jd.npad || col0 >= jd.npad || (c_end > 0 && col0 >= c_end)) return;  // uniform
   double2* A = work + jd.a_off;
   const int64_t ld = jd.npad;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -364,7 +418,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const JobDesc* jobs, int 
       aim[i][j] = d4{0, 0, 0, 0};
     }
   const int ii = lane & 15, kq = lane >> 4;
-  for (int kc = 0; kc < NB; kc += 16) {
+  for (int kc = 0; kc < kd; kc += 16) {
     {
       const int i = t >> 2, k4 = (t & 3) * 4;
       const double2* src = A + (row0 + i) * ld + k + kc + k4;
@@ -416,10 +470,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const JobDesc* jobs, int 
 // v_mfma_f32_16x16x4: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);
 // D lane l, register r -> (row 4(l/16) + r, col l%16).
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, int k, float2* work) {
+__global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, int k, int kd, int r_begin, int c_begin,
+                                                   int c_end, float2* work) {
   const JobDesc jd = jobs[blockIdx.z];
-  const int row0 = k + NB + blockIdx.y * 64, col0 = k + NB + blockIdx.x * 64;
-  if (row0 >= jd.npad || col0 >= jd.npad) return;  // uniform
+  const int row0 = r_begin + blockIdx.y * 64, col0 = c_begin + blockIdx.x * 64;
+  if (row0 >= jd.npad || col0 >= jd.npad || (c_end > 0 && col0 >= c_end)) return;  // uniform
   float2* A = work + jd.a_off;
   const int64_t ld = jd.npad;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -436,7 +491,7 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, i
       t3[i][j] = f4{0, 0, 0, 0};
     }
   const int ii = lane & 15, kq = lane >> 4;
-  for (int kc = 0; kc < NB; kc += 16) {
+  for (int kc = 0; kc < kd; kc += 16) {
     {
       const int i = t >> 2, k4 = (t & 3) * 4;
       const float2* src = A + (row0 + i) * ld + k + kc + k4;
@@ -487,59 +542,83 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, i
 // drivers
 // ------------------------------------------------------------------------------------
 template <typename T>
-static void launch_panel(const JobDesc* jobs, int njobs, int k, int rows, T* work, int32_t* piv, int32_t* info,
-                         hipStream_t s) {
+static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int rows, T* work, int32_t* piv,
+                         int32_t* info, hipStream_t s) {
   constexpr int PT = 512;
   const int S = (rows + PT - 1) / PT;
   switch (S) {
-    case 1: panel_kernel<T, PT, 1, 8><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
-    case 2: panel_kernel<T, PT, 2, 8><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
-    case 3: panel_kernel<T, PT, 3, 8><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
-    case 4: panel_kernel<T, PT, 4, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
-    case 5: panel_kernel<T, PT, 5, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
-    case 6: panel_kernel<T, PT, 6, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
-    case 7: panel_kernel<T, PT, 7, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
-    default: panel_kernel<T, PT, 8, 4><<<njobs, PT, 0, s>>>(jobs, k, work, piv, info); break;
+    case 1: panel_kernel<T, PT, 1, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 2: panel_kernel<T, PT, 2, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 3: panel_kernel<T, PT, 3, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 4: panel_kernel<T, PT, 4, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 5: panel_kernel<T, PT, 5, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 6: panel_kernel<T, PT, 6, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 7: panel_kernel<T, PT, 7, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    default: panel_kernel<T, PT, 8, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
   }
 }
 
-static double step_flops(const GemmProfiler* prof, int njobs, int k) {
+// Algorithmic flops of one trailing-update launch: 8 m c kd per job (complex), over the
+// unpadded rows m and columns c of the updated block.
+static double update_flops(const GemmProfiler* prof, int njobs, int kd, int r_begin, int c_begin, int c_end) {
   double f = 0.0;
   for (int j = 0; j < njobs; ++j) {
-    const double m = (double)(prof->n_true[j] - k - NB);
-    if (m > 0) f += 8.0 * m * m * NB;
+    const int n = prof->n_true[j];
+    const double m = (double)(n - r_begin);
+    const double c = (double)((c_end > 0 ? std::min(c_end, n) : n) - c_begin);
+    if (m > 0 && c > 0) f += 8.0 * m * c * kd;
   }
   return f;
 }
 
+// Blocked right-looking LU with look-ahead over pairs of panels: panels start at every
+// multiple of 2 NB (first) and NB past it (second).  For a pair (k, k + NB):
+//   panel(k) -> interchanges + U12 on all trailing columns -> update of the second
+//   panel's columns only (K = NB) -> panel(k + NB), whose interchanges also permute the
+//   first panel's L rows -> interchanges + delayed first-panel update + U12 of the second
+//   panel on the columns beyond -> one trailing update with K = 2 NB.
+// The big update therefore streams the trailing matrix once per 2 NB columns.  The solves
+// apply the second panel's permutation right after the first panel's triangle.
+template <typename T, typename Gemm>
+static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work, int32_t* piv, int32_t* info,
+                          hipStream_t s, GemmProfiler* prof, Gemm gemm) {
+  auto timed_gemm = [&](int k, int kd, int r_begin, int c_begin, int c_end) {
+    const int rows = npad_max - r_begin;
+    const int cols = (c_end > 0 ? std::min(c_end, npad_max) : npad_max) - c_begin;
+    if (rows <= 0 || cols <= 0) return;
+    dim3 grid(cols / 64, rows / 64, njobs);
+    if (prof) prof->before(s);
+    gemm(grid, k, kd, r_begin, c_begin, c_end);
+    if (prof) prof->after(s, update_flops(prof, njobs, kd, r_begin, c_begin, c_end));
+  };
+  for (int k = 0; k < npad_max; k += 2 * NB) {
+    launch_panel<T>(jobs, njobs, k, 0, npad_max - k, work, piv, info, s);
+    const int rest = npad_max - k - NB;
+    if (rest <= 0) break;
+    swap_trsm_kernel<T, false><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, piv);
+    timed_gemm(k, NB, k + NB, k + NB, k + 2 * NB);  // the second panel's columns
+    launch_panel<T>(jobs, njobs, k + NB, NB, npad_max - k - NB, work, piv, info, s);
+    const int rest2 = npad_max - k - 2 * NB;
+    if (rest2 <= 0) break;
+    swap_trsm_kernel<T, true><<<dim3(rest2 / 64, njobs), 256, 0, s>>>(jobs, k + NB, work, piv);
+    timed_gemm(k, 2 * NB, k + 2 * NB, k + 2 * NB, 0);
+  }
+}
+
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
                    hipStream_t s, GemmProfiler* prof) {
-  for (int k = 0; k < npad_max; k += NB) {
-    launch_panel<double2>(jobs, njobs, k, npad_max - k, work, piv, info, s);
-    const int rest = npad_max - k - NB;
-    if (rest > 0) {
-      const int tiles = rest / 64;
-      swap_trsm_kernel<double2><<<dim3(tiles, njobs), 256, 0, s>>>(jobs, k, work, piv);
-      if (prof) prof->before(s);
-      gemm_f64_kernel<<<dim3(tiles, tiles, njobs), 256, 0, s>>>(jobs, k, work);
-      if (prof) prof->after(s, step_flops(prof, njobs, k));
-    }
-  }
+  lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof,
+                         [&](dim3 g, int k, int kd, int rb, int cb, int ce) {
+                           gemm_f64_kernel<<<g, 256, 0, s>>>(jobs, k, kd, rb, cb, ce, work);
+                         });
 }
 
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
                    hipStream_t s, GemmProfiler* prof) {
-  for (int k = 0; k < npad_max; k += NB) {
-    launch_panel<float2>(jobs, njobs, k, npad_max - k, work, piv, info, s);
-    const int rest = npad_max - k - NB;
-    if (rest > 0) {
-      const int tiles = rest / 64;
-      swap_trsm_kernel<float2><<<dim3(tiles, njobs), 256, 0, s>>>(jobs, k, work, piv);
-      if (prof) prof->before(s);
-      gemm_f32_3m_kernel<<<dim3(tiles, tiles, njobs), 256, 0, s>>>(jobs, k, work);
-      if (prof) prof->after(s, step_flops(prof, njobs, k));
-    }
-  }
+  lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof,
+                        [&](dim3 g, int k, int kd, int rb, int cb, int ce) {
+                          gemm_f32_3m_kernel<<<g, 256, 0, s>>>(jobs, k, kd, rb, cb, ce, work);
+                        });
 }
 
 }  // namespace lsms

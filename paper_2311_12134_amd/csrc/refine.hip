@@ -122,17 +122,21 @@ void launch_residual_norms(const JobDesc* jobs, int njobs, int npad_max, const d
   residual_kernel<<<grid, 256, 0, s>>>(jobs, m64, x, r, tpm, liz_atom, norms, done);
 }
 
+// Backward error of every pending job; jobs that reach tol are marked done, the others
+// are counted in *pending (one int, cleared by the caller before the launch).  Jobs that
+// are flagged already (zero pivot, bad input) are not refined.
 __global__ void refine_step_kernel(int njobs, double* norms, double tol, int32_t* done, int last,
-                                   int32_t* job_info) {
+                                   int32_t* job_info, int32_t* pending) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= njobs || done[j]) return;
   double* nm = norms + j * 8;
   const double berr = nm[1] / (nm[0] * nm[2] + nm[4]);
   nm[3] = berr;
-  if (berr <= tol) {
+  if (berr <= tol || job_info[j] != 0) {
     done[j] = 1;
-  } else if (last) {
-    if (job_info[j] == 0) job_info[j] = -1;
+  } else {
+    atomicAdd(pending, 1);
+    if (last) job_info[j] = -1;
   }
   nm[0] = 0.0;
   nm[1] = 0.0;
@@ -140,9 +144,9 @@ __global__ void refine_step_kernel(int njobs, double* norms, double tol, int32_t
 }
 
 void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double tol, int32_t* done, int last,
-                        int32_t* job_info, hipStream_t s) {
+                        int32_t* job_info, int32_t* pending, hipStream_t s) {
   (void)jobs;
-  refine_step_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(njobs, norms, tol, done, last, job_info);
+  refine_step_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(njobs, norms, tol, done, last, job_info, pending);
 }
 
 __global__ void add_correction_kernel(const JobDesc* jobs, double2* x, const double2* r, const int32_t* done) {

@@ -1,51 +1,52 @@
-// Solves with the blocked LU factors, and the FP64 residual / update of the
-// split-precision iterative refinement.
+// Solves with the blocked LU factors (forward substitution, back substitution, and the
+// transposed pair used by the adjoint).
 //
 // The factorization is the product M = P_1^T L_1 P_2^T L_2 ... P_K^T L_K U of panel
-// interchanges P_p and unit-lower panel factors L_p (stored in the panel's columns,
+// permutations P_p and unit-lower panel factors L_p (stored in the panel's columns,
 // never re-permuted by later panels).  Hence
 //   M X = B   :  X = U^-1 L_K^-1 P_K ... L_1^-1 P_1 B          (trans = 0)
 //   M^T X = B :  X = P_1^T L_1^-T ... P_K^T L_K^-T U^-T B      (trans = 1)
-// One workgroup per job walks the panels.  Each panel's interchanges are applied as one
-// gather of at most 2 NB rows (the permutation list written by the panel kernel), the
-// diagonal NB x NB triangle is solved by one wavefront with cross-lane shuffles (tri.h),
-// and the off-diagonal blocks stream through LDS one coalesced NB x NB tile at a time.
-// Arithmetic is FP64 for both storage types.
+// Every panel costs two launches over the whole batch:
+//   solve_diag_kernel    one workgroup per job: the panel's permutation as one gather of
+//                        at most 2 NB rows, and the NB x NB triangle solved by one
+//                        wavefront with cross-lane shuffles (tri.h);
+//   solve_update_kernel  one workgroup per (64-row strip, job): the off-diagonal block
+//                        times the panel's NB solved rows, on FP64 MFMA 16x16x4 (four real
+//                        products per complex product) from LDS-staged tiles, so the
+//                        factors stream from HBM once per solve.
+// The update is column-oriented (rows below for L and U^T, rows above for U) except for
+// L^T, whose panel rows need a sum over all rows below: there every strip adds its
+// partial product to the panel rows with FP64 atomics.  Arithmetic is FP64 for both
+// storage types of the factors.
 #include "lsms_internal.h"
 #include "tri.h"
 
 namespace lsms {
 
-// Per-thread share of an NB x NRHS block: entry u of thread t is idx = t + 256 u,
-// row idx / NRHS, column idx % NRHS.
-template <int NRHS>
-struct Blk {
-  static constexpr int PER = NB * NRHS / 256;
-};
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <typename T, int NRHS, int TRANS>
-__global__ __launch_bounds__(256) void solve_kernel(const JobDesc* jobs, const T* work, const int32_t* piv,
-                                                    double2* xbuf, int64_t col_off, const int32_t* skip) {
+enum { MODE_L = 0, MODE_U = 1, MODE_UT = 2, MODE_LT = 3 };
+
+template <typename T, int NRHS, int MODE>
+__global__ __launch_bounds__(256) void solve_diag_kernel(const JobDesc* jobs, int k, const T* work,
+                                                         const int32_t* piv, double2* xbuf, int64_t col_off,
+                                                         const int32_t* skip) {
   const int job = blockIdx.x;
   if (skip && skip[job]) return;
   const JobDesc jd = jobs[job];
+  if (k >= jd.npad) return;  // uniform
   const T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
-  const int npad = jd.npad;
   const int32_t* pv = piv + jd.piv_off;
   double2* X = xbuf + jd.x_off + col_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  constexpr int PER = Blk<NRHS>::PER;
   constexpr int HELD = PERM_MAX * NRHS / 256;
-  __shared__ double2 s_T[NB][NB + 1];  // diagonal block, or one NB x NB tile of L / U
-  __shared__ double2 s_X[NB][NRHS];    // right-hand sides of the current panel rows
-  __shared__ double2 s_C[NB][NRHS];    // a chunk of other right-hand-side rows
+  __shared__ double2 s_T[NB][NB + 1];
+  __shared__ double2 s_X[NB][NRHS];
   __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
   auto xrow = [&](int r) { return X + (int64_t)r * NRHS_MAX; };
-
-  // apply the permutation of panel k to X (gather dst <- src), or its inverse
-  auto permute = [&](int k, bool inverse) {
-    const int32_t* lst = pv + perm_off(npad, k);
+  auto permute = [&](int kp, bool inverse) {
+    const int32_t* lst = pv + perm_off(jd.npad, kp);
     const int cnt = lst[0];
     for (int i = t; i < cnt; i += 256) {
       s_dst[i] = lst[2 + i];
@@ -66,174 +67,181 @@ __global__ __launch_bounds__(256) void solve_kernel(const JobDesc* jobs, const T
     }
     __syncthreads();
   };
-  auto load_diag = [&](int k, int which) {  // 0: strict lower (L), 1: upper with diagonal (U)
-    for (int idx = t; idx < NB * NB; idx += 256) {
-      const int q = idx / NB, pp = idx % NB;
-      const bool keep = which ? (pp >= q) : (pp < q);
-      s_T[q][pp] = keep ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
-    }
-  };
-  auto load_tile = [&](int r0, int c0) {  // s_T = A[r0 .. r0+NB, c0 .. c0+NB)
-    for (int idx = t; idx < NB * NB; idx += 256) {
-      const int q = idx / NB, pp = idx % NB;
-      s_T[q][pp] = ld2(A + (int64_t)(r0 + q) * ld + c0 + pp);
-    }
-  };
-  auto load_rows = [&](double2 (*dst)[NRHS], int r0) {
-    for (int idx = t; idx < NB * NRHS; idx += 256) dst[idx / NRHS][idx % NRHS] = xrow(r0 + idx / NRHS)[idx % NRHS];
-  };
-  auto store_rows = [&](double2 (*src)[NRHS], int r0) {
-    for (int idx = t; idx < NB * NRHS; idx += 256) xrow(r0 + idx / NRHS)[idx % NRHS] = src[idx / NRHS][idx % NRHS];
-  };
+  // Panels come in pairs (first at multiples of 2 NB, see lu_factor): the first panel's
+  // L rows are stored after the second panel's permutation, so the forward solve applies
+  // that permutation right after the first triangle, and the transposed solve undoes both
+  // permutations after the first triangle.
+  const bool first = (k % (2 * NB)) == 0;
+  const bool has_second = first && (k + NB < jd.npad);
+  if (MODE == MODE_L && first) permute(k, false);
+  const bool upper = (MODE == MODE_U || MODE == MODE_UT);
+  for (int idx = t; idx < NB * NB; idx += 256) {
+    const int q = idx / NB, pp = idx % NB;
+    const bool keep = upper ? (pp >= q) : (pp < q);
+    s_T[q][pp] = keep ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+  }
+  for (int idx = t; idx < NB * NRHS; idx += 256) s_X[idx / NRHS][idx % NRHS] = xrow(k + idx / NRHS)[idx % NRHS];
+  __syncthreads();
+  if (wave == 0) {
+    if (MODE == MODE_L) tri_unit_lower<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
+    if (MODE == MODE_U) tri_upper<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
+    if (MODE == MODE_UT) tri_upper_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
+    if (MODE == MODE_LT) tri_unit_lower_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
+  }
+  __syncthreads();
+  for (int idx = t; idx < NB * NRHS; idx += 256) xrow(k + idx / NRHS)[idx % NRHS] = s_X[idx / NRHS][idx % NRHS];
+  if (MODE == MODE_L && has_second) {
+    __syncthreads();
+    permute(k + NB, false);
+  }
+  if (MODE == MODE_LT && first) {
+    __syncthreads();
+    if (has_second) permute(k + NB, true);
+    permute(k, true);
+  }
+}
 
-  if (TRANS == 0) {
-    // X <- L_K^-1 P_K ... L_1^-1 P_1 X
-    for (int k = 0; k < npad; k += NB) {
-      permute(k, false);
-      load_diag(k, 0);
-      load_rows(s_X, k);
-      __syncthreads();
-      if (wave == 0) tri_unit_lower<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
-      __syncthreads();
-      store_rows(s_X, k);
-      __syncthreads();
-      for (int r0 = k + NB; r0 < npad; r0 += NB) {  // rows below: X -= L21 X_p
-        load_tile(r0, k);
-        load_rows(s_C, r0);
-        __syncthreads();
+// One 64-row strip:  MODE_L   X[s] -= L[s, P] X[P]      (s below the panel P)
+//                    MODE_U   X[s] -= U[s, P] X[P]      (s above the panel)
+//                    MODE_UT  X[s] -= U[P, s]^T X[P]    (s below)
+//                    MODE_LT  X[P] -= L[s, P]^T X[s]    (s below; atomics into the panel rows)
+// out (64 x NRHS) = A (64 x NB) B (NB x NRHS) with K chunks of 32 staged in LDS.
+template <typename T, int NRHS, int MODE>
+__global__ __launch_bounds__(256) void solve_update_kernel(const JobDesc* jobs, int k, const T* work,
+                                                           double2* xbuf, int64_t col_off, const int32_t* skip) {
+  const int job = blockIdx.y;
+  if (skip && skip[job]) return;
+  const JobDesc jd = jobs[job];
+  const int s0 = (MODE == MODE_U) ? blockIdx.x * 64 : k + NB + blockIdx.x * 64;  // strip rows
+  if (k >= jd.npad) return;
+  if (MODE == MODE_U ? (s0 >= k) : (s0 >= jd.npad)) return;  // uniform
+  const T* A = work + jd.a_off;
+  const int64_t ld = jd.npad;
+  double2* X = xbuf + jd.x_off + col_off;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  constexpr int KC = 32;
+  constexpr int CB = NRHS / 16;  // 16-column output blocks per wave
+  __shared__ double2 sA[KC][64 + 1];      // sA[kk][o]: A[o][k0 + kk] for output row o
+  __shared__ double2 sB[NB][NRHS + 1];    // right-hand operand, NB x NRHS
+  // right-hand operand: the panel rows (L, U, UT) or the strip rows (LT)
+  const int brow = (MODE == MODE_LT) ? s0 : k;
+  for (int idx = t; idx < NB * NRHS; idx += 256)
+    sB[idx / NRHS][idx % NRHS] = X[(int64_t)(brow + idx / NRHS) * NRHS_MAX + idx % NRHS];
+  d4 are[CB], aim[CB];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int idx = t + 256 * u, rr = idx / NRHS, c = idx % NRHS;
-          double2 acc = s_C[rr][c];
-#pragma unroll 8
-          for (int q = 0; q < NB; ++q) acc = cfms(acc, s_T[rr][q], s_X[q][c]);
-          xrow(r0 + rr)[c] = acc;
-        }
-        __syncthreads();
+  for (int cb = 0; cb < CB; ++cb) {
+    are[cb] = d4{0, 0, 0, 0};
+    aim[cb] = d4{0, 0, 0, 0};
+  }
+  const int ii = lane & 15, kq = lane >> 4;
+  for (int k0 = 0; k0 < NB; k0 += KC) {
+    __syncthreads();
+    // stage A[o][k0 .. k0+KC) for the 64 output rows o into sA[kk][o]
+    for (int idx = t; idx < KC * 64; idx += 256) {
+      if (MODE == MODE_L || MODE == MODE_U) {
+        const int o = idx / KC, kk = idx % KC;  // consecutive threads walk a row
+        sA[kk][o] = ld2(A + (int64_t)(s0 + o) * ld + k + k0 + kk);
+      } else if (MODE == MODE_UT) {
+        const int kk = idx / 64, o = idx % 64;  // U[k + k0 + kk][s0 + o]
+        sA[kk][o] = ld2(A + (int64_t)(k + k0 + kk) * ld + s0 + o);
+      } else {
+        const int kk = idx / 64, o = idx % 64;  // L[s0 + k0 + kk][k + o]: sum over strip rows
+        sA[kk][o] = ld2(A + (int64_t)(s0 + k0 + kk) * ld + k + o);
       }
     }
-    // X <- U^-1 X
-    for (int k = npad - NB; k >= 0; k -= NB) {
-      double2 acc[PER];
+    __syncthreads();
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int idx = t + 256 * u;
-        acc[u] = xrow(k + idx / NRHS)[idx % NRHS];
-      }
-      for (int c0 = k + NB; c0 < npad; c0 += NB) {  // X_p -= U12 X_right
-        load_tile(k, c0);
-        load_rows(s_C, c0);
-        __syncthreads();
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      const double2 a = sA[k4 + kq][wave * 16 + ii];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int idx = t + 256 * u, q = idx / NRHS, c = idx % NRHS;
-#pragma unroll 8
-          for (int cc = 0; cc < NB; ++cc) acc[u] = cfms(acc[u], s_T[q][cc], s_C[cc][c]);
-        }
-        __syncthreads();
+      for (int cb = 0; cb < CB; ++cb) {
+        const double2 b = sB[k0 + k4 + kq][cb * 16 + ii];
+        are[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, are[cb], 0, 0, 0);
+        are[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, are[cb], 0, 0, 0);
+        aim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, aim[cb], 0, 0, 0);
+        aim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, aim[cb], 0, 0, 0);
       }
+    }
+  }
+  // D lane l, register r -> output row 16 wave + l/16 + 4r, column 16 cb + l%16
+  const int orow0 = (MODE == MODE_LT) ? k : s0;
 #pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int idx = t + 256 * u;
-        s_X[idx / NRHS][idx % NRHS] = acc[u];
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = wave * 16 + kq + 4 * r, c = cb * 16 + ii;
+      double2* xp = X + (int64_t)(orow0 + o) * NRHS_MAX + c;
+      if (MODE == MODE_LT) {
+        atomicAdd(&xp->x, -are[cb][r]);
+        atomicAdd(&xp->y, -aim[cb][r]);
+      } else {
+        double2 v = *xp;
+        v.x -= are[cb][r];
+        v.y -= aim[cb][r];
+        *xp = v;
       }
-      load_diag(k, 1);
-      __syncthreads();
-      if (wave == 0) tri_upper<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
-      __syncthreads();
-      store_rows(s_X, k);
-      __syncthreads();
+    }
+}
+
+template <typename T, int NRHS, int MODE>
+static void diag(const JobDesc* jobs, int njobs, int k, const T* work, const int32_t* piv, double2* x,
+                 int64_t col_off, const int32_t* skip, hipStream_t s) {
+  solve_diag_kernel<T, NRHS, MODE><<<njobs, 256, 0, s>>>(jobs, k, work, piv, x, col_off, skip);
+}
+
+template <typename T, int NRHS, int MODE>
+static void update(const JobDesc* jobs, int njobs, int k, int strips, const T* work, double2* x, int64_t col_off,
+                   const int32_t* skip, hipStream_t s) {
+  if (strips <= 0) return;
+  solve_update_kernel<T, NRHS, MODE><<<dim3(strips, njobs), 256, 0, s>>>(jobs, k, work, x, col_off, skip);
+}
+
+template <typename T, int NRHS>
+static void solve_all(const JobDesc* jobs, int njobs, int npad_max, const T* work, const int32_t* piv, double2* x,
+                      int64_t col_off, int trans, const int32_t* skip, hipStream_t s) {
+  if (!trans) {
+    for (int k = 0; k < npad_max; k += NB) {
+      diag<T, NRHS, MODE_L>(jobs, njobs, k, work, piv, x, col_off, skip, s);
+      update<T, NRHS, MODE_L>(jobs, njobs, k, (npad_max - k - NB) / 64, work, x, col_off, skip, s);
+    }
+    for (int k = npad_max - NB; k >= 0; k -= NB) {
+      diag<T, NRHS, MODE_U>(jobs, njobs, k, work, piv, x, col_off, skip, s);
+      update<T, NRHS, MODE_U>(jobs, njobs, k, k / 64, work, x, col_off, skip, s);
     }
   } else {
-    // X <- U^-T X (forward over panels)
-    for (int k = 0; k < npad; k += NB) {
-      load_diag(k, 1);
-      load_rows(s_X, k);
-      __syncthreads();
-      if (wave == 0) tri_upper_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
-      __syncthreads();
-      store_rows(s_X, k);
-      __syncthreads();
-      for (int r0 = k + NB; r0 < npad; r0 += NB) {  // X_r -= U12^T X_p
-        load_tile(k, r0);
-        load_rows(s_C, r0);
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int idx = t + 256 * u, rr = idx / NRHS, c = idx % NRHS;
-          double2 a = s_C[rr][c];
-#pragma unroll 8
-          for (int q = 0; q < NB; ++q) a = cfms(a, s_T[q][rr], s_X[q][c]);
-          xrow(r0 + rr)[c] = a;
-        }
-        __syncthreads();
-      }
+    for (int k = 0; k < npad_max; k += NB) {
+      diag<T, NRHS, MODE_UT>(jobs, njobs, k, work, piv, x, col_off, skip, s);
+      update<T, NRHS, MODE_UT>(jobs, njobs, k, (npad_max - k - NB) / 64, work, x, col_off, skip, s);
     }
-    // X <- P_1^T L_1^-T ... P_K^T L_K^-T X (backward over panels)
-    for (int k = npad - NB; k >= 0; k -= NB) {
-      double2 acc[PER];
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int idx = t + 256 * u;
-        acc[u] = xrow(k + idx / NRHS)[idx % NRHS];
-      }
-      for (int r0 = k + NB; r0 < npad; r0 += NB) {  // X_p -= L21^T X_below
-        load_tile(r0, k);
-        load_rows(s_C, r0);
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int idx = t + 256 * u, q = idx / NRHS, c = idx % NRHS;
-#pragma unroll 8
-          for (int rr = 0; rr < NB; ++rr) acc[u] = cfms(acc[u], s_T[rr][q], s_C[rr][c]);
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int idx = t + 256 * u;
-        s_X[idx / NRHS][idx % NRHS] = acc[u];
-      }
-      load_diag(k, 0);
-      __syncthreads();
-      if (wave == 0) tri_unit_lower_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
-      __syncthreads();
-      store_rows(s_X, k);
-      __syncthreads();
-      permute(k, true);
+    for (int k = npad_max - NB; k >= 0; k -= NB) {
+      update<T, NRHS, MODE_LT>(jobs, njobs, k, (npad_max - k - NB) / 64, work, x, col_off, skip, s);
+      diag<T, NRHS, MODE_LT>(jobs, njobs, k, work, piv, x, col_off, skip, s);
     }
   }
 }
 
 template <typename T>
-static void solve_dispatch(const JobDesc* jobs, int njobs, const T* work, const int32_t* piv, double2* x,
-                           int64_t col_off, int nrhs, int trans, const int32_t* skip, hipStream_t s) {
-  if (nrhs == 16) {
-    if (trans)
-      solve_kernel<T, 16, 1><<<njobs, 256, 0, s>>>(jobs, work, piv, x, col_off, skip);
-    else
-      solve_kernel<T, 16, 0><<<njobs, 256, 0, s>>>(jobs, work, piv, x, col_off, skip);
-  } else {
-    if (trans)
-      solve_kernel<T, 32, 1><<<njobs, 256, 0, s>>>(jobs, work, piv, x, col_off, skip);
-    else
-      solve_kernel<T, 32, 0><<<njobs, 256, 0, s>>>(jobs, work, piv, x, col_off, skip);
-  }
+static void solve_dispatch(const JobDesc* jobs, int njobs, int npad_max, const T* work, const int32_t* piv,
+                           double2* x, int64_t col_off, int nrhs, int trans, const int32_t* skip, hipStream_t s) {
+  if (nrhs == 16)
+    solve_all<T, 16>(jobs, njobs, npad_max, work, piv, x, col_off, trans, skip, s);
+  else
+    solve_all<T, 32>(jobs, njobs, npad_max, work, piv, x, col_off, trans, skip, s);
 }
 
-void lu_solve_f64(const JobDesc* jobs, int njobs, const double2* work, const int32_t* piv, double2* x,
-                  int64_t x_col_off, int nrhs, int trans, hipStream_t s) {
-  solve_dispatch<double2>(jobs, njobs, work, piv, x, x_col_off, nrhs, trans, nullptr, s);
+void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
+                  double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s) {
+  solve_dispatch<double2>(jobs, njobs, npad_max, work, piv, x, x_col_off, nrhs, trans, nullptr, s);
 }
 
-void lu_solve_f32(const JobDesc* jobs, int njobs, const float2* work, const int32_t* piv, double2* x,
-                  int64_t x_col_off, int nrhs, int trans, hipStream_t s) {
-  solve_dispatch<float2>(jobs, njobs, work, piv, x, x_col_off, nrhs, trans, nullptr, s);
+void lu_solve_f32(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
+                  double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s) {
+  solve_dispatch<float2>(jobs, njobs, npad_max, work, piv, x, x_col_off, nrhs, trans, nullptr, s);
 }
 
-void lu_solve_f32_skip(const JobDesc* jobs, int njobs, const float2* work, const int32_t* piv, double2* x,
-                       const int32_t* skip, hipStream_t s) {
-  solve_dispatch<float2>(jobs, njobs, work, piv, x, 0, 16, 0, skip, s);
+void lu_solve_f32_skip(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
+                       double2* x, const int32_t* skip, hipStream_t s) {
+  solve_dispatch<float2>(jobs, njobs, npad_max, work, piv, x, 0, 16, 0, skip, s);
 }
 
 }  // namespace lsms

@@ -235,3 +235,20 @@ def test_adjoint_bcc250_vs_fd_sampled(lctx):
         fd = (_gpu_sigma(lctx, w, liz, la, lp, species, J, p1, eta)[0]
               - _gpu_sigma(lctx, w, liz, la, lp, species, J, p2, eta)[0]) / (2 * h)
         assert abs(fd - g[k, l]) <= 1e-6 * np.abs(g).max(), (k, l, fd, g[k, l])
+
+
+def test_split_fallback_to_fp64_when_refinement_cannot_converge(lctx):
+    """With no refinement budget every job is flagged NOCONV and recomputed in FP64."""
+    w = synthetic.workload("bcc16")
+    eta = w["etas"][0]
+    g = _run(lctx, w, eta, precision="split", refine_tol=1e-300, max_refine=0)
+    assert (g["info"] == -1).all()
+    atoms = list(range(16))
+    o = _oracle_atoms(w, eta, atoms, g["liz"])
+    _check_atoms(g, o, atoms, TOL64)
+
+
+def test_split_refinement_reaches_tolerance_quickly(lctx):
+    w = synthetic.workload("bcc250")
+    g = _run(lctx, w, w["etas"][0], precision="split", refine_tol=1e-14, max_refine=3, per_atom=False)
+    assert (g["info"] == 0).all() and (g["berr"] <= 1e-14).all()
