@@ -53,6 +53,8 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   __shared__ double2 s_Lc[PT][IB];
   __shared__ int s_pivall[NB];
   __shared__ int s_pos[PERM_MAX], s_org[PERM_MAX];
+  __shared__ int s_lpos[2 * IB], s_lorg[2 * IB], s_lcnt;
+  __shared__ T s_held[2 * IB][2 * NB - IB];
 
   double2 v[S][IB];
   int first_zero = 0;
@@ -180,18 +182,48 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
     }
     __syncthreads();
     // the leaf's interchanges on the other columns of the panel (whole panel rows), and on
-    // the `left` columns before it (the first panel of a pair, see lu_factor)
-    for (int cc = t; cc < left + NB - IB; cc += PT) {
-      const int cr = cc - left;
-      const int col = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
+    // the `left` columns before it (the first panel of a pair, see lu_factor), applied as
+    // one gather: at most 2 IB rows change, listed as (position, original row) pairs
+    if (t == 0) {
+      int cnt = IB;
+      for (int i = 0; i < IB; ++i) {
+        s_lpos[i] = cl + i;
+        s_lorg[i] = cl + i;
+      }
       for (int q = 0; q < IB; ++q) {
         const int d = cl + q, p = s_piv[q];
-        if (p != d && p > d && p < nrows) {
-          const double2 x = ld2(A + d * ld + col);
-          const double2 y = ld2(A + p * ld + col);
-          st2(A + d * ld + col, y);
-          st2(A + p * ld + col, x);
+        if (p == d || p <= d || p >= nrows) continue;
+        int e = -1;
+        if (p < cl + IB) {
+          e = p - cl;
+        } else {
+          for (int i = IB; i < cnt; ++i)
+            if (s_lpos[i] == p) e = i;
+          if (e < 0) {
+            e = cnt++;
+            s_lpos[e] = p;
+            s_lorg[e] = p;
+          }
         }
+        const int tmp = s_lorg[q];
+        s_lorg[q] = s_lorg[e];
+        s_lorg[e] = tmp;
+      }
+      s_lcnt = cnt;
+    }
+    __syncthreads();
+    {
+      const int ncols = left + NB - IB, cnt = s_lcnt;
+      for (int idx = t; idx < cnt * ncols; idx += PT) {
+        const int e = idx / ncols, cc = idx - e * ncols, cr = cc - left;
+        const int col = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
+        s_held[e][cc] = A[s_lorg[e] * ld + col];
+      }
+      __syncthreads();
+      for (int idx = t; idx < cnt * ncols; idx += PT) {
+        const int e = idx / ncols, cc = idx - e * ncols, cr = cc - left;
+        const int col = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
+        A[s_lpos[e] * ld + col] = s_held[e][cc];
       }
     }
     __syncthreads();
@@ -301,8 +333,9 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  __shared__ double2 s_L[NB][NB + 1];
-  __shared__ double2 s_X[NB][64 + 1];
+  typedef typename LdsOf<T>::type S;
+  __shared__ S s_L[NB][NB + 1];
+  __shared__ S s_X[NB][64 + 1];
   __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
   const int32_t* lst = piv + jd.piv_off + perm_off(jd.npad, k);
   const int cnt = lst[0];
@@ -313,36 +346,36 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   if (SECOND) {  // the first panel's L rows that face this panel
     for (int idx = t; idx < NB * NB; idx += 256) {
       const int q = idx / NB, pp = idx % NB;
-      s_L[q][pp] = ld2(A + (k + q) * ld + (k - NB) + pp);
+      s_L[q][pp] = A[(k + q) * ld + (k - NB) + pp];
     }
   } else {
     for (int idx = t; idx < NB * NB; idx += 256) {
       const int q = idx / NB, pp = idx % NB;
-      s_L[q][pp] = pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+      st2(&s_L[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0));
     }
   }
   __syncthreads();
   // the panel's permutation as a gather on this tile: entry i = wave + 4 s, column = lane
-  double2 held[PERM_MAX / 4];
+  T held[PERM_MAX / 4];
 #pragma unroll
-  for (int s = 0; s < PERM_MAX / 4; ++s) {
-    const int i = wave + 4 * s;
+  for (int u = 0; u < PERM_MAX / 4; ++u) {
+    const int i = wave + 4 * u;
     if (i < cnt) {
       const int dst = s_dst[i];
-      const double2 v = ld2(A + s_src[i] * ld + col0 + lane);
+      const T v = A[s_src[i] * ld + col0 + lane];
       if (dst < k + NB)
         s_X[dst - k][lane] = v;
       else
-        held[s] = v;
+        held[u] = v;
     }
   }
   __syncthreads();  // every source row is read before any destination row is written
 #pragma unroll
-  for (int s = 0; s < PERM_MAX / 4; ++s) {
-    const int i = wave + 4 * s;
+  for (int u = 0; u < PERM_MAX / 4; ++u) {
+    const int i = wave + 4 * u;
     if (i < cnt) {
       const int dst = s_dst[i];
-      if (dst >= k + NB) st2(A + dst * ld + col0 + lane, held[s]);
+      if (dst >= k + NB) A[dst * ld + col0 + lane] = held[u];
     }
   }
   if (SECOND) {
@@ -357,7 +390,7 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
     }
     const int ii = lane & 15, kq = lane >> 4;
     for (int k4 = 0; k4 < NB; k4 += 4) {
-      const double2 a = s_L[wave * 16 + ii][k4 + kq];
+      const double2 a = ld2(&s_L[wave * 16 + ii][k4 + kq]);
       const T* urow = A + (int64_t)(k - NB + k4 + kq) * ld + col0;
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
@@ -372,14 +405,16 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        double2& xv = s_X[wave * 16 + kq + 4 * r][cb * 16 + ii];
+        S* xp = &s_X[wave * 16 + kq + 4 * r][cb * 16 + ii];
+        double2 xv = ld2(xp);
         xv.x -= are[cb][r];
         xv.y -= aim[cb][r];
+        st2(xp, xv);
       }
     __syncthreads();
     for (int idx = t; idx < NB * NB; idx += 256) {  // now the panel's own unit lower triangle
       const int q = idx / NB, pp = idx % NB;
-      s_L[q][pp] = pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+      st2(&s_L[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0));
     }
     __syncthreads();
   }
@@ -388,7 +423,7 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   __syncthreads();
   for (int idx = t; idx < NB * 64; idx += 256) {
     const int q = idx >> 6, cc = idx & 63;
-    st2(A + (k + q) * ld + col0 + cc, s_X[q][cc]);
+    A[(k + q) * ld + col0 + cc] = s_X[q][cc];
   }
 }
 
@@ -550,8 +585,8 @@ static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int ro
     case 1: panel_kernel<T, PT, 1, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
     case 2: panel_kernel<T, PT, 2, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
     case 3: panel_kernel<T, PT, 3, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
-    case 4: panel_kernel<T, PT, 4, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
-    case 5: panel_kernel<T, PT, 5, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 4: panel_kernel<T, PT, 4, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 5: panel_kernel<T, PT, 5, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
     case 6: panel_kernel<T, PT, 6, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
     case 7: panel_kernel<T, PT, 7, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
     default: panel_kernel<T, PT, 8, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;

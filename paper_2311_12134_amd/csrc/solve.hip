@@ -41,7 +41,8 @@ __global__ __launch_bounds__(256) void solve_diag_kernel(const JobDesc* jobs, in
   double2* X = xbuf + jd.x_off + col_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   constexpr int HELD = PERM_MAX * NRHS / 256;
-  __shared__ double2 s_T[NB][NB + 1];
+  typedef typename LdsOf<T>::type S;
+  __shared__ S s_T[NB][NB + 1];
   __shared__ double2 s_X[NB][NRHS];
   __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
   auto xrow = [&](int r) { return X + (int64_t)r * NRHS_MAX; };
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(256) void solve_diag_kernel(const JobDesc* jobs, in
   for (int idx = t; idx < NB * NB; idx += 256) {
     const int q = idx / NB, pp = idx % NB;
     const bool keep = upper ? (pp >= q) : (pp < q);
-    s_T[q][pp] = keep ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0);
+    s_T[q][pp] = keep ? A[(k + q) * ld + k + pp] : S{0, 0};
   }
   for (int idx = t; idx < NB * NRHS; idx += 256) s_X[idx / NRHS][idx % NRHS] = xrow(k + idx / NRHS)[idx % NRHS];
   __syncthreads();
@@ -121,7 +122,8 @@ __global__ __launch_bounds__(256) void solve_update_kernel(const JobDesc* jobs, 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   constexpr int KC = 32;
   constexpr int CB = NRHS / 16;  // 16-column output blocks per wave
-  __shared__ double2 sA[KC][64 + 1];      // sA[kk][o]: A[o][k0 + kk] for output row o
+  typedef typename LdsOf<T>::type S;
+  __shared__ S sA[KC][64 + 1];            // sA[kk][o]: A[o][k0 + kk] for output row o
   __shared__ double2 sB[NB][NRHS + 1];    // right-hand operand, NB x NRHS
   // right-hand operand: the panel rows (L, U, UT) or the strip rows (LT)
   const int brow = (MODE == MODE_LT) ? s0 : k;
@@ -140,19 +142,19 @@ __global__ __launch_bounds__(256) void solve_update_kernel(const JobDesc* jobs, 
     for (int idx = t; idx < KC * 64; idx += 256) {
       if (MODE == MODE_L || MODE == MODE_U) {
         const int o = idx / KC, kk = idx % KC;  // consecutive threads walk a row
-        sA[kk][o] = ld2(A + (int64_t)(s0 + o) * ld + k + k0 + kk);
+        sA[kk][o] = A[(int64_t)(s0 + o) * ld + k + k0 + kk];
       } else if (MODE == MODE_UT) {
         const int kk = idx / 64, o = idx % 64;  // U[k + k0 + kk][s0 + o]
-        sA[kk][o] = ld2(A + (int64_t)(k + k0 + kk) * ld + s0 + o);
+        sA[kk][o] = A[(int64_t)(k + k0 + kk) * ld + s0 + o];
       } else {
         const int kk = idx / 64, o = idx % 64;  // L[s0 + k0 + kk][k + o]: sum over strip rows
-        sA[kk][o] = ld2(A + (int64_t)(s0 + k0 + kk) * ld + k + o);
+        sA[kk][o] = A[(int64_t)(s0 + k0 + kk) * ld + k + o];
       }
     }
     __syncthreads();
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
-      const double2 a = sA[k4 + kq][wave * 16 + ii];
+      const double2 a = ld2(&sA[k4 + kq][wave * 16 + ii]);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
         const double2 b = sB[k0 + k4 + kq][cb * 16 + ii];
