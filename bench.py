@@ -12,6 +12,7 @@ Prints one JSON line; see the design doc for the roofline and baseline definitions.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,17 @@ import numpy as np  # noqa: E402
 METRIC = "atoms/sec through LIZ τ-solve + Kubo trace; % MFMA peak; split vs FP64 at 1e-8"
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64_MFMA = 78.6e12
+GEMM_SOURCE = os.path.join(ROOT, "paper_2311_12134_amd", "csrc", "gemm.hip")
+
+# HBM bytes per launch of the trailing-update kernel on this workload, from two rocprofv3
+# counter runs (FETCH_SIZE, WRITE_SIZE) over one step, each scaled by what the same counter
+# read for a 1 GiB device-to-device copy in the same run (--copy-calibration).  Keyed by
+# (precision, workload) and tied to the sha256 of the kernel source the counters were
+# taken on: any later change to that source makes the figure stale and it is reported as null.
+TRAFFIC = {
+    ("split", "fcc4000"): {"sha256": "5c27de413339949d5cc9a13e34249b395bcc71cde6bc70ac5a634222913a563c",
+                           "bytes_per_launch": 2.4708e10},
+}
 
 
 def log(*a):
@@ -62,6 +74,8 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device-to-device copy before the timed region (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -99,6 +113,15 @@ def main():
         if keep_sigma is not None:
             keep_sigma[eta] = sig.clone()
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written" % (src.numel() * 4, dst.numel() * 4))
+        del src, dst
+
     sig_main = {}
     for i in range(args.warmup):
         step(i, args.precision, sig_main)
@@ -111,7 +134,7 @@ def main():
         step(i, args.precision, sig_main)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    gemm_ms, gemm_launches, gemm_flops = ctx.kernel_stats()
+    gemm_ms, gemm_launches, gemm_flops, gemm_bytes = ctx.kernel_stats()
     ctx.set_profiling(False)
     info_np = info.cpu().numpy()
     ms_per_step = 1e3 * elapsed / args.steps
@@ -136,10 +159,15 @@ def main():
     if gemm_launches:
         avg_s = gemm_ms / gemm_launches / 1e3
         achieved = gemm_flops / gemm_launches / avg_s
+        with open(GEMM_SOURCE, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+        rec = TRAFFIC.get((args.precision, args.workload))
+        traffic = rec["bytes_per_launch"] if rec is not None and rec["sha256"] == digest else None
         out["roofline"] = {"kernel": "gemm_f32_3m_kernel" if args.precision == "split" else "gemm_f64_kernel",
                            "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                           "frac": achieved / peak, "traffic": None,
-                           "launches": gemm_launches, "avg_launch_ms": 1e3 * avg_s}
+                           "frac": achieved / peak, "traffic": traffic,
+                           "launches": gemm_launches, "avg_launch_ms": 1e3 * avg_s,
+                           "alg_bytes_per_launch": gemm_bytes / gemm_launches}
     if not args.no_fp64_compare and args.precision == "split":
         sig64 = {}
         step(0, "fp64", sig64)  # warm-up of the FP64 path (workspace layout differs)

@@ -201,12 +201,16 @@ int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t* n, void* 
  * lsms_set_profiling(ctx, 1) waits for the device, clears the statistics and makes every
  * later lsms_tau_solve record a pair of HIP events around each trailing-update launch on
  * the caller's stream (0 switches recording off).  lsms_kernel_stats waits for the
- * recorded events and returns the summed launch time (ms), the number of launches and
- * their algorithmic flops: 8 m^2 NB per system and launch with m = n - k - NB (the
- * standard complex count of a rank-NB update; the split mode executes 3/4 of it).
+ * recorded events and returns the summed launch time (ms), the number of launches, their
+ * algorithmic flops and their algorithmic bytes.  A launch updates, in every system, the
+ * unpadded block of m rows and c columns with K = kd (64 or 128): 8 m c kd flops (the
+ * standard complex count; the split mode executes 3/4 of it on the matrix cores) and
+ * es (m kd + kd c + 2 m c) bytes, es = 8 (split) or 16 (FP64).  All outputs are host
+ * scalars; the call returns LSMS_E_ARG for a NULL pointer.
  */
 int lsms_set_profiling(lsms_ctx* ctx, int on);
-int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launches, double* alg_flops);
+int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launches, double* alg_flops,
+                      double* alg_bytes);
 
 /*
  * Host-only query of the library's Gaunt table (Sec. II.A: g is built from these

@@ -46,7 +46,7 @@ _PROTOS = {
                                       c_void_p]),
     "lsms_gaunt_table": (c_int, [c_void_p]),
     "lsms_set_profiling": (c_int, [c_void_p, c_int]),
-    "lsms_kernel_stats": (c_int, [c_void_p, P(c_double), P(c_int64), P(c_double)]),
+    "lsms_kernel_stats": (c_int, [c_void_p, P(c_double), P(c_int64), P(c_double), P(c_double)]),
 }
 
 _lib = None

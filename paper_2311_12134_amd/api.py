@@ -170,12 +170,14 @@ class Context:
         check(lib().lsms_set_profiling(self._h, 1 if on else 0))
 
     def kernel_stats(self):
-        """(total ms, launches, algorithmic flops) of the recorded trailing-update launches."""
+        """(total ms, launches, algorithmic flops, algorithmic bytes) of the recorded
+        trailing-update launches."""
         ms = ctypes.c_double(0)
         n = ctypes.c_int64(0)
         fl = ctypes.c_double(0)
-        check(lib().lsms_kernel_stats(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
-        return ms.value, n.value, fl.value
+        by = ctypes.c_double(0)
+        check(lib().lsms_kernel_stats(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl), ctypes.byref(by)))
+        return ms.value, n.value, fl.value, by.value
 
     # -- diagnostic batched solve ------------------------------------------------------
     def batched_lu_solve(self, mats, rhs, precision="fp64"):

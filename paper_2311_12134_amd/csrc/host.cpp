@@ -56,7 +56,7 @@ struct DevBuf {
 struct EventProf : GemmProfiler {
   std::vector<hipEvent_t> pool;
   size_t used = 0;
-  std::vector<double> flops;
+  std::vector<double> flops, bytes;
   hipEvent_t get() {
     if (used < pool.size()) return pool[used++];
     hipEvent_t e = nullptr;
@@ -69,14 +69,16 @@ struct EventProf : GemmProfiler {
     hipEvent_t e = get();
     if (e) hipEventRecord(e, s);
   }
-  void after(hipStream_t s, double f) override {
+  void after(hipStream_t s, double f, double b) override {
     hipEvent_t e = get();
     if (e) hipEventRecord(e, s);
     flops.push_back(f);
+    bytes.push_back(b);
   }
   void reset() {
     used = 0;
     flops.clear();
+    bytes.clear();
   }
   ~EventProf() override {
     for (hipEvent_t e : pool) hipEventDestroy(e);
@@ -730,10 +732,11 @@ extern "C" int lsms_set_profiling(lsms_ctx* ctx, int on) {
   return LSMS_OK;
 }
 
-extern "C" int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launches, double* alg_flops) {
-  if (!ctx || !total_ms || !launches || !alg_flops) return fail(LSMS_E_ARG, "NULL argument");
+extern "C" int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launches, double* alg_flops,
+                                 double* alg_bytes) {
+  if (!ctx || !total_ms || !launches || !alg_flops || !alg_bytes) return fail(LSMS_E_ARG, "NULL argument");
   HIP_TRY(hipSetDevice(ctx->device));
-  double ms = 0.0, fl = 0.0;
+  double ms = 0.0, fl = 0.0, by = 0.0;
   const size_t n = ctx->prof.flops.size();
   for (size_t i = 0; i < n; ++i) {
     hipEvent_t a = ctx->prof.pool[2 * i], b = ctx->prof.pool[2 * i + 1];
@@ -742,10 +745,12 @@ extern "C" int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launc
     HIP_TRY(hipEventElapsedTime(&e, a, b));
     ms += e;
     fl += ctx->prof.flops[i];
+    by += ctx->prof.bytes[i];
   }
   *total_ms = ms;
   *launches = (int64_t)n;
   *alg_flops = fl;
+  *alg_bytes = by;
   return LSMS_OK;
 }
 

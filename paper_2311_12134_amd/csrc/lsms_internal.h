@@ -113,9 +113,16 @@ void launch_init_rhs(const JobDesc* jobs, int njobs, int npad_max, const int32_t
 struct GemmProfiler {
   const int* n_true = nullptr;
   virtual void before(hipStream_t s) = 0;
-  virtual void after(hipStream_t s, double alg_flops) = 0;
+  virtual void after(hipStream_t s, double alg_flops, double alg_bytes) = 0;
   virtual ~GemmProfiler() {}
 };
+
+// Trailing update A22 -= L21 U12: rows [r_begin, npad) x cols [c_begin, c_end or npad),
+// K = kd columns of L from column k; grid = (column tiles, row tiles, jobs).
+void launch_gemm_f64(dim3 grid, const JobDesc* jobs, int k, int kd, int r_begin, int c_begin, int c_end,
+                     double2* work, hipStream_t s);
+void launch_gemm_f32(dim3 grid, const JobDesc* jobs, int k, int kd, int r_begin, int c_begin, int c_end,
+                     float2* work, hipStream_t s);
 
 // Blocked LU with partial pivoting of every job's working matrix.
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,

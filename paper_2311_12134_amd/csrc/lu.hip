@@ -10,7 +10,7 @@
 //                     of the panel is updated by the leaf (triangular solve + rank-IB).
 //   swap_trsm_kernel  applies the panel's row interchanges to the trailing columns and
 //                     forms U12 = L11^-1 A12 (one workgroup per 64-column tile).
-//   gemm_*_kernel     trailing update A22 -= L21 U12 on the matrix cores:
+//   gemm_*_kernel     (gemm.hip) trailing update A22 -= L21 U12 on the matrix cores:
 //                     FP64 MFMA 16x16x4 with the four real products of a complex product,
 //                     or (split mode) FP32 MFMA 16x16x4 with three real products
 //                     (Ar Br, Ai Bi, (Ar+Ai)(Br+Bi)).
@@ -27,7 +27,6 @@
 namespace lsms {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------------------------
 // panel factorization
@@ -428,152 +427,6 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
 }
 
 // ------------------------------------------------------------------------------------
-// trailing update A22 -= L21 U12, FP64 MFMA (4 real products per complex product)
-// 64 x 64 complex tile per workgroup, 4 waves of 32 x 32, K = NB in chunks of 16.
-// v_mfma_f64_16x16x4: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);
-// D lane l, register r -> (row l/16 + 4r, col l%16).
-// ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const JobDesc* jobs, int k, int kd, int r_begin, int c_begin,
-                                                   int c_end, double2* work) {
-  const JobDesc jd = jobs[blockIdx.z];
-  const int row0 = r_begin + blockIdx.y * 64, col0 = c_begin + blockIdx.x * 64;
-  if (row0 >= jd.npad || col0 >= jd.npad || (c_end > 0 && col0 >= c_end)) return;  // uniform
-  double2* A = work + jd.a_off;
-  const int64_t ld = jd.npad;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  __shared__ double2 sA[16][64 + 1];
-  __shared__ double2 sB[16][64 + 1];
-  d4 are[2][2], aim[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      are[i][j] = d4{0, 0, 0, 0};
-      aim[i][j] = d4{0, 0, 0, 0};
-    }
-  const int ii = lane & 15, kq = lane >> 4;
-  for (int kc = 0; kc < kd; kc += 16) {
-    {
-      const int i = t >> 2, k4 = (t & 3) * 4;
-      const double2* src = A + (row0 + i) * ld + k + kc + k4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) sA[k4 + u][i] = src[u];
-      const int kk = t >> 4, j4 = (t & 15) * 4;
-      const double2* srb = A + (k + kc + kk) * ld + col0 + j4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) sB[kk][j4 + u] = srb[u];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k4 = 0; k4 < 16; k4 += 4) {
-      double2 a[2], b[2];
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) a[rb] = sA[k4 + kq][wr * 32 + rb * 16 + ii];
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) b[cb] = sB[k4 + kq][wc * 32 + cb * 16 + ii];
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          are[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb].x, b[cb].x, are[rb][cb], 0, 0, 0);
-          are[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[rb].y, b[cb].y, are[rb][cb], 0, 0, 0);
-          aim[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb].x, b[cb].y, aim[rb][cb], 0, 0, 0);
-          aim[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb].y, b[cb].x, aim[rb][cb], 0, 0, 0);
-        }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wr * 32 + rb * 16 + kq + 4 * r;
-        const int col = col0 + wc * 32 + cb * 16 + ii;
-        double2* cp = A + row * ld + col;
-        double2 cv = *cp;
-        cv.x -= are[rb][cb][r];
-        cv.y -= aim[rb][cb][r];
-        *cp = cv;
-      }
-}
-
-// ------------------------------------------------------------------------------------
-// trailing update, split mode: FP32 storage, FP32 MFMA with three real products.
-// v_mfma_f32_16x16x4: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);
-// D lane l, register r -> (row 4(l/16) + r, col l%16).
-// ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, int k, int kd, int r_begin, int c_begin,
-                                                   int c_end, float2* work) {
-  const JobDesc jd = jobs[blockIdx.z];
-  const int row0 = r_begin + blockIdx.y * 64, col0 = c_begin + blockIdx.x * 64;
-  if (row0 >= jd.npad || col0 >= jd.npad || (c_end > 0 && col0 >= c_end)) return;  // uniform
-  float2* A = work + jd.a_off;
-  const int64_t ld = jd.npad;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  __shared__ float2 sA[16][64 + 1];
-  __shared__ float2 sB[16][64 + 1];
-  f4 t1[2][2], t2[2][2], t3[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      t1[i][j] = f4{0, 0, 0, 0};
-      t2[i][j] = f4{0, 0, 0, 0};
-      t3[i][j] = f4{0, 0, 0, 0};
-    }
-  const int ii = lane & 15, kq = lane >> 4;
-  for (int kc = 0; kc < kd; kc += 16) {
-    {
-      const int i = t >> 2, k4 = (t & 3) * 4;
-      const float2* src = A + (row0 + i) * ld + k + kc + k4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) sA[k4 + u][i] = src[u];
-      const int kk = t >> 4, j4 = (t & 15) * 4;
-      const float2* srb = A + (k + kc + kk) * ld + col0 + j4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) sB[kk][j4 + u] = srb[u];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k4 = 0; k4 < 16; k4 += 4) {
-      float2 a[2], b[2];
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) a[rb] = sA[k4 + kq][wr * 32 + rb * 16 + ii];
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) b[cb] = sB[k4 + kq][wc * 32 + cb * 16 + ii];
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          t1[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb].x, b[cb].x, t1[rb][cb], 0, 0, 0);
-          t2[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb].y, b[cb].y, t2[rb][cb], 0, 0, 0);
-          t3[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb].x + a[rb].y, b[cb].x + b[cb].y, t3[rb][cb],
-                                                            0, 0, 0);
-        }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wr * 32 + rb * 16 + 4 * kq + r;
-        const int col = col0 + wc * 32 + cb * 16 + ii;
-        float2* cp = A + row * ld + col;
-        float2 cv = *cp;
-        cv.x -= t1[rb][cb][r] - t2[rb][cb][r];
-        cv.y -= t3[rb][cb][r] - t1[rb][cb][r] - t2[rb][cb][r];
-        *cp = cv;
-      }
-}
-
-// ------------------------------------------------------------------------------------
 // drivers
 // ------------------------------------------------------------------------------------
 template <typename T>
@@ -593,17 +446,23 @@ static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int ro
   }
 }
 
-// Algorithmic flops of one trailing-update launch: 8 m c kd per job (complex), over the
-// unpadded rows m and columns c of the updated block.
-static double update_flops(const GemmProfiler* prof, int njobs, int kd, int r_begin, int c_begin, int c_end) {
-  double f = 0.0;
+// Algorithmic flops and bytes of one trailing-update launch over the unpadded rows m and
+// columns c of each job's updated block: 8 m c kd flops (complex multiply-add count) and
+// es (m kd + kd c + 2 m c) bytes (L21 and U12 read once, A22 read and written once).
+static void update_cost(const GemmProfiler* prof, int njobs, int kd, int r_begin, int c_begin, int c_end, int es,
+                        double* flops, double* bytes) {
+  double f = 0.0, b = 0.0;
   for (int j = 0; j < njobs; ++j) {
     const int n = prof->n_true[j];
     const double m = (double)(n - r_begin);
     const double c = (double)((c_end > 0 ? std::min(c_end, n) : n) - c_begin);
-    if (m > 0 && c > 0) f += 8.0 * m * c * kd;
+    if (m > 0 && c > 0) {
+      f += 8.0 * m * c * kd;
+      b += (double)es * (m * kd + kd * c + 2.0 * m * c);
+    }
   }
-  return f;
+  *flops = f;
+  *bytes = b;
 }
 
 // Blocked right-looking LU with look-ahead over pairs of panels: panels start at every
@@ -624,7 +483,11 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
     dim3 grid(cols / 64, rows / 64, njobs);
     if (prof) prof->before(s);
     gemm(grid, k, kd, r_begin, c_begin, c_end);
-    if (prof) prof->after(s, update_flops(prof, njobs, kd, r_begin, c_begin, c_end));
+    if (prof) {
+      double f, b;
+      update_cost(prof, njobs, kd, r_begin, c_begin, c_end, (int)sizeof(T), &f, &b);
+      prof->after(s, f, b);
+    }
   };
   for (int k = 0; k < npad_max; k += 2 * NB) {
     launch_panel<T>(jobs, njobs, k, 0, npad_max - k, work, piv, info, s);
@@ -644,7 +507,7 @@ void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, 
                    hipStream_t s, GemmProfiler* prof) {
   lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof,
                          [&](dim3 g, int k, int kd, int rb, int cb, int ce) {
-                           gemm_f64_kernel<<<g, 256, 0, s>>>(jobs, k, kd, rb, cb, ce, work);
+                           launch_gemm_f64(g, jobs, k, kd, rb, cb, ce, work, s);
                          });
 }
 
@@ -652,7 +515,7 @@ void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, i
                    hipStream_t s, GemmProfiler* prof) {
   lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof,
                         [&](dim3 g, int k, int kd, int rb, int cb, int ce) {
-                          gemm_f32_3m_kernel<<<g, 256, 0, s>>>(jobs, k, kd, rb, cb, ce, work);
+                          launch_gemm_f32(g, jobs, k, kd, rb, cb, ce, work, s);
                         });
 }
 
