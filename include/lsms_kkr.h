@@ -209,6 +209,18 @@ int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t* n, void* 
  * scalars; the call returns LSMS_E_ARG for a NULL pointer.
  */
 int lsms_set_profiling(lsms_ctx* ctx, int on);
+
+/*
+ * Tuning of the split-mode trailing update (the FP32 matrix-core part of the LU of Eq. (3)).
+ * knob LSMS_TUNE_GEMM_F32 selects the tiling, 0 .. LSMS_GEMM_F32_VARIANTS - 1, or -1 for
+ * the library's default; every tiling computes the same update (results may differ in
+ * FP32 rounding order only).  Host-side setting of the context, no device work; returns
+ * LSMS_E_ARG for an unknown knob or value.  lsms_get_tuning reports the tiling in effect.
+ */
+#define LSMS_TUNE_GEMM_F32 0
+#define LSMS_GEMM_F32_VARIANTS 7
+int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
+int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
 int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launches, double* alg_flops,
                       double* alg_bytes);
 

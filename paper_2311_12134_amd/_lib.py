@@ -46,6 +46,8 @@ _PROTOS = {
                                       c_void_p]),
     "lsms_gaunt_table": (c_int, [c_void_p]),
     "lsms_set_profiling": (c_int, [c_void_p, c_int]),
+    "lsms_set_tuning": (c_int, [c_void_p, c_int, c_int]),
+    "lsms_get_tuning": (c_int, [c_void_p, c_int, P(c_int)]),
     "lsms_kernel_stats": (c_int, [c_void_p, P(c_double), P(c_int64), P(c_double), P(c_double)]),
 }
 

@@ -169,6 +169,15 @@ class Context:
     def set_profiling(self, on=True):
         check(lib().lsms_set_profiling(self._h, 1 if on else 0))
 
+    def set_gemm_tiling(self, variant):
+        """Tiling of the split-mode trailing update (-1: library default)."""
+        check(lib().lsms_set_tuning(self._h, 0, int(variant)))
+
+    def gemm_tiling(self):
+        v = ctypes.c_int(0)
+        check(lib().lsms_get_tuning(self._h, 0, ctypes.byref(v)))
+        return v.value
+
     def kernel_stats(self):
         """(total ms, launches, algorithmic flops, algorithmic bytes) of the recorded
         trailing-update launches."""

@@ -157,14 +157,196 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, i
       }
 }
 
-void launch_gemm_f64(dim3 grid, const JobDesc* jobs, int k, int kd, int r_begin, int c_begin, int c_end,
-                     double2* work, hipStream_t s) {
+// ------------------------------------------------------------------------------------
+// split-mode trailing update, tiled family.  TM x TN complex tile per workgroup of four
+// waves, each wave a WM x WN sub-tile of (WM/16) x (WN/16) blocks on FP32 MFMA 16x16x4 with
+// the three real products.  K is staged through LDS in chunks of 16 with two buffers: the
+// global loads of chunk i+1 are issued before the MFMAs of chunk i and written to the other
+// buffer after them, so one barrier per chunk suffices and the load latency overlaps the
+// matrix-core work.  Tiles may reach past npad by 64 rows or columns (npad is a multiple of
+// 64): those rows and columns load as zero (their MFMAs run on zeros, so the accumulators
+// never pass through a branch) and nothing is stored there.  The grid is one-dimensional over (job, tile row, tile column); with
+// XCD = true the workgroup index is remapped so that consecutive tiles of one job, which
+// share L21 and U12 panels, run on the same XCD (workgroups are dealt to the eight XCDs
+// round-robin) and hit the same L2.
+// ------------------------------------------------------------------------------------
+template <int TM, int TN, int WM, int WN, bool XCD>
+__global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, int tiles_x, int tiles_y, int k, int kd,
+                                                         int r_begin, int c_begin, int c_end, float2* work) {
+  constexpr int KC = 16;
+  constexpr int WAVES_N = TN / WN;
+  static_assert((TM / WM) * (TN / WN) == 4, "four waves per workgroup");
+  constexpr int BM = WM / 16, BN = WN / 16;
+  constexpr int AP = TM / 64;  // A passes: 64 rows x 16 k per pass, 4 complex per thread
+  constexpr int BP = TN / 64;  // B passes: 16 k x 64 columns per pass
+  constexpr int LA = TM + 16, LB = TN + 16;  // LDS row lengths (k-step offset of 32 banks)
+
+  int T = blockIdx.x;
+  if (XCD) {
+    const int N = gridDim.x, q = N >> 3, r = N & 7, x = T & 7;
+    T = x * q + min(x, r) + (T >> 3);
+  }
+  const int tx = T % tiles_x;
+  T /= tiles_x;
+  const int ty = T % tiles_y;
+  const JobDesc jd = jobs[T / tiles_y];
+  const int row0 = r_begin + ty * TM, col0 = c_begin + tx * TN;
+  const int npad = jd.npad;
+  const int cmax = c_end > 0 ? min(c_end, npad) : npad;
+  if (row0 >= npad || col0 >= cmax) return;  // uniform
+  float2* A = work + jd.a_off;
+  const int64_t ld = npad;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+  const bool active = (row0 + wm * WM < npad) && (col0 + wn * WN < cmax);
+
+  __shared__ float2 sA[2][KC][LA];
+  __shared__ float2 sB[2][KC][LB];
+
+  // global -> register staging of one chunk
+  const int ai = t >> 2, ak = (t & 3) * 4;  // A: row ai of each pass, k quad ak
+  float2 ra[AP][4], rb[BP][4];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int p = 0; p < AP; ++p) {
+      const int row = row0 + p * 64 + ai;
+      if (row0 + p * 64 < npad) {
+        const float4* src = (const float4*)(A + (int64_t)row * ld + k + kc + ak);
+        const float4 v0 = src[0], v1 = src[1];
+        ra[p][0] = make_float2(v0.x, v0.y);
+        ra[p][1] = make_float2(v0.z, v0.w);
+        ra[p][2] = make_float2(v1.x, v1.y);
+        ra[p][3] = make_float2(v1.z, v1.w);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ra[p][u] = make_float2(0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < BP; ++p) {
+      const int kk = t >> 4, j = p * 64 + (t & 15) * 4;
+      if (col0 + p * 64 < cmax) {
+        const float4* src = (const float4*)(A + (int64_t)(k + kc + kk) * ld + col0 + j);
+        const float4 v0 = src[0], v1 = src[1];
+        rb[p][0] = make_float2(v0.x, v0.y);
+        rb[p][1] = make_float2(v0.z, v0.w);
+        rb[p][2] = make_float2(v1.x, v1.y);
+        rb[p][3] = make_float2(v1.z, v1.w);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rb[p][u] = make_float2(0.f, 0.f);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < AP; ++p)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sA[buf][ak + u][p * 64 + ai] = ra[p][u];
+#pragma unroll
+    for (int p = 0; p < BP; ++p) {
+      const int kk = t >> 4, j = p * 64 + (t & 15) * 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sB[buf][kk][j + u] = rb[p][u];
+    }
+  };
+
+  f4 t1[BM][BN], t2[BM][BN], t3[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      t1[i][j] = f4{0, 0, 0, 0};
+      t2[i][j] = f4{0, 0, 0, 0};
+      t3[i][j] = f4{0, 0, 0, 0};
+    }
+  const int ii = lane & 15, kq = lane >> 4;
+
+  load(0);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  for (int kc = 0; kc < kd; kc += KC) {
+    const bool more = kc + KC < kd;
+    if (more) load(kc + KC);
+#pragma unroll
+    for (int k4 = 0; k4 < KC; k4 += 4) {
+      float2 a[BM], b[BN];
+      float as[BM], bs[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) {
+        a[i] = sA[cur][k4 + kq][wm * WM + i * 16 + ii];
+        as[i] = a[i].x + a[i].y;
+      }
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        b[j] = sB[cur][k4 + kq][wn * WN + j * 16 + ii];
+        bs[j] = b[j].x + b[j].y;
+      }
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          t1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].x, t1[i][j], 0, 0, 0);
+          t2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b[j].y, t2[i][j], 0, 0, 0);
+          t3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[i], bs[j], t3[i][j], 0, 0, 0);
+        }
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  if (!active) return;
+  // D lane l, register r -> (row 4(l/16) + r, col l%16) of each 16 x 16 block
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      const int rbase = row0 + wm * WM + i * 16, cbase = col0 + wn * WN + j * 16;
+      if (rbase < npad && cbase < cmax) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float2* cp = A + (int64_t)(rbase + 4 * kq + r) * ld + cbase + ii;
+          float2 cv = *cp;
+          cv.x -= t1[i][j][r] - t2[i][j][r];
+          cv.y -= t3[i][j][r] - t1[i][j][r] - t2[i][j][r];
+          *cp = cv;
+        }
+      }
+    }
+}
+
+void launch_gemm_f64(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin, int c_begin,
+                     int c_end, double2* work, hipStream_t s) {
+  dim3 grid(cols / 64, rows / 64, njobs);
   gemm_f64_kernel<<<grid, 256, 0, s>>>(jobs, k, kd, r_begin, c_begin, c_end, work);
 }
 
-void launch_gemm_f32(dim3 grid, const JobDesc* jobs, int k, int kd, int r_begin, int c_begin, int c_end,
-                     float2* work, hipStream_t s) {
-  gemm_f32_3m_kernel<<<grid, 256, 0, s>>>(jobs, k, kd, r_begin, c_begin, c_end, work);
+template <int TM, int TN, int WM, int WN, bool XCD>
+static void launch_tiled(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
+                         int c_begin, int c_end, float2* work, hipStream_t s) {
+  const int tx = (cols + TN - 1) / TN, ty = (rows + TM - 1) / TM;
+  const int64_t n = (int64_t)tx * ty * njobs;
+  gemm_f32_3m_tiled<TM, TN, WM, WN, XCD><<<(unsigned)n, 256, 0, s>>>(jobs, tx, ty, k, kd, r_begin, c_begin, c_end,
+                                                                     work);
+}
+
+int gemm_f32_variants() { return 7; }
+
+void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
+                     int c_begin, int c_end, float2* work, hipStream_t s) {
+  switch (variant) {
+    case 1: launch_tiled<64, 64, 32, 32, false>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
+    case 2: launch_tiled<64, 64, 32, 32, true>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
+    case 3: launch_tiled<128, 64, 32, 64, true>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
+    case 4: launch_tiled<64, 128, 64, 32, true>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
+    case 5: launch_tiled<128, 128, 64, 64, true>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
+    case 6: launch_tiled<128, 128, 64, 64, false>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
+    default: {
+      dim3 grid(cols / 64, rows / 64, njobs);
+      gemm_f32_3m_kernel<<<grid, 256, 0, s>>>(jobs, k, kd, r_begin, c_begin, c_end, work);
+    }
+  }
 }
 
 }  // namespace lsms

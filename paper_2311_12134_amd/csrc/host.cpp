@@ -88,6 +88,7 @@ struct EventProf : GemmProfiler {
 struct lsms_ctx {
   int device = 0;
   bool profiling = false;
+  int gemm_f32 = -1;  // tiling of the split-mode trailing update, -1: library default
   EventProf prof;
   std::vector<int> n_true;
   size_t workspace_limit = 0;
@@ -99,6 +100,9 @@ struct lsms_ctx {
   int32_t* pinned_flag = nullptr;  // host-visible counter read back between refinement sweeps
   DevBuf fallback;                 // job list of the FP64 fallback
 };
+
+// Tiling of the split-mode trailing update in effect for a context.
+static int gemm_f32_variant(const lsms_ctx* ctx) { return ctx->gemm_f32 >= 0 ? ctx->gemm_f32 : 2; }
 
 struct lsms_factors {
   lsms_ctx* ctx = nullptr;
@@ -627,7 +631,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
       launch_write_status(jd, nj, jinfo, nullptr, info, berr, s);
     } else {
       launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, m64, s);
-      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, s, prof);
+      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, s, prof, gemm_f32_variant(ctx));
       lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
       launch_zero_i32(jdone, nj, s);
       launch_zero(jnorm, 8 * (int64_t)nj, s);
@@ -720,6 +724,22 @@ extern "C" int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* li
                     n_species, (const double2*)J, pa, s);
   launch_kubo_reduce(n_atoms, pa, volume, sigma, (double2*)sigma_tilde, s);
   HIP_TRY(hipGetLastError());
+  return LSMS_OK;
+}
+
+extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
+  if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);
+  if (value < -1 || value >= gemm_f32_variants())
+    return fail(LSMS_E_ARG, "gemm_f32 tiling %d outside [-1, %d)", value, gemm_f32_variants());
+  ctx->gemm_f32 = value;
+  return LSMS_OK;
+}
+
+extern "C" int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value) {
+  if (!ctx || !value) return fail(LSMS_E_ARG, "NULL argument");
+  if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);
+  *value = gemm_f32_variant(ctx);
   return LSMS_OK;
 }
 
@@ -858,7 +878,7 @@ extern "C" int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t
     lu_factor_f64(jd, batch, npad_max, (double2*)abuf, piv, info, s);
     lu_solve_f64(jd, batch, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
   } else {
-    lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s);
+    lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s, nullptr, gemm_f32_variant(ctx));
     lu_solve_f32(jd, batch, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
   }
   launch_store_user(jd, batch, npad_max, bptr, nrhs, xbuf, s);

@@ -118,17 +118,19 @@ struct GemmProfiler {
 };
 
 // Trailing update A22 -= L21 U12: rows [r_begin, npad) x cols [c_begin, c_end or npad),
-// K = kd columns of L from column k; grid = (column tiles, row tiles, jobs).
-void launch_gemm_f64(dim3 grid, const JobDesc* jobs, int k, int kd, int r_begin, int c_begin, int c_end,
-                     double2* work, hipStream_t s);
-void launch_gemm_f32(dim3 grid, const JobDesc* jobs, int k, int kd, int r_begin, int c_begin, int c_end,
-                     float2* work, hipStream_t s);
+// K = kd columns of L from column k; rows x cols is the extent over the largest job.
+// The FP32 update comes in several tilings (variant 0 .. gemm_f32_variants() - 1).
+void launch_gemm_f64(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin, int c_begin,
+                     int c_end, double2* work, hipStream_t s);
+int gemm_f32_variants();
+void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
+                     int c_begin, int c_end, float2* work, hipStream_t s);
 
 // Blocked LU with partial pivoting of every job's working matrix.
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
                    hipStream_t s, GemmProfiler* prof = nullptr);
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof = nullptr);
+                   hipStream_t s, GemmProfiler* prof = nullptr, int gemm_variant = 0);
 // Solve with the factors: trans = 0 solves M X = B, trans = 1 solves M^T X = B (in place on X).
 void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
                   double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);

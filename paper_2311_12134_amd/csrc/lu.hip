@@ -255,15 +255,26 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
             (void)r;
           }
           __syncthreads();
-          for (int idx = t; idx < PT * w; idx += PT) {
-            const int rr = idx / w, cc = idx - rr * w;
-            const int row = r0 + rr;
-            if (row >= cl + IB && row < nrows) {
-              const int col = cl + IB + cc;
-              double2 acc = ld2(A + row * ld + col);
+          // UB elements per thread and round: all loads are issued before the first store,
+          // so their latencies overlap instead of forming one load-store chain
+          constexpr int UB = 4;
+          const int total = PT * w;
+          for (int base = t; base < total; base += PT * UB) {
+            T held[UB];
 #pragma unroll
-              for (int q = 0; q < IB; ++q) acc = cfms(acc, s_Lc[rr][q], s_U[q][cc]);
-              st2(A + row * ld + col, acc);
+            for (int u = 0; u < UB; ++u) {
+              const int idx = base + u * PT, rr = idx / w, row = r0 + rr;
+              if (idx < total && row >= cl + IB && row < nrows) held[u] = A[row * ld + cl + IB + idx - rr * w];
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+              const int idx = base + u * PT, rr = idx / w, cc = idx - rr * w, row = r0 + rr;
+              if (idx < total && row >= cl + IB && row < nrows) {
+                double2 acc = ld2(&held[u]);
+#pragma unroll
+                for (int q = 0; q < IB; ++q) acc = cfms(acc, s_Lc[rr][q], s_U[q][cc]);
+                st2(A + row * ld + cl + IB + cc, acc);
+              }
             }
           }
           __syncthreads();
@@ -480,9 +491,8 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
     const int rows = npad_max - r_begin;
     const int cols = (c_end > 0 ? std::min(c_end, npad_max) : npad_max) - c_begin;
     if (rows <= 0 || cols <= 0) return;
-    dim3 grid(cols / 64, rows / 64, njobs);
     if (prof) prof->before(s);
-    gemm(grid, k, kd, r_begin, c_begin, c_end);
+    gemm(rows, cols, k, kd, r_begin, c_begin, c_end);
     if (prof) {
       double f, b;
       update_cost(prof, njobs, kd, r_begin, c_begin, c_end, (int)sizeof(T), &f, &b);
@@ -506,16 +516,17 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
                    hipStream_t s, GemmProfiler* prof) {
   lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof,
-                         [&](dim3 g, int k, int kd, int rb, int cb, int ce) {
-                           launch_gemm_f64(g, jobs, k, kd, rb, cb, ce, work, s);
+                         [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
+                           launch_gemm_f64(jobs, njobs, rows, cols, k, kd, rb, cb, ce, work, s);
                          });
 }
 
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof) {
+                   hipStream_t s, GemmProfiler* prof, int gemm_variant) {
   lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof,
-                        [&](dim3 g, int k, int kd, int rb, int cb, int ce) {
-                          launch_gemm_f32(g, jobs, k, kd, rb, cb, ce, work, s);
+                        [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
+                          // the narrow update of a pair's second panel (64 columns) keeps the 64 x 64 tiling
+                          launch_gemm_f32(ce > 0 ? 0 : gemm_variant, jobs, njobs, rows, cols, k, kd, rb, cb, ce, work, s);
                         });
 }
 

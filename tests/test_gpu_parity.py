@@ -172,6 +172,35 @@ def test_batched_lu_solve_random_and_singular(lctx):
     assert info[-1] > 0
 
 
+@pytest.mark.parametrize("tiling", list(range(7)))
+def test_split_lu_every_gemm_tiling(lctx, tiling):
+    """FP32 factors without refinement, uneven batch whose trailing blocks end on 64-row and
+    64-column halves of the 128-wide tiles: every tiling of the split-mode update must give
+    a solve accurate to FP32 rounding (refinement would otherwise hide a wrong update)."""
+    rng = np.random.default_rng(11)
+    dev = torch.device("cuda", 0)
+    sizes = [1000, 700, 450, 129, 1]
+    mats, rhs, refs = [], [], []
+    for n in sizes:
+        A = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) / np.sqrt(n) + 2 * np.eye(n)
+        B = rng.normal(size=(n, 3)) + 1j * rng.normal(size=(n, 3))
+        refs.append(np.linalg.solve(A, B))
+        mats.append(torch.from_numpy(A).to(dev))
+        rhs.append(torch.from_numpy(B).to(dev))
+    lctx.set_gemm_tiling(tiling)
+    try:
+        assert lctx.gemm_tiling() == tiling
+        info = lctx.batched_lu_solve(mats, rhs, precision="split").cpu().numpy()
+    finally:
+        lctx.set_gemm_tiling(-1)
+    torch.cuda.synchronize()
+    for k, ref in enumerate(refs):
+        got = rhs[k].cpu().numpy()
+        assert info[k] == 0
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert err <= 2e-5, (tiling, sizes[k], err)
+
+
 def _grad_setup(w):
     import paper_2311_12134_amd as P
     dev = torch.device("cuda", 0)
