@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include "lsms_internal.h"
+#include "strip_mma.h"
 #include "tri.h"
 
 namespace lsms {
@@ -330,11 +331,48 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
 }
 
 // ------------------------------------------------------------------------------------
+// inverse of the panel's unit lower triangle, in place
+// ------------------------------------------------------------------------------------
+// After panel(k) the strictly lower part of the diagonal block holds L11.  One workgroup
+// per job solves L11 X = I (each wavefront 16 columns, FP64 shuffle substitution, tri.h)
+// and overwrites that part with X = L11^-1 (unit diagonal implied).  Every later use of
+// the block wants the inverse: U12 = L11^-1 A12 in swap_trsm_kernel and the diagonal
+// steps of the solves, which thereby become products on the matrix cores.  No later
+// interchange touches the block (pivots of later panels lie below it).
+template <typename T>
+__global__ __launch_bounds__(256) void linv_kernel(const JobDesc* jobs, int k, T* work) {
+  const JobDesc jd = jobs[blockIdx.x];
+  if (k >= jd.npad) return;  // uniform
+  T* A = work + jd.a_off;
+  const int64_t ld = jd.npad;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  typedef typename LdsOf<T>::type S;
+  __shared__ S s_T[NB][NB + 1];
+  __shared__ S s_X[NB][NB + 1];
+  for (int idx = t; idx < NB * NB; idx += 256) {
+    const int q = idx / NB, pp = idx % NB;
+    st2(&s_T[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0));
+    st2(&s_X[q][pp], make_double2(q == pp ? 1.0 : 0.0, 0.0));
+  }
+  __syncthreads();
+  tri_unit_lower<16>(&s_T[0][0], NB + 1, &s_X[0][0], NB + 1, wave * 16, lane);
+  __syncthreads();
+  for (int idx = t; idx < NB * NB; idx += 256) {
+    const int q = idx / NB, pp = idx % NB;
+    if (pp < q) st2(A + (k + q) * ld + k + pp, ld2(&s_X[q][pp]));
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // interchanges + U12 = L11^-1 A12 on one 64-column tile of the trailing matrix
 // ------------------------------------------------------------------------------------
+// The tile's panel rows are gathered through LDS with the panel's permutation (the other
+// permuted rows are written back directly), then U12 = L11^-1 A12 is one 64 x 64 x 64
+// product on the matrix cores with the inverse stored by linv_kernel (FP32 three-product
+// MFMA for FP32 storage, FP64 MFMA otherwise).
 // SECOND: k is the second panel of a pair whose first panel starts at k - NB.  Its
 // trailing columns have not yet received the first panel's update, so after the gather
-// the panel rows get  A12 -= L[k.., k-NB..k) U12_first  (FP64 MFMA) before the solve.
+// the panel rows get  A12 -= L[k.., k-NB..k) U12_first  (same product) before U12.
 template <typename T, bool SECOND>
 __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int k, T* work, const int32_t* piv) {
   const JobDesc jd = jobs[blockIdx.y];
@@ -344,8 +382,8 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   const int64_t ld = jd.npad;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   typedef typename LdsOf<T>::type S;
-  __shared__ S s_L[NB][NB + 1];
-  __shared__ S s_X[NB][64 + 1];
+  __shared__ S s_L[NB][NB + 4];
+  __shared__ S s_X[NB][64 + 4];
   __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
   const int32_t* lst = piv + jd.piv_off + perm_off(jd.npad, k);
   const int cnt = lst[0];
@@ -353,16 +391,20 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
     s_dst[i] = lst[2 + i];
     s_src[i] = lst[2 + PERM_MAX + i];
   }
+  // the inverse of the panel's unit lower triangle, unit diagonal made explicit
+  auto load_linv = [&]() {
+    for (int idx = t; idx < NB * NB; idx += 256) {
+      const int q = idx / NB, pp = idx % NB;
+      st2(&s_L[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(pp == q ? 1.0 : 0.0, 0.0));
+    }
+  };
   if (SECOND) {  // the first panel's L rows that face this panel
     for (int idx = t; idx < NB * NB; idx += 256) {
       const int q = idx / NB, pp = idx % NB;
       s_L[q][pp] = A[(k + q) * ld + (k - NB) + pp];
     }
   } else {
-    for (int idx = t; idx < NB * NB; idx += 256) {
-      const int q = idx / NB, pp = idx % NB;
-      st2(&s_L[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0));
-    }
+    load_linv();
   }
   __syncthreads();
   // the panel's permutation as a gather on this tile: entry i = wave + 4 s, column = lane
@@ -388,53 +430,34 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
       if (dst >= k + NB) A[dst * ld + col0 + lane] = held[u];
     }
   }
+  const int ii = lane & 15;
   if (SECOND) {
     __syncthreads();  // the gathered panel rows are complete in s_X
-    // s_X -= L[k.., k-NB..k) (in s_L) * U[k-NB.., col0..] : wave w owns rows 16w..16w+16
-    typedef double d4_ __attribute__((ext_vector_type(4)));
-    d4_ are[4], aim[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      are[cb] = d4_{0, 0, 0, 0};
-      aim[cb] = d4_{0, 0, 0, 0};
-    }
-    const int ii = lane & 15, kq = lane >> 4;
-    for (int k4 = 0; k4 < NB; k4 += 4) {
-      const double2 a = ld2(&s_L[wave * 16 + ii][k4 + kq]);
-      const T* urow = A + (int64_t)(k - NB + k4 + kq) * ld + col0;
-#pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        const double2 b = ld2(urow + cb * 16 + ii);
-        are[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, are[cb], 0, 0, 0);
-        are[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, are[cb], 0, 0, 0);
-        aim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, aim[cb], 0, 0, 0);
-        aim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, aim[cb], 0, 0, 0);
-      }
-    }
+    // s_X -= L[k.., k-NB..k) (in s_L) U[k-NB.., col0..]: wave w owns rows 16w .. 16w+16
+    StripMma<T, 4> d;
+    d.zero();
+    d.run([&](int i, int kk) { return s_L[wave * 16 + i][kk]; },
+          [&](int kk, int c) { return A[(int64_t)(k - NB + kk) * ld + col0 + c]; }, lane);
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        S* xp = &s_X[wave * 16 + kq + 4 * r][cb * 16 + ii];
-        double2 xv = ld2(xp);
-        xv.x -= are[cb][r];
-        xv.y -= aim[cb][r];
-        st2(xp, xv);
+        S* xp = &s_X[wave * 16 + d.row(r, lane)][cb * 16 + ii];
+        st2(xp, csub(ld2(xp), d.value(cb, r)));
       }
     __syncthreads();
-    for (int idx = t; idx < NB * NB; idx += 256) {  // now the panel's own unit lower triangle
-      const int q = idx / NB, pp = idx % NB;
-      st2(&s_L[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0));
-    }
-    __syncthreads();
+    load_linv();
   }
-  // U12 = L11^-1 A12: each wavefront solves 16 of the tile's columns
-  tri_unit_lower<16>(&s_L[0][0], NB + 1, &s_X[0][0], 64 + 1, wave * 16, lane);
   __syncthreads();
-  for (int idx = t; idx < NB * 64; idx += 256) {
-    const int q = idx >> 6, cc = idx & 63;
-    A[(k + q) * ld + col0 + cc] = s_X[q][cc];
-  }
+  // U12 = L11^-1 A12 straight from the accumulators to the panel rows
+  StripMma<T, 4> u;
+  u.zero();
+  u.run([&](int i, int kk) { return s_L[wave * 16 + i][kk]; }, [&](int kk, int c) { return s_X[kk][c]; }, lane);
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      st2(A + (int64_t)(k + wave * 16 + u.row(r, lane)) * ld + col0 + cb * 16 + ii, u.value(cb, r));
 }
 
 // ------------------------------------------------------------------------------------
@@ -501,11 +524,13 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
   };
   for (int k = 0; k < npad_max; k += 2 * NB) {
     launch_panel<T>(jobs, njobs, k, 0, npad_max - k, work, piv, info, s);
+    linv_kernel<T><<<njobs, 256, 0, s>>>(jobs, k, work);
     const int rest = npad_max - k - NB;
     if (rest <= 0) break;
     swap_trsm_kernel<T, false><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, piv);
     timed_gemm(k, NB, k + NB, k + NB, k + 2 * NB);  // the second panel's columns
     launch_panel<T>(jobs, njobs, k + NB, NB, npad_max - k - NB, work, piv, info, s);
+    linv_kernel<T><<<njobs, 256, 0, s>>>(jobs, k + NB, work);
     const int rest2 = npad_max - k - 2 * NB;
     if (rest2 <= 0) break;
     swap_trsm_kernel<T, true><<<dim3(rest2 / 64, njobs), 256, 0, s>>>(jobs, k + NB, work, piv);

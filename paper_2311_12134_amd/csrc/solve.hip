@@ -3,13 +3,15 @@
 //
 // The factorization is the product M = P_1^T L_1 P_2^T L_2 ... P_K^T L_K U of panel
 // permutations P_p and unit-lower panel factors L_p (stored in the panel's columns,
-// never re-permuted by later panels).  Hence
+// never re-permuted by later panels; the diagonal block of each L_p holds its inverse,
+// written by the factorization).  Hence
 //   M X = B   :  X = U^-1 L_K^-1 P_K ... L_1^-1 P_1 B          (trans = 0)
 //   M^T X = B :  X = P_1^T L_1^-T ... P_K^T L_K^-T U^-T B      (trans = 1)
 // Every panel costs two launches over the whole batch:
 //   solve_diag_kernel    one workgroup per job: the panel's permutation as one gather of
-//                        at most 2 NB rows, and the NB x NB triangle solved by one
-//                        wavefront with cross-lane shuffles (tri.h);
+//                        at most 2 NB rows, then the NB x NB diagonal block: a product
+//                        with the stored inverse (L and L^T, FP64 MFMA) or the triangle
+//                        U solved by one wavefront with cross-lane shuffles (tri.h);
 //   solve_update_kernel  one workgroup per (64-row strip, job): the off-diagonal block
 //                        times the panel's NB solved rows, on FP64 MFMA 16x16x4 (four real
 //                        products per complex product) from LDS-staged tiles, so the
@@ -19,6 +21,7 @@
 // partial product to the panel rows with FP64 atomics.  Arithmetic is FP64 for both
 // storage types of the factors.
 #include "lsms_internal.h"
+#include "strip_mma.h"
 #include "tri.h"
 
 namespace lsms {
@@ -26,6 +29,34 @@ namespace lsms {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 enum { MODE_L = 0, MODE_U = 1, MODE_UT = 2, MODE_LT = 3 };
+
+// One panel permutation of the solution rows (at most PERM_MAX (dst, src) pairs): every
+// source row is read into registers before any destination row is written.
+template <int NRHS>
+__device__ inline void apply_perm(const int32_t* lst, bool inverse, double2* X, int* s_dst, int* s_src, int t) {
+  constexpr int HELD = PERM_MAX * NRHS / 256;
+  const int cnt = lst[0];
+  for (int i = t; i < cnt; i += 256) {
+    s_dst[i] = lst[2 + i];
+    s_src[i] = lst[2 + PERM_MAX + i];
+  }
+  __syncthreads();
+  const int* from = inverse ? s_dst : s_src;
+  const int* to = inverse ? s_src : s_dst;
+  double2 held[HELD];
+#pragma unroll
+  for (int u = 0; u < HELD; ++u) {
+    const int idx = t + 256 * u, i = idx / NRHS, c = idx % NRHS;
+    held[u] = i < cnt ? X[(int64_t)from[i] * NRHS_MAX + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < HELD; ++u) {
+    const int idx = t + 256 * u, i = idx / NRHS, c = idx % NRHS;
+    if (i < cnt) X[(int64_t)to[i] * NRHS_MAX + c] = held[u];
+  }
+  __syncthreads();
+}
 
 template <typename T, int NRHS, int MODE>
 __global__ __launch_bounds__(256) void solve_diag_kernel(const JobDesc* jobs, int k, const T* work,
@@ -47,26 +78,7 @@ __global__ __launch_bounds__(256) void solve_diag_kernel(const JobDesc* jobs, in
   __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
   auto xrow = [&](int r) { return X + (int64_t)r * NRHS_MAX; };
   auto permute = [&](int kp, bool inverse) {
-    const int32_t* lst = pv + perm_off(jd.npad, kp);
-    const int cnt = lst[0];
-    for (int i = t; i < cnt; i += 256) {
-      s_dst[i] = lst[2 + i];
-      s_src[i] = lst[2 + PERM_MAX + i];
-    }
-    __syncthreads();
-    double2 held[HELD];
-#pragma unroll
-    for (int u = 0; u < HELD; ++u) {
-      const int idx = t + 256 * u, i = idx / NRHS, c = idx % NRHS;
-      if (i < cnt) held[u] = xrow(inverse ? s_dst[i] : s_src[i])[c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < HELD; ++u) {
-      const int idx = t + 256 * u, i = idx / NRHS, c = idx % NRHS;
-      if (i < cnt) xrow(inverse ? s_src[i] : s_dst[i])[c] = held[u];
-    }
-    __syncthreads();
+    apply_perm<NRHS>(pv + perm_off(jd.npad, kp), inverse, X, s_dst, s_src, t);
   };
   // Panels come in pairs (first at multiples of 2 NB, see lu_factor): the first panel's
   // L rows are stored after the second panel's permutation, so the forward solve applies
@@ -78,19 +90,32 @@ __global__ __launch_bounds__(256) void solve_diag_kernel(const JobDesc* jobs, in
   const bool upper = (MODE == MODE_U || MODE == MODE_UT);
   for (int idx = t; idx < NB * NB; idx += 256) {
     const int q = idx / NB, pp = idx % NB;
-    const bool keep = upper ? (pp >= q) : (pp < q);
-    s_T[q][pp] = keep ? A[(k + q) * ld + k + pp] : S{0, 0};
+    if (upper)
+      s_T[q][pp] = pp >= q ? A[(k + q) * ld + k + pp] : S{0, 0};
+    else  // the stored inverse of the unit lower triangle, unit diagonal made explicit
+      st2(&s_T[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(pp == q ? 1.0 : 0.0, 0.0));
   }
   for (int idx = t; idx < NB * NRHS; idx += 256) s_X[idx / NRHS][idx % NRHS] = xrow(k + idx / NRHS)[idx % NRHS];
   __syncthreads();
-  if (wave == 0) {
-    if (MODE == MODE_L) tri_unit_lower<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
-    if (MODE == MODE_U) tri_upper<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
-    if (MODE == MODE_UT) tri_upper_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
-    if (MODE == MODE_LT) tri_unit_lower_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
+  if (upper) {
+    if (wave == 0) {
+      if (MODE == MODE_U) tri_upper<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
+      if (MODE == MODE_UT) tri_upper_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
+    }
+    __syncthreads();
+    for (int idx = t; idx < NB * NRHS; idx += 256) xrow(k + idx / NRHS)[idx % NRHS] = s_X[idx / NRHS][idx % NRHS];
+  } else {
+    // X_P = L11^-1 X_P (MODE_L) or L11^-T X_P (MODE_LT); wave w writes rows 16w .. 16w+16
+    StripMma<double2, NRHS / 16> y;
+    y.zero();
+    y.run([&](int i, int kk) { return MODE == MODE_L ? ld2(&s_T[wave * 16 + i][kk]) : ld2(&s_T[kk][wave * 16 + i]); },
+          [&](int kk, int c) { return s_X[kk][c]; }, lane);
+    const int ii = lane & 15;
+#pragma unroll
+    for (int cb = 0; cb < NRHS / 16; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xrow(k + wave * 16 + y.row(r, lane))[cb * 16 + ii] = y.value(cb, r);
   }
-  __syncthreads();
-  for (int idx = t; idx < NB * NRHS; idx += 256) xrow(k + idx / NRHS)[idx % NRHS] = s_X[idx / NRHS][idx % NRHS];
   if (MODE == MODE_L && has_second) {
     __syncthreads();
     permute(k + NB, false);
