@@ -32,6 +32,21 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // ------------------------------------------------------------------------------------
 // panel factorization
 // ------------------------------------------------------------------------------------
+// Pivot keys: a non-negative double orders like its bit pattern, so the magnitude with
+// its 13 lowest mantissa bits replaced by (8191 - local row) is one 64-bit integer whose
+// maximum is the largest magnitude, the lowest row on ties (relative resolution 2^-39).
+// NaN magnitudes get key 0 and never win; key 0 overall means "keep the diagonal row".
+__device__ inline unsigned long long pivot_key(double mag, int row_local) {
+  if (!(mag == mag)) return 0ull;
+  return ((unsigned long long)__double_as_longlong(mag) & ~0x1FFFull) | (unsigned long long)(0x1FFF - row_local);
+}
+__device__ inline int pivot_row(unsigned long long key) { return 0x1FFF - (int)(key & 0x1FFFull); }
+
+__device__ inline double2 wide(double2 a) { return a; }
+__device__ inline double2 wide(float2 a) { return make_double2((double)a.x, (double)a.y); }
+__device__ inline void narrow_to(double2& d, double2 a) { d = a; }
+__device__ inline void narrow_to(float2& d, double2 a) { d = make_float2((float)a.x, (float)a.y); }
+
 template <typename T, int PT, int S, int IB>
 __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, int left, T* work, int32_t* piv,
                                                    int32_t* info) {
@@ -44,20 +59,31 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   constexpr int NW = PT / 64;
 
-  __shared__ double2 s_prow[IB], s_drow[IB];
-  __shared__ double s_rv[NW];
-  __shared__ int s_rr[NW];
+  // Per pivot column one barrier: before it every wave posts its best key (LDS atomic
+  // max into one of three rotating slots) and its candidate row, and the owner of the
+  // diagonal row posts that row (two rotating buffers); after it every thread knows the
+  // pivot row and both rows to exchange.  Column j clears slot (j + 1) % 3: its last
+  // readers (column j - 2) passed barrier j - 1 before anyone reaches column j, and its
+  // next writers (column j + 1) start after barrier j.  A row buffer written before
+  // barrier j is rewritten only before barrier j + 2, after every read of column j.
+  __shared__ unsigned long long s_key[3];
+  __shared__ double2 s_cand[2][NW][IB];
+  __shared__ double2 s_drow[2][IB];
   __shared__ int s_piv[IB];
   __shared__ double2 s_L11[IB][IB];
   __shared__ double2 s_U[IB][NB];
-  __shared__ double2 s_Lc[PT][IB];
   __shared__ int s_pivall[NB];
   __shared__ int s_pos[PERM_MAX], s_org[PERM_MAX];
   __shared__ int s_lpos[2 * IB], s_lorg[2 * IB], s_lcnt;
   __shared__ T s_held[2 * IB][2 * NB - IB];
+  __shared__ T s_Lc[PT][IB];
 
-  double2 v[S][IB];
+  // the leaf in registers in the storage precision; arithmetic is FP64
+  T v[S][IB];
   int first_zero = 0;
+  if (t < 3) s_key[t] = 0ull;
+  __syncthreads();
+  int col = 0;  // pivot columns done so far (selects the rotating slots)
 
   for (int c = 0; c < NB / IB; ++c) {
     const int cl = k + c * IB;
@@ -66,82 +92,67 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       const int r = k + t + s * PT;
 #pragma unroll
       for (int q = 0; q < IB; ++q)
-        v[s][q] = (r >= cl && r < nrows) ? ld2(A + r * ld + cl + q) : make_double2(0.0, 0.0);
+        v[s][q] = (r >= cl && r < nrows) ? A[r * ld + cl + q] : T{0, 0};
     }
-#pragma unroll
-    for (int j = 0; j < IB; ++j) {
+#pragma clang loop unroll(full)
+    for (int j = 0; j < IB; ++j, ++col) {
       const int d = cl + j;
-      // NaN magnitudes never win a comparison; the diagonal row is the fallback pivot, so
-      // the chosen row is always inside the matrix even for non-finite input
-      double best = -1.0;
-      int brow = d;
+      const int buf = col & 1;
+      unsigned long long key = 0ull;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int r = k + t + s * PT;
         if (r >= d && r < nrows) {
-          const double a = fabs(v[s][j].x) + fabs(v[s][j].y);
-          if (a > best) {
-            best = a;
-            brow = r;
-          }
+          const double2 e = wide(v[s][j]);
+          const unsigned long long kk = pivot_key(fabs(e.x) + fabs(e.y), r - k);
+          key = kk > key ? kk : key;
         }
       }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int orow = __shfl_xor(brow, off);
-        if (ob > best || (ob == best && orow < brow)) {
-          best = ob;
-          brow = orow;
-        }
+        const unsigned long long o = __shfl_xor(key, off);
+        key = o > key ? o : key;
       }
-      if (lane == 0) {
-        s_rv[wave] = best;
-        s_rr[wave] = brow;
-      }
-      __syncthreads();
-      best = s_rv[0];
-      brow = s_rr[0];
+      if (key != 0ull) {  // the lane holding the wave's best row posts it
+        const int rl = pivot_row(key);
+        if (rl % PT == t) {
 #pragma unroll
-      for (int w = 1; w < NW; ++w) {
-        const double ob = s_rv[w];
-        const int orow = s_rr[w];
-        if (ob > best || (ob == best && orow < brow)) {
-          best = ob;
-          brow = orow;
+          for (int s = 0; s < S; ++s)
+            if (s == rl / PT) {
+#pragma unroll
+              for (int q = 0; q < IB; ++q) s_cand[buf][wave][q] = wide(v[s][q]);
+            }
         }
       }
-      const int p = (brow >= d && brow < nrows) ? brow : d;
+      if (lane == 0) atomicMax(&s_key[col % 3], key);
       const int od = (d - k) % PT, sd = (d - k) / PT;
-      const int op = (p - k) % PT, sp = (p - k) / PT;
-      if (t == op) {
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-          if (s == sp) {
-#pragma unroll
-            for (int q = 0; q < IB; ++q) s_prow[q] = v[s][q];
-          }
-      }
       if (t == od) {
 #pragma unroll
         for (int s = 0; s < S; ++s)
           if (s == sd) {
 #pragma unroll
-            for (int q = 0; q < IB; ++q) s_drow[q] = v[s][q];
+            for (int q = 0; q < IB; ++q) s_drow[buf][q] = wide(v[s][q]);
           }
       }
+      if (t == 0) s_key[(col + 1) % 3] = 0ull;
+      __syncthreads();
+      const unsigned long long best = s_key[col % 3];
+      int p = best != 0ull ? k + pivot_row(best) : d;
+      const bool from_cand = best != 0ull && p >= d && p < nrows;
+      if (!from_cand) p = d;
+      const double2* prow = from_cand ? s_cand[buf][((p - k) % PT) / 64] : s_drow[buf];
+      const int op = (p - k) % PT, sp = (p - k) / PT;
       if (t == 0) {
         s_piv[j] = p;
         s_pivall[c * IB + j] = p;
         ip[d] = p;
       }
-      __syncthreads();
       if (t == od) {
 #pragma unroll
         for (int s = 0; s < S; ++s)
           if (s == sd) {
 #pragma unroll
-            for (int q = 0; q < IB; ++q) v[s][q] = s_prow[q];
+            for (int q = 0; q < IB; ++q) narrow_to(v[s][q], prow[q]);
           }
       }
       if (t == op && p != d) {
@@ -149,10 +160,10 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
         for (int s = 0; s < S; ++s)
           if (s == sp) {
 #pragma unroll
-            for (int q = 0; q < IB; ++q) v[s][q] = s_drow[q];
+            for (int q = 0; q < IB; ++q) narrow_to(v[s][q], s_drow[buf][q]);
           }
       }
-      const double2 pv = s_prow[j];
+      const double2 pv = prow[j];
       const bool zero = (pv.x == 0.0 && pv.y == 0.0);
       if (zero && first_zero == 0) first_zero = d + 1;
       const double2 inv = zero ? make_double2(0.0, 0.0) : cinv(pv);
@@ -160,10 +171,11 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       for (int s = 0; s < S; ++s) {
         const int r = k + t + s * PT;
         if (r > d && r < nrows) {
-          const double2 l = cmul(v[s][j], inv);
-          v[s][j] = l;
+          const double2 l = cmul(wide(v[s][j]), inv);
+          narrow_to(v[s][j], l);
 #pragma unroll
-          for (int q = j + 1; q < IB; ++q) v[s][q] = cfms(v[s][q], l, s_prow[q]);
+          for (int q = 0; q < IB; ++q)  // full range: j is a constant once unrolled
+            if (q > j) narrow_to(v[s][q], cfms(wide(v[s][q]), l, prow[q]));
         }
       }
     }
@@ -173,11 +185,11 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       const int r = k + t + s * PT;
       if (r >= cl && r < nrows) {
 #pragma unroll
-        for (int q = 0; q < IB; ++q) st2(A + r * ld + cl + q, v[s][q]);
+        for (int q = 0; q < IB; ++q) A[r * ld + cl + q] = v[s][q];
       }
       if (r >= cl && r < cl + IB) {
 #pragma unroll
-        for (int q = 0; q < IB; ++q) s_L11[r - cl][q] = v[s][q];
+        for (int q = 0; q < IB; ++q) s_L11[r - cl][q] = wide(v[s][q]);
       }
     }
     __syncthreads();
@@ -216,48 +228,55 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       const int ncols = left + NB - IB, cnt = s_lcnt;
       for (int idx = t; idx < cnt * ncols; idx += PT) {
         const int e = idx / ncols, cc = idx - e * ncols, cr = cc - left;
-        const int col = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
-        s_held[e][cc] = A[s_lorg[e] * ld + col];
+        const int colx = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
+        s_held[e][cc] = A[s_lorg[e] * ld + colx];
       }
       __syncthreads();
       for (int idx = t; idx < cnt * ncols; idx += PT) {
         const int e = idx / ncols, cc = idx - e * ncols, cr = cc - left;
-        const int col = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
-        A[s_lpos[e] * ld + col] = s_held[e][cc];
+        const int colx = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
+        A[s_lpos[e] * ld + colx] = s_held[e][cc];
       }
     }
     __syncthreads();
     const int w = k + NB - cl - IB;  // panel columns right of the leaf
     if (w > 0) {
+      // U rows of the leaf: forward substitution with the leaf's unit lower triangle,
+      // one column per thread, in place in s_U
+      for (int idx = t; idx < IB * w; idx += PT) {
+        const int q = idx / w, cc = idx - q * w;
+        s_U[q][cc] = ld2(A + (cl + q) * ld + cl + IB + cc);
+      }
+      __syncthreads();
       for (int cc = t; cc < w; cc += PT) {
-        const int col = cl + IB + cc;
-        double2 u[IB];
-#pragma unroll
-        for (int q = 0; q < IB; ++q) {
-          u[q] = ld2(A + (cl + q) * ld + col);
-#pragma unroll
-          for (int pp = 0; pp < q; ++pp) u[q] = cfms(u[q], s_L11[q][pp], u[pp]);
-        }
-#pragma unroll
-        for (int q = 0; q < IB; ++q) {
-          st2(A + (cl + q) * ld + col, u[q]);
-          s_U[q][cc] = u[q];
+#pragma unroll 1
+        for (int q = 1; q < IB; ++q) {
+          double2 u = s_U[q][cc];
+#pragma unroll 4
+          for (int pp = 0; pp < q; ++pp) u = cfms(u, s_L11[q][pp], s_U[pp][cc]);
+          s_U[q][cc] = u;
         }
       }
       __syncthreads();
-#pragma unroll
+      for (int idx = t; idx < IB * w; idx += PT) {
+        const int q = idx / w, cc = idx - q * w;
+        st2(A + (cl + q) * ld + cl + IB + cc, s_U[q][cc]);
+      }
+      __syncthreads();
+      // rank-IB update of the panel right of the leaf: PT rows at a time, their L rows
+      // staged in LDS, consecutive threads on consecutive columns of a row (coalesced);
+      // UB elements per thread and round with all loads issued before the first store
+#pragma unroll 1
       for (int s = 0; s < S; ++s) {
         const int r0 = k + s * PT;
         if (r0 < nrows && r0 + PT > cl + IB) {
-          {
-            const int r = r0 + t;
 #pragma unroll
-            for (int q = 0; q < IB; ++q) s_Lc[t][q] = v[s][q];
-            (void)r;
-          }
+          for (int ss = 0; ss < S; ++ss)  // register slots are indexed by constants only
+            if (ss == s) {
+#pragma unroll
+              for (int q = 0; q < IB; ++q) s_Lc[t][q] = v[ss][q];
+            }
           __syncthreads();
-          // UB elements per thread and round: all loads are issued before the first store,
-          // so their latencies overlap instead of forming one load-store chain
           constexpr int UB = 4;
           const int total = PT * w;
           for (int base = t; base < total; base += PT * UB) {
@@ -265,7 +284,8 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
               const int idx = base + u * PT, rr = idx / w, row = r0 + rr;
-              if (idx < total && row >= cl + IB && row < nrows) held[u] = A[row * ld + cl + IB + idx - rr * w];
+              const bool ok = idx < total && row >= cl + IB && row < nrows;
+              held[u] = ok ? A[row * ld + cl + IB + idx - rr * w] : T{0, 0};
             }
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
@@ -273,7 +293,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
               if (idx < total && row >= cl + IB && row < nrows) {
                 double2 acc = ld2(&held[u]);
 #pragma unroll
-                for (int q = 0; q < IB; ++q) acc = cfms(acc, s_Lc[rr][q], s_U[q][cc]);
+                for (int q = 0; q < IB; ++q) acc = cfms(acc, wide(s_Lc[rr][q]), s_U[q][cc]);
                 st2(A + row * ld + cl + IB + cc, acc);
               }
             }
@@ -282,6 +302,9 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
         }
       }
     }
+    // the next leaf reads columns written above by other threads, and s_U / s_L11 /
+    // s_piv are rewritten by it
+    __syncthreads();
   }
   // The panel's NB interchanges as one permutation of at most 2 NB rows: entries
   // 0..NB-1 are the positions k..k+NB-1, further entries the pivot rows below the panel;
@@ -463,20 +486,24 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
 // ------------------------------------------------------------------------------------
 // drivers
 // ------------------------------------------------------------------------------------
+// Leaf width: FP32 storage keeps the leaf in FP32 registers, so 16 columns fit where FP64
+// storage holds 8; wider leaves halve the passes over the rest of the panel (the
+// panel's memory traffic).  Past 2560 rows the leaf is halved to stay in registers.
 template <typename T>
 static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int rows, T* work, int32_t* piv,
                          int32_t* info, hipStream_t s) {
   constexpr int PT = 512;
+  constexpr int IBW = sizeof(T) == sizeof(float2) ? 16 : 8;
   const int S = (rows + PT - 1) / PT;
   switch (S) {
-    case 1: panel_kernel<T, PT, 1, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
-    case 2: panel_kernel<T, PT, 2, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
-    case 3: panel_kernel<T, PT, 3, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
-    case 4: panel_kernel<T, PT, 4, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
-    case 5: panel_kernel<T, PT, 5, 8><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
-    case 6: panel_kernel<T, PT, 6, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
-    case 7: panel_kernel<T, PT, 7, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
-    default: panel_kernel<T, PT, 8, 4><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 1: panel_kernel<T, PT, 1, IBW><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 2: panel_kernel<T, PT, 2, IBW><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 3: panel_kernel<T, PT, 3, IBW><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 4: panel_kernel<T, PT, 4, IBW><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 5: panel_kernel<T, PT, 5, IBW><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 6: panel_kernel<T, PT, 6, IBW / 2><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    case 7: panel_kernel<T, PT, 7, IBW / 2><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
+    default: panel_kernel<T, PT, 8, IBW / 2><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
   }
 }
 
