@@ -263,9 +263,8 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
         st2(A + (cl + q) * ld + cl + IB + cc, s_U[q][cc]);
       }
       __syncthreads();
-      // rank-IB update of the panel right of the leaf: PT rows at a time, their L rows
-      // staged in LDS, consecutive threads on consecutive columns of a row (coalesced);
-      // UB elements per thread and round with all loads issued before the first store
+      // rank-IB update of the panel right of the leaf, PT rows at a time with their L rows
+      // staged in LDS
 #pragma unroll 1
       for (int s = 0; s < S; ++s) {
         const int r0 = k + s * PT;
@@ -277,24 +276,30 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
               for (int q = 0; q < IB; ++q) s_Lc[t][q] = v[ss][q];
             }
           __syncthreads();
-          constexpr int UB = 4;
-          const int total = PT * w;
-          for (int base = t; base < total; base += PT * UB) {
-            T held[UB];
+          // A[rows, right of the leaf] -= L (s_Lc) U (s_U) on the matrix cores: wave w takes
+          // rows r0 + 64 w .. + 64 in 16-row blocks, the columns in 16-wide blocks (K = IB);
+          // rows above the leaf's last row and columns past w are masked at the store
+          const int ii = lane & 15;
+          for (int rb = 0; rb < 4; ++rb) {
+            const int rbase = r0 + wave * 64 + rb * 16;
+            if (rbase + 16 <= cl + IB || rbase >= nrows) continue;  // uniform per wave
+            for (int cb0 = 0; cb0 < w; cb0 += 16) {
+              StripMma<T, 1, IB> acc;
+              acc.zero();
+              acc.run([&](int i, int kk) { return s_Lc[rbase - r0 + i][kk]; },
+                      [&](int kk, int cc) {
+                        T u;
+                        narrow_to(u, s_U[kk][cb0 + cc]);
+                        return u;
+                      },
+                      lane);
 #pragma unroll
-            for (int u = 0; u < UB; ++u) {
-              const int idx = base + u * PT, rr = idx / w, row = r0 + rr;
-              const bool ok = idx < total && row >= cl + IB && row < nrows;
-              held[u] = ok ? A[row * ld + cl + IB + idx - rr * w] : T{0, 0};
-            }
-#pragma unroll
-            for (int u = 0; u < UB; ++u) {
-              const int idx = base + u * PT, rr = idx / w, cc = idx - rr * w, row = r0 + rr;
-              if (idx < total && row >= cl + IB && row < nrows) {
-                double2 acc = ld2(&held[u]);
-#pragma unroll
-                for (int q = 0; q < IB; ++q) acc = cfms(acc, wide(s_Lc[rr][q]), s_U[q][cc]);
-                st2(A + row * ld + cl + IB + cc, acc);
+              for (int r = 0; r < 4; ++r) {
+                const int row = rbase + acc.row(r, lane), cc = cb0 + ii;
+                if (row >= cl + IB && row < nrows && cc < w) {
+                  T* ap = A + row * ld + cl + IB + cc;
+                  narrow_to(*ap, csub(wide(*ap), acc.value(0, r)));
+                }
               }
             }
           }

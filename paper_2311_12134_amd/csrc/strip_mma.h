@@ -1,5 +1,5 @@
-// A 16-row strip of a product C = A B with K = NB = 64 on the matrix cores, for one
-// wavefront: rows [0, 16) of the strip, CB blocks of 16 columns.  A and B are read
+// A 16-row strip of a product C = A B with K = KD (a multiple of 4, default NB = 64) on
+// the matrix cores, for one wavefront: rows [0, 16) of the strip, CB blocks of 16 columns.  A and B are read
 // through functors a(i, k) and b(k, j) returning the storage's complex type.
 //   float2  : FP32 MFMA 16x16x4 with three real products (Ar Br, Ai Bi, (Ar+Ai)(Br+Bi));
 //             D lane l, register r -> (row 4 (l/16) + r, column l % 16) of a block.
@@ -12,11 +12,11 @@
 
 namespace lsms {
 
-template <typename T, int CB>
+template <typename T, int CB, int KD = NB>
 struct StripMma;
 
-template <int CB>
-struct StripMma<float2, CB> {
+template <int CB, int KD>
+struct StripMma<float2, CB, KD> {
   typedef float f4v __attribute__((ext_vector_type(4)));
   f4v t1[CB], t2[CB], t3[CB];
   __device__ void zero() {
@@ -31,7 +31,7 @@ struct StripMma<float2, CB> {
   __device__ void run(FA a_at, FB b_at, int lane) {
     const int ii = lane & 15, kq = lane >> 4;
 #pragma unroll 4
-    for (int k4 = 0; k4 < NB; k4 += 4) {
+    for (int k4 = 0; k4 < KD; k4 += 4) {
       const float2 a = a_at(ii, k4 + kq);
       const float as = a.x + a.y;
 #pragma unroll
@@ -49,8 +49,8 @@ struct StripMma<float2, CB> {
   }
 };
 
-template <int CB>
-struct StripMma<double2, CB> {
+template <int CB, int KD>
+struct StripMma<double2, CB, KD> {
   typedef double d4v __attribute__((ext_vector_type(4)));
   d4v re[CB], im[CB];
   __device__ void zero() {
@@ -64,7 +64,7 @@ struct StripMma<double2, CB> {
   __device__ void run(FA a_at, FB b_at, int lane) {
     const int ii = lane & 15, kq = lane >> 4;
 #pragma unroll 4
-    for (int k4 = 0; k4 < NB; k4 += 4) {
+    for (int k4 = 0; k4 < KD; k4 += 4) {
       const double2 a = a_at(ii, k4 + kq);
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
