@@ -32,11 +32,11 @@ GEMM_SOURCE = os.path.join(ROOT, "paper_2311_12134_amd", "csrc", "gemm.hip")
 # HBM bytes per launch of the trailing-update kernel on this workload, from two rocprofv3
 # counter runs (FETCH_SIZE, WRITE_SIZE) over one step, each scaled by what the same counter
 # read for a 1 GiB device-to-device copy in the same run (--copy-calibration).  Keyed by
-# (precision, workload) and tied to the sha256 of the kernel source the counters were
+# (precision, workload, tiling) and tied to the sha256 of the kernel source the counters were
 # taken on: any later change to that source makes the figure stale and it is reported as null.
 TRAFFIC = {
-    ("split", "fcc4000"): {"sha256": "5c27de413339949d5cc9a13e34249b395bcc71cde6bc70ac5a634222913a563c",
-                           "bytes_per_launch": 2.4708e10},
+    ("split", "fcc4000", 2): {"sha256": "80be0489add8f92c4a3f2e3a587b9c117fa83967fe6de1d4275f086ec32cd4c2",
+                              "bytes_per_launch": 3.5901e10},
 }
 
 
@@ -137,7 +137,9 @@ def main():
         step(i, args.precision, sig_main)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    gemm_ms, gemm_launches, gemm_flops, gemm_bytes = ctx.kernel_stats()
+    gemm_ms, gemm_launches, gemm_flops, gemm_bytes = ctx.kernel_stats(kind=1)
+    narrow_ms, narrow_launches, narrow_flops, _ = ctx.kernel_stats(kind=0)
+    tiling = ctx.gemm_tiling()
     ctx.set_profiling(False)
     info_np = info.cpu().numpy()
     ms_per_step = 1e3 * elapsed / args.steps
@@ -163,15 +165,22 @@ def main():
     if gemm_launches:
         avg_s = gemm_ms / gemm_launches / 1e3
         achieved = gemm_flops / gemm_launches / avg_s
+        if args.precision == "split":
+            kname = "gemm_f32_3m_tiled" if tiling > 0 else "gemm_f32_3m_kernel"
+        else:
+            kname = "gemm_f64_kernel"
         with open(GEMM_SOURCE, "rb") as f:
             digest = hashlib.sha256(f.read()).hexdigest()
-        rec = TRAFFIC.get((args.precision, args.workload))
+        rec = TRAFFIC.get((args.precision, args.workload, tiling if args.precision == "split" else -1))
         traffic = rec["bytes_per_launch"] if rec is not None and rec["sha256"] == digest else None
-        out["roofline"] = {"kernel": "gemm_f32_3m_kernel" if args.precision == "split" else "gemm_f64_kernel",
-                           "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                           "frac": achieved / peak, "traffic": traffic,
+        out["roofline"] = {"kernel": kname, "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                           "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                            "launches": gemm_launches, "avg_launch_ms": 1e3 * avg_s,
+                           "alg_flops_per_launch": gemm_flops / gemm_launches,
                            "alg_bytes_per_launch": gemm_bytes / gemm_launches}
+    if narrow_launches:
+        out["narrow_update"] = {"launches": narrow_launches, "avg_launch_ms": narrow_ms / narrow_launches,
+                                "achieved_tflops": narrow_flops / (narrow_ms / 1e3) / 1e12}
     if not args.no_fp64_compare and args.precision == "split":
         sig64 = {}
         step(0, "fp64", sig64)  # warm-up of the FP64 path (workspace layout differs)

@@ -201,12 +201,14 @@ int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t* n, void* 
  * lsms_set_profiling(ctx, 1) waits for the device, clears the statistics and makes every
  * later lsms_tau_solve record a pair of HIP events around each trailing-update launch on
  * the caller's stream (0 switches recording off).  lsms_kernel_stats waits for the
- * recorded events and returns the summed launch time (ms), the number of launches, their
- * algorithmic flops and their algorithmic bytes.  A launch updates, in every system, the
- * unpadded block of m rows and c columns with K = kd (64 or 128): 8 m c kd flops (the
+ * recorded events and returns, over the launches of the given kind, the summed launch
+ * time (ms), the number of launches, their algorithmic flops and their algorithmic bytes.
+ * kind 1 selects the wide updates (K = 128, the trailing matrix below a pair of panels),
+ * kind 0 the narrow updates of a pair's second panel (K = 64), -1 both.  A launch updates,
+ * in every system, the unpadded block of m rows and c columns: 8 m c K flops (the
  * standard complex count; the split mode executes 3/4 of it on the matrix cores) and
- * es (m kd + kd c + 2 m c) bytes, es = 8 (split) or 16 (FP64).  All outputs are host
- * scalars; the call returns LSMS_E_ARG for a NULL pointer.
+ * es (m K + K c + 2 m c) bytes, es = 8 (split) or 16 (FP64).  All outputs are host
+ * scalars; the call returns LSMS_E_ARG for a NULL pointer or an unknown kind.
  */
 int lsms_set_profiling(lsms_ctx* ctx, int on);
 
@@ -221,7 +223,7 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
 #define LSMS_GEMM_F32_VARIANTS 7
 int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
 int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
-int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launches, double* alg_flops,
+int lsms_kernel_stats(lsms_ctx* ctx, int kind, double* total_ms, int64_t* launches, double* alg_flops,
                       double* alg_bytes);
 
 /*

@@ -178,14 +178,16 @@ class Context:
         check(lib().lsms_get_tuning(self._h, 0, ctypes.byref(v)))
         return v.value
 
-    def kernel_stats(self):
+    def kernel_stats(self, kind=1):
         """(total ms, launches, algorithmic flops, algorithmic bytes) of the recorded
-        trailing-update launches."""
+        trailing-update launches: kind 1 the wide (K = 128) updates, 0 the narrow ones,
+        -1 all."""
         ms = ctypes.c_double(0)
         n = ctypes.c_int64(0)
         fl = ctypes.c_double(0)
         by = ctypes.c_double(0)
-        check(lib().lsms_kernel_stats(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl), ctypes.byref(by)))
+        check(lib().lsms_kernel_stats(self._h, int(kind), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
+                                      ctypes.byref(by)))
         return ms.value, n.value, fl.value, by.value
 
     # -- diagnostic batched solve ------------------------------------------------------

@@ -57,6 +57,7 @@ struct EventProf : GemmProfiler {
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<double> flops, bytes;
+  std::vector<int> kinds;
   hipEvent_t get() {
     if (used < pool.size()) return pool[used++];
     hipEvent_t e = nullptr;
@@ -69,16 +70,18 @@ struct EventProf : GemmProfiler {
     hipEvent_t e = get();
     if (e) hipEventRecord(e, s);
   }
-  void after(hipStream_t s, double f, double b) override {
+  void after(hipStream_t s, double f, double b, int kind) override {
     hipEvent_t e = get();
     if (e) hipEventRecord(e, s);
     flops.push_back(f);
     bytes.push_back(b);
+    kinds.push_back(kind);
   }
   void reset() {
     used = 0;
     flops.clear();
     bytes.clear();
+    kinds.clear();
   }
   ~EventProf() override {
     for (hipEvent_t e : pool) hipEventDestroy(e);
@@ -752,13 +755,17 @@ extern "C" int lsms_set_profiling(lsms_ctx* ctx, int on) {
   return LSMS_OK;
 }
 
-extern "C" int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launches, double* alg_flops,
+extern "C" int lsms_kernel_stats(lsms_ctx* ctx, int kind, double* total_ms, int64_t* launches, double* alg_flops,
                                  double* alg_bytes) {
   if (!ctx || !total_ms || !launches || !alg_flops || !alg_bytes) return fail(LSMS_E_ARG, "NULL argument");
+  if (kind < -1 || kind > 1) return fail(LSMS_E_ARG, "kind %d is not -1, 0 or 1", kind);
   HIP_TRY(hipSetDevice(ctx->device));
   double ms = 0.0, fl = 0.0, by = 0.0;
+  int64_t count = 0;
   const size_t n = ctx->prof.flops.size();
   for (size_t i = 0; i < n; ++i) {
+    if (kind >= 0 && ctx->prof.kinds[i] != kind) continue;
+    ++count;
     hipEvent_t a = ctx->prof.pool[2 * i], b = ctx->prof.pool[2 * i + 1];
     HIP_TRY(hipEventSynchronize(b));
     float e = 0.f;
@@ -768,7 +775,7 @@ extern "C" int lsms_kernel_stats(lsms_ctx* ctx, double* total_ms, int64_t* launc
     by += ctx->prof.bytes[i];
   }
   *total_ms = ms;
-  *launches = (int64_t)n;
+  *launches = count;
   *alg_flops = fl;
   *alg_bytes = by;
   return LSMS_OK;

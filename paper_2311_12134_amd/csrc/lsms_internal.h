@@ -113,7 +113,8 @@ void launch_init_rhs(const JobDesc* jobs, int njobs, int npad_max, const int32_t
 struct GemmProfiler {
   const int* n_true = nullptr;
   virtual void before(hipStream_t s) = 0;
-  virtual void after(hipStream_t s, double alg_flops, double alg_bytes) = 0;
+  // kind 0: narrow update of a pair's second panel (K = NB); 1: wide update (K = 2 NB)
+  virtual void after(hipStream_t s, double alg_flops, double alg_bytes, int kind) = 0;
   virtual ~GemmProfiler() {}
 };
 

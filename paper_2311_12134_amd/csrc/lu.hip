@@ -551,7 +551,7 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
     if (prof) {
       double f, b;
       update_cost(prof, njobs, kd, r_begin, c_begin, c_end, (int)sizeof(T), &f, &b);
-      prof->after(s, f, b);
+      prof->after(s, f, b, c_end > 0 ? 0 : 1);
     }
   };
   for (int k = 0; k < npad_max; k += 2 * NB) {
