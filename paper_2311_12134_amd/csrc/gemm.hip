@@ -202,6 +202,10 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
 
   __shared__ float2 sA[2][KC][LA];
   __shared__ float2 sB[2][KC][LB];
+  // A is stored transposed (k-major): the four k-quads a wavefront writes would hit the
+  // same LDS banks, so rows are XOR-swizzled by 16 (k / 4); all four k of one MFMA step
+  // share the swizzle, so the 16 rows a read touches stay consecutive
+  auto aswz = [](int kk) { return ((kk >> 2) & 3) << 4; };
 
   // global -> register staging of one chunk
   const int ai = t >> 2, ak = (t & 3) * 4;  // A: row ai of each pass, k quad ak
@@ -242,7 +246,7 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
 #pragma unroll
     for (int p = 0; p < AP; ++p)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) sA[buf][ak + u][p * 64 + ai] = ra[p][u];
+      for (int u = 0; u < 4; ++u) sA[buf][ak + u][(p * 64 + ai) ^ aswz(ak + u)] = ra[p][u];
 #pragma unroll
     for (int p = 0; p < BP; ++p) {
       const int kk = t >> 4, j = p * 64 + (t & 15) * 4;
@@ -275,7 +279,7 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
       float as[BM], bs[BN];
 #pragma unroll
       for (int i = 0; i < BM; ++i) {
-        a[i] = sA[cur][k4 + kq][wm * WM + i * 16 + ii];
+        a[i] = sA[cur][k4 + kq][(wm * WM + i * 16 + ii) ^ aswz(k4)];
         as[i] = a[i].x + a[i].y;
       }
 #pragma unroll
