@@ -410,7 +410,9 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   const int64_t ld = jd.npad;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   typedef typename LdsOf<T>::type S;
-  __shared__ S s_L[NB][NB + 4];
+  // Only the gathered tile lives in LDS; the 64 x 64 left operands (the inverse of the
+  // panel's unit lower triangle, and for SECOND the first panel's facing L rows) are the
+  // same for every tile of a job and are read through the cache by the MFMA operand loads.
   __shared__ S s_X[NB][64 + 4];
   __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
   const int32_t* lst = piv + jd.piv_off + perm_off(jd.npad, k);
@@ -418,21 +420,6 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   for (int i = t; i < cnt; i += 256) {
     s_dst[i] = lst[2 + i];
     s_src[i] = lst[2 + PERM_MAX + i];
-  }
-  // the inverse of the panel's unit lower triangle, unit diagonal made explicit
-  auto load_linv = [&]() {
-    for (int idx = t; idx < NB * NB; idx += 256) {
-      const int q = idx / NB, pp = idx % NB;
-      st2(&s_L[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(pp == q ? 1.0 : 0.0, 0.0));
-    }
-  };
-  if (SECOND) {  // the first panel's L rows that face this panel
-    for (int idx = t; idx < NB * NB; idx += 256) {
-      const int q = idx / NB, pp = idx % NB;
-      s_L[q][pp] = A[(k + q) * ld + (k - NB) + pp];
-    }
-  } else {
-    load_linv();
   }
   __syncthreads();
   // the panel's permutation as a gather on this tile: entry i = wave + 4 s, column = lane
@@ -459,12 +446,12 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
     }
   }
   const int ii = lane & 15;
+  const int row0 = k + wave * 16;  // this wavefront's 16 panel rows
   if (SECOND) {
-    __syncthreads();  // the gathered panel rows are complete in s_X
-    // s_X -= L[k.., k-NB..k) (in s_L) U[k-NB.., col0..]: wave w owns rows 16w .. 16w+16
+    // s_X -= L[k.., k-NB..k) U[k-NB.., col0..]: wave w owns rows 16w .. 16w+16
     StripMma<T, 4> d;
     d.zero();
-    d.run([&](int i, int kk) { return s_L[wave * 16 + i][kk]; },
+    d.run([&](int i, int kk) { return A[(int64_t)(row0 + i) * ld + (k - NB) + kk]; },
           [&](int kk, int c) { return A[(int64_t)(k - NB + kk) * ld + col0 + c]; }, lane);
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
@@ -473,19 +460,25 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
         S* xp = &s_X[wave * 16 + d.row(r, lane)][cb * 16 + ii];
         st2(xp, csub(ld2(xp), d.value(cb, r)));
       }
-    __syncthreads();
-    load_linv();
   }
   __syncthreads();
-  // U12 = L11^-1 A12 straight from the accumulators to the panel rows
+  // U12 = L11^-1 A12 straight from the accumulators to the panel rows (the inverse is
+  // stored below the diagonal; its unit diagonal and zero upper part are implied)
   StripMma<T, 4> u;
   u.zero();
-  u.run([&](int i, int kk) { return s_L[wave * 16 + i][kk]; }, [&](int kk, int c) { return s_X[kk][c]; }, lane);
+  u.run(
+      [&](int i, int kk) {
+        const int q = wave * 16 + i;
+        T l = A[(int64_t)(k + q) * ld + k + kk];
+        if (kk >= q) l = T{kk == q ? 1.0f : 0.0f, 0.0f};
+        return l;
+      },
+      [&](int kk, int c) { return s_X[kk][c]; }, lane);
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      st2(A + (int64_t)(k + wave * 16 + u.row(r, lane)) * ld + col0 + cb * 16 + ii, u.value(cb, r));
+      st2(A + (int64_t)(row0 + u.row(r, lane)) * ld + col0 + cb * 16 + ii, u.value(cb, r));
 }
 
 // ------------------------------------------------------------------------------------
