@@ -4,47 +4,61 @@
 // Structure constants for LIZ members a != b, R = p_a - p_b:
 //   g^{ab}_{LL'} = -4 pi i kappa  sum_{L''} i^{l - l' + l''} C_{L L' L''} h_{l''}(kappa |R|) Y_{L''}(R^)
 // with C the Gaunt integrals of three real harmonics and h_l = j_l + i y_l.
-// Each 16 x 16 block is produced by one wavefront: 49 lanes evaluate
-// (-4 pi i kappa) i^{l''} h_{l''} Y_{L''} once, then every lane contracts four
-// (L, L') entries against the sparse Gaunt table held in constant memory and writes
+// A workgroup produces 64 consecutive 16 x 16 blocks: the harmonics and Hankel functions of
+// each block are evaluated once (four threads per block), then each wavefront contracts its
+// blocks against the Gaunt terms (in LDS, dealt to lanes by term count) and writes
 // -t_a * g (row-scaled by the t-matrix of the row's member), or the identity on the
 // diagonal blocks and on the padding.
+#include <algorithm>
+#include <cstring>
+
 #include "lsms_internal.h"
 #include "ylm.h"
 
 namespace lsms {
 
-__constant__ GauntTable c_gaunt;
+// Gaunt terms dealt to lane slots: the 256 (L, L') pairs sorted by their number of terms and
+// dealt to (group r, lane), so the 64 lanes of a group loop over nearly the same count
+// (16 iterations over the four groups instead of 28 for the natural order).
+constexpr int GT = 7;  // most terms of any (L, L') pair for l, l' <= 3
+struct GauntSlots {
+  double coef[4][64][GT];    // C_{L L' L''} (0 in padding terms)
+  uint16_t l3[4][64][GT];    // L'' | l'' << 8
+  uint16_t pair[4][64];      // L | L' << 4 | ((l - l') mod 4) << 8
+  int32_t nterm[4];          // iterations of group r
+  double ynorm[7][7];        // N_lm of the real harmonics, l, m <= 6
+};
+__constant__ GauntSlots c_slots;
 
-hipError_t upload_gaunt(const GauntTable& g) { return hipMemcpyToSymbol(HIP_SYMBOL(c_gaunt), &g, sizeof(GauntTable)); }
+static int lidx_h(int L) { return L == 0 ? 0 : (L < 4 ? 1 : (L < 9 ? 2 : 3)); }
 
-// One real harmonic Y_{l m} of the unit vector (x, y, z) (see ylm.h for the convention).
-__device__ inline double real_ylm_one(int l, int m, double x, double y, double z) {
-  int am = m < 0 ? -m : m;
-  double c = 1.0, s = 0.0;
-  for (int q = 0; q < am; ++q) {
-    double cn = c * x - s * y;
-    s = c * y + s * x;
-    c = cn;
-  }
-  double qmm = 1.0;
-  for (int q = 1; q < 2 * am; q += 2) qmm *= q;
-  double qa = qmm, qb = 0.0;  // Q_{l'}^{am} for l' = current, previous
-  double qv = qmm;
-  if (l > am) {
-    double q1 = z * (2 * am + 1) * qmm;
-    qb = qmm;
-    qa = q1;
-    for (int ll = am + 2; ll <= l; ++ll) {
-      double qn = ((2 * ll - 1) * z * qa - (ll + am - 1) * qb) / (double)(ll - am);
-      qb = qa;
-      qa = qn;
+hipError_t upload_gaunt(const GauntTable& g) {
+  GauntSlots sl;
+  std::memset(&sl, 0, sizeof(sl));
+  int order[NL * NL];
+  for (int p = 0; p < NL * NL; ++p) order[p] = p;
+  std::stable_sort(order, order + NL * NL, [&](int x, int y) {
+    return (g.start[x + 1] - g.start[x]) < (g.start[y + 1] - g.start[y]);
+  });
+  for (int i = 0; i < NL * NL; ++i) {
+    const int p = order[i], r = i / 64, lane = i % 64;
+    const int L = p / NL, Lp = p % NL;
+    const int e = ((lidx_h(L) - lidx_h(Lp)) % 4 + 4) % 4;
+    sl.pair[r][lane] = (uint16_t)(L | Lp << 4 | e << 8);
+    const int n = g.start[p + 1] - g.start[p];
+    if (n > GT) return hipErrorInvalidValue;
+    sl.nterm[r] = std::max(sl.nterm[r], n);
+    for (int j = 0; j < n; ++j) {
+      const int l3 = g.l3[g.start[p] + j];
+      int ll = 0;
+      while ((ll + 1) * (ll + 1) <= l3) ++ll;
+      sl.coef[r][lane][j] = g.coef[g.start[p] + j];
+      sl.l3[r][lane][j] = (uint16_t)(l3 | ll << 8);
     }
-    qv = qa;
   }
-  double nrm = ylm_norm<6>(l, am);
-  if (m == 0) return nrm * qv;
-  return M_SQRT2 * nrm * qv * (m > 0 ? c : s);
+  for (int l = 0; l <= 6; ++l)
+    for (int m = 0; m <= l; ++m) sl.ynorm[l][m] = ylm_norm<6>(l, m);
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_slots), &sl, sizeof(GauntSlots));
 }
 
 // t_l(z+) = -sin(d) e^{i d} / kappa+, t(z-) = conj(t(z+)).
@@ -66,110 +80,171 @@ void launch_tmatrix(const double* phase, int n_atoms, double2 kappa_plus, double
   tmatrix_kernel<<<(n + 255) / 256, 256, 0, s>>>(phase, n_atoms, kappa_plus, tpm);
 }
 
+__device__ inline int lidx(int L) { return L == 0 ? 0 : (L < 4 ? 1 : (L < 9 ? 2 : 3)); }
+
+// The harmonics Y_{l, +-m} of the unit vector (x, y, z) for one m and l = m .. 6 (see ylm.h).
+__device__ inline void ylm_column(int m, double x, double y, double z, double* Y) {
+  double c = 1.0, s = 0.0;  // (x + i y)^m
+  for (int q = 0; q < m; ++q) {
+    const double cn = c * x - s * y;
+    s = c * y + s * x;
+    c = cn;
+  }
+  double qmm = 1.0;
+  for (int q = 1; q < 2 * m; q += 2) qmm *= q;  // (2m - 1)!!
+  double q2 = 0.0, q1 = qmm;
+  for (int l = m; l <= 6; ++l) {
+    double q;
+    if (l == m)
+      q = qmm;
+    else if (l == m + 1)
+      q = z * (2 * m + 1) * qmm;
+    else
+      q = ((2 * l - 1) * z * q1 - (l + m - 1) * q2) / (double)(l - m);
+    if (l > m) {
+      q2 = q1;
+      q1 = q;
+    }
+    const double nq = c_slots.ynorm[l][m] * q;
+    if (m == 0) {
+      Y[l * l + l] = nq;
+    } else {
+      Y[l * l + l + m] = M_SQRT2 * nq * c;
+      Y[l * l + l - m] = M_SQRT2 * nq * s;
+    }
+  }
+}
+
+// M = 1 - T g for BPW consecutive 16 x 16 blocks (a, b) of one job (row-major over the
+// padded block grid).  Phase 1: four threads per block evaluate the 49 real harmonics of
+// R^ = (p_a - p_b)/|R| (split by |m|) and (-4 pi i kappa) i^l h_l(kappa |R|), l <= 6 (the
+// fourth thread), into LDS.  Phase 2: each wavefront contracts its blocks against the
+// slot-dealt Gaunt terms, applies i^{l - l'} and -t_a, stages the block in LDS and writes it
+// row by row.  Diagonal and padding blocks are the identity / zero.
 template <typename T>
 __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, const double* liz_pos,
                                                        const int32_t* liz_atom, const double2* tpm, double2 kp,
                                                        double2 km, T* work, double2* m64) {
-  __shared__ double2 s_hy[4][NL3];
+  constexpr int BPW = 64;
+  __shared__ double s_coef[4][64][GT];
+  __shared__ uint16_t s_l3[4][64][GT];
+  __shared__ uint16_t s_pair[4][64];
+  __shared__ double s_Y[BPW][NL3 + 1];
+  __shared__ double2 s_H[BPW][7];
+  __shared__ double2 s_G[4][NL][NL + 1];
   const JobDesc jd = jobs[blockIdx.y];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nbp = jd.npad / NL;
-  const int blk = blockIdx.x * 4 + wave;
-  const bool valid = blk < nbp * nbp;
-  const int a = valid ? blk / nbp : 0, b = valid ? blk % nbp : 0;
-  const bool offdiag = valid && a != b && a < jd.nl && b < jd.nl;
+  const int blk0 = blockIdx.x * BPW;
+  if (blk0 >= nbp * nbp) return;  // uniform
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int i = t; i < 4 * 64 * GT; i += 256) {
+    (&s_coef[0][0][0])[i] = (&c_slots.coef[0][0][0])[i];
+    (&s_l3[0][0][0])[i] = (&c_slots.l3[0][0][0])[i];
+  }
+  (&s_pair[0][0])[t] = (&c_slots.pair[0][0])[t];
   const double2 kappa = jd.energy == 0 ? kp : km;
-
-  if (offdiag && lane < NL3) {
-    const double* pa = liz_pos + (jd.liz_off + a) * 3;
-    const double* pb = liz_pos + (jd.liz_off + b) * 3;
-    double rx = pa[0] - pb[0], ry = pa[1] - pb[1], rz = pa[2] - pb[2];
-    double dist = sqrt(rx * rx + ry * ry + rz * rz);
-    double inv = 1.0 / dist;
-    int l3 = 0;
-    while ((l3 + 1) * (l3 + 1) <= lane) ++l3;
-    int m3 = lane - l3 * l3 - l3;
-    double y = real_ylm_one(l3, m3, rx * inv, ry * inv, rz * inv);
-    // h_l(x), x = kappa * dist: h0 = -i e^{ix}/x, h1 = -e^{ix}(x + i)/x^2, upward recurrence
-    double2 x = make_double2(kappa.x * dist, kappa.y * dist);
-    double sx, cx;
-    sincos(x.x, &sx, &cx);
-    double ex = exp(-x.y);
-    double2 eix = make_double2(ex * cx, ex * sx);
-    double2 ix = cinv(x);
-    double2 h0 = cmul(make_double2(eix.y, -eix.x), ix);  // -i e^{ix} / x
-    double2 h = h0;
-    if (l3 >= 1) {
-      double2 t = cmul(eix, make_double2(x.x, x.y + 1.0));
-      double2 h1 = cmul(make_double2(-t.x, -t.y), cmul(ix, ix));
-      double2 hm = h0;
-      h = h1;
-      for (int l = 1; l < l3; ++l) {
-        double2 hn = csub(cmul(make_double2((2 * l + 1) * ix.x, (2 * l + 1) * ix.y), h), hm);
-        hm = h;
-        h = hn;
+  {
+    const int q = t >> 2, part = t & 3, blk = blk0 + q;
+    const int a = blk / nbp, b = blk % nbp;
+    if (blk < nbp * nbp && a != b && a < jd.nl && b < jd.nl) {
+      const double* pa = liz_pos + (jd.liz_off + a) * 3;
+      const double* pb = liz_pos + (jd.liz_off + b) * 3;
+      const double rx = pa[0] - pb[0], ry = pa[1] - pb[1], rz = pa[2] - pb[2];
+      const double dist = sqrt(rx * rx + ry * ry + rz * rz), inv = 1.0 / dist;
+      double* Y = &s_Y[q][0];
+      if (part == 3) {
+        ylm_column(3, rx * inv, ry * inv, rz * inv, Y);
+        // h_l(x), x = kappa |R|: h0 = -i e^{ix}/x, h1 = -e^{ix}(x + i)/x^2, upward recurrence;
+        // stored times (-4 pi i kappa) i^l
+        const double2 x = make_double2(kappa.x * dist, kappa.y * dist);
+        double sx, cx;
+        sincos(x.x, &sx, &cx);
+        const double ex = exp(-x.y);
+        const double2 eix = make_double2(ex * cx, ex * sx);
+        const double2 ix = cinv(x);
+        const double2 pre = make_double2(4.0 * M_PI * kappa.y, -4.0 * M_PI * kappa.x);  // -4 pi i kappa
+        double2 hm = cmul(make_double2(eix.y, -eix.x), ix);                             // h0
+        const double2 tq = cmul(eix, make_double2(x.x, x.y + 1.0));
+        double2 h = cmul(make_double2(-tq.x, -tq.y), cmul(ix, ix));                      // h1
+        s_H[q][0] = cmul(pre, hm);
+        double2 ph = make_double2(0.0, 1.0);  // i^l
+        s_H[q][1] = cmul(cmul(pre, ph), h);
+        for (int l = 1; l < 6; ++l) {
+          const double2 hn = csub(cmul(make_double2((2 * l + 1) * ix.x, (2 * l + 1) * ix.y), h), hm);
+          hm = h;
+          h = hn;
+          ph = make_double2(-ph.y, ph.x);
+          s_H[q][l + 1] = cmul(cmul(pre, ph), h);
+        }
+      } else {
+        ylm_column(part, rx * inv, ry * inv, rz * inv, Y);
+        ylm_column(part + 4, rx * inv, ry * inv, rz * inv, Y);
       }
     }
-    // (-4 pi i kappa) * i^{l''} * h * Y
-    double2 pre = make_double2(4.0 * M_PI * kappa.y, -4.0 * M_PI * kappa.x);  // -4 pi i kappa
-    double2 ph = (l3 & 3) == 0 ? make_double2(1, 0)
-               : (l3 & 3) == 1 ? make_double2(0, 1)
-               : (l3 & 3) == 2 ? make_double2(-1, 0)
-                               : make_double2(0, -1);
-    double2 v = cmul(cmul(pre, ph), h);
-    s_hy[wave][lane] = make_double2(v.x * y, v.y * y);
   }
   __syncthreads();
-  if (!valid) return;
-
-  const int Lp = lane & 15;
-  const int lp = Lp == 0 ? 0 : (Lp < 4 ? 1 : (Lp < 9 ? 2 : 3));
-  double2 t_a = make_double2(0, 0);
-  int atom_a = 0;
-  if (offdiag) atom_a = liz_atom[jd.liz_off + a];
-  const int64_t base = jd.a_off + (int64_t)(a * NL) * jd.npad + b * NL + Lp;
+  const int Lr = lane >> 4, Lc = lane & 15;
+  for (int q = wave; q < BPW; q += 4) {
+    const int blk = blk0 + q;
+    if (blk >= nbp * nbp) break;  // uniform per wavefront
+    const int a = blk / nbp, b = blk % nbp;
+    const int64_t base = (int64_t)(a * NL) * jd.npad + b * NL;
+    if (a != b && a < jd.nl && b < jd.nl) {
+      const int atom_a = liz_atom[jd.liz_off + a];
+      const double2* ta = tpm + atom_a * 8 + jd.energy * 4;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int L = (lane >> 4) + 4 * r;
-    const int l = L == 0 ? 0 : (L < 4 ? 1 : (L < 9 ? 2 : 3));
-    double2 val;
-    if (offdiag) {
-      t_a = tpm[atom_a * 8 + jd.energy * 4 + l];
-      const int pair = L * NL + Lp;
-      double2 g = make_double2(0, 0);
-      for (int q = c_gaunt.start[pair]; q < c_gaunt.start[pair + 1]; ++q) {
-        double2 hy = s_hy[wave][c_gaunt.l3[q]];
-        double cf = c_gaunt.coef[q];
-        g.x += cf * hy.x;
-        g.y += cf * hy.y;
+      for (int r = 0; r < 4; ++r) {
+        const int pr = s_pair[r][lane], L = pr & 15, Lp = (pr >> 4) & 15, e = pr >> 8;
+        double2 g = make_double2(0.0, 0.0);
+        for (int j = 0; j < c_slots.nterm[r]; ++j) {
+          const int lt = s_l3[r][lane][j];
+          const double cy = s_coef[r][lane][j] * s_Y[q][lt & 0xff];
+          const double2 h = s_H[q][lt >> 8];
+          g.x += cy * h.x;
+          g.y += cy * h.y;
+        }
+        // i^{l - l'}, then -t_a
+        const double2 gp = e == 0 ? g : e == 1 ? make_double2(-g.y, g.x) : e == 2 ? make_double2(-g.x, -g.y)
+                                                                                      : make_double2(g.y, -g.x);
+        const double2 tg = cmul(ta[lidx(L)], gp);
+        s_G[wave][L][Lp] = make_double2(-tg.x, -tg.y);
       }
-      int e = ((l - lp) % 4 + 4) % 4;  // i^{l - l'}
-      double2 gp = e == 0 ? g : e == 1 ? make_double2(-g.y, g.x) : e == 2 ? make_double2(-g.x, -g.y)
-                                                                            : make_double2(g.y, -g.x);
-      double2 tg = cmul(t_a, gp);
-      val = make_double2(-tg.x, -tg.y);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int L = Lr + 4 * r;
+        const double2 v = s_G[wave][L][Lc];
+        st2(work + jd.a_off + base + (int64_t)L * jd.npad + Lc, v);
+        if (m64) m64[jd.m_off + base + (int64_t)L * jd.npad + Lc] = v;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     } else {
-      val = make_double2((a == b && L == Lp) ? 1.0 : 0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int L = Lr + 4 * r;
+        const double2 v = make_double2((a == b && L == Lc) ? 1.0 : 0.0, 0.0);
+        st2(work + jd.a_off + base + (int64_t)L * jd.npad + Lc, v);
+        if (m64) m64[jd.m_off + base + (int64_t)L * jd.npad + Lc] = v;
+      }
     }
-    const int64_t idx = base + (int64_t)L * jd.npad;
-    st2(work + idx, val);
-    if (m64) m64[jd.m_off + (int64_t)(a * NL + L) * jd.npad + b * NL + Lp] = val;
   }
 }
 
 void launch_assemble_f64(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
                          const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, double2* work,
                          hipStream_t s) {
-  int nbp = npad_max / NL;
-  dim3 grid((nbp * nbp + 3) / 4, njobs);
+  const int nbp = npad_max / NL;
+  dim3 grid((nbp * nbp + 63) / 64, njobs);
   assemble_kernel<double2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, nullptr);
 }
 
 void launch_assemble_split(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
                            const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, float2* work,
                            double2* m64, hipStream_t s) {
-  int nbp = npad_max / NL;
-  dim3 grid((nbp * nbp + 3) / 4, njobs);
+  const int nbp = npad_max / NL;
+  dim3 grid((nbp * nbp + 63) / 64, njobs);
   assemble_kernel<float2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, m64);
 }
 
