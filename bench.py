@@ -75,7 +75,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gemm-tiling", type=int, default=-1,
-                    help="tiling of the split-mode trailing update (-1: library default)")
+                    help="tiling of the split-mode trailing update (-1: autotune, unless --no-autotune)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tiling")
+    ap.add_argument("--graphs", action="store_true", help="replay factorization + solve from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy before the timed region (scale for HBM counters)")
     args = ap.parse_args()
@@ -101,6 +103,13 @@ def main():
     J = torch.from_numpy(np.ascontiguousarray(w["J"])).to(dev)
     ctx = P.Context(0)
     ctx.set_gemm_tiling(args.gemm_tiling)
+    tune = None
+    if args.gemm_tiling < 0 and not args.no_autotune and args.precision == "split":
+        npad_max = int(-(-16 * int(np.diff(liz.ptr).max()) // 64) * 64)
+        best, ms = ctx.autotune(npad_max, batch=256)
+        tune = {"npad": npad_max, "batch": 256, "best": best, "ms_per_tiling": [round(m, 3) for m in ms]}
+        log("autotuned tiling %d for npad %d: %s ms" % (best, npad_max, tune["ms_per_tiling"]))
+    ctx.set_graphs(args.graphs)
     n_atoms = liz.n_atoms
     tp = torch.empty((liz.total, 16, 16), dtype=torch.complex128, device=dev)
     tm = torch.empty_like(tp)
@@ -157,11 +166,13 @@ def main():
            "config": {"workload": "%s: %s, %d atoms, LIZ %d-%d atoms, lmax 3, eF %.2f Ry, eta cycling %s Ry"
                       % (w["name"], w["lattice"], n_atoms, int(n_true.min() / 16), int(n_true.max() / 16),
                          w["e_fermi"], etas),
-                      "precision": args.precision, "gemm_tiling": ctx.gemm_tiling(),
+                      "precision": args.precision, "gemm_tiling": ctx.gemm_tiling(), "graphs": args.graphs,
                       "parallelism": "single GPU, all atoms batched"},
            "path_tflops_alg": alg_flops_step * args.steps / elapsed / 1e12,
            "path_frac_of_peak": alg_flops_step * args.steps / elapsed / peak,
            "info_nonzero": int((info_np != 0).sum())}
+    if tune is not None:
+        out["autotune"] = tune
     if gemm_launches:
         avg_s = gemm_ms / gemm_launches / 1e3
         achieved = gemm_flops / gemm_launches / avg_s

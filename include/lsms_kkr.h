@@ -221,8 +221,28 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  */
 #define LSMS_TUNE_GEMM_F32 0
 #define LSMS_GEMM_F32_VARIANTS 7
+/*
+ * knob LSMS_TUNE_GRAPHS (0 or 1, default 0): with 1, lsms_tau_solve captures each wave's
+ * factorization and first solve (a fixed sequence of a few hundred launches) into a HIP
+ * graph on a stream of its own the first time a wave shape and buffer set occurs, and from
+ * then on replays that graph on the caller's stream.  Results are bitwise those of the
+ * eager launches.  Graphs are not used while profiling is on.
+ */
+#define LSMS_TUNE_GRAPHS 1
 int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
 int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
+
+/*
+ * Autotuner for the split-mode trailing update: times every tiling on the widest update
+ * of an LU of size npad (K = 128 over the trailing (npad - 128)^2 block) for a synthetic
+ * batch of `batch` systems (bounded random FP32 values, allocated and freed by the call,
+ * npad^2 * 8 * batch bytes), then makes the fastest the context's tiling (as
+ * lsms_set_tuning would).  *best receives it; ms (NULL, or host [LSMS_GEMM_F32_VARIANTS])
+ * the best-of-three launch time of each tiling.  npad: a multiple of 64 in (128, 4096];
+ * batch in [1, 65535].  Synchronous on hip_stream; LSMS_E_ARG for bad sizes,
+ * LSMS_E_NOMEM if the batch cannot be allocated.
+ */
+int lsms_autotune(lsms_ctx* ctx, int npad, int batch, int* best, float* ms, void* hip_stream);
 int lsms_kernel_stats(lsms_ctx* ctx, int kind, double* total_ms, int64_t* launches, double* alg_flops,
                       double* alg_bytes);
 

@@ -48,6 +48,7 @@ _PROTOS = {
     "lsms_set_profiling": (c_int, [c_void_p, c_int]),
     "lsms_set_tuning": (c_int, [c_void_p, c_int, c_int]),
     "lsms_get_tuning": (c_int, [c_void_p, c_int, P(c_int)]),
+    "lsms_autotune": (c_int, [c_void_p, c_int, c_int, P(c_int), P(ctypes.c_float), c_void_p]),
     "lsms_kernel_stats": (c_int, [c_void_p, c_int, P(c_double), P(c_int64), P(c_double), P(c_double)]),
 }
 

@@ -173,6 +173,18 @@ class Context:
         """Tiling of the split-mode trailing update (-1: library default)."""
         check(lib().lsms_set_tuning(self._h, 0, int(variant)))
 
+    def set_graphs(self, on=True):
+        """Replay each wave's factorization and first solve from captured HIP graphs."""
+        check(lib().lsms_set_tuning(self._h, 1, 1 if on else 0))
+
+    def autotune(self, npad, batch=256):
+        """Time every split-mode tiling for systems of padded size npad on a synthetic batch
+        and adopt the fastest; returns (best tiling, [ms per tiling])."""
+        best = ctypes.c_int(-1)
+        ms = (ctypes.c_float * 7)()
+        check(lib().lsms_autotune(self._h, int(npad), int(batch), ctypes.byref(best), ms, _stream()))
+        return best.value, [float(x) for x in ms]
+
     def gemm_tiling(self):
         v = ctypes.c_int(0)
         check(lib().lsms_get_tuning(self._h, 0, ctypes.byref(v)))

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -92,6 +93,9 @@ struct lsms_ctx {
   int device = 0;
   bool profiling = false;
   int gemm_f32 = -1;  // tiling of the split-mode trailing update, -1: library default
+  bool graphs = false;  // replay each wave's factorization + first solve from a HIP graph
+  hipStream_t capture = nullptr;  // non-blocking stream the graphs are captured on
+  std::map<std::vector<intptr_t>, hipGraphExec_t> graph_cache;
   EventProf prof;
   std::vector<int> n_true;
   size_t workspace_limit = 0;
@@ -265,6 +269,8 @@ extern "C" int lsms_destroy(lsms_ctx* ctx) {
   if (ctx->pinned) hipHostFree(ctx->pinned);
   if (ctx->pinned_flag) hipHostFree(ctx->pinned_flag);
   if (ctx->fallback.p) hipFree(ctx->fallback.p);
+  for (auto& kv : ctx->graph_cache) hipGraphExecDestroy(kv.second);
+  if (ctx->capture) hipStreamDestroy(ctx->capture);
   delete ctx;
   return LSMS_OK;
 }
@@ -492,6 +498,49 @@ void launch_zero_i32(int32_t* p, int n, hipStream_t s);
 // ---------------------------------------------------------------------------------
 // tau solve
 // ---------------------------------------------------------------------------------
+// Factorization + first solve of one wave: a fixed launch sequence whose arguments depend
+// only on the wave's shape and buffers, so with graphs on it is captured once (on the
+// context's own non-blocking stream, nothing runs during capture) and replayed on the
+// caller's stream whenever the same shape and buffers come back.  Job descriptors, matrices
+// and right-hand sides are read from device memory at replay, after the caller's stream has
+// written them.
+static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int nj, int npad_max, void* abuf,
+                            int32_t* piv, int32_t* jinfo, double2* xbuf, GemmProfiler* prof, hipStream_t s) {
+  const int variant = gemm_f32_variant(ctx);
+  auto issue = [&](hipStream_t q, GemmProfiler* pr) {
+    if (precision == LSMS_FP64) {
+      lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, q, pr);
+      lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, q);
+    } else {
+      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant);
+      lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, q);
+    }
+  };
+  if (!ctx->graphs || prof) {
+    issue(s, prof);
+    HIP_TRY(hipGetLastError());
+    return LSMS_OK;
+  }
+  const std::vector<intptr_t> key = {precision, nj, npad_max, variant, (intptr_t)jd, (intptr_t)abuf,
+                                     (intptr_t)piv, (intptr_t)jinfo, (intptr_t)xbuf};
+  auto it = ctx->graph_cache.find(key);
+  if (it == ctx->graph_cache.end()) {
+    if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    issue(ctx->capture, nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->capture, &g);
+    if (e != hipSuccess || !g) return fail(LSMS_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(LSMS_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    it = ctx->graph_cache.emplace(key, ex).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, s));
+  return LSMS_OK;
+}
+
 extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
                               const double* liz_pos, const double* phase, double e_fermi, double eta, int precision,
                               double refine_tol, int max_refine, void* tau_plus, void* tau_minus, int32_t* info,
@@ -628,14 +677,14 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     launch_init_rhs(jd, nj, npad_max, liz_atom, tpm, xbuf, s);
     if (precision == LSMS_FP64) {
       launch_assemble_f64(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (double2*)abuf, s);
-      lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, s, prof);
-      lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
+      rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s);
+      if (rc) return rc;
       launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, s);
       launch_write_status(jd, nj, jinfo, nullptr, info, berr, s);
     } else {
       launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, m64, s);
-      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, s, prof, gemm_f32_variant(ctx));
-      lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
+      rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s);
+      if (rc) return rc;
       launch_zero_i32(jdone, nj, s);
       launch_zero(jnorm, 8 * (int64_t)nj, s);
       int left = nj;
@@ -732,6 +781,11 @@ extern "C" int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* li
 
 extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
   if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  if (knob == LSMS_TUNE_GRAPHS) {
+    if (value != 0 && value != 1) return fail(LSMS_E_ARG, "graphs must be 0 or 1 (got %d)", value);
+    ctx->graphs = value == 1;
+    return LSMS_OK;
+  }
   if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);
   if (value < -1 || value >= gemm_f32_variants())
     return fail(LSMS_E_ARG, "gemm_f32 tiling %d outside [-1, %d)", value, gemm_f32_variants());
@@ -741,8 +795,29 @@ extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
 
 extern "C" int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value) {
   if (!ctx || !value) return fail(LSMS_E_ARG, "NULL argument");
+  if (knob == LSMS_TUNE_GRAPHS) {
+    *value = ctx->graphs ? 1 : 0;
+    return LSMS_OK;
+  }
   if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);
   *value = gemm_f32_variant(ctx);
+  return LSMS_OK;
+}
+
+extern "C" int lsms_autotune(lsms_ctx* ctx, int npad, int batch, int* best, float* ms, void* hip_stream) {
+  if (!ctx || !best) return fail(LSMS_E_ARG, "NULL argument");
+  if (npad % PAD != 0 || npad <= 2 * NB || npad > NL * LSMS_MAX_LIZ)
+    return fail(LSMS_E_ARG, "npad %d must be a multiple of %d in (%d, %d]", npad, PAD, 2 * NB, NL * LSMS_MAX_LIZ);
+  if (batch < 1 || batch > 65535) return fail(LSMS_E_ARG, "batch %d outside [1, 65535]", batch);
+  HIP_TRY(hipSetDevice(ctx->device));
+  float t[LSMS_GEMM_F32_VARIANTS];
+  int b = -1;
+  if (gemm_f32_autotune(npad, batch, (hipStream_t)hip_stream, t, &b) != 0 || b < 0)
+    return fail(LSMS_E_NOMEM, "autotuning batch of %d systems of size %d could not run", batch, npad);
+  ctx->gemm_f32 = b;
+  *best = b;
+  if (ms)
+    for (int v = 0; v < LSMS_GEMM_F32_VARIANTS; ++v) ms[v] = t[v];
   return LSMS_OK;
 }
 

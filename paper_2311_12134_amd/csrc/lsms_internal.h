@@ -124,6 +124,9 @@ struct GemmProfiler {
 void launch_gemm_f64(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin, int c_begin,
                      int c_end, double2* work, hipStream_t s);
 int gemm_f32_variants();
+// Times every FP32 tiling on a synthetic batch (batch systems of size npad, widest update);
+// ms[variant] receives the best of three launches, *best the fastest.  Returns 0 or -1.
+int gemm_f32_autotune(int npad, int batch, hipStream_t s, float* ms, int* best);
 void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                      int c_begin, int c_end, float2* work, hipStream_t s);
 

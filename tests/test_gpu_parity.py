@@ -281,3 +281,47 @@ def test_split_refinement_reaches_tolerance_quickly(lctx):
     w = synthetic.workload("bcc250")
     g = _run(lctx, w, w["etas"][0], precision="split", refine_tol=1e-14, max_refine=3, per_atom=False)
     assert (g["info"] == 0).all() and (g["berr"] <= 1e-14).all()
+
+
+@pytest.mark.parametrize("name,precision", [("fcc32", "fp64"), ("fcc32", "split"), ("bcc1940", "split")])
+def test_graph_replay_matches_eager(lctx, name, precision):
+    """Graph-captured factorization + first solve, replayed three times with eager work and
+    synchronizations in between, gives bitwise the eager result every time."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload(name)
+    eta = w["etas"][0]
+    dev = torch.device("cuda", 0)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp = liz.to_device(dev)
+    phase = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(dev)
+    species = torch.from_numpy(w["species"].astype(np.int32)).to(dev)
+    J = torch.from_numpy(np.ascontiguousarray(w["J"])).to(dev)
+    print("[gpu] graphs %s %s" % (name, precision), flush=True)
+
+    def solve():
+        tp, tm, info, berr = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
+        sig, _, _ = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"])
+        torch.cuda.synchronize()
+        return tp.cpu().numpy(), tm.cpu().numpy(), info.cpu().numpy(), sig.cpu().numpy()
+
+    ref = solve()
+    assert (ref[2] == 0).all()
+    lctx.set_graphs(True)
+    try:
+        for rep in range(3):
+            got = solve()
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), (name, precision, rep)
+    finally:
+        lctx.set_graphs(False)
+
+
+def test_autotune_picks_fastest_tiling(lctx):
+    best, ms = lctx.autotune(npad=448, batch=32)
+    assert 0 <= best < 7
+    assert all(np.isfinite(m) and m > 0 for m in ms)
+    assert ms[best] == min(ms)
+    try:
+        assert lctx.gemm_tiling() == best
+    finally:
+        lctx.set_gemm_tiling(-1)
