@@ -71,6 +71,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   __shared__ double2 s_drow[2][IB];
   __shared__ int s_piv[IB];
   __shared__ double2 s_L11[IB][IB];
+  __shared__ double2 s_Li[IB][IB];
   __shared__ double2 s_U[IB][NB];
   __shared__ int s_pivall[NB];
   __shared__ int s_pos[PERM_MAX], s_org[PERM_MAX];
@@ -241,26 +242,45 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
     __syncthreads();
     const int w = k + NB - cl - IB;  // panel columns right of the leaf
     if (w > 0) {
-      // U rows of the leaf: forward substitution with the leaf's unit lower triangle,
-      // one column per thread, in place in s_U
+      // U rows of the leaf, U = L11^-1 A[cl .. cl+IB, right of the leaf]: the first IB
+      // threads each form one column of the inverse of the leaf's unit lower triangle in
+      // registers, then every output is an independent dot product
       for (int idx = t; idx < IB * w; idx += PT) {
         const int q = idx / w, cc = idx - q * w;
         s_U[q][cc] = ld2(A + (cl + q) * ld + cl + IB + cc);
       }
-      __syncthreads();
-      for (int cc = t; cc < w; cc += PT) {
+      if (t < IB) {  // column t of the inverse, row by row (each thread reads only its column)
 #pragma unroll 1
-        for (int q = 1; q < IB; ++q) {
-          double2 u = s_U[q][cc];
+        for (int q = 0; q < IB; ++q) {
+          double2 acc = make_double2(q == t ? 1.0 : 0.0, 0.0);
 #pragma unroll 4
-          for (int pp = 0; pp < q; ++pp) u = cfms(u, s_L11[q][pp], s_U[pp][cc]);
-          s_U[q][cc] = u;
+          for (int pp = t; pp < q; ++pp) acc = cfms(acc, s_L11[q][pp], s_Li[pp][t]);
+          s_Li[q][t] = acc;
         }
       }
       __syncthreads();
-      for (int idx = t; idx < IB * w; idx += PT) {
-        const int q = idx / w, cc = idx - q * w;
-        st2(A + (cl + q) * ld + cl + IB + cc, s_U[q][cc]);
+      {
+        constexpr int OPT = (IB * (NB - IB) + PT - 1) / PT;  // outputs per thread at most
+        double2 res[OPT];
+#pragma unroll
+        for (int o = 0; o < OPT; ++o) {
+          const int idx = t + o * PT, q = idx / w, cc = idx - q * w;
+          double2 acc = make_double2(0.0, 0.0);
+          if (idx < IB * w) {
+            acc = s_U[q][cc];
+#pragma unroll
+            for (int pp = 0; pp < IB; ++pp)
+              if (pp < q) acc = cfma(acc, s_Li[q][pp], s_U[pp][cc]);
+            st2(A + (cl + q) * ld + cl + IB + cc, acc);
+          }
+          res[o] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < OPT; ++o) {
+          const int idx = t + o * PT, q = idx / w, cc = idx - q * w;
+          if (idx < IB * w) s_U[q][cc] = res[o];
+        }
       }
       __syncthreads();
       // rank-IB update of the panel right of the leaf, PT rows at a time with their L rows
@@ -492,6 +512,19 @@ static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int ro
                          int32_t* info, hipStream_t s) {
   constexpr int PT = 512;
   constexpr int IBW = sizeof(T) == sizeof(float2) ? 16 : 8;
+  if constexpr (sizeof(T) == sizeof(float2)) {
+    if (rows <= 3 * 256) {
+      // FP32 storage up to 768 rows: 256-thread workgroups with 8-wide leaves fit two jobs
+      // per CU, which hides more of the short panels' barrier and shuffle latency (past
+      // that the wider leaves of the 512-thread kernel win)
+      const int S2 = (rows + 255) / 256;
+      switch (S2) {
+        case 1: panel_kernel<T, 256, 1, 8><<<njobs, 256, 0, s>>>(jobs, k, left, work, piv, info); return;
+        case 2: panel_kernel<T, 256, 2, 8><<<njobs, 256, 0, s>>>(jobs, k, left, work, piv, info); return;
+        default: panel_kernel<T, 256, 3, 8><<<njobs, 256, 0, s>>>(jobs, k, left, work, piv, info); return;
+      }
+    }
+  }
   const int S = (rows + PT - 1) / PT;
   switch (S) {
     case 1: panel_kernel<T, PT, 1, IBW><<<njobs, PT, 0, s>>>(jobs, k, left, work, piv, info); break;
