@@ -170,15 +170,17 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, i
 // share L21 and U12 panels, run on the same XCD (workgroups are dealt to the eight XCDs
 // round-robin) and hit the same L2.
 // ------------------------------------------------------------------------------------
-template <int TM, int TN, int WM, int WN, bool XCD>
+template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false>
 __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, int tiles_x, int tiles_y, int k, int kd,
                                                          int r_begin, int c_begin, int c_end, float2* work) {
-  constexpr int KC = 16;
+  // KC: K chunk per LDS stage.  PFC: the wave's C elements are loaded two chunks before
+  // the end, so their latency overlaps the last chunks' MFMAs instead of the epilogue.
   constexpr int WAVES_N = TN / WN;
   static_assert((TM / WM) * (TN / WN) == 4, "four waves per workgroup");
   constexpr int BM = WM / 16, BN = WN / 16;
-  constexpr int AP = TM / 64;  // A passes: 64 rows x 16 k per pass, 4 complex per thread
-  constexpr int BP = TN / 64;  // B passes: 16 k x 64 columns per pass
+  constexpr int AQ = KC / 4, BQ = TN / 4;  // complex quads per row of the A / B stage
+  constexpr int AP = TM * AQ / 256;      // A passes, one quad per thread and pass
+  constexpr int BP = KC * BQ / 256;      // B passes
   constexpr int LA = TM + 16, LB = TN + 16;  // LDS row lengths (k-step offset of 32 banks)
 
   int T = blockIdx.x;
@@ -207,15 +209,15 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
   // share the swizzle, so the 16 rows a read touches stay consecutive
   auto aswz = [](int kk) { return ((kk >> 2) & 3) << 4; };
 
-  // global -> register staging of one chunk
-  const int ai = t >> 2, ak = (t & 3) * 4;  // A: row ai of each pass, k quad ak
+  // global -> register staging of one chunk: thread t takes quad t + 256 p of the A stage
+  // (row q / AQ, k 4 (q % AQ)) and of the B stage (k q / BQ, column 4 (q % BQ))
   float2 ra[AP][4], rb[BP][4];
   auto load = [&](int kc) {
 #pragma unroll
     for (int p = 0; p < AP; ++p) {
-      const int row = row0 + p * 64 + ai;
-      if (row0 + p * 64 < npad) {
-        const float4* src = (const float4*)(A + (int64_t)row * ld + k + kc + ak);
+      const int q = t + 256 * p, i = q / AQ, kk = (q % AQ) * 4, row = row0 + i;
+      if (row < npad) {
+        const float4* src = (const float4*)(A + (int64_t)row * ld + k + kc + kk);
         const float4 v0 = src[0], v1 = src[1];
         ra[p][0] = make_float2(v0.x, v0.y);
         ra[p][1] = make_float2(v0.z, v0.w);
@@ -228,8 +230,8 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
     }
 #pragma unroll
     for (int p = 0; p < BP; ++p) {
-      const int kk = t >> 4, j = p * 64 + (t & 15) * 4;
-      if (col0 + p * 64 < cmax) {
+      const int q = t + 256 * p, kk = q / BQ, j = (q % BQ) * 4;
+      if (col0 + j < cmax) {
         const float4* src = (const float4*)(A + (int64_t)(k + kc + kk) * ld + col0 + j);
         const float4 v0 = src[0], v1 = src[1];
         rb[p][0] = make_float2(v0.x, v0.y);
@@ -244,12 +246,14 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int p = 0; p < AP; ++p)
+    for (int p = 0; p < AP; ++p) {
+      const int q = t + 256 * p, i = q / AQ, kk = (q % AQ) * 4;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) sA[buf][ak + u][(p * 64 + ai) ^ aswz(ak + u)] = ra[p][u];
+      for (int u = 0; u < 4; ++u) sA[buf][kk + u][i ^ aswz(kk + u)] = ra[p][u];
+    }
 #pragma unroll
     for (int p = 0; p < BP; ++p) {
-      const int kk = t >> 4, j = p * 64 + (t & 15) * 4;
+      const int q = t + 256 * p, kk = q / BQ, j = (q % BQ) * 4;
 #pragma unroll
       for (int u = 0; u < 4; ++u) sB[buf][kk][j + u] = rb[p][u];
     }
@@ -270,9 +274,24 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
   store(0);
   __syncthreads();
   int cur = 0;
+  float2 cpre[PFC ? BM : 1][PFC ? BN : 1][4];
+  auto load_c = [&]() {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const int rbase = row0 + wm * WM + i * 16, cbase = col0 + wn * WN + j * 16;
+        const bool ok = rbase < npad && cbase < cmax;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          cpre[PFC ? i : 0][PFC ? j : 0][r] =
+              ok ? A[(int64_t)(rbase + 4 * kq + r) * ld + cbase + ii] : make_float2(0.f, 0.f);
+      }
+  };
   for (int kc = 0; kc < kd; kc += KC) {
     const bool more = kc + KC < kd;
     if (more) load(kc + KC);
+    if (PFC && kc == (kd > 2 * KC ? kd - 2 * KC : 0)) load_c();
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
       float2 a[BM], b[BN];
@@ -311,7 +330,7 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           float2* cp = A + (int64_t)(rbase + 4 * kq + r) * ld + cbase + ii;
-          float2 cv = *cp;
+          float2 cv = PFC ? cpre[PFC ? i : 0][PFC ? j : 0][r] : *cp;
           cv.x -= t1[i][j][r] - t2[i][j][r];
           cv.y -= t3[i][j][r] - t1[i][j][r] - t2[i][j][r];
           *cp = cv;
@@ -326,16 +345,16 @@ void launch_gemm_f64(const JobDesc* jobs, int njobs, int rows, int cols, int k, 
   gemm_f64_kernel<<<grid, 256, 0, s>>>(jobs, k, kd, r_begin, c_begin, c_end, work);
 }
 
-template <int TM, int TN, int WM, int WN, bool XCD>
+template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false>
 static void launch_tiled(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                          int c_begin, int c_end, float2* work, hipStream_t s) {
   const int tx = (cols + TN - 1) / TN, ty = (rows + TM - 1) / TM;
   const int64_t n = (int64_t)tx * ty * njobs;
-  gemm_f32_3m_tiled<TM, TN, WM, WN, XCD><<<(unsigned)n, 256, 0, s>>>(jobs, tx, ty, k, kd, r_begin, c_begin, c_end,
-                                                                     work);
+  gemm_f32_3m_tiled<TM, TN, WM, WN, XCD, KC, PFC><<<(unsigned)n, 256, 0, s>>>(jobs, tx, ty, k, kd, r_begin, c_begin,
+                                                                              c_end, work);
 }
 
-int gemm_f32_variants() { return 7; }
+int gemm_f32_variants() { return 9; }
 
 void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                      int c_begin, int c_end, float2* work, hipStream_t s) {
@@ -346,6 +365,8 @@ void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int 
     case 4: launch_tiled<64, 128, 64, 32, true>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
     case 5: launch_tiled<128, 128, 64, 64, true>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
     case 6: launch_tiled<128, 128, 64, 64, false>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
+    case 7: launch_tiled<64, 64, 32, 32, true, 16, true>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
+    case 8: launch_tiled<64, 64, 32, 32, true, 32, false>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
     default: {
       dim3 grid(cols / 64, rows / 64, njobs);
       gemm_f32_3m_kernel<<<grid, 256, 0, s>>>(jobs, k, kd, r_begin, c_begin, c_end, work);

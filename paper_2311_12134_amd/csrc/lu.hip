@@ -379,35 +379,58 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
 }
 
 // ------------------------------------------------------------------------------------
-// inverse of the panel's unit lower triangle, in place
+// inverses of the panel's diagonal triangles, in place
 // ------------------------------------------------------------------------------------
-// After panel(k) the strictly lower part of the diagonal block holds L11.  One workgroup
-// per job solves L11 X = I (each wavefront 16 columns, FP64 shuffle substitution, tri.h)
-// and overwrites that part with X = L11^-1 (unit diagonal implied).  Every later use of
-// the block wants the inverse: U12 = L11^-1 A12 in swap_trsm_kernel and the diagonal
-// steps of the solves, which thereby become products on the matrix cores.  No later
-// interchange touches the block (pivots of later panels lie below it).
+// After panel(k) the diagonal block holds L11 (strictly lower, unit diagonal implied) and
+// U11 (upper with diagonal).  One workgroup per job solves L11 X = I and U11 Y = I (four
+// wavefronts of 16 columns each per triangle, FP64 shuffle substitution, tri.h) and overwrites the block with
+// X = L11^-1 below the diagonal and Y = U11^-1 on and above it.  Every later use of the
+// block wants an inverse: U12 = L11^-1 A12 in swap_trsm_kernel and the four diagonal steps
+// of the solves, which thereby become products on the matrix cores.  No later interchange
+// touches the block (pivots of later panels lie below it), and nothing else reads U11.
 template <typename T>
-__global__ __launch_bounds__(256) void linv_kernel(const JobDesc* jobs, int k, T* work) {
+__global__ __launch_bounds__(512) void linv_kernel(const JobDesc* jobs, int k, T* work) {
   const JobDesc jd = jobs[blockIdx.x];
   if (k >= jd.npad) return;  // uniform
   T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   typedef typename LdsOf<T>::type S;
+  // FP32 storage: both inverses at once (waves 0-3 L11, 4-7 U11, 100 KB of LDS); FP64
+  // storage: one after the other in two arrays (133 KB), waves 4-7 idle
+  constexpr bool BOTH = sizeof(S) == sizeof(float2);
   __shared__ S s_T[NB][NB + 1];
   __shared__ S s_X[NB][NB + 1];
-  for (int idx = t; idx < NB * NB; idx += 256) {
+  __shared__ S s_Y[BOTH ? NB : 1][NB + 1];
+  for (int idx = t; idx < NB * NB; idx += 512) {
     const int q = idx / NB, pp = idx % NB;
-    st2(&s_T[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(0.0, 0.0));
+    s_T[q][pp] = A[(k + q) * ld + k + pp];
+    st2(&s_X[q][pp], make_double2(q == pp ? 1.0 : 0.0, 0.0));
+    if (BOTH) st2(&s_Y[BOTH ? q : 0][pp], make_double2(q == pp ? 1.0 : 0.0, 0.0));
+  }
+  __syncthreads();
+  // the substitutions read only the triangle they need (tri.h)
+  if (wave < 4) tri_unit_lower<16>(&s_T[0][0], NB + 1, &s_X[0][0], NB + 1, wave * 16, lane);
+  if (BOTH && wave >= 4) tri_upper<16>(&s_T[0][0], NB + 1, &s_Y[0][0], NB + 1, (wave - 4) * 16, lane);
+  __syncthreads();
+  if (BOTH) {
+    for (int idx = t; idx < NB * NB; idx += 512) {
+      const int q = idx / NB, pp = idx % NB;
+      A[(k + q) * ld + k + pp] = pp < q ? s_X[q][pp] : s_Y[BOTH ? q : 0][pp];
+    }
+    return;
+  }
+  for (int idx = t; idx < NB * NB; idx += 512) {
+    const int q = idx / NB, pp = idx % NB;
+    if (pp < q) A[(k + q) * ld + k + pp] = s_X[q][pp];
     st2(&s_X[q][pp], make_double2(q == pp ? 1.0 : 0.0, 0.0));
   }
   __syncthreads();
-  tri_unit_lower<16>(&s_T[0][0], NB + 1, &s_X[0][0], NB + 1, wave * 16, lane);
+  if (wave < 4) tri_upper<16>(&s_T[0][0], NB + 1, &s_X[0][0], NB + 1, wave * 16, lane);
   __syncthreads();
-  for (int idx = t; idx < NB * NB; idx += 256) {
+  for (int idx = t; idx < NB * NB; idx += 512) {
     const int q = idx / NB, pp = idx % NB;
-    if (pp < q) st2(A + (k + q) * ld + k + pp, ld2(&s_X[q][pp]));
+    if (pp >= q) A[(k + q) * ld + k + pp] = s_X[q][pp];
   }
 }
 
@@ -582,13 +605,13 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
   };
   for (int k = 0; k < npad_max; k += 2 * NB) {
     launch_panel<T>(jobs, njobs, k, 0, npad_max - k, work, piv, info, s);
-    linv_kernel<T><<<njobs, 256, 0, s>>>(jobs, k, work);
+    linv_kernel<T><<<njobs, 512, 0, s>>>(jobs, k, work);
     const int rest = npad_max - k - NB;
     if (rest <= 0) break;
     swap_trsm_kernel<T, false><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, piv);
     timed_gemm(k, NB, k + NB, k + NB, k + 2 * NB);  // the second panel's columns
     launch_panel<T>(jobs, njobs, k + NB, NB, npad_max - k - NB, work, piv, info, s);
-    linv_kernel<T><<<njobs, 256, 0, s>>>(jobs, k + NB, work);
+    linv_kernel<T><<<njobs, 512, 0, s>>>(jobs, k + NB, work);
     const int rest2 = npad_max - k - 2 * NB;
     if (rest2 <= 0) break;
     swap_trsm_kernel<T, true><<<dim3(rest2 / 64, njobs), 256, 0, s>>>(jobs, k + NB, work, piv);

@@ -3,15 +3,15 @@
 //
 // The factorization is the product M = P_1^T L_1 P_2^T L_2 ... P_K^T L_K U of panel
 // permutations P_p and unit-lower panel factors L_p (stored in the panel's columns,
-// never re-permuted by later panels; the diagonal block of each L_p holds its inverse,
-// written by the factorization).  Hence
+// never re-permuted by later panels; the factorization leaves the inverses of the unit
+// lower and the upper diagonal triangles in each diagonal block).  Hence
 //   M X = B   :  X = U^-1 L_K^-1 P_K ... L_1^-1 P_1 B          (trans = 0)
 //   M^T X = B :  X = P_1^T L_1^-T ... P_K^T L_K^-T U^-T B      (trans = 1)
 // Every panel costs two launches over the whole batch:
 //   solve_diag_kernel    one workgroup per job: the panel's permutation as one gather of
-//                        at most 2 NB rows, then the NB x NB diagonal block: a product
-//                        with the stored inverse (L and L^T, FP64 MFMA) or the triangle
-//                        U solved by one wavefront with cross-lane shuffles (tri.h);
+//                        at most 2 NB rows, then the NB x NB diagonal block as a product
+//                        with the stored inverse (L11^-1, U11^-1 or their transposes) on
+//                        FP64 MFMA;
 //   solve_update_kernel  one workgroup per (64-row strip, job): the off-diagonal block
 //                        times the panel's NB solved rows, on FP64 MFMA 16x16x4 (four real
 //                        products per complex product) from LDS-staged tiles, so the
@@ -22,7 +22,6 @@
 // storage types of the factors.
 #include "lsms_internal.h"
 #include "strip_mma.h"
-#include "tri.h"
 
 namespace lsms {
 
@@ -87,28 +86,24 @@ __global__ __launch_bounds__(256) void solve_diag_kernel(const JobDesc* jobs, in
   const bool first = (k % (2 * NB)) == 0;
   const bool has_second = first && (k + NB < jd.npad);
   if (MODE == MODE_L && first) permute(k, false);
+  // the diagonal block holds L11^-1 below the diagonal (unit diagonal implied) and U11^-1 on
+  // and above it; the step is a product with the needed inverse (transposed for U^T, L^T)
   const bool upper = (MODE == MODE_U || MODE == MODE_UT);
   for (int idx = t; idx < NB * NB; idx += 256) {
     const int q = idx / NB, pp = idx % NB;
     if (upper)
       s_T[q][pp] = pp >= q ? A[(k + q) * ld + k + pp] : S{0, 0};
-    else  // the stored inverse of the unit lower triangle, unit diagonal made explicit
+    else
       st2(&s_T[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(pp == q ? 1.0 : 0.0, 0.0));
   }
   for (int idx = t; idx < NB * NRHS; idx += 256) s_X[idx / NRHS][idx % NRHS] = xrow(k + idx / NRHS)[idx % NRHS];
   __syncthreads();
-  if (upper) {
-    if (wave == 0) {
-      if (MODE == MODE_U) tri_upper<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
-      if (MODE == MODE_UT) tri_upper_trans<NRHS>(&s_T[0][0], NB + 1, &s_X[0][0], NRHS, 0, lane);
-    }
-    __syncthreads();
-    for (int idx = t; idx < NB * NRHS; idx += 256) xrow(k + idx / NRHS)[idx % NRHS] = s_X[idx / NRHS][idx % NRHS];
-  } else {
-    // X_P = L11^-1 X_P (MODE_L) or L11^-T X_P (MODE_LT); wave w writes rows 16w .. 16w+16
+  {
+    // wave w writes rows 16w .. 16w+16 of the panel
+    constexpr bool TRANS = (MODE == MODE_UT || MODE == MODE_LT);
     StripMma<double2, NRHS / 16> y;
     y.zero();
-    y.run([&](int i, int kk) { return MODE == MODE_L ? ld2(&s_T[wave * 16 + i][kk]) : ld2(&s_T[kk][wave * 16 + i]); },
+    y.run([&](int i, int kk) { return TRANS ? ld2(&s_T[kk][wave * 16 + i]) : ld2(&s_T[wave * 16 + i][kk]); },
           [&](int kk, int c) { return s_X[kk][c]; }, lane);
     const int ii = lane & 15;
 #pragma unroll
