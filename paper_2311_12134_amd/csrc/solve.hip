@@ -7,19 +7,23 @@
 // lower and the upper diagonal triangles in each diagonal block).  Hence
 //   M X = B   :  X = U^-1 L_K^-1 P_K ... L_1^-1 P_1 B          (trans = 0)
 //   M^T X = B :  X = P_1^T L_1^-T ... P_K^T L_K^-T U^-T B      (trans = 1)
-// Every panel costs two launches over the whole batch:
-//   solve_diag_kernel    one workgroup per job: the panel's permutation as one gather of
-//                        at most 2 NB rows, then the NB x NB diagonal block as a product
-//                        with the stored inverse (L11^-1, U11^-1 or their transposes) on
-//                        FP64 MFMA;
-//   solve_update_kernel  one workgroup per (64-row strip, job): the off-diagonal block
-//                        times the panel's NB solved rows, on FP64 MFMA 16x16x4 (four real
-//                        products per complex product) from LDS-staged tiles, so the
-//                        factors stream from HBM once per solve.
+// Panels come in pairs (k, k + NB) and every pair costs two launches over the whole batch:
+//   solve_pair_diag_kernel    one workgroup per job: the pair's permutations (gathers of at
+//                             most 2 NB rows), both NB x NB diagonal steps as products with
+//                             the stored inverses (or their transposes) and the coupling block
+//                             between the two panels, on FP64 MFMA;
+//   solve_pair_update_kernel  one workgroup per (64-row strip, job): the strip against the
+//                             pair's 2 NB solved rows (K = 128) on FP64 MFMA 16x16x4 (four real
+//                             products per complex product), operands read straight from the
+//                             factors (FP32 factors widened in registers) and the solution, so
+//                             the factors stream from HBM once per solve and the solution rows
+//                             are read and written once per pair.
 // The update is column-oriented (rows below for L and U^T, rows above for U) except for
-// L^T, whose panel rows need a sum over all rows below: there every strip adds its
-// partial product to the panel rows with FP64 atomics.  Arithmetic is FP64 for both
-// storage types of the factors.
+// L^T, whose pair rows need a sum over all rows below: there every strip adds its partial
+// product to the pair rows with FP64 atomics.  Arithmetic is FP64 for both storage types of
+// the factors.
+#include <type_traits>
+
 #include "lsms_internal.h"
 #include "strip_mma.h"
 
@@ -57,10 +61,44 @@ __device__ inline void apply_perm(const int32_t* lst, bool inverse, double2* X, 
   __syncthreads();
 }
 
+// ------------------------------------------------------------------------------------
+// pair solves: the panels of the factorization come in pairs (k, k + NB), k a multiple of
+// 2 NB (see lu_factor).  One launch per pair solves both diagonal blocks and the coupling
+// block between them; one launch per pair updates every other 64-row strip with K = 2 NB
+// (NB when the job's matrix ends after the first panel).  MFMA operands are read straight
+// from the factors and the solution rows (through the caches); no LDS stage, no barriers
+// in the update.
+// ------------------------------------------------------------------------------------
+
+// Element (q, p) of an operator on a panel's rows at kp, from the stored diagonal block:
+// the inverse of the unit lower triangle (unit diagonal implied) or of the upper one.
+template <typename T>
+__device__ inline double2 lower_inv(const T* A, int64_t ld, int kp, int q, int p) {
+  return p < q ? ld2(A + (int64_t)(kp + q) * ld + kp + p) : make_double2(p == q ? 1.0 : 0.0, 0.0);
+}
+template <typename T>
+__device__ inline double2 upper_inv(const T* A, int64_t ld, int kp, int q, int p) {
+  return p >= q ? ld2(A + (int64_t)(kp + q) * ld + kp + p) : make_double2(0.0, 0.0);
+}
+
+// Y (64 x NRHS) = op (64 x 64) Xin (64 x NRHS in LDS): wave w forms rows 16w .. 16w+16 and
+// hands each element to put(row, column, value).
+template <int NRHS, typename OP, typename PUT>
+__device__ inline void panel_product(OP op, const double2 (*xin)[NRHS], PUT put, int wave, int lane) {
+  StripMma<double2, NRHS / 16> y;
+  y.zero();
+  y.run([&](int i, int kk) { return op(wave * 16 + i, kk); }, [&](int kk, int c) { return xin[kk][c]; }, lane);
+  const int ii = lane & 15;
+#pragma unroll
+  for (int cb = 0; cb < NRHS / 16; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) put(wave * 16 + y.row(r, lane), cb * 16 + ii, y.value(cb, r));
+}
+
 template <typename T, int NRHS, int MODE>
-__global__ __launch_bounds__(256) void solve_diag_kernel(const JobDesc* jobs, int k, const T* work,
-                                                         const int32_t* piv, double2* xbuf, int64_t col_off,
-                                                         const int32_t* skip) {
+__global__ __launch_bounds__(256) void solve_pair_diag_kernel(const JobDesc* jobs, int k, const T* work,
+                                                              const int32_t* piv, double2* xbuf, int64_t col_off,
+                                                              const int32_t* skip) {
   const int job = blockIdx.x;
   if (skip && skip[job]) return;
   const JobDesc jd = jobs[job];
@@ -70,174 +108,190 @@ __global__ __launch_bounds__(256) void solve_diag_kernel(const JobDesc* jobs, in
   const int32_t* pv = piv + jd.piv_off;
   double2* X = xbuf + jd.x_off + col_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  constexpr int HELD = PERM_MAX * NRHS / 256;
-  typedef typename LdsOf<T>::type S;
-  __shared__ S s_T[NB][NB + 1];
-  __shared__ double2 s_X[NB][NRHS];
+  const bool second = k + NB < jd.npad;
+  const int k2 = k + NB;
+  __shared__ double2 s_a[NB][NRHS];
+  __shared__ double2 s_b[NB][NRHS];
   __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
   auto xrow = [&](int r) { return X + (int64_t)r * NRHS_MAX; };
-  auto permute = [&](int kp, bool inverse) {
-    apply_perm<NRHS>(pv + perm_off(jd.npad, kp), inverse, X, s_dst, s_src, t);
+  auto load = [&](double2 (*dst)[NRHS], int r0) {
+    for (int idx = t; idx < NB * NRHS; idx += 256) dst[idx / NRHS][idx % NRHS] = xrow(r0 + idx / NRHS)[idx % NRHS];
   };
-  // Panels come in pairs (first at multiples of 2 NB, see lu_factor): the first panel's
-  // L rows are stored after the second panel's permutation, so the forward solve applies
-  // that permutation right after the first triangle, and the transposed solve undoes both
-  // permutations after the first triangle.
-  const bool first = (k % (2 * NB)) == 0;
-  const bool has_second = first && (k + NB < jd.npad);
-  if (MODE == MODE_L && first) permute(k, false);
-  // the diagonal block holds L11^-1 below the diagonal (unit diagonal implied) and U11^-1 on
-  // and above it; the step is a product with the needed inverse (transposed for U^T, L^T)
-  const bool upper = (MODE == MODE_U || MODE == MODE_UT);
-  for (int idx = t; idx < NB * NB; idx += 256) {
-    const int q = idx / NB, pp = idx % NB;
-    if (upper)
-      s_T[q][pp] = pp >= q ? A[(k + q) * ld + k + pp] : S{0, 0};
-    else
-      st2(&s_T[q][pp], pp < q ? ld2(A + (k + q) * ld + k + pp) : make_double2(pp == q ? 1.0 : 0.0, 0.0));
-  }
-  for (int idx = t; idx < NB * NRHS; idx += 256) s_X[idx / NRHS][idx % NRHS] = xrow(k + idx / NRHS)[idx % NRHS];
-  __syncthreads();
-  {
-    // wave w writes rows 16w .. 16w+16 of the panel
-    constexpr bool TRANS = (MODE == MODE_UT || MODE == MODE_LT);
-    StripMma<double2, NRHS / 16> y;
-    y.zero();
-    y.run([&](int i, int kk) { return TRANS ? ld2(&s_T[kk][wave * 16 + i]) : ld2(&s_T[wave * 16 + i][kk]); },
-          [&](int kk, int c) { return s_X[kk][c]; }, lane);
-    const int ii = lane & 15;
-#pragma unroll
-    for (int cb = 0; cb < NRHS / 16; ++cb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) xrow(k + wave * 16 + y.row(r, lane))[cb * 16 + ii] = y.value(cb, r);
-  }
-  if (MODE == MODE_L && has_second) {
+  auto to_x = [&](int r0, bool keep) {  // result rows to the solution (and to s_b)
+    return [=](int row, int c, double2 v) {
+      xrow(r0 + row)[c] = v;
+      if (keep) s_b[row][c] = v;
+    };
+  };
+  // rows of s_a minus a product: each wave updates only its own rows, after its product
+  auto minus_into_a = [&](int row, int c, double2 v) { s_a[row][c] = csub(s_a[row][c], v); };
+  if (MODE == MODE_L) {
+    // P1, L1^-1, P2 (the first panel's L rows are stored after it), L21 coupling, L2^-1
+    apply_perm<NRHS>(pv + perm_off(jd.npad, k), false, X, s_dst, s_src, t);
+    load(s_a, k);
     __syncthreads();
-    permute(k + NB, false);
-  }
-  if (MODE == MODE_LT && first) {
+    panel_product<NRHS>([&](int q, int p) { return lower_inv(A, ld, k, q, p); }, s_a, to_x(k, true), wave, lane);
+    if (!second) return;
     __syncthreads();
-    if (has_second) permute(k + NB, true);
-    permute(k, true);
+    apply_perm<NRHS>(pv + perm_off(jd.npad, k2), false, X, s_dst, s_src, t);
+    load(s_a, k2);
+    __syncthreads();
+    panel_product<NRHS>([&](int q, int p) { return ld2(A + (int64_t)(k2 + q) * ld + k + p); }, s_b, minus_into_a,
+                        wave, lane);
+    __syncthreads();
+    panel_product<NRHS>([&](int q, int p) { return lower_inv(A, ld, k2, q, p); }, s_a, to_x(k2, false), wave, lane);
+  } else if (MODE == MODE_U) {
+    // U2^-1, U12 coupling, U1^-1
+    if (second) {
+      load(s_a, k2);
+      __syncthreads();
+      panel_product<NRHS>([&](int q, int p) { return upper_inv(A, ld, k2, q, p); }, s_a, to_x(k2, true), wave,
+                          lane);
+      __syncthreads();
+      load(s_a, k);
+      __syncthreads();
+      panel_product<NRHS>([&](int q, int p) { return ld2(A + (int64_t)(k + q) * ld + k2 + p); }, s_b,
+                          minus_into_a, wave, lane);
+    } else {
+      load(s_a, k);
+    }
+    __syncthreads();
+    panel_product<NRHS>([&](int q, int p) { return upper_inv(A, ld, k, q, p); }, s_a, to_x(k, false), wave, lane);
+  } else if (MODE == MODE_UT) {
+    // U1^-T, U12^T coupling, U2^-T
+    load(s_a, k);
+    __syncthreads();
+    panel_product<NRHS>([&](int q, int p) { return upper_inv(A, ld, k, p, q); }, s_a, to_x(k, true), wave, lane);
+    if (!second) return;
+    __syncthreads();
+    load(s_a, k2);
+    __syncthreads();
+    panel_product<NRHS>([&](int q, int p) { return ld2(A + (int64_t)(k + p) * ld + k2 + q); }, s_b, minus_into_a,
+                        wave, lane);
+    __syncthreads();
+    panel_product<NRHS>([&](int q, int p) { return upper_inv(A, ld, k2, p, q); }, s_a, to_x(k2, false), wave,
+                        lane);
+  } else {
+    // MODE_LT: L2^-T, L21^T coupling, L1^-T, then P2^-1 and P1^-1
+    if (second) {
+      load(s_a, k2);
+      __syncthreads();
+      panel_product<NRHS>([&](int q, int p) { return lower_inv(A, ld, k2, p, q); }, s_a, to_x(k2, true), wave,
+                          lane);
+      __syncthreads();
+      load(s_a, k);
+      __syncthreads();
+      panel_product<NRHS>([&](int q, int p) { return ld2(A + (int64_t)(k2 + p) * ld + k + q); }, s_b,
+                          minus_into_a, wave, lane);
+    } else {
+      load(s_a, k);
+    }
+    __syncthreads();
+    panel_product<NRHS>([&](int q, int p) { return lower_inv(A, ld, k, p, q); }, s_a, to_x(k, false), wave, lane);
+    __syncthreads();
+    if (second) apply_perm<NRHS>(pv + perm_off(jd.npad, k2), true, X, s_dst, s_src, t);
+    apply_perm<NRHS>(pv + perm_off(jd.npad, k), true, X, s_dst, s_src, t);
   }
 }
 
-// One 64-row strip:  MODE_L   X[s] -= L[s, P] X[P]      (s below the panel P)
-//                    MODE_U   X[s] -= U[s, P] X[P]      (s above the panel)
-//                    MODE_UT  X[s] -= U[P, s]^T X[P]    (s below)
-//                    MODE_LT  X[P] -= L[s, P]^T X[s]    (s below; atomics into the panel rows)
-// out (64 x NRHS) = A (64 x NB) B (NB x NRHS) with K chunks of 32 staged in LDS.
+// One 64-row strip s against the pair's K = 2 NB rows (NB if the job ends after the first
+// panel):  MODE_L   X[s] -= L[s, pair] X[pair]      (s below the pair)
+//          MODE_U   X[s] -= U[s, pair] X[pair]      (s above)
+//          MODE_UT  X[s] -= U[pair, s]^T X[pair]    (s below)
+//          MODE_LT  X[pair] -= L[s, pair]^T X[s]    (s below; FP64 atomics into the pair rows)
+template <typename T, int NRHS, int MODE, int KD>
+__device__ inline void pair_update(const T* A, int64_t ld, double2* X, int k, int s0, int wave, int lane) {
+  auto xrow = [&](int r) { return X + (int64_t)r * NRHS_MAX; };
+  const int ii = lane & 15;
+  if (MODE == MODE_LT) {
+    // out rows = the pair's KD rows (KD / 16 blocks, dealt to the four waves), K = 64 strip rows
+    for (int rb = wave; rb < KD / 16; rb += 4) {
+      StripMma<double2, NRHS / 16> y;
+      y.zero();
+      y.run([&](int i, int kk) { return ld2(A + (int64_t)(s0 + kk) * ld + k + rb * 16 + i); },
+            [&](int kk, int c) { return xrow(s0 + kk)[c]; }, lane);
+#pragma unroll
+      for (int cb = 0; cb < NRHS / 16; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double2* xp = xrow(k + rb * 16 + y.row(r, lane)) + cb * 16 + ii;
+          const double2 v = y.value(cb, r);
+          atomicAdd(&xp->x, -v.x);
+          atomicAdd(&xp->y, -v.y);
+        }
+    }
+    return;
+  }
+  StripMma<double2, NRHS / 16, KD> y;
+  y.zero();
+  const int r0 = s0 + wave * 16;
+  y.run(
+      [&](int i, int kk) {
+        return MODE == MODE_UT ? ld2(A + (int64_t)(k + kk) * ld + r0 + i) : ld2(A + (int64_t)(r0 + i) * ld + k + kk);
+      },
+      [&](int kk, int c) { return xrow(k + kk)[c]; }, lane);
+#pragma unroll
+  for (int cb = 0; cb < NRHS / 16; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double2* xp = xrow(r0 + y.row(r, lane)) + cb * 16 + ii;
+      *xp = csub(*xp, y.value(cb, r));
+    }
+}
+
 template <typename T, int NRHS, int MODE>
-__global__ __launch_bounds__(256) void solve_update_kernel(const JobDesc* jobs, int k, const T* work,
-                                                           double2* xbuf, int64_t col_off, const int32_t* skip) {
+__global__ __launch_bounds__(256) void solve_pair_update_kernel(const JobDesc* jobs, int k, const T* work,
+                                                                double2* xbuf, int64_t col_off, const int32_t* skip) {
   const int job = blockIdx.y;
   if (skip && skip[job]) return;
   const JobDesc jd = jobs[job];
-  const int s0 = (MODE == MODE_U) ? blockIdx.x * 64 : k + NB + blockIdx.x * 64;  // strip rows
   if (k >= jd.npad) return;
+  const int s0 = (MODE == MODE_U) ? blockIdx.x * 64 : k + 2 * NB + blockIdx.x * 64;
   if (MODE == MODE_U ? (s0 >= k) : (s0 >= jd.npad)) return;  // uniform
   const T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
   double2* X = xbuf + jd.x_off + col_off;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  constexpr int KC = 32;
-  constexpr int CB = NRHS / 16;  // 16-column output blocks per wave
-  typedef typename LdsOf<T>::type S;
-  __shared__ S sA[KC][64 + 1];            // sA[kk][o]: A[o][k0 + kk] for output row o
-  __shared__ double2 sB[NB][NRHS + 1];    // right-hand operand, NB x NRHS
-  // right-hand operand: the panel rows (L, U, UT) or the strip rows (LT)
-  const int brow = (MODE == MODE_LT) ? s0 : k;
-  for (int idx = t; idx < NB * NRHS; idx += 256)
-    sB[idx / NRHS][idx % NRHS] = X[(int64_t)(brow + idx / NRHS) * NRHS_MAX + idx % NRHS];
-  d4 are[CB], aim[CB];
-#pragma unroll
-  for (int cb = 0; cb < CB; ++cb) {
-    are[cb] = d4{0, 0, 0, 0};
-    aim[cb] = d4{0, 0, 0, 0};
-  }
-  const int ii = lane & 15, kq = lane >> 4;
-  for (int k0 = 0; k0 < NB; k0 += KC) {
-    __syncthreads();
-    // stage A[o][k0 .. k0+KC) for the 64 output rows o into sA[kk][o]
-    for (int idx = t; idx < KC * 64; idx += 256) {
-      if (MODE == MODE_L || MODE == MODE_U) {
-        const int o = idx / KC, kk = idx % KC;  // consecutive threads walk a row
-        sA[kk][o] = A[(int64_t)(s0 + o) * ld + k + k0 + kk];
-      } else if (MODE == MODE_UT) {
-        const int kk = idx / 64, o = idx % 64;  // U[k + k0 + kk][s0 + o]
-        sA[kk][o] = A[(int64_t)(k + k0 + kk) * ld + s0 + o];
-      } else {
-        const int kk = idx / 64, o = idx % 64;  // L[s0 + k0 + kk][k + o]: sum over strip rows
-        sA[kk][o] = A[(int64_t)(s0 + k0 + kk) * ld + k + o];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k4 = 0; k4 < KC; k4 += 4) {
-      const double2 a = ld2(&sA[k4 + kq][wave * 16 + ii]);
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        const double2 b = sB[k0 + k4 + kq][cb * 16 + ii];
-        are[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, are[cb], 0, 0, 0);
-        are[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, are[cb], 0, 0, 0);
-        aim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, aim[cb], 0, 0, 0);
-        aim[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, aim[cb], 0, 0, 0);
-      }
-    }
-  }
-  // D lane l, register r -> output row 16 wave + l/16 + 4r, column 16 cb + l%16
-  const int orow0 = (MODE == MODE_LT) ? k : s0;
-#pragma unroll
-  for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int o = wave * 16 + kq + 4 * r, c = cb * 16 + ii;
-      double2* xp = X + (int64_t)(orow0 + o) * NRHS_MAX + c;
-      if (MODE == MODE_LT) {
-        atomicAdd(&xp->x, -are[cb][r]);
-        atomicAdd(&xp->y, -aim[cb][r]);
-      } else {
-        double2 v = *xp;
-        v.x -= are[cb][r];
-        v.y -= aim[cb][r];
-        *xp = v;
-      }
-    }
-}
-
-template <typename T, int NRHS, int MODE>
-static void diag(const JobDesc* jobs, int njobs, int k, const T* work, const int32_t* piv, double2* x,
-                 int64_t col_off, const int32_t* skip, hipStream_t s) {
-  solve_diag_kernel<T, NRHS, MODE><<<njobs, 256, 0, s>>>(jobs, k, work, piv, x, col_off, skip);
-}
-
-template <typename T, int NRHS, int MODE>
-static void update(const JobDesc* jobs, int njobs, int k, int strips, const T* work, double2* x, int64_t col_off,
-                   const int32_t* skip, hipStream_t s) {
-  if (strips <= 0) return;
-  solve_update_kernel<T, NRHS, MODE><<<dim3(strips, njobs), 256, 0, s>>>(jobs, k, work, x, col_off, skip);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (MODE == MODE_U && k + NB >= jd.npad)
+    pair_update<T, NRHS, MODE, NB>(A, ld, X, k, s0, wave, lane);
+  else
+    pair_update<T, NRHS, MODE, 2 * NB>(A, ld, X, k, s0, wave, lane);
 }
 
 template <typename T, int NRHS>
 static void solve_all(const JobDesc* jobs, int njobs, int npad_max, const T* work, const int32_t* piv, double2* x,
                       int64_t col_off, int trans, const int32_t* skip, hipStream_t s) {
+  const int last = ((npad_max - 1) / (2 * NB)) * (2 * NB);  // start of the last pair
+  auto diag = [&](auto mode_tag, int k) {
+    constexpr int MODE = decltype(mode_tag)::value;
+    solve_pair_diag_kernel<T, NRHS, MODE><<<njobs, 256, 0, s>>>(jobs, k, work, piv, x, col_off, skip);
+  };
+  auto update = [&](auto mode_tag, int k, int strips) {
+    constexpr int MODE = decltype(mode_tag)::value;
+    if (strips <= 0) return;
+    solve_pair_update_kernel<T, NRHS, MODE><<<dim3(strips, njobs), 256, 0, s>>>(jobs, k, work, x, col_off, skip);
+  };
+  using L = std::integral_constant<int, MODE_L>;
+  using U = std::integral_constant<int, MODE_U>;
+  using UT = std::integral_constant<int, MODE_UT>;
+  using LT = std::integral_constant<int, MODE_LT>;
   if (!trans) {
-    for (int k = 0; k < npad_max; k += NB) {
-      diag<T, NRHS, MODE_L>(jobs, njobs, k, work, piv, x, col_off, skip, s);
-      update<T, NRHS, MODE_L>(jobs, njobs, k, (npad_max - k - NB) / 64, work, x, col_off, skip, s);
+    for (int k = 0; k < npad_max; k += 2 * NB) {
+      diag(L{}, k);
+      update(L{}, k, (npad_max - k - 2 * NB) / 64);
     }
-    for (int k = npad_max - NB; k >= 0; k -= NB) {
-      diag<T, NRHS, MODE_U>(jobs, njobs, k, work, piv, x, col_off, skip, s);
-      update<T, NRHS, MODE_U>(jobs, njobs, k, k / 64, work, x, col_off, skip, s);
+    for (int k = last; k >= 0; k -= 2 * NB) {
+      diag(U{}, k);
+      update(U{}, k, k / 64);
     }
   } else {
-    for (int k = 0; k < npad_max; k += NB) {
-      diag<T, NRHS, MODE_UT>(jobs, njobs, k, work, piv, x, col_off, skip, s);
-      update<T, NRHS, MODE_UT>(jobs, njobs, k, (npad_max - k - NB) / 64, work, x, col_off, skip, s);
+    for (int k = 0; k < npad_max; k += 2 * NB) {
+      diag(UT{}, k);
+      update(UT{}, k, (npad_max - k - 2 * NB) / 64);
     }
-    for (int k = npad_max - NB; k >= 0; k -= NB) {
-      update<T, NRHS, MODE_LT>(jobs, njobs, k, (npad_max - k - NB) / 64, work, x, col_off, skip, s);
-      diag<T, NRHS, MODE_LT>(jobs, njobs, k, work, piv, x, col_off, skip, s);
+    for (int k = last; k >= 0; k -= 2 * NB) {
+      update(LT{}, k, (npad_max - k - 2 * NB) / 64);
+      diag(LT{}, k);
     }
   }
 }
