@@ -161,6 +161,24 @@ int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, cons
                     void* hip_stream);
 
 /*
+ * Full conductivity tensor: Eq. (10) for every pair of Cartesian directions, with mu
+ * on the centre atom's current J^{m mu}(z2,z1) and nu on the member's J^{n nu}(z1,z2),
+ * then Eq. (7) for each (mu, nu):
+ *   s_m[c][mu][nu] = sum_{a in LIZ_m} Tr[ J^{m mu}(z2,z1) tau^{0a}(z1) J^{a nu}(z1,z2) tau^{a0}(z2) ]
+ *   sigma~[c][mu][nu] = -(1 / (pi * volume)) * sum_m s_m[c][mu][nu]
+ *   sigma[mu][nu]     = 1/4 (sigma~[++] - sigma~[+-] - sigma~[-+] + sigma~[--])   (real part)
+ * Arguments as for lsms_kubo_sigma, except the outputs:
+ *   sigma       device [3][3] double (out), row mu, column nu
+ *   sigma_tilde device [4][3][3] complex (out)
+ *   per_atom    device [n_atoms][4][3][3] complex (out) or NULL
+ * The diagonal equals lsms_kubo_sigma's sigma; the reduction order is fixed.
+ */
+int lsms_kubo_sigma_tensor(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
+                           const void* tau_plus, const void* tau_minus, const int32_t* species, int32_t n_species,
+                           const void* J, double volume, double* sigma, void* sigma_tilde, void* per_atom,
+                           void* hip_stream);
+
+/*
  * Adjoint of the whole path: gradient of L = sum_mu dsigma[mu] sigma_mu with
  * respect to every phase shift, d L / d phase[k][l].  Derived from Eq. (3)
  * (d tau = W dT W^T with W = (1 - T g)^-1) and Eq. (10): one transposed solve
@@ -231,6 +249,16 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * eager launches.  Graphs are not used while profiling is on.
  */
 #define LSMS_TUNE_GRAPHS 1
+/*
+ * knob LSMS_TUNE_CONJ_SYMMETRY (0 or 1, default 0): with 1, lsms_tau_solve factors and
+ * solves only the z+ = eF + i eta systems and writes tau(z-) from them as
+ * tau(z-)_{LL'} = (-1)^{l+l'} conj(tau(z+)_{LL'}), which holds exactly because
+ * kappa- = -conj(kappa+) and t(z-) = conj t(z+) make the structure constants of Eq. (3)
+ * at z- the parity-conjugate of those at z+ (Eq. (7) needs both energies).  Half the
+ * LU work; info and berr of z- repeat those of z+.  Ignored when factors are kept for
+ * the adjoint (lsms_kubo_sigma_grad needs both energies' factors).
+ */
+#define LSMS_TUNE_CONJ_SYMMETRY 2
 int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
 int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
 

@@ -19,9 +19,11 @@ paper by eye:
                   combination Eq. (7), and the all-site form Eq. (9).
 * ``adjoint``  -- d sigma / d phase-shift by forward differentiation of Eq. (3)
                   through a dense inverse.
+* ``resistivity`` -- rho = sigma^-1, the spin sum, and the LIZ-convergence fits
+                  of Eqs. (31)-(34).
 
 Every function is pinned by tests under ``tests/`` against closed forms,
 library special functions, brute force and invariants of the equations.
 """
 
-from . import special, liz, kkr, kubo, adjoint  # noqa: F401
+from . import special, liz, kkr, kubo, adjoint, resistivity  # noqa: F401

@@ -155,6 +155,23 @@ class Context:
                                     float(volume), _ptr(sig), _ptr(st), _ptr(pa), _stream()))
         return sig, st, pa
 
+    def kubo_sigma_tensor(self, liz, liz_atom_dev, tau_plus, tau_minus, species, J, volume, per_atom=False,
+                          out=None):
+        """sigma [3,3] (float64, row mu, column nu), sigma_tilde [4,3,3] (complex128), per-atom sums [N,4,3,3]."""
+        n = liz.n_atoms
+        assert species.dtype == torch.int32 and J.dtype == torch.complex128 and J.is_contiguous()
+        n_species = J.shape[0]
+        if out is None:
+            sig = torch.empty((3, 3), dtype=torch.float64, device=self.device)
+            st = torch.empty((4, 3, 3), dtype=torch.complex128, device=self.device)
+            pa = torch.empty((n, 4, 3, 3), dtype=torch.complex128, device=self.device) if per_atom else None
+        else:
+            sig, st, pa = out
+        check(lib().lsms_kubo_sigma_tensor(self._h, n, liz.ptr.ctypes.data_as(ctypes.c_void_p), _ptr(liz_atom_dev),
+                                           _ptr(tau_plus), _ptr(tau_minus), _ptr(species), n_species, _ptr(J),
+                                           float(volume), _ptr(sig), _ptr(st), _ptr(pa), _stream()))
+        return sig, st, pa
+
     def kubo_sigma_grad(self, factors, liz, liz_atom_dev, phase, tau_plus, tau_minus, species, J, volume, dsigma):
         n = liz.n_atoms
         dphase = torch.empty((n, 4), dtype=torch.float64, device=self.device)
@@ -176,6 +193,16 @@ class Context:
     def set_graphs(self, on=True):
         """Replay each wave's factorization and first solve from captured HIP graphs."""
         check(lib().lsms_set_tuning(self._h, 1, 1 if on else 0))
+
+    def set_conj_symmetry(self, on=True):
+        """Solve z+ only and derive tau(z-) = P conj tau(z+) P (P = diag((-1)^l)); not used
+        when factors are kept for the adjoint."""
+        check(lib().lsms_set_tuning(self._h, 2, 1 if on else 0))
+
+    def conj_symmetry(self):
+        v = ctypes.c_int(0)
+        check(lib().lsms_get_tuning(self._h, 2, ctypes.byref(v)))
+        return bool(v.value)
 
     def autotune(self, npad, batch=256):
         """Time every split-mode tiling for systems of padded size npad on a synthetic batch

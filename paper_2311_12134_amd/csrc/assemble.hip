@@ -270,19 +270,31 @@ void launch_init_rhs(const JobDesc* jobs, int njobs, int npad_max, const int32_t
 }
 
 // tau^{a0}_{LL'} = X[(a, L)][L'] for the first n rows.
-__global__ void copy_tau_kernel(const JobDesc* jobs, const double2* x, double2* tau_plus, double2* tau_minus) {
+__device__ inline int l_of(int L) { return L < 1 ? 0 : L < 4 ? 1 : L < 9 ? 2 : 3; }
+
+// With mirror set, only z+ jobs exist and each also writes the z- block
+// tau(z-)_{LL'} = (-1)^{l+l'} conj(tau(z+)_{LL'}): kappa- = -conj(kappa+) and
+// t(z-) = conj t(z+) give g(z-) = P conj(g(z+)) P, P = diag((-1)^l), hence
+// 1 - t g and its inverse times t transform the same way.
+__global__ void copy_tau_kernel(const JobDesc* jobs, const double2* x, double2* tau_plus, double2* tau_minus,
+                                int mirror) {
   const JobDesc jd = jobs[blockIdx.y];
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= jd.n * NL) return;
   int row = idx / NL, col = idx % NL;
   double2* out = jd.energy == 0 ? tau_plus : tau_minus;
-  out[jd.liz_off * NL * NL + idx] = x[jd.x_off + (int64_t)row * NRHS_MAX + col];
+  const double2 v = x[jd.x_off + (int64_t)row * NRHS_MAX + col];
+  out[jd.liz_off * NL * NL + idx] = v;
+  if (mirror) {
+    const double sg = ((l_of(row % NL) + l_of(col)) & 1) ? -1.0 : 1.0;
+    tau_minus[jd.liz_off * NL * NL + idx] = make_double2(sg * v.x, -sg * v.y);
+  }
 }
 
 void launch_copy_tau(const JobDesc* jobs, int njobs, int npad_max, const double2* x, double2* tau_plus,
-                     double2* tau_minus, hipStream_t s) {
+                     double2* tau_minus, bool mirror, hipStream_t s) {
   dim3 grid((npad_max * NL + 255) / 256, njobs);
-  copy_tau_kernel<<<grid, 256, 0, s>>>(jobs, x, tau_plus, tau_minus);
+  copy_tau_kernel<<<grid, 256, 0, s>>>(jobs, x, tau_plus, tau_minus, mirror ? 1 : 0);
 }
 
 __global__ void check_inputs_kernel(const JobDesc* jobs, const double* liz_pos, const int32_t* liz_atom,
@@ -305,17 +317,22 @@ void launch_check_inputs(const JobDesc* jobs, int njobs, const double* liz_pos, 
 }
 
 __global__ void write_status_kernel(const JobDesc* jobs, int njobs, const int32_t* job_info, const double* norms,
-                                    int32_t* info, double* berr) {
+                                    int32_t* info, double* berr, int mirror) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= njobs) return;
   const JobDesc jd = jobs[j];
+  const double b = norms ? norms[j * 8 + 3] : 0.0;
   info[jd.atom * 2 + jd.energy] = job_info[j];
-  berr[jd.atom * 2 + jd.energy] = norms ? norms[j * 8 + 3] : 0.0;
+  berr[jd.atom * 2 + jd.energy] = b;
+  if (mirror) {  // the z- result is the z+ one transformed: same status
+    info[jd.atom * 2 + 1] = job_info[j];
+    berr[jd.atom * 2 + 1] = b;
+  }
 }
 
 void launch_write_status(const JobDesc* jobs, int njobs, const int32_t* job_info, const double* norms,
-                         int32_t* info, double* berr, hipStream_t s) {
-  write_status_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(jobs, njobs, job_info, norms, info, berr);
+                         int32_t* info, double* berr, bool mirror, hipStream_t s) {
+  write_status_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(jobs, njobs, job_info, norms, info, berr, mirror ? 1 : 0);
 }
 
 __global__ void zero_kernel(double* p, int64_t n) {

@@ -94,6 +94,7 @@ struct lsms_ctx {
   bool profiling = false;
   int gemm_f32 = -1;  // tiling of the split-mode trailing update, -1: library default
   bool graphs = false;  // replay each wave's factorization + first solve from a HIP graph
+  bool conj_symmetry = false;  // solve z+ only and derive z- (tau(z-) = P conj tau(z+) P)
   hipStream_t capture = nullptr;  // non-blocking stream the graphs are captured on
   std::map<std::vector<intptr_t>, hipGraphExec_t> graph_cache;
   EventProf prof;
@@ -560,12 +561,14 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
   hipStream_t s = (hipStream_t)hip_stream;
   HIP_TRY(hipSetDevice(ctx->device));
 
-  // jobs, sorted by size (largest first) so each wave is nearly uniform
+  // jobs, sorted by size (largest first) so each wave is nearly uniform; with the
+  // conjugation symmetry (and no factors kept for the adjoint) only z+ is solved
+  const bool mirror = ctx->conj_symmetry && keep == nullptr;
   std::vector<JobDesc> jobs;
   jobs.reserve(2 * (size_t)n_atoms);
   for (int a = 0; a < n_atoms; ++a) {
     const int nl = (int)(liz_ptr[a + 1] - liz_ptr[a]);
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < (mirror ? 1 : 2); ++e) {
       JobDesc j{};
       j.liz_off = liz_ptr[a];
       j.atom = a;
@@ -679,8 +682,8 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
       launch_assemble_f64(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (double2*)abuf, s);
       rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s);
       if (rc) return rc;
-      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, s);
-      launch_write_status(jd, nj, jinfo, nullptr, info, berr, s);
+      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, s);
+      launch_write_status(jd, nj, jinfo, nullptr, info, berr, mirror, s);
     } else {
       launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, m64, s);
       rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s);
@@ -728,8 +731,8 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, s);
         }
       }
-      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, s);
-      launch_write_status(jd, nj, jinfo, jnorm, info, berr, s);
+      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, s);
+      launch_write_status(jd, nj, jinfo, jnorm, info, berr, mirror, s);
     }
     HIP_TRY(hipGetLastError());
   }
@@ -749,10 +752,10 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
 // ---------------------------------------------------------------------------------
 // Kubo-Greenwood sum
 // ---------------------------------------------------------------------------------
-extern "C" int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
-                               const void* tau_plus, const void* tau_minus, const int32_t* species, int32_t n_species,
-                               const void* J, double volume, double* sigma, void* sigma_tilde, void* per_atom,
-                               void* hip_stream) {
+static int kubo_sigma_common(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
+                             const void* tau_plus, const void* tau_minus, const int32_t* species, int32_t n_species,
+                             const void* J, double volume, double* sigma, void* sigma_tilde, void* per_atom,
+                             bool tensor, void* hip_stream) {
   if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
   int rc = validate_liz_ptr(n_atoms, liz_ptr);
   if (rc) return rc;
@@ -762,8 +765,9 @@ extern "C" int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* li
   if (!(volume > 0.0) || !std::isfinite(volume)) return fail(LSMS_E_ARG, "volume must be positive");
   hipStream_t s = (hipStream_t)hip_stream;
   HIP_TRY(hipSetDevice(ctx->device));
+  const int nq = tensor ? 36 : 12;
   const int64_t off_pa = align_up((int64_t)(n_atoms + 1) * 8, 256);
-  const int64_t bytes = off_pa + align_up((int64_t)n_atoms * 12 * 16, 256);
+  const int64_t bytes = off_pa + align_up((int64_t)n_atoms * nq * 16, 256);
   rc = ensure_pinned(ctx, (size_t)(n_atoms + 1) * 8, s);
   if (rc) return rc;
   rc = ensure_dev(ctx->small, (size_t)bytes, s);
@@ -773,17 +777,33 @@ extern "C" int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* li
   double2* pa = per_atom ? (double2*)per_atom : (double2*)((char*)ctx->small.p + off_pa);
   HIP_TRY(hipMemcpyAsync(ptr_dev, ctx->pinned, (size_t)(n_atoms + 1) * 8, hipMemcpyHostToDevice, s));
   launch_kubo_trace(n_atoms, ptr_dev, liz_atom, (const double2*)tau_plus, (const double2*)tau_minus, species,
-                    n_species, (const double2*)J, pa, s);
-  launch_kubo_reduce(n_atoms, pa, volume, sigma, (double2*)sigma_tilde, s);
+                    n_species, (const double2*)J, pa, tensor, s);
+  launch_kubo_reduce(n_atoms, pa, volume, sigma, (double2*)sigma_tilde, tensor, s);
   HIP_TRY(hipGetLastError());
   return LSMS_OK;
 }
 
+extern "C" int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
+                               const void* tau_plus, const void* tau_minus, const int32_t* species, int32_t n_species,
+                               const void* J, double volume, double* sigma, void* sigma_tilde, void* per_atom,
+                               void* hip_stream) {
+  return kubo_sigma_common(ctx, n_atoms, liz_ptr, liz_atom, tau_plus, tau_minus, species, n_species, J, volume,
+                           sigma, sigma_tilde, per_atom, false, hip_stream);
+}
+
+extern "C" int lsms_kubo_sigma_tensor(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr,
+                                      const int32_t* liz_atom, const void* tau_plus, const void* tau_minus,
+                                      const int32_t* species, int32_t n_species, const void* J, double volume,
+                                      double* sigma, void* sigma_tilde, void* per_atom, void* hip_stream) {
+  return kubo_sigma_common(ctx, n_atoms, liz_ptr, liz_atom, tau_plus, tau_minus, species, n_species, J, volume,
+                           sigma, sigma_tilde, per_atom, true, hip_stream);
+}
+
 extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
   if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
-  if (knob == LSMS_TUNE_GRAPHS) {
-    if (value != 0 && value != 1) return fail(LSMS_E_ARG, "graphs must be 0 or 1 (got %d)", value);
-    ctx->graphs = value == 1;
+  if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY) {
+    if (value != 0 && value != 1) return fail(LSMS_E_ARG, "knob %d takes 0 or 1 (got %d)", knob, value);
+    (knob == LSMS_TUNE_GRAPHS ? ctx->graphs : ctx->conj_symmetry) = value == 1;
     return LSMS_OK;
   }
   if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);
@@ -795,8 +815,8 @@ extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
 
 extern "C" int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value) {
   if (!ctx || !value) return fail(LSMS_E_ARG, "NULL argument");
-  if (knob == LSMS_TUNE_GRAPHS) {
-    *value = ctx->graphs ? 1 : 0;
+  if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY) {
+    *value = (knob == LSMS_TUNE_GRAPHS ? ctx->graphs : ctx->conj_symmetry) ? 1 : 0;
     return LSMS_OK;
   }
   if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);

@@ -150,19 +150,20 @@ void launch_residual(const JobDesc* jobs, int njobs, int npad_max, const double2
 void launch_refine_update(const JobDesc* jobs, int njobs, double2* x, const double2* d, double* norms,
                           double tol, int32_t* done, hipStream_t s);
 // Copy tau^{a0} (first n rows, NL columns) out of each job's solution block.
+// mirror: only z+ jobs were solved; also write the z- blocks and status from them.
 void launch_copy_tau(const JobDesc* jobs, int njobs, int npad_max, const double2* x, double2* tau_plus,
-                     double2* tau_minus, hipStream_t s);
+                     double2* tau_minus, bool mirror, hipStream_t s);
 void launch_write_status(const JobDesc* jobs, int njobs, const int32_t* job_info, const double* norms,
-                         int32_t* info, double* berr, hipStream_t s);
+                         int32_t* info, double* berr, bool mirror, hipStream_t s);
 void launch_check_inputs(const JobDesc* jobs, int njobs, const double* liz_pos, const int32_t* liz_atom,
                          const double* phase, int32_t* job_info, hipStream_t s);
 
-// Kubo-Greenwood sums.
+// Kubo-Greenwood sums: diagonal (per atom [4][3]) or full tensor (per atom [4][3][3]).
 void launch_kubo_trace(int n_atoms, const int64_t* liz_ptr_dev, const int32_t* liz_atom, const double2* tau_plus,
                        const double2* tau_minus, const int32_t* species, int n_species, const double2* J,
-                       double2* per_atom, hipStream_t s);
+                       double2* per_atom, bool tensor, hipStream_t s);
 void launch_kubo_reduce(int n_atoms, const double2* per_atom, double volume, double* sigma, double2* sigma_tilde,
-                        hipStream_t s);
+                        bool tensor, hipStream_t s);
 
 // Adjoint.
 void launch_adjoint_rhs(const JobDesc* jobs, int njobs, int npad_max, const int32_t* liz_atom,

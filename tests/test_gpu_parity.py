@@ -325,3 +325,141 @@ def test_autotune_picks_fastest_tiling(lctx):
         assert lctx.gemm_tiling() == best
     finally:
         lctx.set_gemm_tiling(-1)
+
+
+def _device_inputs(w, liz):
+    dev = torch.device("cuda", 0)
+    la, lp = liz.to_device(dev)
+    phase = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(dev)
+    species = torch.from_numpy(w["species"].astype(np.int32)).to(dev)
+    J = torch.from_numpy(np.ascontiguousarray(w["J"])).to(dev)
+    return la, lp, phase, species, J
+
+
+@pytest.mark.parametrize("name,precision,tol", [("bcc16", "fp64", TOL64), ("fcc32", "split", TOL_SPLIT)])
+def test_tensor_full_vs_oracle(lctx, name, precision, tol):
+    """All nine sigma_{mu nu} (Eq. (10) + Eq. (7)) against the oracle; the diagonal also
+    against lsms_kubo_sigma on the same tau."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload(name)
+    eta = w["etas"][0]
+    print("[gpu] tensor %s %s" % (name, precision), flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    tp, tm, info, _ = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
+    sig, st, pa = lctx.kubo_sigma_tensor(liz, la, tp, tm, species, J, w["volume"], per_atom=True)
+    sd, std, _ = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"])
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()
+    sig, st, pa, sd = sig.cpu().numpy(), st.cpu().numpy(), pa.cpu().numpy(), sd.cpu().numpy()
+    o = kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                   liz_lists=(liz.ptr, liz.atom, liz.pos), tensor=True)
+    scale = np.abs(o["sigma"].real).max()
+    assert np.abs(sig - o["sigma"].real).max() <= tol * scale
+    assert np.abs(st - o["sigma_tilde"]).max() <= tol * np.abs(o["sigma_tilde"]).max()
+    for i in range(liz.n_atoms):
+        ref = o["per_atom"][i]
+        assert np.abs(pa[i] - ref).max() <= tol * np.abs(ref).max(), i
+    assert np.allclose(np.diag(sig), sd, rtol=1e-13, atol=0)
+
+
+def test_fcc4000_split_sampled(lctx):
+    """The 4000-atom fcc alloy in the configuration the benchmark times (split precision, the
+    library's default tiling, all atoms batched): sampled atoms' tau and Kubo tensor sums
+    against the oracle, sigma's diagonal from both Kubo entry points."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("fcc4000")
+    eta = w["etas"][0]
+    print("[gpu] fcc4000 split sampled", flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    tp, tm, info, berr = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision="split")
+    sig, st, pa = lctx.kubo_sigma_tensor(liz, la, tp, tm, species, J, w["volume"], per_atom=True)
+    sd, _, _ = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"])
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all() and (berr.cpu().numpy() <= 1e-14).all()
+    assert np.allclose(np.diag(sig.cpu().numpy()), sd.cpu().numpy(), rtol=1e-13, atol=0)
+    atoms = [0, 1777, 3999]
+    o = kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                   atoms=atoms, liz_lists=(liz.ptr, liz.atom, liz.pos), tensor=True)
+    for i in atoms:
+        sl = slice(int(liz.ptr[i]), int(liz.ptr[i + 1]))
+        for tag, t in (("+", tp), ("-", tm)):
+            ref = o["tau"][i]["col" + tag]
+            got = t[sl].cpu().numpy()
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            assert err <= TOL_SPLIT, "atom %d tau%s rel err %.3e" % (i, tag, err)
+        ref = o["per_atom"][i]
+        err = np.abs(pa[i].cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err <= TOL_SPLIT, "atom %d Kubo tensor rel err %.3e" % (i, err)
+
+
+def test_liz_sweep_and_spin_vs_oracle(lctx):
+    """The LIZ-radius sweep (Sec. II.C, Sec. IV): sigma tensor and rho = sigma^-1 at three
+    radii of the pure fcc crystal, spin-polarized with two phase-shift sets, against the
+    oracle's per-channel sums; then both fits on the three points."""
+    from paper_2311_12134_amd import resistivity as R
+    from oracle import resistivity as O
+    w = synthetic.workload("fcc32")
+    eta = w["etas"][0]
+    a = w["a"]
+    radii = [0.75 * a, 1.1 * a, 1.3 * a]
+    phase_dn = np.ascontiguousarray(w["phase"] * 0.8)
+    print("[gpu] liz sweep fcc32 radii %s" % radii, flush=True)
+    got = R.liz_sweep(lctx, w["pos"], w["cell"], w["species"], w["phase"], w["J"], w["e_fermi"], eta, radii,
+                      w["volume"], precision="fp64", phase_down=phase_dn)
+    assert [g["liz_max"] for g in got] == [13, 19, 43]
+    for g, r in zip(got, radii):
+        up = kubo.sigma(w["pos"], w["cell"], r, w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                        volume=w["volume"], tensor=True)["sigma"].real
+        dn = kubo.sigma(w["pos"], w["cell"], r, w["species"], phase_dn, w["J"], w["e_fermi"], eta,
+                        volume=w["volume"], tensor=True)["sigma"].real
+        tot = O.spin_sum(up, dn)
+        scale = np.abs(tot).max()
+        assert np.abs(g["sigma_up"] - up).max() <= TOL64 * np.abs(up).max()
+        assert np.abs(g["sigma_down"] - dn).max() <= TOL64 * np.abs(dn).max()
+        assert np.abs(g["sigma"] - tot).max() <= TOL64 * scale
+        rho = O.resistivity(tot)
+        assert np.abs(g["rho"] - rho).max() <= 1e-9 * np.abs(rho).max()
+    rx = np.array([g["rho"][0, 0] for g in got])
+    assert np.allclose(R.fit_linear(radii, rx), O.fit_linear(radii, rx), rtol=1e-9)
+
+
+@pytest.mark.parametrize("name,precision,tol", [("bcc16", "fp64", TOL64), ("fcc32", "split", TOL_SPLIT),
+                                                ("bcc1940", "split", TOL_SPLIT)])
+def test_conj_symmetry_mode(lctx, name, precision, tol):
+    """z+ solved alone, z- derived as P conj(tau(z+)) P: z+ blocks bitwise those of the full
+    solve, z- blocks and the Kubo sums against the oracle (which solves both energies)."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload(name)
+    eta = w["etas"][0]
+    print("[gpu] conj symmetry %s %s" % (name, precision), flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    full = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
+    lctx.set_conj_symmetry(True)
+    try:
+        assert lctx.conj_symmetry()
+        tp, tm, info, berr = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
+    finally:
+        lctx.set_conj_symmetry(False)
+    _, _, pa = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], per_atom=True)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    assert (info == 0).all() and np.array_equal(info[:, 0], info[:, 1])
+    assert np.array_equal(berr.cpu().numpy()[:, 0], berr.cpu().numpy()[:, 1])
+    if np.ptp(np.diff(liz.ptr)) == 0:  # uniform sizes: identical waves for z+, so bitwise
+        assert torch.equal(tp, full[0])
+    sizes = np.diff(liz.ptr)
+    atoms = [0, 5] if liz.n_atoms < 100 else [int(np.argmin(sizes)), int(np.argmax(sizes)), 1000]
+    o = kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                   atoms=atoms, liz_lists=(liz.ptr, liz.atom, liz.pos))
+    pa = pa.cpu().numpy()
+    for i in atoms:
+        sl = slice(int(liz.ptr[i]), int(liz.ptr[i + 1]))
+        for tag, t in (("+", tp), ("-", tm)):
+            ref = o["tau"][i]["col" + tag]
+            err = np.linalg.norm(t[sl].cpu().numpy() - ref) / np.linalg.norm(ref)
+            assert err <= tol, "atom %d tau%s rel err %.3e" % (i, tag, err)
+        err = np.abs(pa[i] - o["per_atom"][i]).max() / np.abs(o["per_atom"][i]).max()
+        assert err <= tol, "atom %d Kubo rel err %.3e" % (i, err)

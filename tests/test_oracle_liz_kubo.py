@@ -131,3 +131,56 @@ def test_sigma_converges_as_eta_shrinks():
     d1 = np.abs(vals[0] - vals[1]).max()
     d2 = np.abs(vals[1] - vals[2]).max()
     assert d2 < d1 and np.all(np.isfinite(vals))
+
+
+def test_tensor_diagonal_equals_diagonal_sums():
+    w = synthetic.workload("bcc16")
+    args = (w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], w["etas"][0])
+    rd = kubo.sigma(*args, atoms=[0, 3])
+    rt = kubo.sigma(*args, atoms=[0, 3], tensor=True)
+    assert rt["sigma_tilde"].shape == (4, 3, 3) and rt["sigma"].shape == (3, 3)
+    diag = np.stack([rt["sigma_tilde"][:, m, m] for m in range(3)], axis=1)
+    assert np.allclose(diag, rd["sigma_tilde"], rtol=1e-13, atol=0)
+    off = rt["sigma_tilde"][:, 0, 1]
+    assert np.abs(off).max() > 1e-3 * np.abs(diag).max()  # random currents: off-diagonal terms are not small
+
+
+def test_tensor_lsms_sum_equals_all_site_form_on_closed_cluster():
+    """Eq. (10) and Eq. (9) agree for every (mu, nu) when the LIZ spans the cluster."""
+    rng = np.random.default_rng(22)
+    pos = np.array([[0, 0, 0], [4.1, 0.3, -0.2], [0.5, 4.4, 0.1], [-0.2, 0.6, 3.9]])
+    species = np.array([0, 1, 1, 0], dtype=np.int32)
+    phase = np.array([[0.8, 0.2, 0.6, 0.01], [0.7, 0.25, 0.3, 0.01]])[species]
+    J = synthetic.current_matrices(2, rng)
+    r10 = kubo.sigma(pos, None, 50.0, species, phase, J, 0.65, 0.01, volume=400.0, tensor=True)
+    r9 = kubo.sigma_all_sites(pos, species, phase, J, 0.65, 0.01, 400.0, tensor=True)
+    assert np.allclose(r10["sigma_tilde"], r9["sigma_tilde"], rtol=1e-11)
+    # Eq. (9) alone: cyclic trace + relabelling m <-> n give sigma~_{mu nu}(z1, z2) = sigma~_{nu mu}(z2, z1)
+    st = r9["sigma_tilde"]
+    for c, (z1, z2) in enumerate(kubo.COMBOS):
+        assert np.allclose(st[c], st[kubo.COMBO_INDEX[(z2, z1)]].T, rtol=1e-11)
+
+
+def test_tensor_places_mu_on_the_centre_current():
+    """Eq. (10) puts mu on J^{m mu} (centre atom) and nu on J^{n nu} (LIZ member).
+
+    Species A loses its y current and species B its x current; with the outer sum
+    over A atoms only, s_yx vanishes exactly, and s_xy (the B members' terms) is what
+    the diagonal sum gains when B's x slot is given B's y current.
+    """
+    w = synthetic.workload("bcc16")
+    sp = np.asarray(w["species"])
+    A = int(sp[0])
+    B = 1 - A
+    centres = [int(i) for i in np.nonzero(sp == A)[0][:2]]
+    J1 = np.array(w["J"])
+    J1[A, :, 1] = 0.0
+    J1[B, :, 0] = 0.0
+    J2 = J1.copy()
+    J2[B, :, 0] = w["J"][B, :, 1]
+    base = (w["pos"], w["cell"], w["r_liz"], sp, w["phase"])
+    s1 = kubo.sigma(*base, J1, w["e_fermi"], w["etas"][0], atoms=centres, tensor=True)["sigma_tilde"]
+    s2 = kubo.sigma(*base, J2, w["e_fermi"], w["etas"][0], atoms=centres)["sigma_tilde"]
+    assert np.all(s1[:, 1, 0] == 0)
+    assert np.abs(s1[:, 0, 1]).max() > 1e-3 * np.abs(s1[:, 0, 0]).max()
+    assert np.allclose(s2[:, 0], s1[:, 0, 0] + s1[:, 0, 1], rtol=1e-12)
