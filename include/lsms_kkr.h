@@ -46,7 +46,7 @@ extern "C" {
 
 #define LSMS_LMAX 3
 #define LSMS_NL 16        /* (LSMS_LMAX + 1)^2 channels per site */
-#define LSMS_MAX_LIZ 256  /* largest LIZ (members) a single solve accepts */
+#define LSMS_MAX_LIZ 1024 /* largest LIZ (members) a single solve accepts (n = 16384) */
 
 typedef enum {
   LSMS_OK = 0,
@@ -108,6 +108,17 @@ int lsms_build_liz(lsms_ctx* ctx, int32_t n_atoms, const double* pos, const doub
                    int64_t capacity, int64_t* liz_ptr, int32_t* liz_atom, double* liz_pos, int64_t* needed);
 
 /*
+ * As lsms_build_liz, for the listed centre atoms only: every other atom gets an empty
+ * LIZ (liz_ptr[a + 1] == liz_ptr[a]), which lsms_tau_solve and the Kubo sums skip.
+ * The members of a centre's LIZ are the same as in the full build.
+ *   n_centres >= 1, centres host [n_centres] in [0, n_atoms) (duplicates allowed)
+ * Cost O(n_centres * n_atoms) instead of O(n_atoms^2).
+ */
+int lsms_build_liz_subset(lsms_ctx* ctx, int32_t n_atoms, const double* pos, const double* cell, double r_liz,
+                          int32_t n_centres, const int32_t* centres, int64_t capacity, int64_t* liz_ptr,
+                          int32_t* liz_atom, double* liz_pos, int64_t* needed);
+
+/*
  * tau solve (Eq. (3)-(4)): for every atom m and both energies z+- = e_fermi +- i eta,
  * assemble M = 1 - T g over LIZ_m, factor it, and solve M X = E0 t_m so that
  * block a of X is tau^{a0}(z) (the row tau^{0a} equals its transpose, since
@@ -131,6 +142,11 @@ int lsms_build_liz(lsms_ctx* ctx, int32_t n_atoms, const double* pos, const doub
  *   hip_stream  hipStream_t (NULL = null stream)
  * Device memory used: the jobs are processed in waves that fit the workspace
  * limit (all at once when keep != NULL, else LSMS_E_NOMEM).
+ * An atom whose LIZ is empty (liz_ptr[a + 1] == liz_ptr[a]) is skipped: no system is
+ * solved for it and its info and berr are 0 (not allowed with keep).  This lets a
+ * caller solve a subset of a structure's atoms with the structure's phase array.
+ * Panels of more than 2 C rows (C = LSMS_TUNE_TSLU_CHUNK, default 2048, so LIZ of more
+ * than 256 members) choose their pivot rows by tournament pivoting (see lsms_set_tuning).
  */
 int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
                    const double* liz_pos, const double* phase, double e_fermi, double eta, int precision,
@@ -153,7 +169,8 @@ int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const
  *   sigma      device [3] double (out)
  *   sigma_tilde device [4][3] complex (out)
  *   per_atom   device [n_atoms][4][3] complex (out) or NULL
- * The reduction over atoms has a fixed order (bitwise reproducible).
+ * The reduction over atoms has a fixed order (bitwise reproducible).  Atoms with an
+ * empty LIZ contribute nothing.
  */
 int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
                     const void* tau_plus, const void* tau_minus, const int32_t* species, int32_t n_species,
@@ -259,6 +276,16 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * the adjoint (lsms_kubo_sigma_grad needs both energies' factors).
  */
 #define LSMS_TUNE_CONJ_SYMMETRY 2
+/*
+ * knob LSMS_TUNE_TSLU_CHUNK (a multiple of 64 in [64, 2048], default 2048): a panel of the
+ * LU with more than 2 C rows is not factored by one workgroup but by tournament pivoting
+ * (communication-avoiding LU): chunks of C rows each nominate 64 rows by partial
+ * pivoting, one more partial-pivoting factorization of the nominees picks the panel's 64
+ * pivot rows, and the rows below are L21 = A21 U11^-1.  C is raised where needed so that
+ * the nominees fit one 4096-row block.  Smaller C exercises the path on smaller systems;
+ * the result is a stable LU either way (tau agrees to rounding).
+ */
+#define LSMS_TUNE_TSLU_CHUNK 3
 int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
 int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
 

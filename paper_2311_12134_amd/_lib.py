@@ -35,6 +35,8 @@ _PROTOS = {
     "lsms_destroy": (c_int, [c_void_p]),
     "lsms_build_liz": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_double, c_int64, c_void_p, c_void_p,
                                c_void_p, P(c_int64)]),
+    "lsms_build_liz_subset": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_double, c_int32, c_void_p, c_int64,
+                                      c_void_p, c_void_p, c_void_p, P(c_int64)]),
     "lsms_tau_solve": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_int,
                                c_double, c_int, c_void_p, c_void_p, c_void_p, c_void_p, P(c_void_p), c_void_p]),
     "lsms_kubo_sigma": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,

@@ -51,8 +51,10 @@ def gaunt_table():
     return out
 
 
-def build_liz(pos, cell, r_liz):
-    """LIZ construction in the library (host C++); no context or GPU needed."""
+def build_liz(pos, cell, r_liz, centres=None):
+    """LIZ construction in the library (host C++); no context or GPU needed.  With
+    ``centres`` only those atoms get their LIZ (the others an empty one, which the solves
+    and Kubo sums skip)."""
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     n = pos.shape[0]
     cellp = None
@@ -61,16 +63,25 @@ def build_liz(pos, cell, r_liz):
         cellp = cell.ctypes.data_as(ctypes.c_void_p)
     ptr = np.zeros(n + 1, dtype=np.int64)
     needed = ctypes.c_int64(0)
-    rc = lib().lsms_build_liz(None, n, pos.ctypes.data_as(ctypes.c_void_p), cellp, float(r_liz), 0,
-                              ptr.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(needed))
+    if centres is None:
+        def call(cap, atom, disp):
+            return lib().lsms_build_liz(None, n, pos.ctypes.data_as(ctypes.c_void_p), cellp, float(r_liz), cap,
+                                        ptr.ctypes.data_as(ctypes.c_void_p), atom, disp, ctypes.byref(needed))
+    else:
+        cen = np.ascontiguousarray(centres, dtype=np.int32)
+
+        def call(cap, atom, disp):
+            return lib().lsms_build_liz_subset(None, n, pos.ctypes.data_as(ctypes.c_void_p), cellp, float(r_liz),
+                                               int(cen.size), cen.ctypes.data_as(ctypes.c_void_p), cap,
+                                               ptr.ctypes.data_as(ctypes.c_void_p), atom, disp,
+                                               ctypes.byref(needed))
+    rc = call(0, None, None)
     if rc not in (_lib.LSMS_OK, _lib.LSMS_E_CAPACITY):
         check(rc)
     cap = needed.value
     atom = np.zeros(cap, dtype=np.int32)
     disp = np.zeros((cap, 3), dtype=np.float64)
-    check(lib().lsms_build_liz(None, n, pos.ctypes.data_as(ctypes.c_void_p), cellp, float(r_liz), cap,
-                               ptr.ctypes.data_as(ctypes.c_void_p), atom.ctypes.data_as(ctypes.c_void_p),
-                               disp.ctypes.data_as(ctypes.c_void_p), ctypes.byref(needed)))
+    check(call(cap, atom.ctypes.data_as(ctypes.c_void_p), disp.ctypes.data_as(ctypes.c_void_p)))
     return Liz(ptr, atom, disp)
 
 
@@ -193,6 +204,16 @@ class Context:
     def set_graphs(self, on=True):
         """Replay each wave's factorization and first solve from captured HIP graphs."""
         check(lib().lsms_set_tuning(self._h, 1, 1 if on else 0))
+
+    def set_tslu_chunk(self, rows=2048):
+        """Rows per chunk of the tournament-pivoting panels (used for panels taller than
+        2 * rows; a multiple of 64 in [64, 2048])."""
+        check(lib().lsms_set_tuning(self._h, 3, int(rows)))
+
+    def tslu_chunk(self):
+        v = ctypes.c_int(0)
+        check(lib().lsms_get_tuning(self._h, 3, ctypes.byref(v)))
+        return v.value
 
     def set_conj_symmetry(self, on=True):
         """Solve z+ only and derive tau(z-) = P conj tau(z+) P (P = diag((-1)^l)); not used

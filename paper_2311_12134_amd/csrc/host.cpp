@@ -95,6 +95,8 @@ struct lsms_ctx {
   int gemm_f32 = -1;  // tiling of the split-mode trailing update, -1: library default
   bool graphs = false;  // replay each wave's factorization + first solve from a HIP graph
   bool conj_symmetry = false;  // solve z+ only and derive z- (tau(z-) = P conj tau(z+) P)
+  int tslu_chunk = 2048;       // rows per chunk of the tall-panel tournament
+  DevBuf tall;                 // tall-panel scratch
   hipStream_t capture = nullptr;  // non-blocking stream the graphs are captured on
   std::map<std::vector<intptr_t>, hipGraphExec_t> graph_cache;
   EventProf prof;
@@ -138,6 +140,23 @@ static int ensure_dev(DevBuf& b, size_t bytes, hipStream_t s) {
   hipError_t e = hipMalloc(&b.p, bytes);
   if (e != hipSuccess) return fail(LSMS_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
   b.bytes = bytes;
+  return LSMS_OK;
+}
+
+// Scratch for the tournament-pivoting panels of a batch of njobs systems of padded size
+// npad_max (none below 2 chunks).  The chunk is raised if needed so that the candidates
+// of all chunks (NB rows each) form a block of at most 4096 rows.
+static int tall_scratch(lsms_ctx* ctx, int njobs, int npad_max, TallScratch* ts, hipStream_t s) {
+  const int min_chunk = ((npad_max + 64 * NB - 1) / (64 * NB)) * NB;
+  ts->chunk = std::max(ctx->tslu_chunk, min_chunk);
+  ts->njobs = njobs;
+  ts->npad_max = npad_max;
+  ts->base = nullptr;
+  const size_t bytes = tall_scratch_bytes(njobs, npad_max, ts->chunk);
+  if (bytes == 0) return LSMS_OK;
+  int rc = ensure_dev(ctx->tall, bytes, s);
+  if (rc) return rc;
+  ts->base = ctx->tall.p;
   return LSMS_OK;
 }
 
@@ -281,10 +300,10 @@ extern "C" int lsms_destroy(lsms_ctx* ctx) {
 // ---------------------------------------------------------------------------------
 static inline int64_t quant(double v) { return (int64_t)floor(v * 1e9 + 0.5); }
 
-extern "C" int lsms_build_liz(lsms_ctx* ctx, int32_t n_atoms, const double* pos, const double* cell, double r_liz,
-                              int64_t capacity, int64_t* liz_ptr, int32_t* liz_atom, double* liz_pos,
-                              int64_t* needed) {
-  (void)ctx;
+// centre: nullptr (every atom) or a per-atom flag; atoms without it get an empty LIZ.
+static int build_liz_impl(int32_t n_atoms, const double* pos, const double* cell, double r_liz, int64_t capacity,
+                          int64_t* liz_ptr, int32_t* liz_atom, double* liz_pos, int64_t* needed,
+                          const std::vector<char>* centre) {
   if (!pos || !needed || !liz_ptr) return fail(LSMS_E_ARG, "NULL argument");
   if (n_atoms <= 0) return fail(LSMS_E_ARG, "n_atoms must be positive");
   if (!(r_liz > 0.0) || !std::isfinite(r_liz)) return fail(LSMS_E_ARG, "r_liz must be a positive finite number");
@@ -334,6 +353,10 @@ extern "C" int lsms_build_liz(lsms_ctx* ctx, int32_t n_atoms, const double* pos,
   liz_ptr[0] = 0;
   for (int i = 0; i < n_atoms; ++i) {
     mem.clear();
+    if (centre && !(*centre)[i]) {
+      liz_ptr[i + 1] = total;
+      continue;
+    }
     const double* pi = pos + 3 * (size_t)i;
     for (int j = 0; j < n_atoms; ++j) {
       const double* pj = pos + 3 * (size_t)j;
@@ -401,6 +424,27 @@ extern "C" int lsms_build_liz(lsms_ctx* ctx, int32_t n_atoms, const double* pos,
   return LSMS_OK;
 }
 
+extern "C" int lsms_build_liz(lsms_ctx* ctx, int32_t n_atoms, const double* pos, const double* cell, double r_liz,
+                              int64_t capacity, int64_t* liz_ptr, int32_t* liz_atom, double* liz_pos,
+                              int64_t* needed) {
+  (void)ctx;
+  return build_liz_impl(n_atoms, pos, cell, r_liz, capacity, liz_ptr, liz_atom, liz_pos, needed, nullptr);
+}
+
+extern "C" int lsms_build_liz_subset(lsms_ctx* ctx, int32_t n_atoms, const double* pos, const double* cell,
+                                     double r_liz, int32_t n_centres, const int32_t* centres, int64_t capacity,
+                                     int64_t* liz_ptr, int32_t* liz_atom, double* liz_pos, int64_t* needed) {
+  (void)ctx;
+  if (n_atoms <= 0) return fail(LSMS_E_ARG, "n_atoms must be positive");
+  if (n_centres < 1 || !centres) return fail(LSMS_E_ARG, "at least one centre atom is needed");
+  std::vector<char> mask((size_t)n_atoms, 0);
+  for (int c = 0; c < n_centres; ++c) {
+    if (centres[c] < 0 || centres[c] >= n_atoms) return fail(LSMS_E_ARG, "centre %d out of range", centres[c]);
+    mask[centres[c]] = 1;
+  }
+  return build_liz_impl(n_atoms, pos, cell, r_liz, capacity, liz_ptr, liz_atom, liz_pos, needed, &mask);
+}
+
 // ---------------------------------------------------------------------------------
 // scheduling helpers
 // ---------------------------------------------------------------------------------
@@ -421,13 +465,15 @@ static JobBytes job_bytes(int npad, int precision) {
   return b;
 }
 
-static int validate_liz_ptr(int32_t n_atoms, const int64_t* liz_ptr) {
+// allow_empty: an atom with no LIZ members is skipped (its outputs are zero).
+static int validate_liz_ptr(int32_t n_atoms, const int64_t* liz_ptr, bool allow_empty = false) {
   if (n_atoms <= 0) return fail(LSMS_E_ARG, "n_atoms must be positive");
   if (!liz_ptr) return fail(LSMS_E_ARG, "liz_ptr is NULL");
   if (liz_ptr[0] != 0) return fail(LSMS_E_ARG, "liz_ptr[0] must be 0");
   for (int i = 0; i < n_atoms; ++i) {
     int64_t nl = liz_ptr[i + 1] - liz_ptr[i];
-    if (nl < 1 || nl > LSMS_MAX_LIZ) return fail(LSMS_E_ARG, "LIZ of atom %d has %lld members", i, (long long)nl);
+    if (nl < (allow_empty ? 0 : 1) || nl > LSMS_MAX_LIZ)
+      return fail(LSMS_E_ARG, "LIZ of atom %d has %lld members", i, (long long)nl);
   }
   return LSMS_OK;
 }
@@ -508,12 +554,15 @@ void launch_zero_i32(int32_t* p, int n, hipStream_t s);
 static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int nj, int npad_max, void* abuf,
                             int32_t* piv, int32_t* jinfo, double2* xbuf, GemmProfiler* prof, hipStream_t s) {
   const int variant = gemm_f32_variant(ctx);
+  TallScratch ts;
+  int rc = tall_scratch(ctx, nj, npad_max, &ts, s);
+  if (rc) return rc;
   auto issue = [&](hipStream_t q, GemmProfiler* pr) {
     if (precision == LSMS_FP64) {
-      lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, q, pr);
+      lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, q, pr, ts);
       lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, q);
     } else {
-      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant);
+      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, ts);
       lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, q);
     }
   };
@@ -523,7 +572,8 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
     return LSMS_OK;
   }
   const std::vector<intptr_t> key = {precision, nj, npad_max, variant, (intptr_t)jd, (intptr_t)abuf,
-                                     (intptr_t)piv, (intptr_t)jinfo, (intptr_t)xbuf};
+                                     (intptr_t)piv, (intptr_t)jinfo, (intptr_t)xbuf, ts.chunk,
+                                     (intptr_t)ts.base};
   auto it = ctx->graph_cache.find(key);
   if (it == ctx->graph_cache.end()) {
     if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
@@ -547,7 +597,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
                               double refine_tol, int max_refine, void* tau_plus, void* tau_minus, int32_t* info,
                               double* berr, lsms_factors** keep, void* hip_stream) {
   if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
-  int rc = validate_liz_ptr(n_atoms, liz_ptr);
+  int rc = validate_liz_ptr(n_atoms, liz_ptr, keep == nullptr);
   if (rc) return rc;
   if (!liz_atom || !liz_pos || !phase || !tau_plus || !tau_minus || !info || !berr)
     return fail(LSMS_E_ARG, "NULL device pointer");
@@ -568,6 +618,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
   jobs.reserve(2 * (size_t)n_atoms);
   for (int a = 0; a < n_atoms; ++a) {
     const int nl = (int)(liz_ptr[a + 1] - liz_ptr[a]);
+    if (nl == 0) continue;  // skipped atom
     for (int e = 0; e < (mirror ? 1 : 2); ++e) {
       JobDesc j{};
       j.liz_off = liz_ptr[a];
@@ -580,6 +631,12 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     }
   }
   std::stable_sort(jobs.begin(), jobs.end(), [](const JobDesc& x, const JobDesc& y) { return x.npad > y.npad; });
+  if ((int64_t)jobs.size() < (mirror ? 1 : 2) * (int64_t)n_atoms) {  // skipped atoms report info 0, berr 0
+    launch_zero_i32(info, 2 * n_atoms, s);
+    launch_zero(berr, 2 * (int64_t)n_atoms, s);
+    HIP_TRY(hipGetLastError());
+  }
+  if (jobs.empty()) return LSMS_OK;
   const int64_t small_fixed = align_up((int64_t)n_atoms * 8 * 16, 256);  // tpm
   const int64_t limit = (int64_t)ctx->workspace_limit;
   std::vector<Wave> waves = make_waves(jobs, precision, limit, keep != nullptr);
@@ -727,7 +784,10 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           launch_zero_i32(finfo, nf, s);
           const int fpad = fb[0].npad;
           launch_init_rhs(fjd, nf, fpad, liz_atom, tpm, xbuf, s);
-          lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s);
+          TallScratch fts;
+          rc = tall_scratch(ctx, nf, fpad, &fts, s);
+          if (rc) return rc;
+          lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s, nullptr, fts);
           lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, s);
         }
       }
@@ -757,7 +817,7 @@ static int kubo_sigma_common(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_
                              const void* J, double volume, double* sigma, void* sigma_tilde, void* per_atom,
                              bool tensor, void* hip_stream) {
   if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
-  int rc = validate_liz_ptr(n_atoms, liz_ptr);
+  int rc = validate_liz_ptr(n_atoms, liz_ptr, true);
   if (rc) return rc;
   if (!liz_atom || !tau_plus || !tau_minus || !species || !J || !sigma || !sigma_tilde)
     return fail(LSMS_E_ARG, "NULL device pointer");
@@ -801,6 +861,12 @@ extern "C" int lsms_kubo_sigma_tensor(lsms_ctx* ctx, int32_t n_atoms, const int6
 
 extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
   if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  if (knob == LSMS_TUNE_TSLU_CHUNK) {
+    if (value < NB || value > 2048 || value % NB != 0)
+      return fail(LSMS_E_ARG, "tournament chunk %d must be a multiple of %d in [%d, 2048]", value, NB, NB);
+    ctx->tslu_chunk = value;
+    return LSMS_OK;
+  }
   if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY) {
     if (value != 0 && value != 1) return fail(LSMS_E_ARG, "knob %d takes 0 or 1 (got %d)", knob, value);
     (knob == LSMS_TUNE_GRAPHS ? ctx->graphs : ctx->conj_symmetry) = value == 1;
@@ -815,6 +881,10 @@ extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
 
 extern "C" int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value) {
   if (!ctx || !value) return fail(LSMS_E_ARG, "NULL argument");
+  if (knob == LSMS_TUNE_TSLU_CHUNK) {
+    *value = ctx->tslu_chunk;
+    return LSMS_OK;
+  }
   if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY) {
     *value = (knob == LSMS_TUNE_GRAPHS ? ctx->graphs : ctx->conj_symmetry) ? 1 : 0;
     return LSMS_OK;
@@ -974,13 +1044,16 @@ extern "C" int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t
   std::memcpy(hp + jd_bytes, A, batch * sizeof(void*));
   std::memcpy(hp + jd_bytes + ptr_bytes, B, batch * sizeof(void*));
   HIP_TRY(hipMemcpyAsync(jd, hp, (size_t)host_bytes, hipMemcpyHostToDevice, s));
+  TallScratch ts;
+  rc = tall_scratch(ctx, batch, npad_max, &ts, s);
+  if (rc) return rc;
   launch_zero_i32(info, batch, s);
   launch_load_user(jd, batch, npad_max, aptr, bptr, nrhs, prec, abuf, xbuf, s);
   if (prec == LSMS_FP64) {
-    lu_factor_f64(jd, batch, npad_max, (double2*)abuf, piv, info, s);
+    lu_factor_f64(jd, batch, npad_max, (double2*)abuf, piv, info, s, nullptr, ts);
     lu_solve_f64(jd, batch, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
   } else {
-    lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s, nullptr, gemm_f32_variant(ctx));
+    lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s, nullptr, gemm_f32_variant(ctx), ts);
     lu_solve_f32(jd, batch, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
   }
   launch_store_user(jd, batch, npad_max, bptr, nrhs, xbuf, s);

@@ -68,6 +68,8 @@ struct JobDesc {
   int32_t n;        // NL * nl
   int32_t npad;     // n rounded up to PAD
   int32_t info;     // host-side scratch
+  int32_t ld;       // leading dimension if not npad (0: npad); set for the tall-panel sub-problems
+  int32_t pad_;
 };
 
 constexpr int NRHS_MAX = 32;  // columns of the solution block (16 forward, 32 adjoint)
@@ -131,10 +133,19 @@ void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int 
                      int c_begin, int c_end, float2* work, hipStream_t s);
 
 // Blocked LU with partial pivoting of every job's working matrix.
+// Panels taller than 2 * chunk rows are factored with tournament pivoting (lu.hip);
+// they need device scratch laid out for the wave's job count and padded size.
+struct TallScratch {
+  int chunk = 0;         // rows per tournament chunk (64 .. 2048, a multiple of 64)
+  void* base = nullptr;  // tall_scratch_bytes(njobs, npad_max, chunk) bytes, or nullptr if none needed
+  int njobs = 0, npad_max = 0;
+};
+size_t tall_scratch_bytes(int njobs, int npad_max, int chunk);
+
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof = nullptr);
+                   hipStream_t s, GemmProfiler* prof, const TallScratch& tall);
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof = nullptr, int gemm_variant = 0);
+                   hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall);
 // Solve with the factors: trans = 0 solves M X = B, trans = 1 solves M^T X = B (in place on X).
 void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
                   double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);

@@ -47,13 +47,57 @@ __device__ inline double2 wide(float2 a) { return make_double2((double)a.x, (dou
 __device__ inline void narrow_to(double2& d, double2 a) { d = a; }
 __device__ inline void narrow_to(float2& d, double2 a) { d = make_float2((float)a.x, (float)a.y); }
 
+// The NB interchanges of a panel starting at row k (pivall[q]: the row exchanged with
+// k + q at step q) as one permutation of at most 2 NB rows, written to lst: entries
+// 0..NB-1 are the positions k..k+NB-1, further entries the pivot rows below the panel;
+// org[e] is the original row that ends up at position pos[e].  Executed by one wavefront;
+// returns the number of entries (the same in every lane).
+__device__ inline int write_perm_list(int k, const int* pivall, int* s_pos, int* s_org, int32_t* lst, int lane) {
+  for (int i = lane; i < NB; i += 64) {
+    s_pos[i] = k + i;
+    s_org[i] = k + i;
+  }
+  int cnt = NB;
+  for (int q = 0; q < NB; ++q) {
+    const int d = k + q, p = pivall[q];
+    if (p == d) continue;
+    int e;
+    if (p < k + NB) {
+      e = p - k;
+    } else {
+      const unsigned long long m = __ballot(NB + lane < cnt && s_pos[NB + lane] == p);
+      if (m) {
+        e = NB + __ffsll((long long)m) - 1;
+      } else {
+        e = cnt;
+        if (lane == 0) {
+          s_pos[cnt] = p;
+          s_org[cnt] = p;
+        }
+        ++cnt;
+      }
+    }
+    if (lane == 0) {
+      const int tmp = s_org[q];
+      s_org[q] = s_org[e];
+      s_org[e] = tmp;
+    }
+  }
+  if (lane == 0) lst[0] = cnt;
+  for (int i = lane; i < cnt; i += 64) {
+    lst[2 + i] = s_pos[i];
+    lst[2 + PERM_MAX + i] = s_org[i];
+  }
+  return cnt;
+}
+
 template <typename T, int PT, int S, int IB>
 __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, int left, T* work, int32_t* piv,
                                                    int32_t* info) {
   const JobDesc jd = jobs[blockIdx.x];
   if (k >= jd.npad) return;  // uniform over the workgroup
   T* A = work + jd.a_off;
-  const int64_t ld = jd.npad;
+  const int64_t ld = jd.ld > 0 ? jd.ld : jd.npad;
   const int nrows = jd.npad;
   int32_t* ip = piv + jd.piv_off;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -331,48 +375,9 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
     // s_piv are rewritten by it
     __syncthreads();
   }
-  // The panel's NB interchanges as one permutation of at most 2 NB rows: entries
-  // 0..NB-1 are the positions k..k+NB-1, further entries the pivot rows below the panel;
-  // s_org[e] is the original row that ends up at position s_pos[e].
+  // The panel's NB interchanges as one permutation of at most 2 NB rows.
   __syncthreads();
-  if (wave == 0) {
-    for (int i = lane; i < NB; i += 64) {
-      s_pos[i] = k + i;
-      s_org[i] = k + i;
-    }
-    int cnt = NB;
-    for (int q = 0; q < NB; ++q) {
-      const int d = k + q, p = s_pivall[q];
-      if (p == d) continue;
-      int e;
-      if (p < k + NB) {
-        e = p - k;
-      } else {
-        const unsigned long long m = __ballot(NB + lane < cnt && s_pos[NB + lane] == p);
-        if (m) {
-          e = NB + __ffsll((long long)m) - 1;
-        } else {
-          e = cnt;
-          if (lane == 0) {
-            s_pos[cnt] = p;
-            s_org[cnt] = p;
-          }
-          ++cnt;
-        }
-      }
-      if (lane == 0) {
-        const int tmp = s_org[q];
-        s_org[q] = s_org[e];
-        s_org[e] = tmp;
-      }
-    }
-    int32_t* lst = ip + perm_off(nrows, k);
-    if (lane == 0) lst[0] = cnt;
-    for (int i = lane; i < cnt; i += 64) {
-      lst[2 + i] = s_pos[i];
-      lst[2 + PERM_MAX + i] = s_org[i];
-    }
-  }
+  if (wave == 0) write_perm_list(k, s_pivall, s_pos, s_org, ip + perm_off(nrows, k), lane);
   if (t == 0 && first_zero != 0) {
     if (info[blockIdx.x] == 0) info[blockIdx.x] = first_zero;
   }
@@ -525,6 +530,242 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
 }
 
 // ------------------------------------------------------------------------------------
+// tall panels: tournament pivoting
+// ------------------------------------------------------------------------------------
+// A panel of R rows keeps R / PT rows per thread in registers, which bounds the
+// one-workgroup panel kernel to 4096 rows.  Taller panels (LIZ of several hundred to
+// ~1000 sites) choose their NB pivot rows by a tournament over many workgroups instead
+// (communication-avoiding LU, Grigori, Demmel and Xiang 2011):
+//   1. the panel is cut into chunks of C rows, copied to scratch, and every chunk is
+//      factored with partial pivoting by the panel kernel (one workgroup each); the NB
+//      rows its pivots bring to the top are the chunk's candidates;
+//   2. the original values of all candidates are gathered into one block and factored
+//      with partial pivoting once more; the NB rows chosen there, in that order, are the
+//      panel's pivot rows, and that block's top NB x NB factors are the panel's L11, U11;
+//   3. the interchanges that bring those rows to the top (same permutation-list format
+//      as the panel kernel's) are applied to the panel (and the `left` columns), L11\U11
+//      is written over the diagonal block, and after linv_kernel the rows below are
+//      L21 = A21 U11^-1, one 64 x 64 x 64 product per 16-row strip on the matrix cores.
+// Every step is an ordinary launch over the batch: no workgroup waits for another.
+
+struct TallLayout {
+  int nc_max;
+  int64_t w1, w2, p1, p2, g2, sub1, sub2, si1, si2, total;  // byte offsets
+};
+
+static TallLayout tall_layout(int njobs, int npad_max, int chunk) {
+  TallLayout L{};
+  L.nc_max = (npad_max + chunk - 1) / chunk;
+  auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
+  int64_t off = 0;
+  L.w1 = off;  // [job][npad_max][NB] elements of at most 16 bytes
+  off += al((int64_t)njobs * npad_max * NB * 16);
+  L.w2 = off;  // [job][nc_max * NB][NB]
+  off += al((int64_t)njobs * L.nc_max * NB * NB * 16);
+  L.p1 = off;  // [job][nc_max][piv_ints(chunk)]
+  off += al((int64_t)njobs * L.nc_max * piv_ints(chunk) * 4);
+  L.p2 = off;  // [job][piv_ints(nc_max * NB)]
+  off += al((int64_t)njobs * piv_ints(L.nc_max * NB) * 4);
+  L.g2 = off;  // [job][nc_max * NB] global row of each candidate
+  off += al((int64_t)njobs * L.nc_max * NB * 4);
+  L.sub1 = off;
+  off += al((int64_t)njobs * L.nc_max * sizeof(JobDesc));
+  L.sub2 = off;
+  off += al((int64_t)njobs * sizeof(JobDesc));
+  L.si1 = off;
+  off += al((int64_t)njobs * L.nc_max * 4);
+  L.si2 = off;
+  off += al((int64_t)njobs * 4);
+  L.total = off;
+  return L;
+}
+
+size_t tall_scratch_bytes(int njobs, int npad_max, int chunk) {
+  if (chunk <= 0 || npad_max <= 2 * chunk) return 0;
+  return (size_t)tall_layout(njobs, npad_max, chunk).total;
+}
+
+// Sub-problem descriptors for this panel: chunk c of job j is rows [c C, ...) of the
+// job's panel copy (leading dimension NB); chunks past a job's rows are empty (npad 0).
+__global__ void tslu_setup_kernel(const JobDesc* jobs, int njobs, int k, int chunk, int nc_max, int npad_max,
+                                  JobDesc* sub1, JobDesc* sub2, int32_t* si1, int32_t* si2) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= njobs * nc_max) return;
+  const int j = idx / nc_max, c = idx - j * nc_max;
+  const int rows = jobs[j].npad - k;
+  const int nc = rows > 0 ? (rows + chunk - 1) / chunk : 0;
+  JobDesc d{};
+  if (c < nc) {
+    const int r = min(chunk, rows - c * chunk);  // a multiple of NB, at least NB
+    d.a_off = ((int64_t)j * npad_max + (int64_t)c * chunk) * NB;
+    d.piv_off = ((int64_t)j * nc_max + c) * piv_ints(chunk);
+    d.n = r;
+    d.npad = r;
+    d.ld = NB;
+  }
+  sub1[idx] = d;
+  si1[idx] = 0;
+  if (c == 0) {
+    JobDesc e{};
+    if (nc > 0) {
+      e.a_off = (int64_t)j * nc_max * NB * NB;
+      e.piv_off = (int64_t)j * piv_ints(nc_max * NB);
+      e.n = nc * NB;
+      e.npad = nc * NB;
+      e.ld = NB;
+    }
+    sub2[j] = e;
+    si2[j] = 0;
+  }
+}
+
+// rows [k, npad) x cols [k, k + NB) of each job into its panel copy
+template <typename T>
+__global__ void tslu_copy_kernel(const JobDesc* jobs, int k, int npad_max, const T* work, T* w1) {
+  const JobDesc jd = jobs[blockIdx.y];
+  const int rows = jd.npad - k;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rows <= 0 || idx >= (int64_t)rows * NB) return;
+  const int r = (int)(idx / NB), q = (int)(idx - (int64_t)r * NB);
+  w1[((int64_t)blockIdx.y * npad_max + r) * NB + q] = work[jd.a_off + (int64_t)(k + r) * jd.npad + k + q];
+}
+
+// Candidates of chunk (blockIdx.x) of job (blockIdx.y): the original rows that the chunk's
+// interchanges moved to its first NB positions, gathered from the (unmodified) panel.
+template <typename T>
+__global__ __launch_bounds__(256) void tslu_gather_kernel(const JobDesc* jobs, int k, int chunk, int nc_max,
+                                                          const JobDesc* sub1, const int32_t* p1, const T* work,
+                                                          T* w2, int32_t* g2) {
+  const int j = blockIdx.y, c = blockIdx.x;
+  const JobDesc sd = sub1[j * nc_max + c];
+  if (sd.npad == 0) return;
+  const JobDesc jd = jobs[j];
+  const int32_t* lst = p1 + sd.piv_off + perm_off(sd.npad, 0);
+  const int64_t base = (int64_t)j * nc_max * NB + (int64_t)c * NB;
+  for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
+    const int e = idx / NB, q = idx - e * NB;
+    const int gid = k + c * chunk + lst[2 + PERM_MAX + e];
+    w2[(base + e) * NB + q] = work[jd.a_off + (int64_t)gid * jd.npad + k + q];
+    if (q == 0) g2[base + e] = gid;
+  }
+}
+
+// Position (index into pos/row lists of cnt <= PERM_MAX entries) of value v, or -1.
+__device__ inline int find_entry(const int* arr, int cnt, int v, int lane) {
+  const unsigned long long m0 = __ballot(lane < cnt && arr[lane] == v);
+  if (m0) return __ffsll((long long)m0) - 1;
+  const unsigned long long m1 = __ballot(lane + 64 < cnt && arr[lane + 64] == v);
+  return m1 ? 64 + __ffsll((long long)m1) - 1 : -1;
+}
+
+// The tournament's winners become the panel's pivot rows: interchanges, permutation list,
+// L11\U11 from the final factorization, zero-pivot report.  One workgroup per job.
+template <typename T>
+__global__ __launch_bounds__(256) void tslu_apply_kernel(const JobDesc* jobs, int k, int left, int nc_max,
+                                                         const JobDesc* sub2, const int32_t* p2, const T* w2,
+                                                         const int32_t* g2, const int32_t* si2, T* work,
+                                                         int32_t* piv, int32_t* info) {
+  const int j = blockIdx.x;
+  const JobDesc jd = jobs[j];
+  if (k >= jd.npad) return;  // uniform
+  const JobDesc rd = sub2[j];
+  T* A = work + jd.a_off;
+  const int64_t ld = jd.npad;
+  int32_t* ip = piv + jd.piv_off;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  __shared__ int s_sel[NB], s_pivall[NB];
+  __shared__ int s_mpos[PERM_MAX], s_mrow[PERM_MAX];
+  __shared__ int s_pos[PERM_MAX], s_org[PERM_MAX], s_cnt;
+  __shared__ T s_held[PERM_MAX][33];
+  const int32_t* lst2 = p2 + rd.piv_off + perm_off(rd.npad, 0);
+  if (t < NB) s_sel[t] = g2[(int64_t)j * nc_max * NB + lst2[2 + PERM_MAX + t]];
+  __syncthreads();
+  if (wave == 0) {
+    // Interchanges that bring s_sel[q] to position k + q for q = 0, 1, ... in turn, as
+    // partial pivoting records them: (s_mpos[e], s_mrow[e]) lists the positions whose row
+    // has changed and the row each now holds (at most 2 NB entries).
+    int cnt = 0;
+    for (int q = 0; q < NB; ++q) {
+      const int row = s_sel[q], d = k + q;
+      const int er = find_entry(s_mrow, cnt, row, lane);
+      const int p = er >= 0 ? s_mpos[er] : row;  // where that row is now
+      if (lane == 0) s_pivall[q] = p;
+      if (p != d) {
+        const int ed = find_entry(s_mpos, cnt, d, lane);
+        const int at_d = ed >= 0 ? s_mrow[ed] : d;
+        if (lane == 0) {
+          if (ed >= 0) {
+            s_mrow[ed] = row;
+          } else {
+            s_mpos[cnt] = d;
+            s_mrow[cnt] = row;
+          }
+          const int e2 = ed >= 0 ? cnt : cnt + 1;
+          if (er >= 0) {
+            s_mrow[er] = at_d;
+          } else {
+            s_mpos[e2] = p;
+            s_mrow[e2] = at_d;
+          }
+        }
+        cnt += (ed >= 0 ? 0 : 1) + (er >= 0 ? 0 : 1);
+      }
+    }
+    for (int q = lane; q < NB; q += 64) ip[k + q] = s_pivall[q];
+    const int c = write_perm_list(k, s_pivall, s_pos, s_org, ip + perm_off(jd.npad, k), lane);
+    if (lane == 0) s_cnt = c;  // (pos, org) stay in LDS for the other wavefronts
+  }
+  __syncthreads();
+  // the permutation on the panel's columns and the `left` columns before them
+  const int cnt = s_cnt;
+  const int ncols = left + NB;
+  for (int c0 = 0; c0 < ncols; c0 += 32) {
+    for (int idx = t; idx < cnt * 32; idx += 256) {
+      const int e = idx >> 5, cc = idx & 31;
+      if (c0 + cc < ncols) s_held[e][cc] = A[(int64_t)s_org[e] * ld + (k - left) + c0 + cc];
+    }
+    __syncthreads();
+    for (int idx = t; idx < cnt * 32; idx += 256) {
+      const int e = idx >> 5, cc = idx & 31;
+      if (c0 + cc < ncols) A[(int64_t)s_pos[e] * ld + (k - left) + c0 + cc] = s_held[e][cc];
+    }
+    __syncthreads();
+  }
+  // L11\U11 of the chosen rows, as the final factorization left them
+  const T* top = w2 + (int64_t)j * nc_max * NB * NB;
+  for (int idx = t; idx < NB * NB; idx += 256) {
+    const int q = idx / NB, pp = idx - q * NB;
+    A[(int64_t)(k + q) * ld + k + pp] = top[(int64_t)q * NB + pp];
+  }
+  if (t == 0 && si2[j] != 0 && info[j] == 0) info[j] = k + si2[j];
+}
+
+// L21 = A21 U11^-1 below the diagonal block (U11^-1 on and above the block's diagonal,
+// written by linv_kernel): wave w of workgroup (x, job) takes rows k + NB + 64 x + 16 w.
+template <typename T>
+__global__ __launch_bounds__(256) void tslu_l21_kernel(const JobDesc* jobs, int k, T* work) {
+  const JobDesc jd = jobs[blockIdx.y];
+  const int lane = threadIdx.x & 63, ii = lane & 15;
+  const int r0 = k + NB + blockIdx.x * 64 + (threadIdx.x >> 6) * 16;
+  if (k >= jd.npad || r0 >= jd.npad) return;  // uniform per wavefront; no barrier below
+  T* A = work + jd.a_off;
+  const int64_t ld = jd.npad;
+  StripMma<T, 4> d;
+  d.zero();
+  d.run([&](int i, int kk) { return A[(int64_t)(r0 + i) * ld + k + kk]; },
+        [&](int kk, int c) {
+          T u = A[(int64_t)(k + kk) * ld + k + c];
+          if (kk > c) u = T{0, 0};
+          return u;
+        },
+        lane);
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) st2(A + (int64_t)(r0 + d.row(r, lane)) * ld + k + cb * 16 + ii, d.value(cb, r));
+}
+
+// ------------------------------------------------------------------------------------
 // drivers
 // ------------------------------------------------------------------------------------
 // Leaf width: FP32 storage keeps the leaf in FP32 registers, so 16 columns fit where FP64
@@ -561,6 +802,41 @@ static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int ro
   }
 }
 
+// One panel (and the inverses of its diagonal triangles): the register-resident panel
+// kernel, or the tournament for panels taller than 2 chunk rows.
+template <typename T>
+static void panel_step(const JobDesc* jobs, int njobs, int npad_max, int k, int left, T* work, int32_t* piv,
+                       int32_t* info, const TallScratch& ts, hipStream_t s) {
+  const int rows = npad_max - k;
+  if (ts.chunk > 0 && rows > 2 * ts.chunk && ts.base) {
+    const TallLayout L = tall_layout(ts.njobs, ts.npad_max, ts.chunk);
+    char* b = (char*)ts.base;
+    T* w1 = (T*)(b + L.w1);
+    T* w2 = (T*)(b + L.w2);
+    int32_t* p1 = (int32_t*)(b + L.p1);
+    int32_t* p2 = (int32_t*)(b + L.p2);
+    int32_t* g2 = (int32_t*)(b + L.g2);
+    JobDesc* sub1 = (JobDesc*)(b + L.sub1);
+    JobDesc* sub2 = (JobDesc*)(b + L.sub2);
+    int32_t* si1 = (int32_t*)(b + L.si1);
+    int32_t* si2 = (int32_t*)(b + L.si2);
+    const int nc_max = L.nc_max;
+    tslu_setup_kernel<<<(njobs * nc_max + 255) / 256, 256, 0, s>>>(jobs, njobs, k, ts.chunk, nc_max, ts.npad_max,
+                                                                 sub1, sub2, si1, si2);
+    tslu_copy_kernel<T><<<dim3((unsigned)(((int64_t)rows * NB + 255) / 256), njobs), 256, 0, s>>>(
+        jobs, k, ts.npad_max, work, w1);
+    launch_panel<T>(sub1, njobs * nc_max, 0, 0, ts.chunk, w1, p1, si1, s);
+    tslu_gather_kernel<T><<<dim3(nc_max, njobs), 256, 0, s>>>(jobs, k, ts.chunk, nc_max, sub1, p1, work, w2, g2);
+    launch_panel<T>(sub2, njobs, 0, 0, ((rows + ts.chunk - 1) / ts.chunk) * NB, w2, p2, si2, s);
+    tslu_apply_kernel<T><<<njobs, 256, 0, s>>>(jobs, k, left, nc_max, sub2, p2, w2, g2, si2, work, piv, info);
+    linv_kernel<T><<<njobs, 512, 0, s>>>(jobs, k, work);
+    if (rows > NB) tslu_l21_kernel<T><<<dim3((rows - NB + 63) / 64, njobs), 256, 0, s>>>(jobs, k, work);
+    return;
+  }
+  launch_panel<T>(jobs, njobs, k, left, rows, work, piv, info, s);
+  linv_kernel<T><<<njobs, 512, 0, s>>>(jobs, k, work);
+}
+
 // Algorithmic flops and bytes of one trailing-update launch over the unpadded rows m and
 // columns c of each job's updated block: 8 m c kd flops (complex multiply-add count) and
 // es (m kd + kd c + 2 m c) bytes (L21 and U12 read once, A22 read and written once).
@@ -590,7 +866,7 @@ static void update_cost(const GemmProfiler* prof, int njobs, int kd, int r_begin
 // apply the second panel's permutation right after the first panel's triangle.
 template <typename T, typename Gemm>
 static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work, int32_t* piv, int32_t* info,
-                          hipStream_t s, GemmProfiler* prof, Gemm gemm) {
+                          hipStream_t s, GemmProfiler* prof, const TallScratch& tall, Gemm gemm) {
   auto timed_gemm = [&](int k, int kd, int r_begin, int c_begin, int c_end) {
     const int rows = npad_max - r_begin;
     const int cols = (c_end > 0 ? std::min(c_end, npad_max) : npad_max) - c_begin;
@@ -604,14 +880,12 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
     }
   };
   for (int k = 0; k < npad_max; k += 2 * NB) {
-    launch_panel<T>(jobs, njobs, k, 0, npad_max - k, work, piv, info, s);
-    linv_kernel<T><<<njobs, 512, 0, s>>>(jobs, k, work);
+    panel_step<T>(jobs, njobs, npad_max, k, 0, work, piv, info, tall, s);
     const int rest = npad_max - k - NB;
     if (rest <= 0) break;
     swap_trsm_kernel<T, false><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, piv);
     timed_gemm(k, NB, k + NB, k + NB, k + 2 * NB);  // the second panel's columns
-    launch_panel<T>(jobs, njobs, k + NB, NB, npad_max - k - NB, work, piv, info, s);
-    linv_kernel<T><<<njobs, 512, 0, s>>>(jobs, k + NB, work);
+    panel_step<T>(jobs, njobs, npad_max, k + NB, NB, work, piv, info, tall, s);
     const int rest2 = npad_max - k - 2 * NB;
     if (rest2 <= 0) break;
     swap_trsm_kernel<T, true><<<dim3(rest2 / 64, njobs), 256, 0, s>>>(jobs, k + NB, work, piv);
@@ -620,16 +894,16 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
 }
 
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof) {
-  lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof,
+                   hipStream_t s, GemmProfiler* prof, const TallScratch& tall) {
+  lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall,
                          [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
                            launch_gemm_f64(jobs, njobs, rows, cols, k, kd, rb, cb, ce, work, s);
                          });
 }
 
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof, int gemm_variant) {
-  lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof,
+                   hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall) {
+  lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall,
                         [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
                           // the narrow update of a pair's second panel (64 columns) keeps the 64 x 64 tiling
                           launch_gemm_f32(ce > 0 ? 0 : gemm_variant, jobs, njobs, rows, cols, k, kd, rb, cb, ce, work, s);

@@ -172,6 +172,18 @@ def _workload(name):
         return dict(name=name, pos=pos, cell=cell, species=species, phase_species=phase_sp, J=J,
                     r_liz=2.2 * a, e_fermi=0.7, etas=(0.003,), lattice="bcc-disordered", a=a,
                     r_liz_literal="1.6a")
+    if name == "bcc16000":
+        # the paper's large-LIZ setting (Sec. III: 16,000-atom bcc, ~1000-atom LIZ): random
+        # binary bcc alloy, 20x20x20 cells, LIZ radius 4.9a (965 members, n = 15440)
+        rng = np.random.default_rng(BASE_SEED + 7)
+        a = 5.7
+        pos, cell = bcc_supercell(a, 20)
+        species = species_iid(len(pos), [0.5, 0.5], rng)
+        phase_sp = np.array([[0.8, 0.2, 0.6, 0.01], [0.7, 0.25, 0.3, 0.01]])
+        J = current_matrices(2, rng)
+        return dict(name=name, pos=pos, cell=cell, species=species, phase_species=phase_sp, J=J,
+                    r_liz=4.9 * a, e_fermi=0.65, etas=(0.002,), lattice="bcc", a=a,
+                    r_liz_literal="approximately a 1000-atom LIZ")
     if name == "bcc16":
         # small random binary bcc alloy for exhaustive checks (2x2x2 cells, LIZ 27)
         rng = np.random.default_rng(BASE_SEED + 6)
@@ -186,7 +198,7 @@ def _workload(name):
     raise KeyError(name)
 
 
-WORKLOADS = ("fcc32", "bcc250", "fcc4000", "bcc1940", "bcc250grad", "bcc16")
+WORKLOADS = ("fcc32", "bcc250", "fcc4000", "bcc1940", "bcc250grad", "bcc16", "bcc16000")
 
 
 def workload(name):

@@ -102,3 +102,35 @@ def test_create_rejects_lmax_before_touching_a_device():
     h = ctypes.c_void_p()
     assert lib().lsms_create(0, 4, 0, ctypes.byref(h)) == -1
     assert b"lmax" in lib().lsms_last_error()
+
+
+def test_liz_subset_matches_full_build():
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc250")
+    full = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    cen = [3, 100, 100, 249]
+    sub = P.build_liz(w["pos"], w["cell"], w["r_liz"], centres=cen)
+    sizes = np.diff(sub.ptr)
+    assert (sizes[[3, 100, 249]] > 0).all() and sizes.sum() == sum(np.diff(full.ptr)[[3, 100, 249]])
+    for i in range(250):
+        if i in cen:
+            a, b = slice(full.ptr[i], full.ptr[i + 1]), slice(sub.ptr[i], sub.ptr[i + 1])
+            assert np.array_equal(full.atom[a], sub.atom[b]) and np.array_equal(full.pos[a], sub.pos[b])
+        else:
+            assert sizes[i] == 0
+
+
+def test_liz_paper_scale_membership():
+    """bcc16000 at r_LIZ = 4.9a: 965 members, exactly the images within the radius
+    (brute force over periodic images for one centre)."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc16000")
+    L = P.build_liz(w["pos"], w["cell"], w["r_liz"], centres=[7])
+    assert np.diff(L.ptr)[7] == 965
+    d = w["pos"][None, :, :] - w["pos"][7][None, None, :]
+    shifts = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)], dtype=float)
+    imgs = (d + (shifts @ w["cell"])[:, None, :]).reshape(-1, 3)
+    r = np.linalg.norm(imgs, axis=1)
+    assert int((r < w["r_liz"]).sum()) == 965
+    got = np.sort(np.linalg.norm(L.pos[L.ptr[7]:L.ptr[8]], axis=1))
+    assert np.allclose(got, np.sort(r[r < w["r_liz"]]), rtol=0, atol=1e-9)

@@ -463,3 +463,105 @@ def test_conj_symmetry_mode(lctx, name, precision, tol):
             assert err <= tol, "atom %d tau%s rel err %.3e" % (i, tag, err)
         err = np.abs(pa[i] - o["per_atom"][i]).max() / np.abs(o["per_atom"][i]).max()
         assert err <= tol, "atom %d Kubo rel err %.3e" % (i, err)
+
+
+@pytest.mark.parametrize("name,precision,chunk,tol", [("bcc250", "fp64", 256, TOL64), ("bcc250", "split", 128, TOL_SPLIT),
+                                                      ("bcc1940", "split", 192, TOL_SPLIT)])
+def test_tournament_panels_vs_oracle(lctx, name, precision, chunk, tol):
+    """Panels taller than 2 chunk rows take the tournament-pivoting path (on LIZ of a few
+    hundred sites with the default chunk; forced here with small chunks): sampled atoms
+    against the oracle; bcc1940 mixes LIZ sizes, so jobs of one wave have different chunk
+    counts."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload(name)
+    eta = w["etas"][0]
+    print("[gpu] tournament %s %s chunk %d" % (name, precision, chunk), flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    lctx.set_tslu_chunk(chunk)
+    try:
+        assert lctx.tslu_chunk() == chunk
+        tp, tm, info, berr = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
+        _, _, pa = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], per_atom=True)
+        torch.cuda.synchronize()
+    finally:
+        lctx.set_tslu_chunk(2048)
+    assert (info.cpu().numpy() == 0).all()
+    sizes = np.diff(liz.ptr)
+    atoms = [0, 77, 249] if name == "bcc250" else [int(np.argmin(sizes)), int(np.argmax(sizes)), 1000]
+    o = kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                   atoms=atoms, liz_lists=(liz.ptr, liz.atom, liz.pos))
+    pa = pa.cpu().numpy()
+    for i in atoms:
+        sl = slice(int(liz.ptr[i]), int(liz.ptr[i + 1]))
+        for tag, t in (("+", tp), ("-", tm)):
+            ref = o["tau"][i]["col" + tag]
+            err = np.linalg.norm(t[sl].cpu().numpy() - ref) / np.linalg.norm(ref)
+            assert err <= tol, "atom %d tau%s rel err %.3e" % (i, tag, err)
+        err = np.abs(pa[i] - o["per_atom"][i]).max() / np.abs(o["per_atom"][i]).max()
+        assert err <= tol, "atom %d Kubo rel err %.3e" % (i, err)
+
+
+def test_batched_lu_solve_tall_panels(lctx):
+    """The diagnostic batched solve with tournament panels on random systems (FP64),
+    against numpy; sizes not multiples of 64, uneven in one batch."""
+    rng = np.random.default_rng(12)
+    ns = [700, 1100, 333]
+    print("[gpu] batched tall panels %s" % ns, flush=True)
+    A = [rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) for n in ns]
+    B = [rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3)) for n in ns]
+    Ad = [torch.from_numpy(a).to("cuda") for a in A]
+    Bd = [torch.from_numpy(b).to("cuda") for b in B]
+    lctx.set_tslu_chunk(128)
+    try:
+        info = lctx.batched_lu_solve(Ad, Bd, precision="fp64")
+        torch.cuda.synchronize()
+    finally:
+        lctx.set_tslu_chunk(2048)
+    assert (info.cpu().numpy() == 0).all()
+    for a, b, x in zip(A, B, Bd):
+        ref = np.linalg.solve(a, b)
+        assert np.abs(x.cpu().numpy() - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_paper_scale_liz_bcc16000(lctx):
+    """The paper's large-LIZ setting (16,000-atom bcc alloy, 965-site LIZ, n = 15440) in split
+    precision with the default tournament chunk: two sampled centres (empty LIZ for the other
+    atoms); the refined solution's backward error, and the oracle's own block rows of
+    M = 1 - t g applied to the GPU's tau column (residual of the oracle's system) for
+    sampled members."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc16000")
+    eta = w["etas"][0]
+    centres = [0, 12345]
+    print("[gpu] paper-scale LIZ bcc16000 centres %s" % centres, flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"], centres=centres)
+    assert list(np.diff(liz.ptr)[centres]) == [965, 965] and liz.total == 2 * 965
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    tp, tm, info, berr = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision="split")
+    sig, _, pa = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], per_atom=True)
+    torch.cuda.synchronize()
+    info, berr, pa = info.cpu().numpy(), berr.cpu().numpy(), pa.cpu().numpy()
+    assert (info == 0).all() and (berr[centres] <= 1e-14).all()
+    others = np.setdiff1d(np.arange(liz.n_atoms), centres)
+    assert (berr[others] == 0).all() and not pa[others].any() and np.isfinite(sig.cpu().numpy()).all()
+    _, _, kp, km = kkr.energies(w["e_fermi"], eta)
+    tpl, tmi = kkr.t_matrix(w["phase"], kp)
+    rng = np.random.default_rng(4)
+    for m in centres:
+        sl = slice(int(liz.ptr[m]), int(liz.ptr[m + 1]))
+        P_ = liz.pos[sl]
+        mem = liz.atom[sl]
+        for tag, tt, kap, tau in (("+", tpl, kp, tp), ("-", tmi, km, tm)):
+            X = tau[sl].cpu().numpy()  # [members, 16, 16]
+            tdiag = np.stack([kkr.expand_t(tt[a]) for a in mem])  # [members, 16]
+            for a in [0, 1] + list(rng.choice(np.arange(2, len(mem)), 4, replace=False)):
+                others_b = np.array([b for b in range(len(mem)) if b != a])
+                g = kkr.g0_blocks(P_[a] - P_[others_b], kap)  # [n-1, 16, 16]
+                tg = tdiag[a][None, :, None] * g
+                r = X[a] - np.einsum("bij,bjk->ik", tg, X[others_b])
+                if a == 0:
+                    r = r - np.diag(tdiag[0])
+                scale = (np.linalg.norm(X[a]) + sum(np.linalg.norm(tg[q]) * np.linalg.norm(X[b])
+                                                    for q, b in enumerate(others_b)) + (a == 0) * np.linalg.norm(tdiag[0]))
+                assert np.linalg.norm(r) <= 1e-12 * scale, (m, tag, a, np.linalg.norm(r) / scale)
