@@ -286,6 +286,14 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * the result is a stable LU either way (tau agrees to rounding).
  */
 #define LSMS_TUNE_TSLU_CHUNK 3
+/*
+ * knob LSMS_TUNE_LOOKAHEAD (0 or 1, default 0): with 1, lsms_tau_solve factors the first
+ * panel of the next pair on a second stream of the context (default priority) while the
+ * rest of the current trailing update runs on the caller's stream; events order them and
+ * the call's work is complete on the caller's stream when its last launch is.  Results
+ * are bitwise those of 0.  Not used inside captured graphs (LSMS_TUNE_GRAPHS).
+ */
+#define LSMS_TUNE_LOOKAHEAD 4
 int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
 int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
 

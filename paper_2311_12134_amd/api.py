@@ -205,6 +205,10 @@ class Context:
         """Replay each wave's factorization and first solve from captured HIP graphs."""
         check(lib().lsms_set_tuning(self._h, 1, 1 if on else 0))
 
+    def set_lookahead(self, on=True):
+        """Factor the next pair's first panel on a second stream during the trailing update."""
+        check(lib().lsms_set_tuning(self._h, 4, 1 if on else 0))
+
     def set_tslu_chunk(self, rows=2048):
         """Rows per chunk of the tournament-pivoting panels (used for panels taller than
         2 * rows; a multiple of 64 in [64, 2048])."""

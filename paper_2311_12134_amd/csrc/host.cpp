@@ -97,6 +97,8 @@ struct lsms_ctx {
   bool conj_symmetry = false;  // solve z+ only and derive z- (tau(z-) = P conj tau(z+) P)
   int tslu_chunk = 2048;       // rows per chunk of the tall-panel tournament
   DevBuf tall;                 // tall-panel scratch
+  bool lookahead = false;      // factor the next pair's first panel on a side stream
+  SideStream side;             // created on first use
   hipStream_t capture = nullptr;  // non-blocking stream the graphs are captured on
   std::map<std::vector<intptr_t>, hipGraphExec_t> graph_cache;
   EventProf prof;
@@ -289,8 +291,12 @@ extern "C" int lsms_destroy(lsms_ctx* ctx) {
   if (ctx->pinned) hipHostFree(ctx->pinned);
   if (ctx->pinned_flag) hipHostFree(ctx->pinned_flag);
   if (ctx->fallback.p) hipFree(ctx->fallback.p);
+  if (ctx->tall.p) hipFree(ctx->tall.p);
   for (auto& kv : ctx->graph_cache) hipGraphExecDestroy(kv.second);
   if (ctx->capture) hipStreamDestroy(ctx->capture);
+  if (ctx->side.update_done) hipEventDestroy(ctx->side.update_done);
+  if (ctx->side.panel_done) hipEventDestroy(ctx->side.panel_done);
+  if (ctx->side.stream) hipStreamDestroy(ctx->side.stream);
   delete ctx;
   return LSMS_OK;
 }
@@ -551,18 +557,36 @@ void launch_zero_i32(int32_t* p, int n, hipStream_t s);
 // caller's stream whenever the same shape and buffers come back.  Job descriptors, matrices
 // and right-hand sides are read from device memory at replay, after the caller's stream has
 // written them.
+static int side_stream(lsms_ctx* ctx, const SideStream** out) {
+  *out = nullptr;
+  if (!ctx->lookahead) return LSMS_OK;
+  if (!ctx->side.stream) {
+    HIP_TRY(hipStreamCreateWithFlags(&ctx->side.stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ctx->side.update_done, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ctx->side.panel_done, hipEventDisableTiming));
+  }
+  *out = &ctx->side;
+  return LSMS_OK;
+}
+
 static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int nj, int npad_max, void* abuf,
                             int32_t* piv, int32_t* jinfo, double2* xbuf, GemmProfiler* prof, hipStream_t s) {
   const int variant = gemm_f32_variant(ctx);
   TallScratch ts;
   int rc = tall_scratch(ctx, nj, npad_max, &ts, s);
   if (rc) return rc;
+  const SideStream* side = nullptr;
+  const bool capture = ctx->graphs && !prof;
+  if (!capture) {  // captured graphs keep the single-stream order
+    rc = side_stream(ctx, &side);
+    if (rc) return rc;
+  }
   auto issue = [&](hipStream_t q, GemmProfiler* pr) {
     if (precision == LSMS_FP64) {
-      lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, q, pr, ts);
+      lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, q, pr, ts, side);
       lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, q);
     } else {
-      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, ts);
+      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, ts, side);
       lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, q);
     }
   };
@@ -861,6 +885,11 @@ extern "C" int lsms_kubo_sigma_tensor(lsms_ctx* ctx, int32_t n_atoms, const int6
 
 extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
   if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  if (knob == LSMS_TUNE_LOOKAHEAD) {
+    if (value != 0 && value != 1) return fail(LSMS_E_ARG, "look-ahead takes 0 or 1 (got %d)", value);
+    ctx->lookahead = value == 1;
+    return LSMS_OK;
+  }
   if (knob == LSMS_TUNE_TSLU_CHUNK) {
     if (value < NB || value > 2048 || value % NB != 0)
       return fail(LSMS_E_ARG, "tournament chunk %d must be a multiple of %d in [%d, 2048]", value, NB, NB);
@@ -883,6 +912,10 @@ extern "C" int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value) {
   if (!ctx || !value) return fail(LSMS_E_ARG, "NULL argument");
   if (knob == LSMS_TUNE_TSLU_CHUNK) {
     *value = ctx->tslu_chunk;
+    return LSMS_OK;
+  }
+  if (knob == LSMS_TUNE_LOOKAHEAD) {
+    *value = ctx->lookahead ? 1 : 0;
     return LSMS_OK;
   }
   if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY) {

@@ -142,10 +142,18 @@ struct TallScratch {
 };
 size_t tall_scratch_bytes(int njobs, int npad_max, int chunk);
 
+// Optional second stream for the look-ahead panel (lu.hip); nullptr: one stream.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t update_done = nullptr;  // the next panel's columns are updated
+  hipEvent_t panel_done = nullptr;   // that panel is factored
+};
+
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof, const TallScratch& tall);
+                   hipStream_t s, GemmProfiler* prof, const TallScratch& tall, const SideStream* side = nullptr);
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall);
+                   hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall,
+                   const SideStream* side = nullptr);
 // Solve with the factors: trans = 0 solves M X = B, trans = 1 solves M^T X = B (in place on X).
 void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
                   double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);

@@ -864,9 +864,16 @@ static void update_cost(const GemmProfiler* prof, int njobs, int kd, int r_begin
 //   panel on the columns beyond -> one trailing update with K = 2 NB.
 // The big update therefore streams the trailing matrix once per 2 NB columns.  The solves
 // apply the second panel's permutation right after the first panel's triangle.
+// With a side stream, the trailing update is split at the next pair's first panel: its
+// NB columns are updated first, then that panel (and its inverses) is factored on the
+// side stream while the rest of the update runs on the main one.  The two touch disjoint
+// data (the panel reads and writes only its own columns and the diagonal block; the
+// update reads the L and U12 rows of this pair and writes columns past the panel), and the
+// next pair's interchanges wait for both.
 template <typename T, typename Gemm>
 static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work, int32_t* piv, int32_t* info,
-                          hipStream_t s, GemmProfiler* prof, const TallScratch& tall, Gemm gemm) {
+                          hipStream_t s, GemmProfiler* prof, const TallScratch& tall, const SideStream* side,
+                          Gemm gemm) {
   auto timed_gemm = [&](int k, int kd, int r_begin, int c_begin, int c_end) {
     const int rows = npad_max - r_begin;
     const int cols = (c_end > 0 ? std::min(c_end, npad_max) : npad_max) - c_begin;
@@ -879,8 +886,13 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
       prof->after(s, f, b, c_end > 0 ? 0 : 1);
     }
   };
+  bool ahead = false;  // this pair's first panel was factored on the side stream
   for (int k = 0; k < npad_max; k += 2 * NB) {
-    panel_step<T>(jobs, njobs, npad_max, k, 0, work, piv, info, tall, s);
+    if (ahead)
+      (void)hipStreamWaitEvent(s, side->panel_done, 0);
+    else
+      panel_step<T>(jobs, njobs, npad_max, k, 0, work, piv, info, tall, s);
+    ahead = false;
     const int rest = npad_max - k - NB;
     if (rest <= 0) break;
     swap_trsm_kernel<T, false><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, piv);
@@ -889,24 +901,38 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
     const int rest2 = npad_max - k - 2 * NB;
     if (rest2 <= 0) break;
     swap_trsm_kernel<T, true><<<dim3(rest2 / 64, njobs), 256, 0, s>>>(jobs, k + NB, work, piv);
-    timed_gemm(k, 2 * NB, k + 2 * NB, k + 2 * NB, 0);
+    if (side && rest2 > NB) {
+      timed_gemm(k, 2 * NB, k + 2 * NB, k + 2 * NB, k + 3 * NB);  // the next first panel's columns
+      (void)hipEventRecord(side->update_done, s);
+      (void)hipStreamWaitEvent(side->stream, side->update_done, 0);
+      panel_step<T>(jobs, njobs, npad_max, k + 2 * NB, 0, work, piv, info, tall, side->stream);
+      (void)hipEventRecord(side->panel_done, side->stream);
+      ahead = true;
+      timed_gemm(k, 2 * NB, k + 2 * NB, k + 3 * NB, 0);
+    } else {
+      timed_gemm(k, 2 * NB, k + 2 * NB, k + 2 * NB, 0);
+    }
   }
 }
 
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof, const TallScratch& tall) {
-  lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall,
+                   hipStream_t s, GemmProfiler* prof, const TallScratch& tall, const SideStream* side) {
+  lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall, side,
                          [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
                            launch_gemm_f64(jobs, njobs, rows, cols, k, kd, rb, cb, ce, work, s);
                          });
 }
 
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall) {
-  lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall,
+                   hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall,
+                   const SideStream* side) {
+  lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall, side,
                         [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
-                          // the narrow update of a pair's second panel (64 columns) keeps the 64 x 64 tiling
-                          launch_gemm_f32(ce > 0 ? 0 : gemm_variant, jobs, njobs, rows, cols, k, kd, rb, cb, ce, work, s);
+                          // the narrow update of a pair's second panel (64 columns, K = NB) keeps the
+                          // 64 x 64 tiling; the K = 2 NB updates (split or not at the look-ahead panel)
+                          // use the chosen tiling, so every element sums in the same order either way
+                          launch_gemm_f32(ce > 0 && kd == NB ? 0 : gemm_variant, jobs, njobs, rows, cols, k, kd, rb,
+                                          cb, ce, work, s);
                         });
 }
 

@@ -565,3 +565,29 @@ def test_paper_scale_liz_bcc16000(lctx):
                 scale = (np.linalg.norm(X[a]) + sum(np.linalg.norm(tg[q]) * np.linalg.norm(X[b])
                                                     for q, b in enumerate(others_b)) + (a == 0) * np.linalg.norm(tdiag[0]))
                 assert np.linalg.norm(r) <= 1e-12 * scale, (m, tag, a, np.linalg.norm(r) / scale)
+
+
+@pytest.mark.parametrize("name,precision,chunk", [("fcc32", "fp64", 2048), ("bcc250", "split", 2048),
+                                                  ("bcc1940", "split", 2048), ("bcc250", "split", 256)])
+def test_lookahead_matches_single_stream(lctx, name, precision, chunk):
+    """The look-ahead schedule (next first panel on a second stream) gives bitwise the
+    single-stream result, also with tournament panels."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload(name)
+    eta = w["etas"][0]
+    print("[gpu] look-ahead %s %s chunk %d" % (name, precision, chunk), flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    lctx.set_tslu_chunk(chunk)
+    try:
+        lctx.set_lookahead(False)
+        a = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
+        lctx.set_lookahead(True)
+        b = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
+        torch.cuda.synchronize()
+    finally:
+        lctx.set_lookahead(False)
+        lctx.set_tslu_chunk(2048)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert (a[2].cpu().numpy() == 0).all()
