@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--paper-scale-atoms", type=int, default=26,
                     help="atoms of the 16,000-atom bcc alloy (965-site LIZ) timed in the separately reported "
                          "paper-scale leg (0: skip)")
+    ap.add_argument("--paper-scale-only", action="store_true",
+                    help="run only the paper-scale leg (for profiling it) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy before the timed region (scale for HBM counters)")
     args = ap.parse_args()
@@ -140,6 +142,13 @@ def main():
     import torch
     import paper_2311_12134_amd as P
     import synthetic
+
+    if args.paper_scale_only:
+        ctx = P.Context(0)
+        res = paper_scale_leg(P, torch, ctx, max(args.paper_scale_atoms, 1), args.precision)
+        ctx.close()
+        print(json.dumps(res), flush=True)
+        return
 
     w = synthetic.workload(args.workload)
     etas = list(w["etas"])
