@@ -134,3 +134,12 @@ def test_liz_paper_scale_membership():
     assert int((r < w["r_liz"]).sum()) == 965
     got = np.sort(np.linalg.norm(L.pos[L.ptr[7]:L.ptr[8]], axis=1))
     assert np.allclose(got, np.sort(r[r < w["r_liz"]]), rtol=0, atol=1e-9)
+
+
+def test_liz_above_limit_is_rejected():
+    """r_LIZ = 5.0a in bcc gives 1037 sites, more than the 1024 the solves accept."""
+    import paper_2311_12134_amd as P
+    from paper_2311_12134_amd._lib import LsmsError
+    w = synthetic.workload("bcc16000")
+    with pytest.raises(LsmsError):
+        P.build_liz(w["pos"], w["cell"], 5.0 * w["a"], centres=[0])

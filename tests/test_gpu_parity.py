@@ -591,3 +591,67 @@ def test_lookahead_matches_single_stream(lctx, name, precision, chunk):
     for x, y in zip(a, b):
         assert torch.equal(x, y)
     assert (a[2].cpu().numpy() == 0).all()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("split", TOL_SPLIT)])
+def test_single_site_and_small_open_clusters(lctx, precision, tol):
+    """Degenerate sizes: an isolated atom (LIZ of 1 site, n = 16 padded to 64: tau = t
+    exactly), a pair and a triangle of an open cluster, in one batch, against the oracle."""
+    import paper_2311_12134_amd as P
+    pos = np.array([[0.0, 0.0, 0.0], [4.2, 0.3, 0.1], [0.4, 4.1, -0.3], [40.0, 0.0, 0.0], [47.0, 1.0, 0.0]])
+    species = np.array([0, 1, 0, 1, 0], dtype=np.int32)
+    phase = np.array([[0.8, 0.2, 0.6, 0.01], [0.7, 0.25, 0.3, 0.01]])[species]
+    J = synthetic.current_matrices(2, np.random.default_rng(31))
+    w = dict(pos=pos, cell=None, r_liz=7.5, species=species, phase=phase, J=J, e_fermi=0.65, volume=900.0)
+    print("[gpu] small open clusters %s" % precision, flush=True)
+    liz = P.build_liz(pos, None, w["r_liz"])
+    assert list(np.diff(liz.ptr)) == [3, 3, 3, 2, 2]
+    iso = P.build_liz(pos, None, 5.0)
+    assert np.diff(iso.ptr)[3] == 1
+    for L in (liz, iso):
+        la, lp, ph, sp, Jd = _device_inputs(w, L)
+        tp, tm, info, _ = lctx.tau_solve(L, la, lp, ph, w["e_fermi"], 0.004, precision=precision)
+        _, _, pa = lctx.kubo_sigma(L, la, tp, tm, sp, Jd, w["volume"], per_atom=True)
+        torch.cuda.synchronize()
+        assert (info.cpu().numpy() == 0).all()
+        o = kubo.sigma(pos, None, w["r_liz"], species, phase, J, w["e_fermi"], 0.004, volume=w["volume"],
+                       liz_lists=(L.ptr, L.atom, L.pos))
+        for i in range(5):
+            sl = slice(int(L.ptr[i]), int(L.ptr[i + 1]))
+            for tag, t in (("+", tp), ("-", tm)):
+                ref = o["tau"][i]["col" + tag]
+                err = np.linalg.norm(t[sl].cpu().numpy() - ref) / np.linalg.norm(ref)
+                assert err <= tol, (i, tag, err)
+            ref = o["per_atom"][i]
+            assert np.abs(pa[i].cpu().numpy() - ref).max() <= tol * np.abs(ref).max(), i
+    # the isolated atom: tau^{00} = t exactly (diagonal, no scattering partners)
+    _, _, kp, _ = kkr.energies(w["e_fermi"], 0.004)
+    t3 = kkr.expand_t(kkr.t_matrix(phase, kp)[0][3])
+    la, lp, ph, sp, Jd = _device_inputs(w, iso)
+    tp = lctx.tau_solve(iso, la, lp, ph, w["e_fermi"], 0.004, precision=precision)[0]
+    got = tp[int(iso.ptr[3])].cpu().numpy()
+    assert np.abs(got - np.diag(t3)).max() <= 1e-15 * np.abs(t3).max() * 16
+
+
+def test_one_centre_subset(lctx):
+    """Only one centre of a structure solved (every other atom's LIZ empty): its tau and
+    Kubo sum equal those of the full run, the skipped atoms report zeros."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc250")
+    eta = w["etas"][0]
+    print("[gpu] one-centre subset bcc250", flush=True)
+    full = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    sub = P.build_liz(w["pos"], w["cell"], w["r_liz"], centres=[77])
+    res = []
+    for L in (full, sub):
+        la, lp, ph, sp, Jd = _device_inputs(w, L)
+        tp, tm, info, berr = lctx.tau_solve(L, la, lp, ph, w["e_fermi"], eta, precision="fp64")
+        _, st, pa = lctx.kubo_sigma(L, la, tp, tm, sp, Jd, w["volume"], per_atom=True)
+        torch.cuda.synchronize()
+        res.append((L, tp.cpu().numpy(), info.cpu().numpy(), pa.cpu().numpy(), st.cpu().numpy()))
+    (F, tpf, _, paf, _), (S, tps, infos, pas, sts) = res
+    a, b = slice(F.ptr[77], F.ptr[78]), slice(S.ptr[77], S.ptr[78])
+    assert np.allclose(tps[b], tpf[a], rtol=0, atol=1e-13 * np.abs(tpf[a]).max())
+    assert np.allclose(pas[77], paf[77], rtol=1e-12)
+    assert (infos == 0).all() and not np.delete(pas, 77, axis=0).any()
+    assert np.allclose(sts, -pas[77] / (np.pi * w["volume"]), rtol=1e-14)
