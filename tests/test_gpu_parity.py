@@ -655,3 +655,56 @@ def test_one_centre_subset(lctx):
     assert np.allclose(pas[77], paf[77], rtol=1e-12)
     assert (infos == 0).all() and not np.delete(pas, 77, axis=0).any()
     assert np.allclose(sts, -pas[77] / (np.pi * w["volume"]), rtol=1e-14)
+
+
+def test_adjoint_with_tournament_panels(lctx):
+    """The adjoint's transposed solves reuse factors whose panels came from the tournament
+    (250-atom alloy, 256-row chunks): the gradient equals the one from register panels
+    (itself checked against the oracle and finite differences) to 1e-9."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc250grad")
+    eta = w["etas"][0]
+    liz, la, lp, species, J = _grad_setup(w)
+    dsig = torch.tensor([1.0, 0.0, 0.0], dtype=torch.float64, device="cuda")
+    print("[gpu] adjoint with tournament panels bcc250", flush=True)
+
+    def grad():
+        ph = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(torch.device("cuda", 0)).requires_grad_(True)
+        sig = P.KuboSigma.apply(ph, lctx, liz, la, lp, species, J, w["volume"], w["e_fermi"], eta)
+        sig.backward(dsig)
+        return ph.grad.cpu().numpy()
+
+    ref = grad()
+    lctx.set_tslu_chunk(256)
+    try:
+        g = grad()
+    finally:
+        lctx.set_tslu_chunk(2048)
+    assert np.abs(g - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_graph_replay_with_tournament_panels(lctx):
+    """Captured factorization + first solve with tournament panels (chunk 256), replayed three
+    times with eager work in between: bitwise the eager result."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc250")
+    eta = w["etas"][0]
+    print("[gpu] graphs with tournament panels bcc250", flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    lctx.set_tslu_chunk(256)
+    try:
+        def solve():
+            tp, tm, info, _ = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision="split")
+            torch.cuda.synchronize()
+            return tp.cpu().numpy(), tm.cpu().numpy(), info.cpu().numpy()
+        ref = solve()
+        assert (ref[2] == 0).all()
+        lctx.set_graphs(True)
+        for rep in range(3):
+            got = solve()
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), rep
+    finally:
+        lctx.set_graphs(False)
+        lctx.set_tslu_chunk(2048)
