@@ -29,6 +29,13 @@ __host__ __device__ inline double2 cfms(double2 a, double2 b, double2 c) {
 __host__ __device__ inline double2 cfma(double2 a, double2 b, double2 c) {
   return make_double2(a.x + (b.x * c.x - b.y * c.y), a.y + (b.x * c.y + b.y * c.x));
 }
+// the same in single precision (split-mode panel updates in the storage precision)
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cfms(float2 a, float2 b, float2 c) {
+  return make_float2(a.x - (b.x * c.x - b.y * c.y), a.y - (b.x * c.y + b.y * c.x));
+}
 __host__ __device__ inline double2 cinv(double2 a) {
   // Smith-style scaling avoids overflow for large components.
   if (fabs(a.x) >= fabs(a.y)) {

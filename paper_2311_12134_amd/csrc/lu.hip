@@ -4,10 +4,11 @@
 // All jobs of a wave advance through the same panel steps; every panel is a few
 // launches over the whole batch (panels come in look-ahead pairs, see lu_factor_any):
 //   panel_kernel      one workgroup per job factors rows [k, n) x cols [k, k+NB) with
-//                     partial pivoting (pivot = largest |re|+|im|, first on ties) in FP64:
-//                     IB-wide leaves live in registers (rows distributed cyclically over
-//                     the workgroup), every pivot swaps the whole panel row, and the rest
-//                     of the panel is updated by the leaf (triangular solve + rank-IB).
+//                     partial pivoting (pivot = largest |re|+|im|, first on ties, keys
+//                     compared in FP64): IB-wide leaves live in registers (rows distributed
+//                     cyclically over the workgroup) and are updated in the storage
+//                     precision, every pivot swaps the whole panel row, and the rest of the
+//                     panel is updated by the leaf (triangular solve + rank-IB).
 //   swap_trsm_kernel  applies the panel's row interchanges to the trailing columns and
 //                     forms U12 = L11^-1 A12 (one workgroup per 64-column tile).
 //   gemm_*_kernel     (gemm.hip) trailing update A22 -= L21 U12 on the matrix cores:
@@ -111,8 +112,8 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   // next writers (column j + 1) start after barrier j.  A row buffer written before
   // barrier j is rewritten only before barrier j + 2, after every read of column j.
   __shared__ unsigned long long s_key[3];
-  __shared__ double2 s_cand[2][NW][IB];
-  __shared__ double2 s_drow[2][IB];
+  __shared__ T s_cand[2][NW][IB];
+  __shared__ T s_drow[2][IB];
   __shared__ int s_piv[IB];
   __shared__ double2 s_L11[IB][IB];
   __shared__ double2 s_Li[IB][IB];
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
           for (int s = 0; s < S; ++s)
             if (s == rl / PT) {
 #pragma unroll
-              for (int q = 0; q < IB; ++q) s_cand[buf][wave][q] = wide(v[s][q]);
+              for (int q = 0; q < IB; ++q) s_cand[buf][wave][q] = v[s][q];
             }
         }
       }
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
         for (int s = 0; s < S; ++s)
           if (s == sd) {
 #pragma unroll
-            for (int q = 0; q < IB; ++q) s_drow[buf][q] = wide(v[s][q]);
+            for (int q = 0; q < IB; ++q) s_drow[buf][q] = v[s][q];
           }
       }
       if (t == 0) s_key[(col + 1) % 3] = 0ull;
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       int p = best != 0ull ? k + pivot_row(best) : d;
       const bool from_cand = best != 0ull && p >= d && p < nrows;
       if (!from_cand) p = d;
-      const double2* prow = from_cand ? s_cand[buf][((p - k) % PT) / 64] : s_drow[buf];
+      const T* prow = from_cand ? s_cand[buf][((p - k) % PT) / 64] : s_drow[buf];
       const int op = (p - k) % PT, sp = (p - k) / PT;
       if (t == 0) {
         s_piv[j] = p;
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
         for (int s = 0; s < S; ++s)
           if (s == sd) {
 #pragma unroll
-            for (int q = 0; q < IB; ++q) narrow_to(v[s][q], prow[q]);
+            for (int q = 0; q < IB; ++q) v[s][q] = prow[q];
           }
       }
       if (t == op && p != d) {
@@ -205,22 +206,25 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
         for (int s = 0; s < S; ++s)
           if (s == sp) {
 #pragma unroll
-            for (int q = 0; q < IB; ++q) narrow_to(v[s][q], s_drow[buf][q]);
+            for (int q = 0; q < IB; ++q) v[s][q] = s_drow[buf][q];
           }
       }
-      const double2 pv = prow[j];
+      const double2 pv = wide(prow[j]);
       const bool zero = (pv.x == 0.0 && pv.y == 0.0);
       if (zero && first_zero == 0) first_zero = d + 1;
-      const double2 inv = zero ? make_double2(0.0, 0.0) : cinv(pv);
+      T inv;  // the pivot's inverse in FP64, rounded once to the storage precision
+      narrow_to(inv, zero ? make_double2(0.0, 0.0) : cinv(pv));
+      // the leaf's rank-1 update in the storage precision (FP32 in split mode, like the
+      // trailing updates; the pivot keys above compare these values in FP64)
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int r = k + t + s * PT;
         if (r > d && r < nrows) {
-          const double2 l = cmul(wide(v[s][j]), inv);
-          narrow_to(v[s][j], l);
+          const T l = cmul(v[s][j], inv);
+          v[s][j] = l;
 #pragma unroll
           for (int q = 0; q < IB; ++q)  // full range: j is a constant once unrolled
-            if (q > j) narrow_to(v[s][q], cfms(wide(v[s][q]), l, prow[q]));
+            if (q > j) v[s][q] = cfms(v[s][q], l, prow[q]);
         }
       }
     }
