@@ -59,7 +59,7 @@ typedef enum {
 
 typedef enum {
   LSMS_FP64 = 0,  /* whole factorization and solve in FP64 */
-  LSMS_SPLIT = 1  /* FP32 trailing updates + FP64 panels, residuals, refinement */
+  LSMS_SPLIT = 1  /* FP32 LU updates, FP64 pivot selection, residuals, refinement */
 } lsms_precision;
 
 /* Per-job status codes written to info[] by lsms_tau_solve. */

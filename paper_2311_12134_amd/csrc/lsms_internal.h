@@ -57,7 +57,7 @@ __device__ inline double2 ld2(const float2* p) {
 __device__ inline void st2(double2* p, double2 v) { *p = v; }
 __device__ inline void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
 // LDS element type matching a storage type: FP32 factors stay FP32 in LDS (half the
-// footprint, so two workgroups share a CU); arithmetic is FP64 either way.
+// footprint, so two workgroups share a CU).
 template <typename T> struct LdsOf { typedef double2 type; };
 template <> struct LdsOf<float2> { typedef float2 type; };
 

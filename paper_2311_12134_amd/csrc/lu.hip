@@ -124,7 +124,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   __shared__ T s_held[2 * IB][2 * NB - IB];
   __shared__ T s_Lc[PT][IB];
 
-  // the leaf in registers in the storage precision; arithmetic is FP64
+  // the leaf in registers in the storage precision (its updates too; pivot keys in FP64)
   T v[S][IB];
   int first_zero = 0;
   if (t < 3) s_key[t] = 0ull;
