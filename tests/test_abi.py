@@ -143,3 +143,39 @@ def test_liz_above_limit_is_rejected():
     w = synthetic.workload("bcc16000")
     with pytest.raises(LsmsError):
         P.build_liz(w["pos"], w["cell"], 5.0 * w["a"], centres=[0])
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/lsms_kkr.h compiles as C99 and a C program linked against the library can
+    call the host entry points (LIZ construction, Gaunt table, error text)."""
+    import shutil
+    import subprocess
+    from paper_2311_12134_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi_check.c"
+    src.write_text(r"""
+#include <stdio.h>
+#include "lsms_kkr.h"
+int main(void) {
+  double pos[6] = {0, 0, 0, 3.0, 0, 0};
+  int64_t ptr[3], needed = 0;
+  int32_t atom[4];
+  double disp[12];
+  double gaunt[16 * 16 * 49];
+  int rc = lsms_build_liz(NULL, 2, pos, NULL, 4.0, 4, ptr, atom, disp, &needed);
+  if (rc != LSMS_OK || needed != 4 || ptr[1] != 2 || ptr[2] != 4 || atom[0] != 0 || atom[1] != 1) return 1;
+  if (lsms_build_liz(NULL, 2, pos, NULL, -1.0, 4, ptr, atom, disp, &needed) != LSMS_E_ARG) return 2;
+  if (lsms_last_error()[0] == 0) return 3;
+  if (lsms_gaunt_table(gaunt) != LSMS_OK || gaunt[0] < 0.28 || gaunt[0] > 0.29) return 4;
+  printf("ok %lld\n", (long long)needed);
+  return 0;
+}
+""")
+    exe = tmp_path / "abi_check"
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                    "-L", libdir, "-llsms_kkr", "-Wl,-rpath," + libdir], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip() == "ok 4", (out.returncode, out.stdout, out.stderr)
