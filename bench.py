@@ -64,6 +64,39 @@ def cpu_baseline(w, eta, n_sample):
                       "blocks + Kubo traces), %.1f s" % (n_sample, eta, dt)}
 
 
+def adjoint_leg(P, torch, ctx):
+    """The gradient configuration (250-atom bcc A0.5B0.5 alloy, LIZ 89 sites, FP64):
+    sigma with its factors kept, then d sigma_xx / d delta_l for all 250 x 4 phase shifts
+    through the hand-written adjoint; one warm-up and one timed forward + backward."""
+    import synthetic
+    w = synthetic.workload("bcc250grad")
+    dev = torch.device("cuda", 0)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp = liz.to_device(dev)
+    species = torch.from_numpy(w["species"].astype(np.int32)).to(dev)
+    J = torch.from_numpy(np.ascontiguousarray(w["J"])).to(dev)
+    eta = w["etas"][0]
+    dsig = torch.tensor([1.0, 0.0, 0.0], dtype=torch.float64, device=dev)
+
+    def run():
+        ph = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(dev).requires_grad_(True)
+        t0 = time.perf_counter()
+        sig = P.KuboSigma.apply(ph, ctx, liz, la, lp, species, J, w["volume"], w["e_fermi"], eta)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sig.backward(dsig)
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1, ph.grad
+
+    run()
+    tf, tb, g = run()
+    log("adjoint leg: forward %.1f ms, backward %.1f ms" % (1e3 * tf, 1e3 * tb))
+    return {"workload": "bcc250grad: random bcc A0.5B0.5, 250 atoms, LIZ 89 sites (n = 1424), FP64, "
+                        "d sigma_xx / d delta_l for 250 x 4 phase shifts",
+            "forward_ms": 1e3 * tf, "backward_ms": 1e3 * tb, "backward_over_forward": tb / tf,
+            "grad_finite": bool(torch.isfinite(g).all().item())}
+
+
 def paper_scale_leg(P, torch, ctx, n_sample, precision):
     """The paper's large-LIZ setting (16,000-atom bcc alloy, LIZ of 965 sites, n = 15440):
     a seeded sample of centre atoms (the others get empty LIZ and are skipped), one warm-up
@@ -129,6 +162,8 @@ def main():
     ap.add_argument("--paper-scale-atoms", type=int, default=26,
                     help="atoms of the 16,000-atom bcc alloy (965-site LIZ) timed in the separately reported "
                          "paper-scale leg (0: skip)")
+    ap.add_argument("--no-adjoint-leg", action="store_true",
+                    help="skip the separately reported gradient run (250-atom bcc alloy, d sigma_xx / d delta)")
     ap.add_argument("--paper-scale-only", action="store_true",
                     help="run only the paper-scale leg (for profiling it) and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -291,6 +326,8 @@ def main():
         log("conj-symmetry leg: %.1f ms/step, %.1f atoms/s" % (1e3 * tc / args.steps, n_atoms * args.steps / tc))
     if args.paper_scale_atoms > 0:
         out["paper_scale_liz"] = paper_scale_leg(P, torch, ctx, args.paper_scale_atoms, args.precision)
+    if not args.no_adjoint_leg:
+        out["adjoint"] = adjoint_leg(P, torch, ctx)
     ctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, etas[0], args.cpu_sample)
