@@ -294,6 +294,18 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * are bitwise those of 0.  Not used inside captured graphs (LSMS_TUNE_GRAPHS).
  */
 #define LSMS_TUNE_LOOKAHEAD 4
+/*
+ * knob LSMS_TUNE_SYMMETRIC (0 or 1, default 0): with 1, split-mode lsms_tau_solve works on
+ * the complex-symmetric form S = T^{1/2} M T^{-1/2} = 1 - T^{1/2} g T^{1/2} (g is symmetric by
+ * reciprocity; T^{1/2} holds the principal square roots of the t_l, so no t is inverted):
+ * S Y = T^{1/2} E0 is solved with an unpivoted L D L^T factorization in FP32 (half the
+ * trailing-update work of the LU), refined in FP64 against an FP64 copy of S, and
+ * tau^{a0} = t_a^{1/2} Y_a.  Systems whose refinement does not converge (e.g. large
+ * element growth without pivoting) fall back to the FP64 LU with partial pivoting of S, as
+ * in the LU path.  Used only for systems of at most 4096 rows and without kept factors;
+ * otherwise the LU path runs.  Not the paper's LU: reported apart from the LU rate.
+ */
+#define LSMS_TUNE_SYMMETRIC 5
 int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
 int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
 

@@ -209,6 +209,11 @@ class Context:
         """Factor the next pair's first panel on a second stream during the trailing update."""
         check(lib().lsms_set_tuning(self._h, 4, 1 if on else 0))
 
+    def set_symmetric(self, on=True):
+        """Split mode: symmetric form and L D L^T (no pivoting) with FP64 refinement and
+        fallback, instead of the LU (systems of at most 4096 rows, no kept factors)."""
+        check(lib().lsms_set_tuning(self._h, 5, 1 if on else 0))
+
     def set_tslu_chunk(self, rows=2048):
         """Rows per chunk of the tournament-pivoting panels (used for panels taller than
         2 * rows; a multiple of 64 in [64, 2048])."""

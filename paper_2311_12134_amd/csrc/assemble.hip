@@ -61,8 +61,21 @@ hipError_t upload_gaunt(const GauntTable& g) {
   return hipMemcpyToSymbol(HIP_SYMBOL(c_slots), &sl, sizeof(GauntSlots));
 }
 
-// t_l(z+) = -sin(d) e^{i d} / kappa+, t(z-) = conj(t(z+)).
-__global__ void tmatrix_kernel(const double* phase, int n_atoms, double2 kp, double2* tpm) {
+// principal square root, formed without cancellation
+__device__ inline double2 csqrt_p(double2 z) {
+  const double r = hypot(z.x, z.y);
+  if (r == 0.0) return make_double2(0.0, 0.0);
+  if (z.x >= 0.0) {
+    const double u = sqrt(0.5 * (r + z.x));
+    return make_double2(u, z.y / (2.0 * u));
+  }
+  const double v = sqrt(0.5 * (r - z.x));
+  return make_double2(fabs(z.y) / (2.0 * v), z.y >= 0.0 ? v : -v);
+}
+
+// t_l(z+) = -sin(d) e^{i d} / kappa+, t(z-) = conj(t(z+)); spm (optional): their principal
+// square roots, the scaling of the symmetric form T^{1/2} (1 - g T) T^{-1/2} = 1 - T^{1/2} g T^{1/2}.
+__global__ void tmatrix_kernel(const double* phase, int n_atoms, double2 kp, double2* tpm, double2* spm) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n_atoms * 4) return;
   int atom = idx / 4, l = idx % 4;
@@ -71,13 +84,19 @@ __global__ void tmatrix_kernel(const double* phase, int n_atoms, double2 kp, dou
   sincos(d, &sd, &cd_);
   double2 num = make_double2(-sd * cd_, -sd * sd);  // -sin d (cos d + i sin d)
   double2 t = cmul(num, cinv(kp));
+  const double2 tm = make_double2(t.x, -t.y);
   tpm[atom * 8 + l] = t;
-  tpm[atom * 8 + 4 + l] = make_double2(t.x, -t.y);
+  tpm[atom * 8 + 4 + l] = tm;
+  if (spm) {
+    spm[atom * 8 + l] = csqrt_p(t);
+    spm[atom * 8 + 4 + l] = csqrt_p(tm);
+  }
 }
 
-void launch_tmatrix(const double* phase, int n_atoms, double2 kappa_plus, double2* tpm, hipStream_t s) {
+void launch_tmatrix(const double* phase, int n_atoms, double2 kappa_plus, double2* tpm, double2* spm,
+                    hipStream_t s) {
   int n = n_atoms * 4;
-  tmatrix_kernel<<<(n + 255) / 256, 256, 0, s>>>(phase, n_atoms, kappa_plus, tpm);
+  tmatrix_kernel<<<(n + 255) / 256, 256, 0, s>>>(phase, n_atoms, kappa_plus, tpm, spm);
 }
 
 __device__ inline int lidx(int L) { return L == 0 ? 0 : (L < 4 ? 1 : (L < 9 ? 2 : 3)); }
@@ -121,10 +140,11 @@ __device__ inline void ylm_column(int m, double x, double y, double z, double* Y
 // fourth thread), into LDS.  Phase 2: each wavefront contracts its blocks against the
 // slot-dealt Gaunt terms, applies i^{l - l'} and -t_a, stages the block in LDS and writes it
 // row by row.  Diagonal and padding blocks are the identity / zero.
+// spm != nullptr: the symmetric form, blocks -s_a g_ab s_b (s = t^{1/2}) instead of -t_a g_ab.
 template <typename T>
 __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, const double* liz_pos,
                                                        const int32_t* liz_atom, const double2* tpm, double2 kp,
-                                                       double2 km, T* work, double2* m64) {
+                                                       double2 km, T* work, double2* m64, const double2* spm) {
   constexpr int BPW = 64;
   __shared__ double s_coef[4][64][GT];
   __shared__ uint16_t s_l3[4][64][GT];
@@ -192,6 +212,8 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
     if (a != b && a < jd.nl && b < jd.nl) {
       const int atom_a = liz_atom[jd.liz_off + a];
       const double2* ta = tpm + atom_a * 8 + jd.energy * 4;
+      const double2* sa = spm ? spm + atom_a * 8 + jd.energy * 4 : nullptr;
+      const double2* sb = spm ? spm + liz_atom[jd.liz_off + b] * 8 + jd.energy * 4 : nullptr;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int pr = s_pair[r][lane], L = pr & 15, Lp = (pr >> 4) & 15, e = pr >> 8;
@@ -206,7 +228,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
         // i^{l - l'}, then -t_a
         const double2 gp = e == 0 ? g : e == 1 ? make_double2(-g.y, g.x) : e == 2 ? make_double2(-g.x, -g.y)
                                                                                       : make_double2(g.y, -g.x);
-        const double2 tg = cmul(ta[lidx(L)], gp);
+        const double2 tg = spm ? cmul(cmul(sa[lidx(L)], gp), sb[lidx(Lp)]) : cmul(ta[lidx(L)], gp);
         s_G[wave][L][Lp] = make_double2(-tg.x, -tg.y);
       }
       __builtin_amdgcn_wave_barrier();
@@ -237,15 +259,15 @@ void launch_assemble_f64(const JobDesc* jobs, int njobs, int npad_max, const dou
                          hipStream_t s) {
   const int nbp = npad_max / NL;
   dim3 grid((nbp * nbp + 63) / 64, njobs);
-  assemble_kernel<double2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, nullptr);
+  assemble_kernel<double2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, nullptr, nullptr);
 }
 
 void launch_assemble_split(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
                            const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, float2* work,
-                           double2* m64, hipStream_t s) {
+                           double2* m64, const double2* spm, hipStream_t s) {
   const int nbp = npad_max / NL;
   dim3 grid((nbp * nbp + 63) / 64, njobs);
-  assemble_kernel<float2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, m64);
+  assemble_kernel<float2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, m64, spm);
 }
 
 // B = E0 t_centre: rows (0, L) carry t_l of the centre on the diagonal.
@@ -276,14 +298,16 @@ __device__ inline int l_of(int L) { return L < 1 ? 0 : L < 4 ? 1 : L < 9 ? 2 : 3
 // tau(z-)_{LL'} = (-1)^{l+l'} conj(tau(z+)_{LL'}): kappa- = -conj(kappa+) and
 // t(z-) = conj t(z+) give g(z-) = P conj(g(z+)) P, P = diag((-1)^l), hence
 // 1 - t g and its inverse times t transform the same way.
+// With spm (symmetric form) the solution is Y = S^-1 T^{1/2} E0 and tau^{a0} = s_a Y_a.
 __global__ void copy_tau_kernel(const JobDesc* jobs, const double2* x, double2* tau_plus, double2* tau_minus,
-                                int mirror) {
+                                int mirror, const double2* spm, const int32_t* liz_atom) {
   const JobDesc jd = jobs[blockIdx.y];
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= jd.n * NL) return;
   int row = idx / NL, col = idx % NL;
   double2* out = jd.energy == 0 ? tau_plus : tau_minus;
-  const double2 v = x[jd.x_off + (int64_t)row * NRHS_MAX + col];
+  double2 v = x[jd.x_off + (int64_t)row * NRHS_MAX + col];
+  if (spm) v = cmul(spm[liz_atom[jd.liz_off + row / NL] * 8 + jd.energy * 4 + l_of(row % NL)], v);
   out[jd.liz_off * NL * NL + idx] = v;
   if (mirror) {
     const double sg = ((l_of(row % NL) + l_of(col)) & 1) ? -1.0 : 1.0;
@@ -292,9 +316,9 @@ __global__ void copy_tau_kernel(const JobDesc* jobs, const double2* x, double2* 
 }
 
 void launch_copy_tau(const JobDesc* jobs, int njobs, int npad_max, const double2* x, double2* tau_plus,
-                     double2* tau_minus, bool mirror, hipStream_t s) {
+                     double2* tau_minus, bool mirror, const double2* spm, const int32_t* liz_atom, hipStream_t s) {
   dim3 grid((npad_max * NL + 255) / 256, njobs);
-  copy_tau_kernel<<<grid, 256, 0, s>>>(jobs, x, tau_plus, tau_minus, mirror ? 1 : 0);
+  copy_tau_kernel<<<grid, 256, 0, s>>>(jobs, x, tau_plus, tau_minus, mirror ? 1 : 0, spm, liz_atom);
 }
 
 __global__ void check_inputs_kernel(const JobDesc* jobs, const double* liz_pos, const int32_t* liz_atom,

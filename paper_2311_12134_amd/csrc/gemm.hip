@@ -170,11 +170,13 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, i
 // share L21 and U12 panels, run on the same XCD (workgroups are dealt to the eight XCDs
 // round-robin) and hit the same L2.
 // ------------------------------------------------------------------------------------
-template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false>
+template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false>
 __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, int tiles_x, int tiles_y, int k, int kd,
                                                          int r_begin, int c_begin, int c_end, float2* work) {
   // KC: K chunk per LDS stage.  PFC: the wave's C elements are loaded two chunks before
   // the end, so their latency overlaps the last chunks' MFMAs instead of the epilogue.
+  // TRI: only the tiles on and below the diagonal of the (square) updated block, numbered
+  // row by row (tile row y holds y + 1 tiles) -- the symmetric factorization's update.
   constexpr int WAVES_N = TN / WN;
   static_assert((TM / WM) * (TN / WN) == 4, "four waves per workgroup");
   constexpr int BM = WM / 16, BN = WN / 16;
@@ -188,10 +190,22 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
     const int N = gridDim.x, q = N >> 3, r = N & 7, x = T & 7;
     T = x * q + min(x, r) + (T >> 3);
   }
-  const int tx = T % tiles_x;
-  T /= tiles_x;
-  const int ty = T % tiles_y;
-  const JobDesc jd = jobs[T / tiles_y];
+  int tx, ty, job;
+  if (TRI) {
+    const int per = tiles_y * (tiles_y + 1) / 2, u = T % per;
+    job = T / per;
+    int y = (int)((sqrtf(8.0f * (float)u + 1.0f) - 1.0f) * 0.5f);
+    while (y * (y + 1) / 2 > u) --y;
+    while ((y + 1) * (y + 2) / 2 <= u) ++y;
+    ty = y;
+    tx = u - y * (y + 1) / 2;
+  } else {
+    tx = T % tiles_x;
+    T /= tiles_x;
+    ty = T % tiles_y;
+    job = T / tiles_y;
+  }
+  const JobDesc jd = jobs[job];
   const int row0 = r_begin + ty * TM, col0 = c_begin + tx * TN;
   const int npad = jd.npad;
   const int cmax = c_end > 0 ? min(c_end, npad) : npad;
@@ -345,13 +359,20 @@ void launch_gemm_f64(const JobDesc* jobs, int njobs, int rows, int cols, int k, 
   gemm_f64_kernel<<<grid, 256, 0, s>>>(jobs, k, kd, r_begin, c_begin, c_end, work);
 }
 
-template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false>
+template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false>
 static void launch_tiled(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                          int c_begin, int c_end, float2* work, hipStream_t s) {
   const int tx = (cols + TN - 1) / TN, ty = (rows + TM - 1) / TM;
-  const int64_t n = (int64_t)tx * ty * njobs;
-  gemm_f32_3m_tiled<TM, TN, WM, WN, XCD, KC, PFC><<<(unsigned)n, 256, 0, s>>>(jobs, tx, ty, k, kd, r_begin, c_begin,
-                                                                              c_end, work);
+  const int64_t n = TRI ? (int64_t)ty * (ty + 1) / 2 * njobs : (int64_t)tx * ty * njobs;
+  gemm_f32_3m_tiled<TM, TN, WM, WN, XCD, KC, PFC, TRI><<<(unsigned)n, 256, 0, s>>>(jobs, tx, ty, k, kd, r_begin,
+                                                                                   c_begin, c_end, work);
+}
+
+// Lower-triangle tiles only (rows and columns start together): the update
+// A22 -= L21 (D L21^T) of the symmetric factorization, 64 x 64 tiles, XCD-ordered.
+void launch_gemm_f32_lower(const JobDesc* jobs, int njobs, int rows, int k, int kd, int rc_begin, float2* work,
+                           hipStream_t s) {
+  launch_tiled<64, 64, 32, 32, true, 16, false, true>(jobs, njobs, rows, rows, k, kd, rc_begin, rc_begin, 0, work, s);
 }
 
 int gemm_f32_variants() { return 9; }

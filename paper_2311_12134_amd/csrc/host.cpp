@@ -98,6 +98,7 @@ struct lsms_ctx {
   int tslu_chunk = 2048;       // rows per chunk of the tall-panel tournament
   DevBuf tall;                 // tall-panel scratch
   bool lookahead = false;      // factor the next pair's first panel on a side stream
+  bool symmetric = false;      // split mode: symmetric form and L D L^T instead of LU
   SideStream side;             // created on first use
   hipStream_t capture = nullptr;  // non-blocking stream the graphs are captured on
   std::map<std::vector<intptr_t>, hipGraphExec_t> graph_cache;
@@ -570,7 +571,8 @@ static int side_stream(lsms_ctx* ctx, const SideStream** out) {
 }
 
 static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int nj, int npad_max, void* abuf,
-                            int32_t* piv, int32_t* jinfo, double2* xbuf, GemmProfiler* prof, hipStream_t s) {
+                            int32_t* piv, int32_t* jinfo, double2* xbuf, GemmProfiler* prof, hipStream_t s,
+                            bool sym = false) {
   const int variant = gemm_f32_variant(ctx);
   TallScratch ts;
   int rc = tall_scratch(ctx, nj, npad_max, &ts, s);
@@ -586,7 +588,10 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
       lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, q, pr, ts, side);
       lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, q);
     } else {
-      lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, ts, side);
+      if (sym)
+        ldlt_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant);
+      else
+        lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, ts, side);
       lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, q);
     }
   };
@@ -597,7 +602,7 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
   }
   const std::vector<intptr_t> key = {precision, nj, npad_max, variant, (intptr_t)jd, (intptr_t)abuf,
                                      (intptr_t)piv, (intptr_t)jinfo, (intptr_t)xbuf, ts.chunk,
-                                     (intptr_t)ts.base};
+                                     (intptr_t)ts.base, sym ? 1 : 0};
   auto it = ctx->graph_cache.find(key);
   if (it == ctx->graph_cache.end()) {
     if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
@@ -661,7 +666,10 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     HIP_TRY(hipGetLastError());
   }
   if (jobs.empty()) return LSMS_OK;
-  const int64_t small_fixed = align_up((int64_t)n_atoms * 8 * 16, 256);  // tpm
+  // the symmetric form (split mode, no kept factors, systems of at most 4096 rows)
+  const bool sym = ctx->symmetric && precision == LSMS_SPLIT && keep == nullptr && jobs[0].npad <= 4096;
+  const int64_t tpm_bytes = align_up((int64_t)n_atoms * 8 * 16, 256);
+  const int64_t small_fixed = 2 * tpm_bytes;  // tpm | spm
   const int64_t limit = (int64_t)ctx->workspace_limit;
   std::vector<Wave> waves = make_waves(jobs, precision, limit, keep != nullptr);
   int64_t max_wave = 0;
@@ -723,13 +731,15 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     sbase = (char*)ctx->small.p;
   }
   double2* tpm = (double2*)sbase;
+  double2* spm = sym ? (double2*)(sbase + tpm_bytes) : nullptr;
+  const double2* rhs_t = sym ? spm : tpm;  // diagonal of the right-hand side's first block
   JobDesc* jobs_dev = (JobDesc*)(sbase + off_jobs);
   int32_t* job_info = (int32_t*)(sbase + off_info);
   double* norms = (double*)(sbase + off_norm);
   int32_t* done = (int32_t*)(sbase + off_done);
   int32_t* pending = (int32_t*)(sbase + off_pend);
   HIP_TRY(hipMemcpyAsync(jobs_dev, ctx->pinned, (size_t)njobs_all * sizeof(JobDesc), hipMemcpyHostToDevice, s));
-  launch_tmatrix(phase, n_atoms, kp, tpm, s);
+  launch_tmatrix(phase, n_atoms, kp, tpm, spm, s);
 
   for (size_t w = 0; w < waves.size(); ++w) {
     const Wave& wv = waves[w];
@@ -758,23 +768,24 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
       prof = &ctx->prof;
     }
     launch_check_inputs(jd, nj, liz_pos, liz_atom, phase, jinfo, s);
-    launch_init_rhs(jd, nj, npad_max, liz_atom, tpm, xbuf, s);
+    launch_init_rhs(jd, nj, npad_max, liz_atom, rhs_t, xbuf, s);
     if (precision == LSMS_FP64) {
       launch_assemble_f64(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (double2*)abuf, s);
       rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s);
       if (rc) return rc;
-      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, s);
+      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, nullptr, liz_atom,
+                      s);
       launch_write_status(jd, nj, jinfo, nullptr, info, berr, mirror, s);
     } else {
-      launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, m64, s);
-      rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s);
+      launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, m64, spm, s);
+      rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s, sym);
       if (rc) return rc;
       launch_zero_i32(jdone, nj, s);
       launch_zero(jnorm, 8 * (int64_t)nj, s);
       int left = nj;
       for (int it = 0; it <= max_refine; ++it) {
         const int last = it == max_refine;
-        launch_residual_norms(jd, nj, npad_max, m64, xbuf, rbuf, tpm, liz_atom, jnorm, jdone, s);
+        launch_residual_norms(jd, nj, npad_max, m64, xbuf, rbuf, rhs_t, liz_atom, jnorm, jdone, s);
         launch_zero_i32(pending, 1, s);
         launch_refine_step(jd, nj, jnorm, refine_tol, jdone, last, jinfo, pending, s);
         // read back how many jobs still miss the tolerance: stop as soon as none does
@@ -807,7 +818,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           HIP_TRY(hipMemcpy(fjd, fb.data(), fb.size() * sizeof(JobDesc), hipMemcpyHostToDevice));
           launch_zero_i32(finfo, nf, s);
           const int fpad = fb[0].npad;
-          launch_init_rhs(fjd, nf, fpad, liz_atom, tpm, xbuf, s);
+          launch_init_rhs(fjd, nf, fpad, liz_atom, rhs_t, xbuf, s);
           TallScratch fts;
           rc = tall_scratch(ctx, nf, fpad, &fts, s);
           if (rc) return rc;
@@ -815,7 +826,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, s);
         }
       }
-      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, s);
+      launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, spm, liz_atom, s);
       launch_write_status(jd, nj, jinfo, jnorm, info, berr, mirror, s);
     }
     HIP_TRY(hipGetLastError());
@@ -885,9 +896,9 @@ extern "C" int lsms_kubo_sigma_tensor(lsms_ctx* ctx, int32_t n_atoms, const int6
 
 extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
   if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
-  if (knob == LSMS_TUNE_LOOKAHEAD) {
-    if (value != 0 && value != 1) return fail(LSMS_E_ARG, "look-ahead takes 0 or 1 (got %d)", value);
-    ctx->lookahead = value == 1;
+  if (knob == LSMS_TUNE_LOOKAHEAD || knob == LSMS_TUNE_SYMMETRIC) {
+    if (value != 0 && value != 1) return fail(LSMS_E_ARG, "knob %d takes 0 or 1 (got %d)", knob, value);
+    (knob == LSMS_TUNE_LOOKAHEAD ? ctx->lookahead : ctx->symmetric) = value == 1;
     return LSMS_OK;
   }
   if (knob == LSMS_TUNE_TSLU_CHUNK) {
@@ -914,8 +925,8 @@ extern "C" int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value) {
     *value = ctx->tslu_chunk;
     return LSMS_OK;
   }
-  if (knob == LSMS_TUNE_LOOKAHEAD) {
-    *value = ctx->lookahead ? 1 : 0;
+  if (knob == LSMS_TUNE_LOOKAHEAD || knob == LSMS_TUNE_SYMMETRIC) {
+    *value = (knob == LSMS_TUNE_LOOKAHEAD ? ctx->lookahead : ctx->symmetric) ? 1 : 0;
     return LSMS_OK;
   }
   if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY) {

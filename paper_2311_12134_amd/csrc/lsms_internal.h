@@ -102,7 +102,8 @@ struct GauntTable {
 hipError_t upload_gaunt(const GauntTable& g);
 
 // t_l(z+-) for every atom: tpm[atom][e][l] (complex), e = 0 (+), 1 (-).
-void launch_tmatrix(const double* phase, int n_atoms, double2 kappa_plus, double2* tpm, hipStream_t s);
+void launch_tmatrix(const double* phase, int n_atoms, double2 kappa_plus, double2* tpm, double2* spm,
+                    hipStream_t s);
 
 // M = 1 - T g over each job's LIZ (padded with identity), written to the working
 // matrix (double2 or float2) and, if m64 != nullptr, also to the FP64 copy.
@@ -111,7 +112,7 @@ void launch_assemble_f64(const JobDesc* jobs, int njobs, int npad_max, const dou
                          hipStream_t s);
 void launch_assemble_split(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
                            const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, float2* work,
-                           double2* m64, hipStream_t s);
+                           double2* m64, const double2* spm, hipStream_t s);
 // B = E0 t_centre in the solution block (first NL columns), zero elsewhere.
 void launch_init_rhs(const JobDesc* jobs, int njobs, int npad_max, const int32_t* liz_atom, const double2* tpm,
                      double2* x, hipStream_t s);
@@ -138,6 +139,8 @@ int gemm_f32_variants();
 int gemm_f32_autotune(int npad, int batch, hipStream_t s, float* ms, int* best);
 void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                      int c_begin, int c_end, float2* work, hipStream_t s);
+void launch_gemm_f32_lower(const JobDesc* jobs, int njobs, int rows, int k, int kd, int rc_begin, float2* work,
+                           hipStream_t s);
 
 // Blocked LU with partial pivoting of every job's working matrix.
 // Panels taller than 2 * chunk rows are factored with tournament pivoting (lu.hip);
@@ -161,6 +164,10 @@ void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, 
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
                    hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall,
                    const SideStream* side = nullptr);
+// Symmetric factorization S = L D L^T of complex-symmetric systems (no pivoting), stored as
+// an LU with U = D L^T so the LU solves apply; npad_max <= 4096.
+void ldlt_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
+                     hipStream_t s, GemmProfiler* prof, int gemm_variant);
 // Solve with the factors: trans = 0 solves M X = B, trans = 1 solves M^T X = B (in place on X).
 void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
                   double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);
@@ -178,7 +185,7 @@ void launch_refine_update(const JobDesc* jobs, int njobs, double2* x, const doub
 // Copy tau^{a0} (first n rows, NL columns) out of each job's solution block.
 // mirror: only z+ jobs were solved; also write the z- blocks and status from them.
 void launch_copy_tau(const JobDesc* jobs, int njobs, int npad_max, const double2* x, double2* tau_plus,
-                     double2* tau_minus, bool mirror, hipStream_t s);
+                     double2* tau_minus, bool mirror, const double2* spm, const int32_t* liz_atom, hipStream_t s);
 void launch_write_status(const JobDesc* jobs, int njobs, const int32_t* job_info, const double* norms,
                          int32_t* info, double* berr, bool mirror, hipStream_t s);
 void launch_check_inputs(const JobDesc* jobs, int njobs, const double* liz_pos, const int32_t* liz_atom,

@@ -708,3 +708,38 @@ def test_graph_replay_with_tournament_panels(lctx):
     finally:
         lctx.set_graphs(False)
         lctx.set_tslu_chunk(2048)
+
+
+@pytest.mark.parametrize("name", ["fcc32", "bcc250", "bcc1940"])
+def test_symmetric_ldlt_vs_oracle(lctx, name):
+    """Split mode on the symmetric form 1 - T^1/2 g T^1/2 with L D L^T (no pivoting), FP64
+    refinement against the FP64 copy of S: sampled atoms' tau and Kubo sums against the
+    oracle (which solves M X = T E0 by LU), and the backward error reached."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload(name)
+    eta = w["etas"][0]
+    print("[gpu] symmetric LDLT %s" % name, flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    lctx.set_symmetric(True)
+    try:
+        tp, tm, info, berr = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision="split")
+        _, _, pa = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], per_atom=True)
+        torch.cuda.synchronize()
+    finally:
+        lctx.set_symmetric(False)
+    assert (info.cpu().numpy() == 0).all() and (berr.cpu().numpy() <= 1e-14).all()
+    sizes = np.diff(liz.ptr)
+    atoms = ([0, 5, 31] if name == "fcc32" else [0, 77, 249] if name == "bcc250"
+             else [int(np.argmin(sizes)), int(np.argmax(sizes)), 1000])
+    o = kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                   atoms=atoms, liz_lists=(liz.ptr, liz.atom, liz.pos))
+    pa = pa.cpu().numpy()
+    for i in atoms:
+        sl = slice(int(liz.ptr[i]), int(liz.ptr[i + 1]))
+        for tag, t in (("+", tp), ("-", tm)):
+            ref = o["tau"][i]["col" + tag]
+            err = np.linalg.norm(t[sl].cpu().numpy() - ref) / np.linalg.norm(ref)
+            assert err <= TOL_SPLIT, "atom %d tau%s rel err %.3e" % (i, tag, err)
+        err = np.abs(pa[i] - o["per_atom"][i]).max() / np.abs(o["per_atom"][i]).max()
+        assert err <= TOL_SPLIT, "atom %d Kubo rel err %.3e" % (i, err)
