@@ -211,7 +211,7 @@ class Context:
 
     def set_symmetric(self, on=True):
         """Split mode: symmetric form and L D L^T (no pivoting) with FP64 refinement and
-        fallback, instead of the LU (systems of at most 4096 rows, no kept factors)."""
+        fallback, instead of the LU (not with kept factors)."""
         check(lib().lsms_set_tuning(self._h, 5, 1 if on else 0))
 
     def set_tslu_chunk(self, rows=2048):

@@ -99,6 +99,7 @@ struct lsms_ctx {
   DevBuf tall;                 // tall-panel scratch
   bool lookahead = false;      // factor the next pair's first panel on a side stream
   bool symmetric = false;      // split mode: symmetric form and L D L^T instead of LU
+  DevBuf ldlt;                 // scratch of its tall panels
   SideStream side;             // created on first use
   hipStream_t capture = nullptr;  // non-blocking stream the graphs are captured on
   std::map<std::vector<intptr_t>, hipGraphExec_t> graph_cache;
@@ -293,6 +294,7 @@ extern "C" int lsms_destroy(lsms_ctx* ctx) {
   if (ctx->pinned_flag) hipHostFree(ctx->pinned_flag);
   if (ctx->fallback.p) hipFree(ctx->fallback.p);
   if (ctx->tall.p) hipFree(ctx->tall.p);
+  if (ctx->ldlt.p) hipFree(ctx->ldlt.p);
   for (auto& kv : ctx->graph_cache) hipGraphExecDestroy(kv.second);
   if (ctx->capture) hipStreamDestroy(ctx->capture);
   if (ctx->side.update_done) hipEventDestroy(ctx->side.update_done);
@@ -577,6 +579,10 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
   TallScratch ts;
   int rc = tall_scratch(ctx, nj, npad_max, &ts, s);
   if (rc) return rc;
+  if (sym) {
+    rc = ensure_dev(ctx->ldlt, ldlt_scratch_bytes(nj), s);
+    if (rc) return rc;
+  }
   const SideStream* side = nullptr;
   const bool capture = ctx->graphs && !prof;
   if (!capture) {  // captured graphs keep the single-stream order
@@ -589,7 +595,7 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
       lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, q);
     } else {
       if (sym)
-        ldlt_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant);
+        ldlt_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, 2 * ts.chunk, ctx->ldlt.p);
       else
         lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, ts, side);
       lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, q);
@@ -602,7 +608,7 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
   }
   const std::vector<intptr_t> key = {precision, nj, npad_max, variant, (intptr_t)jd, (intptr_t)abuf,
                                      (intptr_t)piv, (intptr_t)jinfo, (intptr_t)xbuf, ts.chunk,
-                                     (intptr_t)ts.base, sym ? 1 : 0};
+                                     (intptr_t)ts.base, sym ? 1 : 0, (intptr_t)ctx->ldlt.p};
   auto it = ctx->graph_cache.find(key);
   if (it == ctx->graph_cache.end()) {
     if (!ctx->capture) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
@@ -666,8 +672,8 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     HIP_TRY(hipGetLastError());
   }
   if (jobs.empty()) return LSMS_OK;
-  // the symmetric form (split mode, no kept factors, systems of at most 4096 rows)
-  const bool sym = ctx->symmetric && precision == LSMS_SPLIT && keep == nullptr && jobs[0].npad <= 4096;
+  // the symmetric form (split mode, no kept factors)
+  const bool sym = ctx->symmetric && precision == LSMS_SPLIT && keep == nullptr;
   const int64_t tpm_bytes = align_up((int64_t)n_atoms * 8 * 16, 256);
   const int64_t small_fixed = 2 * tpm_bytes;  // tpm | spm
   const int64_t limit = (int64_t)ctx->workspace_limit;

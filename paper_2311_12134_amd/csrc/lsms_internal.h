@@ -165,9 +165,11 @@ void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, i
                    hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall,
                    const SideStream* side = nullptr);
 // Symmetric factorization S = L D L^T of complex-symmetric systems (no pivoting), stored as
-// an LU with U = D L^T so the LU solves apply; npad_max <= 4096.
+// an LU with U = D L^T so the LU solves apply.  Panels taller than tall_rows take the
+// diagonal-block path, which needs ldlt_scratch_bytes(njobs) bytes of device scratch.
+size_t ldlt_scratch_bytes(int njobs);
 void ldlt_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                     hipStream_t s, GemmProfiler* prof, int gemm_variant);
+                     hipStream_t s, GemmProfiler* prof, int gemm_variant, int tall_rows, void* scratch);
 // Solve with the factors: trans = 0 solves M X = B, trans = 1 solves M^T X = B (in place on X).
 void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
                   double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);

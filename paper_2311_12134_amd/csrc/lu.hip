@@ -933,8 +933,9 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
 
 // U[k + q][c] = D[q] L[c][k + q] for c in [k + NB, npad): one 64-column tile per workgroup,
 // transposed through LDS.  Runs before linv_kernel (D is read off the diagonal block).
+// from_inverse: the diagonal block already holds the inverses (tall panels), D = 1 / diag.
 template <typename T>
-__global__ __launch_bounds__(256) void sym_u12_kernel(const JobDesc* jobs, int k, T* work) {
+__global__ __launch_bounds__(256) void sym_u12_kernel(const JobDesc* jobs, int k, T* work, int from_inverse) {
   const JobDesc jd = jobs[blockIdx.y];
   const int c0 = k + NB + blockIdx.x * 64;
   if (k >= jd.npad || c0 >= jd.npad) return;  // uniform
@@ -943,7 +944,13 @@ __global__ __launch_bounds__(256) void sym_u12_kernel(const JobDesc* jobs, int k
   __shared__ T s_t[64][NB + 1];
   __shared__ T s_d[NB];
   const int t = threadIdx.x;
-  if (t < NB) s_d[t] = A[(int64_t)(k + t) * ld + k + t];
+  if (t < NB) {
+    const T dd = A[(int64_t)(k + t) * ld + k + t];
+    if (from_inverse)
+      narrow_to(s_d[t], cinv(wide(dd)));
+    else
+      s_d[t] = dd;
+  }
   for (int idx = t; idx < 64 * NB; idx += 256) {
     const int i = idx / NB, q = idx - i * NB;
     s_t[i][q] = A[(int64_t)(c0 + i) * ld + k + q];
@@ -955,8 +962,69 @@ __global__ __launch_bounds__(256) void sym_u12_kernel(const JobDesc* jobs, int k
   }
 }
 
+// Tall panels of the symmetric factorization: without pivoting a panel is its diagonal
+// block (factored in place by the panel kernel as a 64-row sub-problem with the job's
+// leading dimension) and L21 = A21 U11^-1 below it (tslu_l21_kernel).  Sub-problem j of a
+// step covers job j's block at (k, k); its pivots and list go to scratch, and the job's own
+// list for the panel is the identity.
+__global__ void sym_tall_setup_kernel(const JobDesc* jobs, int njobs, int k, JobDesc* sub, int32_t* sinfo,
+                                      int32_t* piv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= njobs) return;
+  const JobDesc jd = jobs[j];
+  JobDesc d{};
+  if (k < jd.npad) {
+    d.a_off = jd.a_off + (int64_t)k * jd.npad + k;
+    d.ld = jd.npad;
+    d.n = NB;
+    d.npad = NB;
+    d.piv_off = (int64_t)j * piv_ints(NB);
+    // the job's permutation list for this panel: the identity
+    int32_t* ip = piv + jd.piv_off;
+    int32_t* lst = ip + perm_off(jd.npad, k);
+    lst[0] = NB;
+    for (int i = 0; i < NB; ++i) {
+      ip[k + i] = k + i;
+      lst[2 + i] = k + i;
+      lst[2 + PERM_MAX + i] = k + i;
+    }
+  }
+  sub[j] = d;
+  sinfo[j] = 0;
+}
+
+__global__ void sym_tall_info_kernel(int njobs, int k, const int32_t* sinfo, int32_t* info) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < njobs && sinfo[j] != 0 && info[j] == 0) info[j] = k + sinfo[j];
+}
+
+size_t ldlt_scratch_bytes(int njobs) {
+  return (size_t)njobs * (sizeof(JobDesc) + 4 * (size_t)piv_ints(NB) + 4) + 3 * 256;
+}
+
 void ldlt_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                     hipStream_t s, GemmProfiler* prof, int gemm_variant) {
+                     hipStream_t s, GemmProfiler* prof, int gemm_variant, int tall_rows, void* scratch) {
+  JobDesc* sub = (JobDesc*)scratch;
+  int32_t* spiv = (int32_t*)((char*)scratch + (njobs * sizeof(JobDesc) + 255) / 256 * 256);
+  int32_t* sinfo = spiv + (int64_t)njobs * piv_ints(NB);
+  // one panel with its U12 rows and inverses; tall panels as above
+  auto panel = [&](int k) {
+    const int rows = npad_max - k, rest = rows - NB;
+    if (rows > tall_rows && scratch) {
+      sym_tall_setup_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(jobs, njobs, k, sub, sinfo, piv);
+      launch_panel<float2>(sub, njobs, 0, 0, NB, work, spiv, sinfo, s, 1);
+      sym_tall_info_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(njobs, k, sinfo, info);
+      linv_kernel<float2><<<njobs, 512, 0, s>>>(jobs, k, work);
+      if (rest > 0) {
+        tslu_l21_kernel<float2><<<dim3((rest + 63) / 64, njobs), 256, 0, s>>>(jobs, k, work);
+        sym_u12_kernel<float2><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, 1);
+      }
+      return;
+    }
+    launch_panel<float2>(jobs, njobs, k, 0, rows, work, piv, info, s, 1);
+    if (rest > 0) sym_u12_kernel<float2><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, 0);
+    linv_kernel<float2><<<njobs, 512, 0, s>>>(jobs, k, work);
+  };
   auto timed = [&](int k, int kd, int rb, bool lower, int c_end) {
     const int rows = npad_max - rb;
     if (rows <= 0) return;
@@ -981,16 +1049,12 @@ void ldlt_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work,
   };
   (void)gemm_variant;
   for (int k = 0; k < npad_max; k += 2 * NB) {
-    launch_panel<float2>(jobs, njobs, k, 0, npad_max - k, work, piv, info, s, 1);
+    panel(k);
     const int rest = npad_max - k - NB;
-    if (rest > 0) sym_u12_kernel<float2><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work);
-    linv_kernel<float2><<<njobs, 512, 0, s>>>(jobs, k, work);
     if (rest <= 0) break;
     timed(k, NB, k + NB, false, k + 2 * NB);  // the second panel's columns
-    launch_panel<float2>(jobs, njobs, k + NB, 0, npad_max - k - NB, work, piv, info, s, 1);
+    panel(k + NB);
     const int rest2 = npad_max - k - 2 * NB;
-    if (rest2 > 0) sym_u12_kernel<float2><<<dim3(rest2 / 64, njobs), 256, 0, s>>>(jobs, k + NB, work);
-    linv_kernel<float2><<<njobs, 512, 0, s>>>(jobs, k + NB, work);
     if (rest2 <= 0) break;
     timed(k, 2 * NB, k + 2 * NB, true, 0);
   }

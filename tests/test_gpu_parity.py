@@ -710,24 +710,27 @@ def test_graph_replay_with_tournament_panels(lctx):
         lctx.set_tslu_chunk(2048)
 
 
-@pytest.mark.parametrize("name", ["fcc32", "bcc250", "bcc1940"])
-def test_symmetric_ldlt_vs_oracle(lctx, name):
+@pytest.mark.parametrize("name,chunk", [("fcc32", 2048), ("bcc250", 2048), ("bcc1940", 2048), ("bcc250", 256)])
+def test_symmetric_ldlt_vs_oracle(lctx, name, chunk):
     """Split mode on the symmetric form 1 - T^1/2 g T^1/2 with L D L^T (no pivoting), FP64
     refinement against the FP64 copy of S: sampled atoms' tau and Kubo sums against the
-    oracle (which solves M X = T E0 by LU), and the backward error reached."""
+    oracle (which solves M X = T E0 by LU), and the backward error reached.  With 256-row
+    chunks the panels taller than 512 rows take the diagonal-block path of tall panels."""
     import paper_2311_12134_amd as P
     w = synthetic.workload(name)
     eta = w["etas"][0]
-    print("[gpu] symmetric LDLT %s" % name, flush=True)
+    print("[gpu] symmetric LDLT %s chunk %d" % (name, chunk), flush=True)
     liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
     la, lp, phase, species, J = _device_inputs(w, liz)
     lctx.set_symmetric(True)
+    lctx.set_tslu_chunk(chunk)
     try:
         tp, tm, info, berr = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision="split")
         _, _, pa = lctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], per_atom=True)
         torch.cuda.synchronize()
     finally:
         lctx.set_symmetric(False)
+        lctx.set_tslu_chunk(2048)
     assert (info.cpu().numpy() == 0).all() and (berr.cpu().numpy() <= 1e-14).all()
     sizes = np.diff(liz.ptr)
     atoms = ([0, 5, 31] if name == "fcc32" else [0, 77, 249] if name == "bcc250"
