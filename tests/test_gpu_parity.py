@@ -746,3 +746,32 @@ def test_symmetric_ldlt_vs_oracle(lctx, name, chunk):
             assert err <= TOL_SPLIT, "atom %d tau%s rel err %.3e" % (i, tag, err)
         err = np.abs(pa[i] - o["per_atom"][i]).max() / np.abs(o["per_atom"][i]).max()
         assert err <= TOL_SPLIT, "atom %d Kubo rel err %.3e" % (i, err)
+
+
+def test_symmetric_ldlt_with_conj_symmetry(lctx):
+    """Both algorithmic savings at once (z+ only, tau(z-) by conjugation; symmetric form with
+    L D L^T): sampled atoms of the 250-atom alloy against the oracle."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc250")
+    eta = w["etas"][0]
+    print("[gpu] symmetric LDLT + conj symmetry bcc250", flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    lctx.set_symmetric(True)
+    lctx.set_conj_symmetry(True)
+    try:
+        tp, tm, info, berr = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision="split")
+        torch.cuda.synchronize()
+    finally:
+        lctx.set_symmetric(False)
+        lctx.set_conj_symmetry(False)
+    assert (info.cpu().numpy() == 0).all() and (berr.cpu().numpy() <= 1e-14).all()
+    atoms = [0, 77, 249]
+    o = kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                   atoms=atoms, liz_lists=(liz.ptr, liz.atom, liz.pos))
+    for i in atoms:
+        sl = slice(int(liz.ptr[i]), int(liz.ptr[i + 1]))
+        for tag, t in (("+", tp), ("-", tm)):
+            ref = o["tau"][i]["col" + tag]
+            err = np.linalg.norm(t[sl].cpu().numpy() - ref) / np.linalg.norm(ref)
+            assert err <= TOL_SPLIT, "atom %d tau%s rel err %.3e" % (i, tag, err)
