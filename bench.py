@@ -44,24 +44,36 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, eta, n_sample):
-    """The oracle as it stands on a few atoms of the same workload (host cores)."""
+def cpu_baseline(w, eta, n_sample, n_single=3):
+    """The oracle as it stands on a few atoms of the same workload (host cores), and on a
+    smaller sample with its BLAS held to one thread."""
     from oracle import kubo
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count()
     import paper_2311_12134_amd as P
     liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
-    atoms = list(range(n_sample))
-    t0 = time.perf_counter()
-    kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta, atoms=atoms,
-               liz_lists=(liz.ptr, liz.atom, liz.pos))
-    dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "atoms/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d atoms of the 4000-atom fcc alloy at eta=%g (both energies, assembly + LU + both tau "
-                      "blocks + Kubo traces), %.1f s" % (n_sample, eta, dt)}
+
+    def run(atoms):
+        t0 = time.perf_counter()
+        kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                   atoms=atoms, liz_lists=(liz.ptr, liz.atom, liz.pos))
+        return time.perf_counter() - t0
+
+    dt = run(list(range(n_sample)))
+    what = "of the %s workload at eta=%g (both energies, assembly + LU + both tau blocks + Kubo traces)" % (
+        w["name"], eta)
+    res = {"value": n_sample / dt, "unit": "atoms/s", "cores": int(threads), "kind": "oracle",
+           "sample": "%d atoms %s, %.1f s" % (n_sample, what, dt)}
+    if threadpool_limits is not None and n_single > 0:
+        with threadpool_limits(limits=1):
+            d1 = run(list(range(n_single)))
+        res["single_thread"] = {"value": n_single / d1, "unit": "atoms/s", "cores": 1,
+                                "sample": "%d atoms %s, %.1f s" % (n_single, what, d1)}
+    return res
 
 
 def adjoint_leg(P, torch, ctx):
