@@ -9,8 +9,10 @@
  *   2. assembles M = 1 - t g over that LIZ at z = eF +- i eta  (Eq. (3)-(4), Eq. (7)),
  *      g = free-electron structure constants (spherical Hankel functions
  *      times Gaunt coefficients times real spherical harmonics),
- *   3. factors M (complex LU with partial pivoting) and solves for the tau
- *      blocks tau^{a0} linking every LIZ member a to the centre (Eq. (3), Eq. (10)),
+ *   3. factors M (complex LU with partial pivoting; panels of more than 4096 rows by
+ *      tournament pivoting; optionally the symmetric form by L D L^T, see
+ *      LSMS_TUNE_SYMMETRIC) and solves for the tau blocks tau^{a0} linking every LIZ
+ *      member a to the centre (Eq. (3), Eq. (10)),
  *   4. contracts tau with current matrix elements into the Kubo-Greenwood
  *      sums of Eq. (10) and combines the four energy pairs with Eq. (7).
  *
@@ -88,7 +90,7 @@ int lsms_destroy(lsms_ctx* ctx);
 
 /*
  * LIZ construction (Sec. II.A, Fig. 1; the inner sum of Eq. (10) runs over
- * the LIZ of m).  Host-only, synchronous.
+ * the LIZ of m).  Host-only, synchronous; ctx is not used (may be NULL).
  *   pos      host [n_atoms][3]  atom positions (bohr)
  *   cell     host [3][3]        lattice vectors as rows, or NULL for an open cluster
  *   r_liz    LIZ radius (bohr, > 0); a member is any periodic image R_j + T of
