@@ -775,3 +775,35 @@ def test_symmetric_ldlt_with_conj_symmetry(lctx):
             ref = o["tau"][i]["col" + tag]
             err = np.linalg.norm(t[sl].cpu().numpy() - ref) / np.linalg.norm(ref)
             assert err <= TOL_SPLIT, "atom %d tau%s rel err %.3e" % (i, tag, err)
+
+
+def test_argument_errors_are_reported(lctx):
+    """Bad arguments fail synchronously with the library's message, before any device work;
+    a context whose workspace cannot hold one system reports LSMS_E_NOMEM."""
+    import paper_2311_12134_amd as P
+    from paper_2311_12134_amd._lib import LsmsError
+    w = synthetic.workload("bcc16")
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    print("[gpu] argument errors", flush=True)
+    for knob_call in (lambda: lctx.set_tslu_chunk(100), lambda: lctx.set_tslu_chunk(4096),
+                      lambda: lctx.set_gemm_tiling(99)):
+        with pytest.raises(LsmsError):
+            knob_call()
+    with pytest.raises(LsmsError):
+        lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], 0.0)
+    with pytest.raises(LsmsError):
+        lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], 0.002, precision="split", refine_tol=-1.0)
+    tp, tm, info, _ = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], 0.002)
+    with pytest.raises(LsmsError):
+        lctx.kubo_sigma(liz, la, tp, tm, species, J, -1.0)
+    with pytest.raises(LsmsError):
+        lctx.autotune(npad=100, batch=4)
+    small = P.Context(0, workspace_limit=1 << 20)
+    try:
+        with pytest.raises(LsmsError, match="workspace|bytes"):
+            small.tau_solve(liz, la, lp, phase, w["e_fermi"], 0.002)
+    finally:
+        small.close()
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()  # the context still works after the refused calls
