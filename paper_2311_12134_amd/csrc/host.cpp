@@ -595,7 +595,7 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
       lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, q);
     } else {
       if (sym)
-        ldlt_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, 2 * ts.chunk, ctx->ldlt.p);
+        ldlt_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, NB, ctx->ldlt.p);
       else
         lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, ts, side);
       lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, q);
