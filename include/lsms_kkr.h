@@ -304,8 +304,9 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * trailing-update work of the LU), refined in FP64 against an FP64 copy of S, and
  * tau^{a0} = t_a^{1/2} Y_a.  Systems whose refinement does not converge (e.g. large
  * element growth without pivoting) fall back to the FP64 LU with partial pivoting of S, as
- * in the LU path.  Panels taller than 2 C rows (LSMS_TUNE_TSLU_CHUNK) factor only their
- * diagonal block and form L21 = A21 U11^-1.  Not used with kept factors (the LU path runs).
+ * in the LU path.  With no pivots to choose, each panel factors only its diagonal block
+ * and forms L21 = A21 U11^-1 on the matrix cores.  Not used with kept factors (the LU path
+ * runs).
  * Not the paper's LU: reported apart from the LU rate.
  */
 #define LSMS_TUNE_SYMMETRIC 5

@@ -962,9 +962,10 @@ __global__ __launch_bounds__(256) void sym_u12_kernel(const JobDesc* jobs, int k
   }
 }
 
-// Tall panels of the symmetric factorization: without pivoting a panel is its diagonal
-// block (factored in place by the panel kernel as a 64-row sub-problem with the job's
-// leading dimension) and L21 = A21 U11^-1 below it (tslu_l21_kernel).  Sub-problem j of a
+// Panels of the symmetric factorization: without pivoting a panel is its diagonal block
+// (factored in place by the panel kernel as a 64-row sub-problem with the job's leading
+// dimension) and L21 = A21 U11^-1 below it (tslu_l21_kernel), so no pass over the panel's
+// whole height is needed; panels of at most tall_rows rows may instead use the panel kernel.  Sub-problem j of a
 // step covers job j's block at (k, k); its pivots and list go to scratch, and the job's own
 // list for the panel is the identity.
 __global__ void sym_tall_setup_kernel(const JobDesc* jobs, int njobs, int k, JobDesc* sub, int32_t* sinfo,
