@@ -146,3 +146,49 @@ def liz_sweep(ctx, pos, cell, species, phase, J, e_fermi, eta, radii, volume, pr
             rec["sigma_up"], rec["sigma_down"] = sig_ch
         out.append(rec)
     return out
+
+
+def main(argv=None):
+    """Command line: LIZ-radius sweep of one synthetic workload with both fits, one JSON line."""
+    import argparse
+    import json
+    import time
+
+    import torch
+
+    from .api import Context
+
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--workload", default="bcc250")
+    ap.add_argument("--radii", default="0.95,1.2,1.5,1.7,1.9,2.2",
+                    help="LIZ radii in units of the lattice constant (between shells)")
+    ap.add_argument("--precision", default="split", choices=["split", "fp64"])
+    ap.add_argument("--spin-scale", type=float, default=0.0,
+                    help="if > 0, a second spin channel with phase shifts scaled by this factor")
+    args = ap.parse_args(argv)
+    import synthetic  # seeded inputs (repository root on the path)
+
+    w = synthetic.workload(args.workload)
+    radii = [float(x) * w["a"] for x in args.radii.split(",")]
+    ctx = Context(0)
+    t0 = time.perf_counter()
+    recs = liz_sweep(ctx, w["pos"], w["cell"], w["species"], w["phase"], w["J"], w["e_fermi"], w["etas"][0], radii,
+                     w["volume"], precision=args.precision,
+                     phase_down=w["phase"] * args.spin_scale if args.spin_scale > 0 else None)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.close()
+    r = [x["r_liz"] for x in recs]
+    rho = [x["rho"][0][0] for x in recs]
+    out = {"workload": args.workload, "precision": args.precision, "seconds": el,
+           "radii_bohr": r, "liz_sites": [x["liz_max"] for x in recs], "rho_xx": rho,
+           "sigma_xx": [x["sigma"][0][0] for x in recs]}
+    if len(r) >= 2:
+        out["lower_bound_fit"] = dict(zip(("c0", "c1"), fit_linear(r, rho)))
+    if len(r) >= 3:
+        out["upper_bound_fit"] = dict(zip(("b0", "b1"), fit_upper(r, rho)))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
