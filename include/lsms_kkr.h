@@ -136,7 +136,11 @@ int lsms_build_liz_subset(lsms_ctx* ctx, int32_t n_atoms, const double* pos, con
  *             or after max_refine corrections (then info = LSMS_INFO_NOCONV and
  *             the job is recomputed in FP64)
  *   tau_plus, tau_minus device [liz_ptr[n]][16][16] complex (out): tau^{a0}_{LL'}
- *   info      device [n_atoms][2] int32 (out), per atom and energy (0 = +, 1 = -)
+ *   info      device [n_atoms][2] int32 (out), per atom and energy (0 = +, 1 = -):
+ *             0; LSMS_INFO_NOCONV when the split-mode refinement missed refine_tol (or, in
+ *             the symmetric form, met a zero pivot) and the system was recomputed by the
+ *             FP64 LU (tau valid); k > 0 for an exact zero pivot of the FP64 LU (tau not
+ *             valid); LSMS_INFO_BADINPUT
  *   berr      device [n_atoms][2] double (out): final backward error (split mode),
  *             0 in FP64 mode
  *   keep      NULL, or receives a library-owned handle that keeps every LU factor

@@ -549,6 +549,8 @@ void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double to
 void launch_add_correction(const JobDesc* jobs, int njobs, int npad_max, double2* x, const double2* r,
                            const int32_t* done, hipStream_t s);
 void launch_zero_i32(int32_t* p, int n, hipStream_t s);
+void launch_zero_pivot_to_fallback(int njobs, int32_t* job_info, hipStream_t s);
+void launch_fallback_status(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info, hipStream_t s);
 }  // namespace lsms
 
 // ---------------------------------------------------------------------------------
@@ -786,6 +788,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
       launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, m64, spm, s);
       rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s, sym);
       if (rc) return rc;
+      if (sym) launch_zero_pivot_to_fallback(nj, jinfo, s);
       launch_zero_i32(jdone, nj, s);
       launch_zero(jnorm, 8 * (int64_t)nj, s);
       int left = nj;
@@ -802,9 +805,10 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
         lu_solve_f32_skip(jd, nj, npad_max, (const float2*)abuf, piv, rbuf, jdone, s);
         launch_add_correction(jd, nj, npad_max, xbuf, rbuf, jdone, s);
       }
-      if (left > 0) {
-        // Jobs whose refinement did not converge (info = NOCONV) are recomputed in FP64:
-        // the FP64 copy of M is factored in place and solved directly.
+      if (left > 0 || sym) {
+        // Jobs whose refinement did not converge (info = NOCONV; in the symmetric form also
+        // those that met a zero pivot) are recomputed in FP64: the FP64 copy of the matrix
+        // is factored in place with partial pivoting and solved directly.
         std::vector<int32_t> hinfo(nj);
         HIP_TRY(hipMemcpy(hinfo.data(), jinfo, nj * sizeof(int32_t), hipMemcpyDeviceToHost));
         std::vector<JobDesc> fb;
@@ -830,6 +834,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           if (rc) return rc;
           lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s, nullptr, fts);
           lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, s);
+          launch_fallback_status(nf, fjd, finfo, jinfo, s);
         }
       }
       launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, spm, liz_atom, s);

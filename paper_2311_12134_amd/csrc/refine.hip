@@ -143,6 +143,27 @@ __global__ void refine_step_kernel(int njobs, double* norms, double tol, int32_t
   nm[2] = 0.0;
 }
 
+// Symmetric form (no pivoting): an exact zero pivot says nothing about S itself, so the
+// system goes to the FP64 LU with partial pivoting like one whose refinement failed.
+__global__ void zero_pivot_to_fallback_kernel(int njobs, int32_t* job_info) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < njobs && job_info[j] > 0) job_info[j] = -1;
+}
+
+void launch_zero_pivot_to_fallback(int njobs, int32_t* job_info, hipStream_t s) {
+  zero_pivot_to_fallback_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(njobs, job_info);
+}
+
+// After the FP64 fallback: a zero pivot of the partial-pivoting LU marks the system singular.
+__global__ void fallback_status_kernel(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < nf && finfo[f] > 0) job_info[fjobs[f].info] = finfo[f];
+}
+
+void launch_fallback_status(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info, hipStream_t s) {
+  fallback_status_kernel<<<(nf + 255) / 256, 256, 0, s>>>(nf, fjobs, finfo, job_info);
+}
+
 void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double tol, int32_t* done, int last,
                         int32_t* job_info, int32_t* pending, hipStream_t s) {
   (void)jobs;

@@ -807,3 +807,19 @@ def test_argument_errors_are_reported(lctx):
         small.close()
     torch.cuda.synchronize()
     assert (info.cpu().numpy() == 0).all()  # the context still works after the refused calls
+
+
+def test_symmetric_fallback_to_fp64_lu(lctx):
+    """Symmetric form with no refinement budget: every system is flagged and recomputed by
+    the FP64 LU with partial pivoting of S, then scaled back (tau = T^1/2 Y): FP64 parity."""
+    w = synthetic.workload("bcc16")
+    eta = w["etas"][0]
+    lctx.set_symmetric(True)
+    try:
+        g = _run(lctx, w, eta, precision="split", refine_tol=1e-300, max_refine=0)
+    finally:
+        lctx.set_symmetric(False)
+    assert (g["info"] == -1).all()
+    atoms = list(range(16))
+    o = _oracle_atoms(w, eta, atoms, g["liz"])
+    _check_atoms(g, o, atoms, TOL64)
