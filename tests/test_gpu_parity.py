@@ -823,3 +823,30 @@ def test_symmetric_fallback_to_fp64_lu(lctx):
     atoms = list(range(16))
     o = _oracle_atoms(w, eta, atoms, g["liz"])
     _check_atoms(g, o, atoms, TOL64)
+
+
+def test_graph_replay_symmetric(lctx):
+    """Captured symmetric factorization + first solve, replayed three times: bitwise the eager
+    result."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc250")
+    eta = w["etas"][0]
+    print("[gpu] graphs with the symmetric form bcc250", flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+    lctx.set_symmetric(True)
+    try:
+        def solve():
+            tp, tm, info, _ = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision="split")
+            torch.cuda.synchronize()
+            return tp.cpu().numpy(), tm.cpu().numpy(), info.cpu().numpy()
+        ref = solve()
+        assert (ref[2] == 0).all()
+        lctx.set_graphs(True)
+        for rep in range(3):
+            got = solve()
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), rep
+    finally:
+        lctx.set_graphs(False)
+        lctx.set_symmetric(False)
