@@ -43,6 +43,40 @@ __device__ inline unsigned long long pivot_key(double mag, int row_local) {
 }
 __device__ inline int pivot_row(unsigned long long key) { return 0x1FFF - (int)(key & 0x1FFFull); }
 
+// One lane's 64-bit key moved within its 16-lane row by the DPP pattern CTRL.
+template <int CTRL>
+__device__ inline unsigned long long dpp_key(unsigned long long x) {
+  const int lo = (int)(unsigned)x, hi = (int)(unsigned)(x >> 32);
+  const unsigned rlo = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  const unsigned rhi = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)rhi << 32) | rlo;
+}
+__device__ inline unsigned long long umax64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+__device__ inline unsigned long long lane_key(unsigned long long x, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+// Largest key of the wavefront, the same in every lane: the maximum within each 16-lane
+// row by DPP (quad exchanges 1 and 2, half-row mirror, row mirror; each step combines
+// groups that already agree), then the four rows' maxima read as scalars.
+__device__ inline unsigned long long wave_max_key(unsigned long long key) {
+  key = umax64(key, dpp_key<0xB1>(key));   // quad_perm [1, 0, 3, 2]
+  key = umax64(key, dpp_key<0x4E>(key));   // quad_perm [2, 3, 0, 1]
+  key = umax64(key, dpp_key<0x141>(key));  // row_half_mirror
+  key = umax64(key, dpp_key<0x140>(key));  // row_mirror
+  return umax64(umax64(lane_key(key, 0), lane_key(key, 16)), umax64(lane_key(key, 32), lane_key(key, 48)));
+}
+
+// Inverse of a pivot in FP64.  Values stored in FP32 have squared magnitudes well inside
+// the FP64 range, so conj(a) / |a|^2 needs one division; FP64 storage keeps the scaled
+// (Smith) form.
+__device__ inline double2 pivot_inverse(double2 a, float2) {
+  const double rn = 1.0 / (a.x * a.x + a.y * a.y);
+  return make_double2(a.x * rn, -a.y * rn);
+}
+__device__ inline double2 pivot_inverse(double2 a, double2) { return cinv(a); }
+
 __device__ inline double2 wide(double2 a) { return a; }
 __device__ inline double2 wide(float2 a) { return make_double2((double)a.x, (double)a.y); }
 __device__ inline void narrow_to(double2& d, double2 a) { d = a; }
@@ -124,7 +158,6 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   __shared__ int s_pos[PERM_MAX], s_org[PERM_MAX];
   __shared__ int s_lpos[2 * IB], s_lorg[2 * IB], s_lcnt;
   __shared__ T s_held[2 * IB][2 * NB - IB];
-  __shared__ T s_Lc[PT][IB];
 
   // the leaf in registers in the storage precision (its updates too; pivot keys in FP64)
   T v[S][IB];
@@ -156,11 +189,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
           key = kk > key ? kk : key;
         }
       }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const unsigned long long o = __shfl_xor(key, off);
-        key = o > key ? o : key;
-      }
+      key = wave_max_key(key);
       if (key != 0ull) {  // the lane holding the wave's best row posts it (never with nopiv)
         const int rl = pivot_row(key);
         if (rl % PT == t) {
@@ -215,18 +244,41 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       const bool zero = (pv.x == 0.0 && pv.y == 0.0);
       if (zero && first_zero == 0) first_zero = d + 1;
       T inv;  // the pivot's inverse in FP64, rounded once to the storage precision
-      narrow_to(inv, zero ? make_double2(0.0, 0.0) : cinv(pv));
+      narrow_to(inv, zero ? make_double2(0.0, 0.0) : pivot_inverse(pv, T{}));
       // the leaf's rank-1 update in the storage precision (FP32 in split mode, like the
-      // trailing updates; the pivot keys above compare these values in FP64)
+      // trailing updates; the pivot keys above compare these values in FP64).  While the
+      // leaf takes at most half of the registers, rows on or above the pivot take a zero
+      // multiplier (which leaves them as they are) so the update has no branches, and each
+      // pivot-row entry is read from LDS once for all S row slots; wider leaves (and eight
+      // row slots) update the slots one by one under a branch, which keeps fewer values live.
+      if constexpr (S * IB * (int)sizeof(T) / 4 <= 128 && S < 8) {
+        T l[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int r = k + t + s * PT;
-        if (r > d && r < nrows) {
-          const T l = cmul(v[s][j], inv);
-          v[s][j] = l;
+        for (int s = 0; s < S; ++s) {
+          const int r = k + t + s * PT;
+          const bool below = r > d && r < nrows;
+          l[s] = below ? cmul(v[s][j], inv) : T{0, 0};
+          if (below) v[s][j] = l[s];
+        }
 #pragma unroll
-          for (int q = 0; q < IB; ++q)  // full range: j is a constant once unrolled
-            if (q > j) v[s][q] = cfms(v[s][q], l, prow[q]);
+        for (int q = 0; q < IB; ++q) {  // full range: j is a constant once unrolled
+          if (q > j) {
+            const T pq = prow[q];
+#pragma unroll
+            for (int s = 0; s < S; ++s) v[s][q] = cfms(v[s][q], l[s], pq);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int r = k + t + s * PT;
+          if (r > d && r < nrows) {
+            const T l = cmul(v[s][j], inv);
+            v[s][j] = l;
+#pragma unroll
+            for (int q = 0; q < IB; ++q)
+              if (q > j) v[s][q] = cfms(v[s][q], l, prow[q]);
+          }
         }
       }
     }
@@ -333,47 +385,65 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
         }
       }
       __syncthreads();
-      // rank-IB update of the panel right of the leaf, PT rows at a time with their L rows
-      // staged in LDS
+      // rank-IB update of the panel right of the leaf on the matrix cores: each wave updates
+      // its own 64 rows of every PT-row slab, RBP 16-row blocks at a time.  The leaf's L rows
+      // are read back from memory (stored before the barrier above; the leaf registers are
+      // free by now), and all old values and L operands of a group are loaded before its
+      // first product, so a group waits for memory once instead of once per 16 x 16 tile.
+      // Rows above the leaf's last row and columns past w are masked at the load and store.
+      constexpr int CBM = (NB - IB + 15) / 16;                  // 16-column blocks, at most
+      constexpr int VRB = CBM * 4 * (int)sizeof(T) / 4;          // registers per block's old values
+      constexpr int RBP = VRB * 4 <= 96 ? 4 : (VRB * 2 <= 96 ? 2 : 1);
+      typedef StripMma<T, 1, IB> Mma;
+      const int ii = lane & 15, kq = lane >> 4;
 #pragma unroll 1
       for (int s = 0; s < S; ++s) {
-        const int r0 = k + s * PT;
-        if (r0 < nrows && r0 + PT > cl + IB) {
+#pragma unroll 1
+        for (int g = 0; g < 4; g += RBP) {
+          const int gbase = k + s * PT + wave * 64 + g * 16;
+          if (gbase >= nrows || gbase + RBP * 16 <= cl + IB) continue;  // uniform per wave
+          T lop[RBP][IB / 4];
+          T old[RBP][CBM][4];
 #pragma unroll
-          for (int ss = 0; ss < S; ++ss)  // register slots are indexed by constants only
-            if (ss == s) {
+          for (int b = 0; b < RBP; ++b) {
+            const int rl = gbase + b * 16 + ii;
 #pragma unroll
-              for (int q = 0; q < IB; ++q) s_Lc[t][q] = v[ss][q];
-            }
-          __syncthreads();
-          // A[rows, right of the leaf] -= L (s_Lc) U (s_U) on the matrix cores: wave w takes
-          // rows r0 + 64 w .. + 64 in 16-row blocks, the columns in 16-wide blocks (K = IB);
-          // rows above the leaf's last row and columns past w are masked at the store
-          const int ii = lane & 15;
-          for (int rb = 0; rb < 4; ++rb) {
-            const int rbase = r0 + wave * 64 + rb * 16;
-            if (rbase + 16 <= cl + IB || rbase >= nrows) continue;  // uniform per wave
-            for (int cb0 = 0; cb0 < w; cb0 += 16) {
-              StripMma<T, 1, IB> acc;
-              acc.zero();
-              acc.run([&](int i, int kk) { return s_Lc[rbase - r0 + i][kk]; },
-                      [&](int kk, int cc) {
-                        T u;
-                        narrow_to(u, s_U[kk][cb0 + cc]);
-                        return u;
-                      },
-                      lane);
+            for (int q = 0; q < IB / 4; ++q) lop[b][q] = rl < nrows ? A[rl * ld + cl + 4 * q + kq] : T{0, 0};
+#pragma unroll
+            for (int cb = 0; cb < CBM; ++cb)
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int row = rbase + acc.row(r, lane), cc = cb0 + ii;
+                const int row = gbase + b * 16 + Mma::row(r, lane), cc = cb * 16 + ii;
+                old[b][cb][r] = (row >= cl + IB && row < nrows && cc < w) ? A[row * ld + cl + IB + cc] : T{0, 0};
+              }
+          }
+#pragma unroll
+          for (int b = 0; b < RBP; ++b) {
+            const int rbase = gbase + b * 16;
+            if (rbase + 16 <= cl + IB || rbase >= nrows) continue;  // uniform per wave
+#pragma unroll
+            for (int cb = 0; cb < CBM; ++cb) {
+              if (cb * 16 >= w) continue;  // uniform
+              Mma acc;
+              acc.zero();
+              acc.run_regs(lop[b],
+                           [&](int kk, int cc) {
+                             T u;
+                             narrow_to(u, s_U[kk][cb * 16 + cc]);
+                             return u;
+                           },
+                           lane);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = rbase + Mma::row(r, lane), cc = cb * 16 + ii;
                 if (row >= cl + IB && row < nrows && cc < w) {
-                  T* ap = A + row * ld + cl + IB + cc;
-                  narrow_to(*ap, csub(wide(*ap), acc.value(0, r)));
+                  T nv;
+                  narrow_to(nv, csub(wide(old[b][cb][r]), acc.value(0, r)));
+                  A[row * ld + cl + IB + cc] = nv;
                 }
               }
             }
           }
-          __syncthreads();
         }
       }
     }

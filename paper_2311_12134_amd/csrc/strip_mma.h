@@ -43,6 +43,22 @@ struct StripMma<float2, CB, KD> {
       }
     }
   }
+  // as run, with this lane's A values (row l % 16, k 4 q + l / 16) already in registers
+  template <typename FB>
+  __device__ void run_regs(const float2 (&a)[KD / 4], FB b_at, int lane) {
+    const int ii = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < KD / 4; ++q) {
+      const float as = a[q].x + a[q].y;
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const float2 b = b_at(4 * q + kq, c * 16 + ii);
+        t1[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].x, b.x, t1[c], 0, 0, 0);
+        t2[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q].y, b.y, t2[c], 0, 0, 0);
+        t3[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, b.x + b.y, t3[c], 0, 0, 0);
+      }
+    }
+  }
   __device__ static int row(int r, int lane) { return 4 * (lane >> 4) + r; }
   __device__ double2 value(int c, int r) const {
     return make_double2((double)(t1[c][r] - t2[c][r]), (double)(t3[c][r] - t1[c][r] - t2[c][r]));
@@ -73,6 +89,21 @@ struct StripMma<double2, CB, KD> {
         re[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re[c], 0, 0, 0);
         im[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im[c], 0, 0, 0);
         im[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im[c], 0, 0, 0);
+      }
+    }
+  }
+  template <typename FB>
+  __device__ void run_regs(const double2 (&a)[KD / 4], FB b_at, int lane) {
+    const int ii = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < KD / 4; ++q) {
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const double2 b = b_at(4 * q + kq, c * 16 + ii);
+        re[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].x, b.x, re[c], 0, 0, 0);
+        re[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[q].y, b.y, re[c], 0, 0, 0);
+        im[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].x, b.y, im[c], 0, 0, 0);
+        im[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].y, b.x, im[c], 0, 0, 0);
       }
     }
   }
