@@ -82,6 +82,38 @@ __device__ inline double2 wide(float2 a) { return make_double2((double)a.x, (dou
 __device__ inline void narrow_to(double2& d, double2 a) { d = a; }
 __device__ inline void narrow_to(float2& d, double2 a) { d = make_float2((float)a.x, (float)a.y); }
 
+// IB consecutive elements of one row, moved 16 bytes at a time (rows start 16-byte aligned)
+template <int IB>
+__device__ inline void load_row(const float2* p, float2 (&d)[IB]) {
+#pragma unroll
+  for (int u = 0; u < IB / 2; ++u) {
+    const float4 x = ((const float4*)p)[u];
+    d[2 * u] = make_float2(x.x, x.y);
+    d[2 * u + 1] = make_float2(x.z, x.w);
+  }
+}
+template <int IB>
+__device__ inline void load_row(const double2* p, double2 (&d)[IB]) {
+#pragma unroll
+  for (int u = 0; u < IB; ++u) d[u] = p[u];
+}
+template <int IB>
+__device__ inline void store_row(float2* p, const float2 (&d)[IB]) {
+#pragma unroll
+  for (int u = 0; u < IB / 2; ++u) ((float4*)p)[u] = make_float4(d[2 * u].x, d[2 * u].y, d[2 * u + 1].x, d[2 * u + 1].y);
+}
+template <int IB>
+__device__ inline void store_row(double2* p, const double2 (&d)[IB]) {
+#pragma unroll
+  for (int u = 0; u < IB; ++u) p[u] = d[u];
+}
+// Orders LDS traffic between the lanes of one wavefront (its LDS operations run in order).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The NB interchanges of a panel starting at row k (pivall[q]: the row exchanged with
 // k + q at step q) as one permutation of at most 2 NB rows, written to lst: entries
 // 0..NB-1 are the positions k..k+NB-1, further entries the pivot rows below the panel;
@@ -158,6 +190,10 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   __shared__ int s_pos[PERM_MAX], s_org[PERM_MAX];
   __shared__ int s_lpos[2 * IB], s_lorg[2 * IB], s_lcnt;
   __shared__ T s_held[2 * IB][2 * NB - IB];
+  // The next leaf stays on chip for 16-wide FP32 leaves of at most half of the registers
+  // (the other shapes run out of registers or occupancy with it).
+  constexpr bool KEEP_NEXT = sizeof(T) == sizeof(float2) && IB == 16 && S * IB * 2 <= 128;
+  __shared__ T s_X[KEEP_NEXT ? PT : 1][IB + 1];  // next leaf, MFMA layout -> one row per thread (wave-private rows)
 
   // the leaf in registers in the storage precision (its updates too; pivot keys in FP64)
   T v[S][IB];
@@ -168,12 +204,17 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
 
   for (int c = 0; c < NB / IB; ++c) {
     const int cl = k + c * IB;
+    if (c == 0 || !KEEP_NEXT) {  // otherwise the leaf came from the previous leaf's rank update
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int r = k + t + s * PT;
+      for (int s = 0; s < S; ++s) {
+        const int r = k + t + s * PT;
+        if (r >= cl && r < nrows) {
+          load_row<IB>(A + r * ld + cl, v[s]);
+        } else {
 #pragma unroll
-      for (int q = 0; q < IB; ++q)
-        v[s][q] = (r >= cl && r < nrows) ? A[r * ld + cl + q] : T{0, 0};
+          for (int q = 0; q < IB; ++q) v[s][q] = T{0, 0};
+        }
+      }
     }
 #pragma clang loop unroll(full)
     for (int j = 0; j < IB; ++j, ++col) {
@@ -286,10 +327,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int r = k + t + s * PT;
-      if (r >= cl && r < nrows) {
-#pragma unroll
-        for (int q = 0; q < IB; ++q) A[r * ld + cl + q] = v[s][q];
-      }
+      if (r >= cl && r < nrows) store_row<IB>(A + r * ld + cl, v[s]);
       if (r >= cl && r < cl + IB) {
 #pragma unroll
         for (int q = 0; q < IB; ++q) s_L11[r - cl][q] = wide(v[s][q]);
@@ -387,20 +425,26 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       __syncthreads();
       // rank-IB update of the panel right of the leaf on the matrix cores: each wave updates
       // its own 64 rows of every PT-row slab, RBP 16-row blocks at a time.  The leaf's L rows
-      // are read back from memory (stored before the barrier above; the leaf registers are
-      // free by now), and all old values and L operands of a group are loaded before its
-      // first product, so a group waits for memory once instead of once per 16 x 16 tile.
-      // Rows above the leaf's last row and columns past w are masked at the load and store.
-      constexpr int CBM = (NB - IB + 15) / 16;                  // 16-column blocks, at most
-      constexpr int VRB = CBM * 4 * (int)sizeof(T) / 4;          // registers per block's old values
-      constexpr int RBP = VRB * 4 <= 96 ? 4 : (VRB * 2 <= 96 ? 2 : 1);
+      // are read back from memory (stored before the barrier above), and all old values and
+      // L operands of a group are loaded before its first product, so a group waits for
+      // memory once instead of once per 16 x 16 tile.  The first IB columns right of the leaf
+      // are the next leaf: their results go through the wave's own rows of s_X straight into
+      // the leaf registers (the slab's old leaf values are dead by then), so the next leaf is
+      // neither stored here nor loaded again; the other columns are written back.  Rows above
+      // the leaf's last row and columns past w are masked at the load and store.
+      constexpr int CBM = (NB - IB + 15) / 16;          // 16-column blocks, at most
+      constexpr int VRB = CBM * 4 * (int)sizeof(T) / 4;  // registers per block's old values
+      // with the next leaf kept on chip its registers stay live through the update, so the
+      // groups are two blocks (one with four row slots)
+      constexpr int RBP = KEEP_NEXT ? (S >= 4 ? 1 : 2) : (VRB * 4 <= 96 ? 4 : (VRB * 2 <= 96 ? 2 : 1));
       typedef StripMma<T, 1, IB> Mma;
       const int ii = lane & 15, kq = lane >> 4;
 #pragma unroll 1
       for (int s = 0; s < S; ++s) {
+        const int r0 = k + s * PT;
 #pragma unroll 1
         for (int g = 0; g < 4; g += RBP) {
-          const int gbase = k + s * PT + wave * 64 + g * 16;
+          const int gbase = r0 + wave * 64 + g * 16;
           if (gbase >= nrows || gbase + RBP * 16 <= cl + IB) continue;  // uniform per wave
           T lop[RBP][IB / 4];
           T old[RBP][CBM][4];
@@ -439,11 +483,28 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
                 if (row >= cl + IB && row < nrows && cc < w) {
                   T nv;
                   narrow_to(nv, csub(wide(old[b][cb][r]), acc.value(0, r)));
-                  A[row * ld + cl + IB + cc] = nv;
+                  if (KEEP_NEXT && cc < IB)
+                    s_X[row - r0][cc] = nv;
+                  else
+                    A[row * ld + cl + IB + cc] = nv;
                 }
               }
             }
           }
+        }
+        if constexpr (KEEP_NEXT) {
+          wave_sync();
+          // the next leaf's rows of this slab (rows above it or past the matrix are zero);
+          // register slots are indexed by constants only
+          const int r = r0 + t;
+          const bool in = r >= cl + IB && r < nrows;
+#pragma unroll
+          for (int ss = 0; ss < S; ++ss)
+            if (ss == s) {
+#pragma unroll
+              for (int q = 0; q < IB; ++q) v[ss][q] = in ? s_X[t][q] : T{0, 0};
+            }
+          wave_sync();  // every lane has its row before the next slab writes s_X
         }
       }
     }
