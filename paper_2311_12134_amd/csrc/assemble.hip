@@ -134,12 +134,27 @@ __device__ inline void ylm_column(int m, double x, double y, double z, double* Y
   }
 }
 
-// M = 1 - T g for BPW consecutive 16 x 16 blocks (a, b) of one job (row-major over the
-// padded block grid).  Phase 1: four threads per block evaluate the 49 real harmonics of
+// Pair p of the upper triangle a <= b < n of an n x n grid, numbered row by row (row a
+// starts at a n - a (a - 1) / 2); p past the end gives some a <= b, unused.
+__device__ inline void pair_of(int p, int n, int& a, int& b) {
+  const double w = 2.0 * n + 1.0;
+  int r = (int)((w - sqrt(fmax(w * w - 8.0 * p, 0.0))) * 0.5);
+  r = min(max(r, 0), n - 1);
+  while (r > 0 && r * n - r * (r - 1) / 2 > p) --r;
+  while (r < n - 1 && (r + 1) * n - (r + 1) * r / 2 <= p) ++r;
+  a = r;
+  b = r + (p - (r * n - r * (r - 1) / 2));
+}
+
+// M = 1 - T g for BPW consecutive pairs a <= b of 16 x 16 blocks of one job (the upper
+// triangle of the padded block grid, row by row).  The structure constants are reciprocal,
+// g^{ba}_{LL'} = g^{ab}_{L'L} (R -> -R flips Y_{L''} by (-1)^{l''} = (-1)^{l+l'} on the Gaunt
+// terms, which cancels the i^{l-l'} phase change of the swap), so one evaluation per pair
+// gives both blocks.  Phase 1: four threads per pair evaluate the 49 real harmonics of
 // R^ = (p_a - p_b)/|R| (split by |m|) and (-4 pi i kappa) i^l h_l(kappa |R|), l <= 6 (the
-// fourth thread), into LDS.  Phase 2: each wavefront contracts its blocks against the
-// slot-dealt Gaunt terms, applies i^{l - l'} and -t_a, stages the block in LDS and writes it
-// row by row.  Diagonal and padding blocks are the identity / zero.
+// fourth thread), into LDS.  Phase 2: each wavefront contracts its pairs against the
+// slot-dealt Gaunt terms, applies i^{l - l'}, stages g^{ab} in LDS and writes the rows of
+// -t_a g^{ab} and of -t_b (g^{ab})^T.  Diagonal and padding blocks are the identity / zero.
 // spm != nullptr: the symmetric form, blocks -s_a g_ab s_b (s = t^{1/2}) instead of -t_a g_ab.
 template <typename T>
 __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, const double* liz_pos,
@@ -154,8 +169,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
   __shared__ double2 s_G[4][NL][NL + 1];
   const JobDesc jd = jobs[blockIdx.y];
   const int nbp = jd.npad / NL;
-  const int blk0 = blockIdx.x * BPW;
-  if (blk0 >= nbp * nbp) return;  // uniform
+  const int npairs = nbp * (nbp + 1) / 2;
+  const int p0 = blockIdx.x * BPW;
+  if (p0 >= npairs) return;  // uniform
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   for (int i = t; i < 4 * 64 * GT; i += 256) {
     (&s_coef[0][0][0])[i] = (&c_slots.coef[0][0][0])[i];
@@ -164,9 +180,10 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
   (&s_pair[0][0])[t] = (&c_slots.pair[0][0])[t];
   const double2 kappa = jd.energy == 0 ? kp : km;
   {
-    const int q = t >> 2, part = t & 3, blk = blk0 + q;
-    const int a = blk / nbp, b = blk % nbp;
-    if (blk < nbp * nbp && a != b && a < jd.nl && b < jd.nl) {
+    const int q = t >> 2, part = t & 3, pp = p0 + q;
+    int a, b;
+    pair_of(pp, nbp, a, b);
+    if (pp < npairs && a != b && b < jd.nl) {  // a < b < nl
       const double* pa = liz_pos + (jd.liz_off + a) * 3;
       const double* pb = liz_pos + (jd.liz_off + b) * 3;
       const double rx = pa[0] - pb[0], ry = pa[1] - pb[1], rz = pa[2] - pb[2];
@@ -205,15 +222,13 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
   __syncthreads();
   const int Lr = lane >> 4, Lc = lane & 15;
   for (int q = wave; q < BPW; q += 4) {
-    const int blk = blk0 + q;
-    if (blk >= nbp * nbp) break;  // uniform per wavefront
-    const int a = blk / nbp, b = blk % nbp;
-    const int64_t base = (int64_t)(a * NL) * jd.npad + b * NL;
-    if (a != b && a < jd.nl && b < jd.nl) {
-      const int atom_a = liz_atom[jd.liz_off + a];
-      const double2* ta = tpm + atom_a * 8 + jd.energy * 4;
-      const double2* sa = spm ? spm + atom_a * 8 + jd.energy * 4 : nullptr;
-      const double2* sb = spm ? spm + liz_atom[jd.liz_off + b] * 8 + jd.energy * 4 : nullptr;
+    const int pp = p0 + q;
+    if (pp >= npairs) break;  // uniform per wavefront
+    int a, b;
+    pair_of(pp, nbp, a, b);
+    const int64_t base_ab = (int64_t)(a * NL) * jd.npad + b * NL;
+    const int64_t base_ba = (int64_t)(b * NL) * jd.npad + a * NL;
+    if (a != b && b < jd.nl) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int pr = s_pair[r][lane], L = pr & 15, Lp = (pr >> 4) & 15, e = pr >> 8;
@@ -225,30 +240,44 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
           g.x += cy * h.x;
           g.y += cy * h.y;
         }
-        // i^{l - l'}, then -t_a
-        const double2 gp = e == 0 ? g : e == 1 ? make_double2(-g.y, g.x) : e == 2 ? make_double2(-g.x, -g.y)
-                                                                                      : make_double2(g.y, -g.x);
-        const double2 tg = spm ? cmul(cmul(sa[lidx(L)], gp), sb[lidx(Lp)]) : cmul(ta[lidx(L)], gp);
-        s_G[wave][L][Lp] = make_double2(-tg.x, -tg.y);
+        // i^{l - l'}
+        s_G[wave][L][Lp] = e == 0 ? g : e == 1 ? make_double2(-g.y, g.x) : e == 2 ? make_double2(-g.x, -g.y)
+                                                                                    : make_double2(g.y, -g.x);
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      const int atom_a = liz_atom[jd.liz_off + a], atom_b = liz_atom[jd.liz_off + b];
+      const double2* ta = tpm + atom_a * 8 + jd.energy * 4;
+      const double2* tb = tpm + atom_b * 8 + jd.energy * 4;
+      const double2* sa = spm ? spm + atom_a * 8 + jd.energy * 4 : nullptr;
+      const double2* sb = spm ? spm + atom_b * 8 + jd.energy * 4 : nullptr;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int L = Lr + 4 * r;
-        const double2 v = s_G[wave][L][Lc];
-        st2(work + jd.a_off + base + (int64_t)L * jd.npad + Lc, v);
-        if (m64) m64[jd.m_off + base + (int64_t)L * jd.npad + Lc] = v;
+        // block (a, b): -t_a g^{ab} (rows scaled), or -s_a g^{ab} s_b
+        const double2 gab = s_G[wave][L][Lc];
+        const double2 vab = spm ? cmul(cmul(sa[lidx(L)], gab), sb[lidx(Lc)]) : cmul(ta[lidx(L)], gab);
+        st2(work + jd.a_off + base_ab + (int64_t)L * jd.npad + Lc, make_double2(-vab.x, -vab.y));
+        if (m64) m64[jd.m_off + base_ab + (int64_t)L * jd.npad + Lc] = make_double2(-vab.x, -vab.y);
+        // block (b, a): g^{ba}_{L Lc} = g^{ab}_{Lc L}
+        const double2 gba = s_G[wave][Lc][L];
+        const double2 vba = spm ? cmul(cmul(sb[lidx(L)], gba), sa[lidx(Lc)]) : cmul(tb[lidx(L)], gba);
+        st2(work + jd.a_off + base_ba + (int64_t)L * jd.npad + Lc, make_double2(-vba.x, -vba.y));
+        if (m64) m64[jd.m_off + base_ba + (int64_t)L * jd.npad + Lc] = make_double2(-vba.x, -vba.y);
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    } else {
+    } else {  // identity on the diagonal, zero off it (both blocks of an off-diagonal pair)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int L = Lr + 4 * r;
         const double2 v = make_double2((a == b && L == Lc) ? 1.0 : 0.0, 0.0);
-        st2(work + jd.a_off + base + (int64_t)L * jd.npad + Lc, v);
-        if (m64) m64[jd.m_off + base + (int64_t)L * jd.npad + Lc] = v;
+        st2(work + jd.a_off + base_ab + (int64_t)L * jd.npad + Lc, v);
+        if (m64) m64[jd.m_off + base_ab + (int64_t)L * jd.npad + Lc] = v;
+        if (a != b) {
+          st2(work + jd.a_off + base_ba + (int64_t)L * jd.npad + Lc, v);
+          if (m64) m64[jd.m_off + base_ba + (int64_t)L * jd.npad + Lc] = v;
+        }
       }
     }
   }
@@ -258,7 +287,7 @@ void launch_assemble_f64(const JobDesc* jobs, int njobs, int npad_max, const dou
                          const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, double2* work,
                          hipStream_t s) {
   const int nbp = npad_max / NL;
-  dim3 grid((nbp * nbp + 63) / 64, njobs);
+  dim3 grid((nbp * (nbp + 1) / 2 + 63) / 64, njobs);
   assemble_kernel<double2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, nullptr, nullptr);
 }
 
@@ -266,7 +295,7 @@ void launch_assemble_split(const JobDesc* jobs, int njobs, int npad_max, const d
                            const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, float2* work,
                            double2* m64, const double2* spm, hipStream_t s) {
   const int nbp = npad_max / NL;
-  dim3 grid((nbp * nbp + 63) / 64, njobs);
+  dim3 grid((nbp * (nbp + 1) / 2 + 63) / 64, njobs);
   assemble_kernel<float2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, m64, spm);
 }
 
