@@ -576,6 +576,137 @@ __global__ __launch_bounds__(512) void linv_kernel(const JobDesc* jobs, int k, T
   }
 }
 
+// FP32 storage: the same inverses blocked in 16 x 16 blocks (indices i, m in 0..3).  One
+// wavefront per diagonal block forms X_ii = L_ii^-1 or Y_ii = U_ii^-1 (16-step FP64
+// substitutions), then the off-diagonal blocks follow from FP64 matrix-core products:
+//   X_ij = -sum_{j <= m < i} (X_ii L_im) X_mj,   Y_ij = -sum_{i < m <= j} (Y_ii U_im) Y_mj,
+// first the six products W = X_ii L_im and the six Y_ii U_im, then the blocks one, two and
+// three steps off the diagonal (waves 0-3 the lower triangle, 4-7 the upper one).  Results
+// are kept in FP64 and rounded once to FP32 at the store.
+__device__ inline void lower_pair(int task, int& i, int& m) {  // (1,0) (2,0) (2,1) (3,0) (3,1) (3,2)
+  i = 1 + (task >= 1) + (task >= 3);
+  m = task - i * (i - 1) / 2;
+}
+__global__ __launch_bounds__(512) void linv_blocked_kernel(const JobDesc* jobs, int k, float2* work) {
+  constexpr int B = 16;
+  const JobDesc jd = jobs[blockIdx.x];
+  if (k >= jd.npad) return;  // uniform
+  float2* A = work + jd.a_off;
+  const int64_t ld = jd.npad;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  __shared__ float2 s_T[NB][NB + 1];           // L11 \ U11 as factored
+  __shared__ double2 s_V[NB][NB + 1];          // X = L11^-1 below the diagonal, Y = U11^-1 on and above
+  __shared__ double2 s_W[2][6][B][B + 1];      // X_ii L_im (index i (i - 1) / 2 + m) and Y_mm U_mi
+  for (int idx = t; idx < NB * NB; idx += 512) {
+    const int q = idx / NB, pp = idx % NB;
+    s_T[q][pp] = A[(k + q) * ld + k + pp];
+  }
+  __syncthreads();
+  const int c = lane & 15, g = lane >> 4;  // a lane's column and row group (rows g + 4 j)
+  const bool lower = wave < 4;
+  // diagonal blocks
+  {
+    const int o = (wave & 3) * B;
+    double2 x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = make_double2(g + 4 * j == c ? 1.0 : 0.0, 0.0);
+    if (lower) {
+#pragma unroll
+      for (int q = 0; q < B; ++q) {  // x_q is final: broadcast it down its column
+        const double2 xq = shfl2(x[q / 4], (q & 3) * 16 + c);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = g + 4 * j;
+          if (r > q) x[j] = cfms(x[j], ld2(&s_T[o + r][o + q]), xq);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (g + 4 * j > c) s_V[o + g + 4 * j][o + c] = x[j];
+    } else {
+#pragma unroll
+      for (int q = B - 1; q >= 0; --q) {  // y_q /= U_qq, then broadcast it up its column
+        if (g == (q & 3)) x[q / 4] = cmul(x[q / 4], cinv(ld2(&s_T[o + q][o + q])));
+        const double2 yq = shfl2(x[q / 4], (q & 3) * 16 + c);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = g + 4 * j;
+          if (r < q) x[j] = cfms(x[j], ld2(&s_T[o + r][o + q]), yq);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (g + 4 * j <= c) s_V[o + g + 4 * j][o + c] = x[j];
+    }
+  }
+  __syncthreads();
+  typedef StripMma<double2, 1, B> Mma;
+  // the inverted diagonal block d as an operand (unit diagonal of X implied, zeros outside)
+  auto diag_at = [&](int d, int r, int cc) -> double2 {
+    const int o = d * B;
+    if (lower) return r > cc ? s_V[o + r][o + cc] : make_double2(r == cc ? 1.0 : 0.0, 0.0);
+    return r <= cc ? s_V[o + r][o + cc] : make_double2(0.0, 0.0);
+  };
+  // W products: lower X_ii L_im (i > m), upper Y_mm U_mi (m < i), six each over four waves
+  for (int task = wave & 3; task < 6; task += 4) {
+    int i, m;
+    lower_pair(task, i, m);
+    Mma acc;
+    acc.zero();
+    if (lower)
+      acc.run([&](int r, int kk) { return diag_at(i, r, kk); },
+              [&](int kk, int cc) { return ld2(&s_T[i * B + kk][m * B + cc]); }, lane);
+    else
+      acc.run([&](int r, int kk) { return diag_at(m, r, kk); },
+              [&](int kk, int cc) { return ld2(&s_T[m * B + kk][i * B + cc]); }, lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s_W[lower ? 0 : 1][task][Mma::row(r, lane)][c] = acc.value(0, r);
+  }
+  __syncthreads();
+  // blocks dd steps off the diagonal: lower X_{i, i-dd}, upper Y_{i-dd, i}, i = dd .. 3
+#pragma unroll 1
+  for (int dd = 1; dd < 4; ++dd) {
+    const int i = dd + (wave & 3);
+    if (i < 4) {
+      const int j = i - dd;
+      Mma acc;
+      acc.zero();
+      for (int m = j; m < i; ++m) {  // lower: W_im X_mj; upper: (Y_jj U_jm... ) as W(j, m) Y_mi
+        if (lower)
+          acc.run([&](int r, int kk) { return s_W[0][i * (i - 1) / 2 + m][r][kk]; },
+                  [&](int kk, int cc) { return m == j ? diag_at(j, kk, cc) : s_V[m * B + kk][j * B + cc]; }, lane);
+        else {
+          const int mm = m + 1;  // Y_{j, i} = -sum_{j < mm <= i} (Y_jj U_{j mm}) Y_{mm, i}
+          acc.run([&](int r, int kk) { return s_W[1][mm * (mm - 1) / 2 + j][r][kk]; },
+                  [&](int kk, int cc) { return mm == i ? diag_at(i, kk, cc) : s_V[mm * B + kk][i * B + cc]; }, lane);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double2 v = acc.value(0, r);
+        const int rr = Mma::row(r, lane);
+        if (lower)
+          s_V[i * B + rr][j * B + c] = make_double2(-v.x, -v.y);
+        else
+          s_V[j * B + rr][i * B + c] = make_double2(-v.x, -v.y);
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < NB * NB; idx += 512) {
+    const int q = idx / NB, pp = idx % NB;
+    st2(A + (k + q) * ld + k + pp, s_V[q][pp]);
+  }
+}
+
+template <typename T>
+static void launch_linv(const JobDesc* jobs, int njobs, int k, T* work, hipStream_t s) {
+  if constexpr (sizeof(T) == sizeof(float2))
+    linv_blocked_kernel<<<njobs, 512, 0, s>>>(jobs, k, work);
+  else
+    linv_kernel<T><<<njobs, 512, 0, s>>>(jobs, k, work);
+}
+
 // ------------------------------------------------------------------------------------
 // interchanges + U12 = L11^-1 A12 on one 64-column tile of the trailing matrix
 // ------------------------------------------------------------------------------------
@@ -966,12 +1097,12 @@ static void panel_step(const JobDesc* jobs, int njobs, int npad_max, int k, int 
     tslu_gather_kernel<T><<<dim3(nc_max, njobs), 256, 0, s>>>(jobs, k, ts.chunk, nc_max, sub1, p1, work, w2, g2);
     launch_panel<T>(sub2, njobs, 0, 0, ((rows + ts.chunk - 1) / ts.chunk) * NB, w2, p2, si2, s);
     tslu_apply_kernel<T><<<njobs, 256, 0, s>>>(jobs, k, left, nc_max, sub2, p2, w2, g2, si2, work, piv, info);
-    linv_kernel<T><<<njobs, 512, 0, s>>>(jobs, k, work);
+    launch_linv<T>(jobs, njobs, k, work, s);
     if (rows > NB) tslu_l21_kernel<T><<<dim3((rows - NB + 63) / 64, njobs), 256, 0, s>>>(jobs, k, work);
     return;
   }
   launch_panel<T>(jobs, njobs, k, left, rows, work, piv, info, s);
-  linv_kernel<T><<<njobs, 512, 0, s>>>(jobs, k, work);
+  launch_linv<T>(jobs, njobs, k, work, s);
 }
 
 // Algorithmic flops and bytes of one trailing-update launch over the unpadded rows m and
@@ -1146,7 +1277,7 @@ void ldlt_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work,
       sym_tall_setup_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(jobs, njobs, k, sub, sinfo, piv);
       launch_panel<float2>(sub, njobs, 0, 0, NB, work, spiv, sinfo, s, 1);
       sym_tall_info_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(njobs, k, sinfo, info);
-      linv_kernel<float2><<<njobs, 512, 0, s>>>(jobs, k, work);
+      launch_linv<float2>(jobs, njobs, k, work, s);
       if (rest > 0) {
         tslu_l21_kernel<float2><<<dim3((rest + 63) / 64, njobs), 256, 0, s>>>(jobs, k, work);
         sym_u12_kernel<float2><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, 1);
@@ -1155,7 +1286,7 @@ void ldlt_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work,
     }
     launch_panel<float2>(jobs, njobs, k, 0, rows, work, piv, info, s, 1);
     if (rest > 0) sym_u12_kernel<float2><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, 0);
-    linv_kernel<float2><<<njobs, 512, 0, s>>>(jobs, k, work);
+    launch_linv<float2>(jobs, njobs, k, work, s);
   };
   auto timed = [&](int k, int kd, int rb, bool lower, int c_end) {
     const int rows = npad_max - rb;
