@@ -4,12 +4,15 @@
 // row tau^{0a}(z) = X_a(z)^T (reciprocity of the complex-symmetric T^-1 - g):
 //   s_m[c][mu][nu] += Tr[ J^{m mu}(z2,z1) X_a(z1)^T J^{a nu}(z1,z2) X_a(z2) ]
 //                  = sum_{ij} (J0_mu X1^T)_{ij} (Ja_nu X2)_{ji}
-// Thread (i, j) of the 16 x 16 workgroup forms one entry of each product for the four
-// combos and three directions, then accumulates either the diagonal mu = nu (12 sums)
-// or the full tensor (36 sums: the same six products per combo, nine pairings), and
-// the workgroup reduces at the end.  The sum over atoms then runs in a fixed order in a
-// single workgroup, so sigma is reproducible.
+// Wavefront c of the workgroup takes combo c: per member it forms the six 16 x 16 x 16
+// products P_mu = J0_mu X1^T and Q_nu = X2^T Ja_nu^T = (Ja_nu X2)^T on the FP64 matrix
+// cores (both land in the same accumulator layout, so entry (i, j) of P_mu meets entry
+// (j, i) of Ja_nu X2 in the same lane and register), then accumulates per lane either the
+// diagonal mu = nu (three sums) or the full tensor (nine pairings), and reduces over the
+// lanes at the end.  The sum over atoms then runs in a fixed order in a single
+// workgroup, so sigma is reproducible.
 #include "lsms_internal.h"
+#include "strip_mma.h"
 
 namespace lsms {
 
@@ -29,7 +32,7 @@ __global__ __launch_bounds__(256) void kubo_trace_kernel(const int64_t* liz_ptr,
   __shared__ double2 sJ0[12][NL][NL + 1];
   __shared__ double2 sJa[12][NL][NL + 1];
   __shared__ double2 sX[2][NL][NL + 1];
-  __shared__ double2 sred[4][NQ];
+  __shared__ double2 sred[NQ];
   const int s0 = species[atom];
   // an out-of-range species index poisons this atom's sums instead of reading past J
   bool bad = s0 < 0 || s0 >= n_species;
@@ -45,10 +48,14 @@ __global__ __launch_bounds__(256) void kubo_trace_kernel(const int64_t* liz_ptr,
     const int cm = idx / (NL * NL), e = idx % (NL * NL);
     sJ0[cm][e / NL][e % NL] = J[((int64_t)s0 * 12 + cm) * NL * NL + e];
   }
-  double2 acc[NQ];
+  constexpr int NC = TENSOR ? 9 : 3;  // accumulators of this wavefront's combo
+  const int lane = t & 63, wave = t >> 6;
+  const int c = wave, z1 = combo_z1(c), z2 = combo_z2(c), crev = z2 * 2 + z1;
+  double2 acc[NC];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int q = 0; q < NC; ++q) acc[q] = make_double2(0.0, 0.0);
   int cur = -1;
+  typedef StripMma<double2, 1, NL> Mma;
   for (int a = 0; a < nl; ++a) {
     __syncthreads();
     const int sa = species[liz_atom[off + a]];
@@ -62,50 +69,41 @@ __global__ __launch_bounds__(256) void kubo_trace_kernel(const int64_t* liz_ptr,
       cur = sa;
     }
     __syncthreads();
+    Mma P[3], Q[3];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int z1 = combo_z1(c), z2 = combo_z2(c);
-      const int crev = z2 * 2 + z1;
-      double2 p1[3], p2[3];
+    for (int mu = 0; mu < 3; ++mu) {
+      P[mu].zero();
+      P[mu].run([&](int r, int k) { return sJ0[crev * 3 + mu][r][k]; }, [&](int k, int q) { return sX[z1][q][k]; },
+                lane);
+      Q[mu].zero();
+      Q[mu].run([&](int r, int k) { return sX[z2][k][r]; }, [&](int k, int q) { return sJa[c * 3 + mu][q][k]; },
+                lane);
+    }
 #pragma unroll
-      for (int mu = 0; mu < 3; ++mu) {
-        p1[mu] = make_double2(0.0, 0.0);
-        p2[mu] = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-          p1[mu] = cfma(p1[mu], sJ0[crev * 3 + mu][i][k], sX[z1][j][k]);  // (J0_mu X1^T)_{ij}
-          p2[mu] = cfma(p2[mu], sJa[c * 3 + mu][j][k], sX[z2][k][i]);     // (Ja_mu X2)_{ji}
-        }
-      }
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int mu = 0; mu < 3; ++mu) {
         if (TENSOR) {
 #pragma unroll
-          for (int nu = 0; nu < 3; ++nu) acc[c * 9 + mu * 3 + nu] = cfma(acc[c * 9 + mu * 3 + nu], p1[mu], p2[nu]);
+          for (int nu = 0; nu < 3; ++nu) acc[mu * 3 + nu] = cfma(acc[mu * 3 + nu], P[mu].value(0, r), Q[nu].value(0, r));
         } else {
-          acc[c * 3 + mu] = cfma(acc[c * 3 + mu], p1[mu], p2[mu]);
+          acc[mu] = cfma(acc[mu], P[mu].value(0, r), Q[mu].value(0, r));
         }
       }
-    }
   }
-  // workgroup reduction of the accumulators (fixed order)
-  const int lane = t & 63, wave = t >> 6;
+  // reduction of each wavefront's accumulators over its lanes (fixed order)
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
+  for (int q = 0; q < NC; ++q) {
     double2 v = acc[q];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
       v.x += __shfl_xor(v.x, o);
       v.y += __shfl_xor(v.y, o);
     }
-    if (lane == 0) sred[wave][q] = v;
+    if (lane == 0) sred[c * NC + q] = v;
   }
   __syncthreads();
-  if (t < NQ) {
-    double2 v = sred[0][t];
-    for (int w = 1; w < 4; ++w) v = cadd(v, sred[w][t]);
-    per_atom[(int64_t)atom * NQ + t] = v;
-  }
+  if (t < NQ) per_atom[(int64_t)atom * NQ + t] = sred[t];
 }
 
 void launch_kubo_trace(int n_atoms, const int64_t* liz_ptr_dev, const int32_t* liz_atom, const double2* tau_plus,
