@@ -530,6 +530,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
 // block wants an inverse: U12 = L11^-1 A12 in swap_trsm_kernel and the four diagonal steps
 // of the solves, which thereby become products on the matrix cores.  No later interchange
 // touches the block (pivots of later panels lie below it), and nothing else reads U11.
+// This form serves FP64 storage; FP32 storage takes the blocked kernel below.
 template <typename T>
 __global__ __launch_bounds__(512) void linv_kernel(const JobDesc* jobs, int k, T* work) {
   const JobDesc jd = jobs[blockIdx.x];
@@ -712,7 +713,7 @@ static void launch_linv(const JobDesc* jobs, int njobs, int k, T* work, hipStrea
 // ------------------------------------------------------------------------------------
 // The tile's panel rows are gathered through LDS with the panel's permutation (the other
 // permuted rows are written back directly), then U12 = L11^-1 A12 is one 64 x 64 x 64
-// product on the matrix cores with the inverse stored by linv_kernel (FP32 three-product
+// product on the matrix cores with the inverse stored by the inverse kernel (FP32 three-product
 // MFMA for FP32 storage, FP64 MFMA otherwise).
 // SECOND: k is the second panel of a pair whose first panel starts at k - NB.  Its
 // trailing columns have not yet received the first panel's update, so after the gather
@@ -812,7 +813,7 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
 //      panel's pivot rows, and that block's top NB x NB factors are the panel's L11, U11;
 //   3. the interchanges that bring those rows to the top (same permutation-list format
 //      as the panel kernel's) are applied to the panel (and the `left` columns), L11\U11
-//      is written over the diagonal block, and after linv_kernel the rows below are
+//      is written over the diagonal block, and after the inverses the rows below are
 //      L21 = A21 U11^-1, one 64 x 64 x 64 product per 16-row strip on the matrix cores.
 // Every step is an ordinary launch over the batch: no workgroup waits for another.
 
@@ -1009,7 +1010,7 @@ __global__ __launch_bounds__(256) void tslu_apply_kernel(const JobDesc* jobs, in
 }
 
 // L21 = A21 U11^-1 below the diagonal block (U11^-1 on and above the block's diagonal,
-// written by linv_kernel): wave w of workgroup (x, job) takes rows k + NB + 64 x + 16 w.
+// written by the inverse kernel): wave w of workgroup (x, job) takes rows k + NB + 64 x + 16 w.
 template <typename T>
 __global__ __launch_bounds__(256) void tslu_l21_kernel(const JobDesc* jobs, int k, T* work) {
   const JobDesc jd = jobs[blockIdx.y];
@@ -1194,7 +1195,7 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
 // the LU solves and the diagonal-block inverses apply unchanged.
 
 // U[k + q][c] = D[q] L[c][k + q] for c in [k + NB, npad): one 64-column tile per workgroup,
-// transposed through LDS.  Runs before linv_kernel (D is read off the diagonal block).
+// transposed through LDS.  Runs before the inverse kernel (D is read off the diagonal block).
 // from_inverse: the diagonal block already holds the inverses (tall panels), D = 1 / diag.
 template <typename T>
 __global__ __launch_bounds__(256) void sym_u12_kernel(const JobDesc* jobs, int k, T* work, int from_inverse) {
