@@ -546,8 +546,6 @@ void launch_residual_norms(const JobDesc* jobs, int njobs, int npad_max, const d
                            const int32_t* done, hipStream_t s);
 void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double tol, int32_t* done, int last,
                         int32_t* job_info, int32_t* pending, hipStream_t s);
-void launch_add_correction(const JobDesc* jobs, int njobs, int npad_max, double2* x, const double2* r,
-                           const int32_t* done, hipStream_t s);
 void launch_zero_i32(int32_t* p, int n, hipStream_t s);
 void launch_zero_pivot_to_fallback(int njobs, int32_t* job_info, hipStream_t s);
 void launch_fallback_status(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info, hipStream_t s);
@@ -600,7 +598,10 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
         ldlt_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, NB, ctx->ldlt.p);
       else
         lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, ts, side);
-      lu_solve_f32(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, q);
+      // the first solve in FP32 on a rounded copy of the right-hand side (refined below)
+      launch_x32(jd, nj, npad_max, 0, xbuf, xbuf, nullptr, q);
+      lu_solve_f32_single(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, nullptr, q);
+      launch_x32(jd, nj, npad_max, 1, nullptr, xbuf, nullptr, q);
     }
   };
   if (!ctx->graphs || prof) {
@@ -802,8 +803,10 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
         HIP_TRY(hipStreamSynchronize(s));
         left = ctx->pinned_flag[0];
         if (last || left == 0) break;
-        lu_solve_f32_skip(jd, nj, npad_max, (const float2*)abuf, piv, rbuf, jdone, s);
-        launch_add_correction(jd, nj, npad_max, xbuf, rbuf, jdone, s);
+        // correction: FP32 solve on the rounded residual, added to the FP64 solution
+        launch_x32(jd, nj, npad_max, 0, rbuf, xbuf, jdone, s);
+        lu_solve_f32_single(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, jdone, s);
+        launch_x32(jd, nj, npad_max, 2, nullptr, xbuf, jdone, s);
       }
       if (left > 0 || sym) {
         // Jobs whose refinement did not converge (info = NOCONV; in the symmetric form also

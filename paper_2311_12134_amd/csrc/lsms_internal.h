@@ -175,9 +175,15 @@ void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* w
                   double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);
 void lu_solve_f32(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
                   double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);
-// Correction solve of the refinement (16 columns) that skips the jobs flagged in skip[].
-void lu_solve_f32_skip(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
-                       double2* x, const int32_t* skip, hipStream_t s);
+// The split-mode refinement's solves (16 columns) in FP32 on the FP32 copy of the right-hand
+// side in columns 16 .. 23 of each solution row (launch_x32 fills and drains it); jobs
+// flagged in skip[] (may be null) are left alone.
+void lu_solve_f32_single(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
+                         double2* x, const int32_t* skip, hipStream_t s);
+// mode 0: FP32 copy <- src columns 0 .. 15 (rounded); 1: x columns 0 .. 15 <- the copy;
+// 2: x columns 0 .. 15 += the copy (src used by mode 0 only; jobs flagged in done skipped)
+void launch_x32(const JobDesc* jobs, int njobs, int npad_max, int mode, const double2* src, double2* x,
+                const int32_t* done, hipStream_t s);
 
 // Split-mode refinement helpers.
 void launch_residual(const JobDesc* jobs, int njobs, int npad_max, const double2* m64, const double2* x,

@@ -170,21 +170,31 @@ void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double to
   refine_step_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(njobs, norms, tol, done, last, job_info, pending);
 }
 
-__global__ void add_correction_kernel(const JobDesc* jobs, double2* x, const double2* r, const int32_t* done) {
+// The split-mode refinement solves in FP32 in columns 16 .. 23 of each solution row (the
+// forward solves use columns 0 .. 15 only): mode 0 rounds src columns 0 .. 15 into that copy,
+// mode 1 widens the copy into x, mode 2 adds it to x (the correction of a refinement step).
+__global__ void x32_kernel(const JobDesc* jobs, int mode, const double2* src, double2* x, const int32_t* done) {
   const int job = blockIdx.y;
-  if (done[job]) return;
+  if (done && done[job]) return;
   const JobDesc jd = jobs[job];
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= jd.npad * NL) return;
   const int row = idx / NL, c = idx % NL;
   const int64_t o = jd.x_off + (int64_t)row * NRHS_MAX + c;
-  x[o] = cadd(x[o], r[o]);
+  float2* v = (float2*)(x + jd.x_off) + 2 * 16 + (int64_t)row * 2 * NRHS_MAX + c;
+  if (mode == 0) {
+    const double2 a = src[o];
+    *v = make_float2((float)a.x, (float)a.y);
+  } else {
+    const double2 d = make_double2((double)v->x, (double)v->y);
+    x[o] = mode == 1 ? d : cadd(x[o], d);
+  }
 }
 
-void launch_add_correction(const JobDesc* jobs, int njobs, int npad_max, double2* x, const double2* r,
-                           const int32_t* done, hipStream_t s) {
+void launch_x32(const JobDesc* jobs, int njobs, int npad_max, int mode, const double2* src, double2* x,
+                const int32_t* done, hipStream_t s) {
   dim3 grid((npad_max * NL + 255) / 256, njobs);
-  add_correction_kernel<<<grid, 256, 0, s>>>(jobs, x, r, done);
+  x32_kernel<<<grid, 256, 0, s>>>(jobs, mode, src, x, done);
 }
 
 __global__ void zero_i32_kernel(int32_t* p, int n) {

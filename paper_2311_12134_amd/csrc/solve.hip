@@ -21,7 +21,10 @@
 // The update is column-oriented (rows below for L and U^T, rows above for U) except for
 // L^T, whose pair rows need a sum over all rows below: there every strip adds its partial
 // product to the pair rows with FP64 atomics.  Arithmetic is FP64 for both storage types of
-// the factors.
+// the factors, except in the split-mode refinement: its forward solves (L and U) with the
+// FP32 factors run in FP32 (three-product FP32 MFMA) on an FP32 copy of the right-hand side,
+// since a solve with FP32 factors is no more accurate than FP32 however it is summed; the
+// residuals and the accumulation of the solution stay FP64.
 #include <type_traits>
 
 #include "lsms_internal.h"
@@ -33,10 +36,43 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 enum { MODE_L = 0, MODE_U = 1, MODE_UT = 2, MODE_LT = 3 };
 
+// The solution block of a job: FP64 rows of NRHS_MAX columns, or the FP32 copy the split-mode
+// refinement solves on, which lives in columns 16 .. 23 of the same rows (2 NRHS_MAX float2
+// per row; the forward solves use columns 0 .. 15 only).
+template <typename XT>
+struct XView;
+template <>
+struct XView<double2> {
+  static constexpr int LD = NRHS_MAX;
+  __device__ static double2* base(double2* xbuf, const JobDesc& jd, int64_t col_off) {
+    return xbuf + jd.x_off + col_off;
+  }
+};
+template <>
+struct XView<float2> {
+  static constexpr int LD = 2 * NRHS_MAX;
+  __device__ static float2* base(double2* xbuf, const JobDesc& jd, int64_t) {
+    return (float2*)(xbuf + jd.x_off) + 2 * 16;
+  }
+};
+// a factor element in the solve's precision
+template <typename XT, typename T>
+__device__ inline XT fac(const T* p);
+template <>
+__device__ inline double2 fac<double2, double2>(const double2* p) { return *p; }
+template <>
+__device__ inline double2 fac<double2, float2>(const float2* p) { return ld2(p); }
+template <>
+__device__ inline float2 fac<float2, float2>(const float2* p) { return *p; }
+__device__ inline double2 xminus(double2 x, double2 v) { return csub(x, v); }
+__device__ inline float2 xminus(float2 x, double2 v) { return make_float2(x.x - (float)v.x, x.y - (float)v.y); }
+__device__ inline void xput(double2& d, double2 v) { d = v; }
+__device__ inline void xput(float2& d, double2 v) { d = make_float2((float)v.x, (float)v.y); }
+
 // One panel permutation of the solution rows (at most PERM_MAX (dst, src) pairs): every
 // source row is read into registers before any destination row is written.
-template <int NRHS>
-__device__ inline void apply_perm(const int32_t* lst, bool inverse, double2* X, int* s_dst, int* s_src, int t) {
+template <int NRHS, typename XT>
+__device__ inline void apply_perm(const int32_t* lst, bool inverse, XT* X, int* s_dst, int* s_src, int t) {
   constexpr int HELD = PERM_MAX * NRHS / 256;
   const int cnt = lst[0];
   for (int i = t; i < cnt; i += 256) {
@@ -46,17 +82,18 @@ __device__ inline void apply_perm(const int32_t* lst, bool inverse, double2* X, 
   __syncthreads();
   const int* from = inverse ? s_dst : s_src;
   const int* to = inverse ? s_src : s_dst;
-  double2 held[HELD];
+  constexpr int LD = XView<XT>::LD;
+  XT held[HELD];
 #pragma unroll
   for (int u = 0; u < HELD; ++u) {
     const int idx = t + 256 * u, i = idx / NRHS, c = idx % NRHS;
-    held[u] = i < cnt ? X[(int64_t)from[i] * NRHS_MAX + c] : make_double2(0.0, 0.0);
+    held[u] = i < cnt ? X[(int64_t)from[i] * LD + c] : XT{};
   }
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < HELD; ++u) {
     const int idx = t + 256 * u, i = idx / NRHS, c = idx % NRHS;
-    if (i < cnt) X[(int64_t)to[i] * NRHS_MAX + c] = held[u];
+    if (i < cnt) X[(int64_t)to[i] * LD + c] = held[u];
   }
   __syncthreads();
 }
@@ -72,20 +109,20 @@ __device__ inline void apply_perm(const int32_t* lst, bool inverse, double2* X, 
 
 // Element (q, p) of an operator on a panel's rows at kp, from the stored diagonal block:
 // the inverse of the unit lower triangle (unit diagonal implied) or of the upper one.
-template <typename T>
-__device__ inline double2 lower_inv(const T* A, int64_t ld, int kp, int q, int p) {
-  return p < q ? ld2(A + (int64_t)(kp + q) * ld + kp + p) : make_double2(p == q ? 1.0 : 0.0, 0.0);
+template <typename XT, typename T>
+__device__ inline XT lower_inv(const T* A, int64_t ld, int kp, int q, int p) {
+  return p < q ? fac<XT>(A + (int64_t)(kp + q) * ld + kp + p) : XT{p == q ? 1.0f : 0.0f, 0.0f};
 }
-template <typename T>
-__device__ inline double2 upper_inv(const T* A, int64_t ld, int kp, int q, int p) {
-  return p >= q ? ld2(A + (int64_t)(kp + q) * ld + kp + p) : make_double2(0.0, 0.0);
+template <typename XT, typename T>
+__device__ inline XT upper_inv(const T* A, int64_t ld, int kp, int q, int p) {
+  return p >= q ? fac<XT>(A + (int64_t)(kp + q) * ld + kp + p) : XT{};
 }
 
 // Y (64 x NRHS) = op (64 x 64) Xin (64 x NRHS in LDS): wave w forms rows 16w .. 16w+16 and
 // hands each element to put(row, column, value).
-template <int NRHS, typename OP, typename PUT>
-__device__ inline void panel_product(OP op, const double2 (*xin)[NRHS], PUT put, int wave, int lane) {
-  StripMma<double2, NRHS / 16> y;
+template <int NRHS, typename XT, typename OP, typename PUT>
+__device__ inline void panel_product(OP op, const XT (*xin)[NRHS], PUT put, int wave, int lane) {
+  StripMma<XT, NRHS / 16> y;
   y.zero();
   y.run([&](int i, int kk) { return op(wave * 16 + i, kk); }, [&](int kk, int c) { return xin[kk][c]; }, lane);
   const int ii = lane & 15;
@@ -95,7 +132,7 @@ __device__ inline void panel_product(OP op, const double2 (*xin)[NRHS], PUT put,
     for (int r = 0; r < 4; ++r) put(wave * 16 + y.row(r, lane), cb * 16 + ii, y.value(cb, r));
 }
 
-template <typename T, int NRHS, int MODE>
+template <typename T, typename XT, int NRHS, int MODE>
 __global__ __launch_bounds__(256) void solve_pair_diag_kernel(const JobDesc* jobs, int k, const T* work,
                                                               const int32_t* piv, double2* xbuf, int64_t col_off,
                                                               const int32_t* skip) {
@@ -106,91 +143,91 @@ __global__ __launch_bounds__(256) void solve_pair_diag_kernel(const JobDesc* job
   const T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
   const int32_t* pv = piv + jd.piv_off;
-  double2* X = xbuf + jd.x_off + col_off;
+  XT* X = XView<XT>::base(xbuf, jd, col_off);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const bool second = k + NB < jd.npad;
   const int k2 = k + NB;
-  __shared__ double2 s_a[NB][NRHS];
-  __shared__ double2 s_b[NB][NRHS];
+  __shared__ XT s_a[NB][NRHS];
+  __shared__ XT s_b[NB][NRHS];
   __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
-  auto xrow = [&](int r) { return X + (int64_t)r * NRHS_MAX; };
-  auto load = [&](double2 (*dst)[NRHS], int r0) {
+  auto xrow = [&](int r) { return X + (int64_t)r * XView<XT>::LD; };
+  auto load = [&](XT (*dst)[NRHS], int r0) {
     for (int idx = t; idx < NB * NRHS; idx += 256) dst[idx / NRHS][idx % NRHS] = xrow(r0 + idx / NRHS)[idx % NRHS];
   };
   auto to_x = [&](int r0, bool keep) {  // result rows to the solution (and to s_b)
     return [=](int row, int c, double2 v) {
-      xrow(r0 + row)[c] = v;
-      if (keep) s_b[row][c] = v;
+      xput(xrow(r0 + row)[c], v);
+      if (keep) xput(s_b[row][c], v);
     };
   };
   // rows of s_a minus a product: each wave updates only its own rows, after its product
-  auto minus_into_a = [&](int row, int c, double2 v) { s_a[row][c] = csub(s_a[row][c], v); };
+  auto minus_into_a = [&](int row, int c, double2 v) { s_a[row][c] = xminus(s_a[row][c], v); };
   if (MODE == MODE_L) {
     // P1, L1^-1, P2 (the first panel's L rows are stored after it), L21 coupling, L2^-1
-    apply_perm<NRHS>(pv + perm_off(jd.npad, k), false, X, s_dst, s_src, t);
+    apply_perm<NRHS, XT>(pv + perm_off(jd.npad, k), false, X, s_dst, s_src, t);
     load(s_a, k);
     __syncthreads();
-    panel_product<NRHS>([&](int q, int p) { return lower_inv(A, ld, k, q, p); }, s_a, to_x(k, true), wave, lane);
+    panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, k, q, p); }, s_a, to_x(k, true), wave, lane);
     if (!second) return;
     __syncthreads();
-    apply_perm<NRHS>(pv + perm_off(jd.npad, k2), false, X, s_dst, s_src, t);
+    apply_perm<NRHS, XT>(pv + perm_off(jd.npad, k2), false, X, s_dst, s_src, t);
     load(s_a, k2);
     __syncthreads();
-    panel_product<NRHS>([&](int q, int p) { return ld2(A + (int64_t)(k2 + q) * ld + k + p); }, s_b, minus_into_a,
+    panel_product<NRHS, XT>([&](int q, int p) { return fac<XT>(A + (int64_t)(k2 + q) * ld + k + p); }, s_b, minus_into_a,
                         wave, lane);
     __syncthreads();
-    panel_product<NRHS>([&](int q, int p) { return lower_inv(A, ld, k2, q, p); }, s_a, to_x(k2, false), wave, lane);
+    panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, k2, q, p); }, s_a, to_x(k2, false), wave, lane);
   } else if (MODE == MODE_U) {
     // U2^-1, U12 coupling, U1^-1
     if (second) {
       load(s_a, k2);
       __syncthreads();
-      panel_product<NRHS>([&](int q, int p) { return upper_inv(A, ld, k2, q, p); }, s_a, to_x(k2, true), wave,
+      panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, k2, q, p); }, s_a, to_x(k2, true), wave,
                           lane);
       __syncthreads();
       load(s_a, k);
       __syncthreads();
-      panel_product<NRHS>([&](int q, int p) { return ld2(A + (int64_t)(k + q) * ld + k2 + p); }, s_b,
+      panel_product<NRHS, XT>([&](int q, int p) { return fac<XT>(A + (int64_t)(k + q) * ld + k2 + p); }, s_b,
                           minus_into_a, wave, lane);
     } else {
       load(s_a, k);
     }
     __syncthreads();
-    panel_product<NRHS>([&](int q, int p) { return upper_inv(A, ld, k, q, p); }, s_a, to_x(k, false), wave, lane);
+    panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, k, q, p); }, s_a, to_x(k, false), wave, lane);
   } else if (MODE == MODE_UT) {
     // U1^-T, U12^T coupling, U2^-T
     load(s_a, k);
     __syncthreads();
-    panel_product<NRHS>([&](int q, int p) { return upper_inv(A, ld, k, p, q); }, s_a, to_x(k, true), wave, lane);
+    panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, k, p, q); }, s_a, to_x(k, true), wave, lane);
     if (!second) return;
     __syncthreads();
     load(s_a, k2);
     __syncthreads();
-    panel_product<NRHS>([&](int q, int p) { return ld2(A + (int64_t)(k + p) * ld + k2 + q); }, s_b, minus_into_a,
+    panel_product<NRHS, XT>([&](int q, int p) { return fac<XT>(A + (int64_t)(k + p) * ld + k2 + q); }, s_b, minus_into_a,
                         wave, lane);
     __syncthreads();
-    panel_product<NRHS>([&](int q, int p) { return upper_inv(A, ld, k2, p, q); }, s_a, to_x(k2, false), wave,
+    panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, k2, p, q); }, s_a, to_x(k2, false), wave,
                         lane);
   } else {
     // MODE_LT: L2^-T, L21^T coupling, L1^-T, then P2^-1 and P1^-1
     if (second) {
       load(s_a, k2);
       __syncthreads();
-      panel_product<NRHS>([&](int q, int p) { return lower_inv(A, ld, k2, p, q); }, s_a, to_x(k2, true), wave,
+      panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, k2, p, q); }, s_a, to_x(k2, true), wave,
                           lane);
       __syncthreads();
       load(s_a, k);
       __syncthreads();
-      panel_product<NRHS>([&](int q, int p) { return ld2(A + (int64_t)(k2 + p) * ld + k + q); }, s_b,
+      panel_product<NRHS, XT>([&](int q, int p) { return fac<XT>(A + (int64_t)(k2 + p) * ld + k + q); }, s_b,
                           minus_into_a, wave, lane);
     } else {
       load(s_a, k);
     }
     __syncthreads();
-    panel_product<NRHS>([&](int q, int p) { return lower_inv(A, ld, k, p, q); }, s_a, to_x(k, false), wave, lane);
+    panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, k, p, q); }, s_a, to_x(k, false), wave, lane);
     __syncthreads();
-    if (second) apply_perm<NRHS>(pv + perm_off(jd.npad, k2), true, X, s_dst, s_src, t);
-    apply_perm<NRHS>(pv + perm_off(jd.npad, k), true, X, s_dst, s_src, t);
+    if (second) apply_perm<NRHS, XT>(pv + perm_off(jd.npad, k2), true, X, s_dst, s_src, t);
+    apply_perm<NRHS, XT>(pv + perm_off(jd.npad, k), true, X, s_dst, s_src, t);
   }
 }
 
@@ -199,11 +236,11 @@ __global__ __launch_bounds__(256) void solve_pair_diag_kernel(const JobDesc* job
 //          MODE_U   X[s] -= U[s, pair] X[pair]      (s above)
 //          MODE_UT  X[s] -= U[pair, s]^T X[pair]    (s below)
 //          MODE_LT  X[pair] -= L[s, pair]^T X[s]    (s below; FP64 atomics into the pair rows)
-template <typename T, int NRHS, int MODE, int KD>
-__device__ inline void pair_update(const T* A, int64_t ld, double2* X, int k, int s0, int wave, int lane) {
-  auto xrow = [&](int r) { return X + (int64_t)r * NRHS_MAX; };
+template <typename T, typename XT, int NRHS, int MODE, int KD>
+__device__ inline void pair_update(const T* A, int64_t ld, XT* X, int k, int s0, int wave, int lane) {
+  auto xrow = [&](int r) { return X + (int64_t)r * XView<XT>::LD; };
   const int ii = lane & 15;
-  if (MODE == MODE_LT) {
+  if constexpr (MODE == MODE_LT) {
     // out rows = the pair's KD rows (KD / 16 blocks, dealt to the four waves), K = 64 strip rows
     for (int rb = wave; rb < KD / 16; rb += 4) {
       StripMma<double2, NRHS / 16> y;
@@ -222,24 +259,25 @@ __device__ inline void pair_update(const T* A, int64_t ld, double2* X, int k, in
     }
     return;
   }
-  StripMma<double2, NRHS / 16, KD> y;
+  StripMma<XT, NRHS / 16, KD> y;
   y.zero();
   const int r0 = s0 + wave * 16;
   y.run(
       [&](int i, int kk) {
-        return MODE == MODE_UT ? ld2(A + (int64_t)(k + kk) * ld + r0 + i) : ld2(A + (int64_t)(r0 + i) * ld + k + kk);
+        return MODE == MODE_UT ? fac<XT>(A + (int64_t)(k + kk) * ld + r0 + i)
+                               : fac<XT>(A + (int64_t)(r0 + i) * ld + k + kk);
       },
       [&](int kk, int c) { return xrow(k + kk)[c]; }, lane);
 #pragma unroll
   for (int cb = 0; cb < NRHS / 16; ++cb)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      double2* xp = xrow(r0 + y.row(r, lane)) + cb * 16 + ii;
-      *xp = csub(*xp, y.value(cb, r));
+      XT* xp = xrow(r0 + y.row(r, lane)) + cb * 16 + ii;
+      *xp = xminus(*xp, y.value(cb, r));
     }
 }
 
-template <typename T, int NRHS, int MODE>
+template <typename T, typename XT, int NRHS, int MODE>
 __global__ __launch_bounds__(256) void solve_pair_update_kernel(const JobDesc* jobs, int k, const T* work,
                                                                 double2* xbuf, int64_t col_off, const int32_t* skip) {
   const int job = blockIdx.y;
@@ -250,26 +288,26 @@ __global__ __launch_bounds__(256) void solve_pair_update_kernel(const JobDesc* j
   if (MODE == MODE_U ? (s0 >= k) : (s0 >= jd.npad)) return;  // uniform
   const T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
-  double2* X = xbuf + jd.x_off + col_off;
+  XT* X = XView<XT>::base(xbuf, jd, col_off);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (MODE == MODE_U && k + NB >= jd.npad)
-    pair_update<T, NRHS, MODE, NB>(A, ld, X, k, s0, wave, lane);
+    pair_update<T, XT, NRHS, MODE, NB>(A, ld, X, k, s0, wave, lane);
   else
-    pair_update<T, NRHS, MODE, 2 * NB>(A, ld, X, k, s0, wave, lane);
+    pair_update<T, XT, NRHS, MODE, 2 * NB>(A, ld, X, k, s0, wave, lane);
 }
 
-template <typename T, int NRHS>
+template <typename T, typename XT, int NRHS>
 static void solve_all(const JobDesc* jobs, int njobs, int npad_max, const T* work, const int32_t* piv, double2* x,
                       int64_t col_off, int trans, const int32_t* skip, hipStream_t s) {
   const int last = ((npad_max - 1) / (2 * NB)) * (2 * NB);  // start of the last pair
   auto diag = [&](auto mode_tag, int k) {
     constexpr int MODE = decltype(mode_tag)::value;
-    solve_pair_diag_kernel<T, NRHS, MODE><<<njobs, 256, 0, s>>>(jobs, k, work, piv, x, col_off, skip);
+    solve_pair_diag_kernel<T, XT, NRHS, MODE><<<njobs, 256, 0, s>>>(jobs, k, work, piv, x, col_off, skip);
   };
   auto update = [&](auto mode_tag, int k, int strips) {
     constexpr int MODE = decltype(mode_tag)::value;
     if (strips <= 0) return;
-    solve_pair_update_kernel<T, NRHS, MODE><<<dim3(strips, njobs), 256, 0, s>>>(jobs, k, work, x, col_off, skip);
+    solve_pair_update_kernel<T, XT, NRHS, MODE><<<dim3(strips, njobs), 256, 0, s>>>(jobs, k, work, x, col_off, skip);
   };
   using L = std::integral_constant<int, MODE_L>;
   using U = std::integral_constant<int, MODE_U>;
@@ -284,7 +322,7 @@ static void solve_all(const JobDesc* jobs, int njobs, int npad_max, const T* wor
       diag(U{}, k);
       update(U{}, k, k / 64);
     }
-  } else {
+  } else if constexpr (std::is_same<XT, double2>::value) {  // transposed solves: FP64 only
     for (int k = 0; k < npad_max; k += 2 * NB) {
       diag(UT{}, k);
       update(UT{}, k, (npad_max - k - 2 * NB) / 64);
@@ -300,9 +338,9 @@ template <typename T>
 static void solve_dispatch(const JobDesc* jobs, int njobs, int npad_max, const T* work, const int32_t* piv,
                            double2* x, int64_t col_off, int nrhs, int trans, const int32_t* skip, hipStream_t s) {
   if (nrhs == 16)
-    solve_all<T, 16>(jobs, njobs, npad_max, work, piv, x, col_off, trans, skip, s);
+    solve_all<T, double2, 16>(jobs, njobs, npad_max, work, piv, x, col_off, trans, skip, s);
   else
-    solve_all<T, 32>(jobs, njobs, npad_max, work, piv, x, col_off, trans, skip, s);
+    solve_all<T, double2, 32>(jobs, njobs, npad_max, work, piv, x, col_off, trans, skip, s);
 }
 
 void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
@@ -315,9 +353,9 @@ void lu_solve_f32(const JobDesc* jobs, int njobs, int npad_max, const float2* wo
   solve_dispatch<float2>(jobs, njobs, npad_max, work, piv, x, x_col_off, nrhs, trans, nullptr, s);
 }
 
-void lu_solve_f32_skip(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
-                       double2* x, const int32_t* skip, hipStream_t s) {
-  solve_dispatch<float2>(jobs, njobs, npad_max, work, piv, x, 0, 16, 0, skip, s);
+void lu_solve_f32_single(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
+                         double2* x, const int32_t* skip, hipStream_t s) {
+  solve_all<float2, float2, 16>(jobs, njobs, npad_max, work, piv, x, 0, 0, skip, s);
 }
 
 }  // namespace lsms
