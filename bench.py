@@ -294,7 +294,7 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None,
-           "dtype": "fp32 LU updates + fp64 pivot keys/residuals/refinement" if args.precision == "split" else "f64",
+           "dtype": "fp32 LU updates and refinement solves + fp64 pivot keys/residuals/solution" if args.precision == "split" else "f64",
            "data": "synthetic (seeded structure, phase shifts and current matrices)",
            "config": {"workload": "%s: %s, %d atoms, LIZ %d-%d atoms, lmax 3, eF %.2f Ry, eta cycling %s Ry"
                       % (w["name"], w["lattice"], n_atoms, int(n_true.min() / 16), int(n_true.max() / 16),
