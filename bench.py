@@ -196,6 +196,11 @@ def main():
                     help="skip the separately reported gradient run (250-atom bcc alloy, d sigma_xx / d delta)")
     ap.add_argument("--paper-scale-only", action="store_true",
                     help="run only the paper-scale leg (for profiling it) and print its JSON object")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="alternate the waves between two streams (LSMS_TUNE_PIPELINE)")
+    ap.add_argument("--workspace-frac", type=float, default=0.8,
+                    help="wave workspace as a fraction of free HBM after the inputs are allocated "
+                         "(the library's own default is 0.6, which leaves more room for the caller)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy before the timed region (scale for HBM counters)")
     args = ap.parse_args()
@@ -227,7 +232,9 @@ def main():
     phase = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(dev)
     species = torch.from_numpy(w["species"].astype(np.int32)).to(dev)
     J = torch.from_numpy(np.ascontiguousarray(w["J"])).to(dev)
-    ctx = P.Context(0)
+    ws = int(args.workspace_frac * torch.cuda.mem_get_info()[0]) if args.workspace_frac > 0 else 0
+    ctx = P.Context(0, workspace_limit=ws)
+    ctx.set_pipeline(args.pipeline)
     ctx.set_gemm_tiling(args.gemm_tiling)
     tune = None
     if args.gemm_tiling < 0 and not args.no_autotune and args.precision == "split":
@@ -300,6 +307,7 @@ def main():
                       % (w["name"], w["lattice"], n_atoms, int(n_true.min() / 16), int(n_true.max() / 16),
                          w["e_fermi"], etas),
                       "precision": args.precision, "gemm_tiling": ctx.gemm_tiling(), "graphs": args.graphs,
+                      "pipeline": args.pipeline, "workspace_frac": args.workspace_frac or 0.6,
                       "parallelism": "single GPU, all atoms batched"},
            "path_tflops_alg": alg_flops_step * args.steps / elapsed / 1e12,
            "path_frac_of_peak": alg_flops_step * args.steps / elapsed / peak,

@@ -314,6 +314,23 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * Not the paper's LU: reported apart from the LU rate.
  */
 #define LSMS_TUNE_SYMMETRIC 5
+/*
+ * knob LSMS_TUNE_PIPELINE (0 or 1, default 0): with 1 and a batch of two or more waves,
+ * lsms_tau_solve alternates waves between the caller's stream and a second, non-blocking
+ * stream of the context (default priority), each with half of the workspace, and issues
+ * the next wave's assembly, factorization and first solve before the current wave's
+ * refinement, so memory-bound refinement overlaps matrix-core factorization.  The call's
+ * work is complete on the caller's stream when its last launch is (an event joins the
+ * second stream).  When all systems share one padded size, every system goes through the
+ * same kernels as with 0 and the results are bitwise those of 0; with uneven sizes the
+ * waves group the systems differently, and since a wave's panel launches are shaped by its
+ * largest system, a system may take a different panel variant (leaf width) and round
+ * differently.  Not used with kept factors, the symmetric form, the look-ahead stream,
+ * tournament panels (LIZ above 2 C rows) or profiling (lsms_set_profiling).  Off by
+ * default: on the 4000-atom fcc alloy it measured within 0.3 % of one stream, since halving
+ * the waves costs about what the overlap gains.
+ */
+#define LSMS_TUNE_PIPELINE 6
 int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
 int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
 

@@ -214,6 +214,17 @@ class Context:
         fallback, instead of the LU (not with kept factors)."""
         check(lib().lsms_set_tuning(self._h, 5, 1 if on else 0))
 
+    def set_pipeline(self, on=True):
+        """Alternate waves between two streams so one wave's refinement overlaps the next
+        wave's factorization (default off; with one padded size the results are bitwise the
+        same)."""
+        check(lib().lsms_set_tuning(self._h, 6, 1 if on else 0))
+
+    def pipeline(self):
+        v = ctypes.c_int(0)
+        check(lib().lsms_get_tuning(self._h, 6, ctypes.byref(v)))
+        return bool(v.value)
+
     def set_tslu_chunk(self, rows=2048):
         """Rows per chunk of the tournament-pivoting panels (used for panels taller than
         2 * rows; a multiple of 64 in [64, 2048])."""

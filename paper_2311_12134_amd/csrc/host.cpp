@@ -113,6 +113,9 @@ struct lsms_ctx {
   size_t pinned_bytes = 0;
   int32_t* pinned_flag = nullptr;  // host-visible counter read back between refinement sweeps
   DevBuf fallback;                 // job list of the FP64 fallback
+  bool pipeline = false;           // alternate waves between two streams (see lsms_tau_solve)
+  hipStream_t pipe = nullptr;      // the second stream (non-blocking, default priority)
+  hipEvent_t pipe_start = nullptr, pipe_end = nullptr;
 };
 
 // Tiling of the split-mode trailing update in effect for a context.
@@ -300,6 +303,9 @@ extern "C" int lsms_destroy(lsms_ctx* ctx) {
   if (ctx->side.update_done) hipEventDestroy(ctx->side.update_done);
   if (ctx->side.panel_done) hipEventDestroy(ctx->side.panel_done);
   if (ctx->side.stream) hipStreamDestroy(ctx->side.stream);
+  if (ctx->pipe_start) hipEventDestroy(ctx->pipe_start);
+  if (ctx->pipe_end) hipEventDestroy(ctx->pipe_end);
+  if (ctx->pipe) hipStreamDestroy(ctx->pipe);
   delete ctx;
   return LSMS_OK;
 }
@@ -680,10 +686,28 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
   const int64_t tpm_bytes = align_up((int64_t)n_atoms * 8 * 16, 256);
   const int64_t small_fixed = 2 * tpm_bytes;  // tpm | spm
   const int64_t limit = (int64_t)ctx->workspace_limit;
-  std::vector<Wave> waves = make_waves(jobs, precision, limit, keep != nullptr);
+  // Pipelining: with two or more waves, waves alternate between the caller's stream and a
+  // second one, each stream with its own half of the workspace, and the next wave's
+  // assembly, factorization and first solve are issued before this wave's refinement loop
+  // (whose host reads wait on its own stream only), so HBM-bound refinement overlaps
+  // matrix-core factorization.  Waves on one stream run in order, which is what makes
+  // reusing a half safe.  Not used where waves would share other context scratch (kept
+  // factors, the symmetric form's tall-panel scratch, tournament panels, the look-ahead
+  // stream) or with kernel profiling (its timings assume one stream).
+  bool pipe = ctx->pipeline && keep == nullptr && !ctx->profiling && !sym && !ctx->lookahead &&
+              jobs[0].npad <= 2 * std::max(ctx->tslu_chunk, NB);
+  std::vector<Wave> waves;
+  if (pipe) {
+    waves = make_waves(jobs, precision, limit / 2, false);
+    int64_t mw = 0;
+    for (auto& w : waves) mw = std::max(mw, w.bytes);
+    if (waves.size() < 2 || mw > limit / 2) pipe = false;
+  }
+  if (!pipe) waves = make_waves(jobs, precision, limit, keep != nullptr);
   int64_t max_wave = 0;
   for (auto& w : waves) max_wave = std::max(max_wave, w.bytes);
-  if (max_wave > limit) {
+  max_wave = align_up(max_wave, 256);
+  if (max_wave > (pipe ? limit / 2 : limit)) {
     return fail(LSMS_E_NOMEM, "a wave needs %lld bytes of workspace but the limit is %lld%s", (long long)max_wave,
                 (long long)limit, keep ? " (keep requires every factor to stay resident)" : "");
   }
@@ -726,12 +750,13 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     wbase = (char*)fac->work;
     sbase = wbase + max_wave;
   } else {
-    if (ctx->work.bytes < (size_t)max_wave) {
+    const size_t need = (size_t)max_wave * (pipe ? 2 : 1);
+    if (ctx->work.bytes < need) {
       // grow with slack, so alternating precisions or slightly larger waves do not
       // reallocate (and re-map) tens of GB on every call
-      const size_t want = std::min((size_t)limit, std::max((size_t)max_wave + ((size_t)max_wave >> 2),
-                                                           2 * ctx->work.bytes));
-      rc = ensure_dev(ctx->work, std::max(want, (size_t)max_wave), s);
+      const size_t want = std::min((size_t)limit, std::max(need + (need >> 2), 2 * ctx->work.bytes));
+      if (ctx->pipe) HIP_TRY(hipStreamSynchronize(ctx->pipe));  // a previous call's second stream
+      rc = ensure_dev(ctx->work, std::max(want, need), s);
       if (rc) return rc;
     }
     rc = ensure_dev(ctx->small, (size_t)small_bytes, s);
@@ -750,7 +775,40 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
   HIP_TRY(hipMemcpyAsync(jobs_dev, ctx->pinned, (size_t)njobs_all * sizeof(JobDesc), hipMemcpyHostToDevice, s));
   launch_tmatrix(phase, n_atoms, kp, tpm, spm, s);
 
-  for (size_t w = 0; w < waves.size(); ++w) {
+  if (pipe) {
+    if (!ctx->pipe) {
+      HIP_TRY(hipStreamCreateWithFlags(&ctx->pipe, hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&ctx->pipe_start, hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&ctx->pipe_end, hipEventDisableTiming));
+    }
+    // the second stream starts after the uploads above
+    HIP_TRY(hipEventRecord(ctx->pipe_start, s));
+    HIP_TRY(hipStreamWaitEvent(ctx->pipe, ctx->pipe_start, 0));
+  }
+  hipStream_t const caller = s;
+  struct WaveBufs {
+    void* abuf;
+    double2 *m64, *xbuf, *rbuf;
+    int32_t* piv;
+  };
+  auto bufs_of = [&](size_t w) {
+    char* p = wbase + (pipe ? (int64_t)(w & 1) * max_wave : 0);
+    WaveBufs b;
+    b.abuf = p;
+    p += wave_sizes[5 * w];
+    b.m64 = (double2*)p;
+    p += wave_sizes[5 * w + 1];
+    b.xbuf = (double2*)p;
+    p += wave_sizes[5 * w + 2];
+    b.rbuf = (double2*)p;
+    p += wave_sizes[5 * w + 3];
+    b.piv = (int32_t*)p;
+    return b;
+  };
+  // stage 1 of a wave: inputs, right-hand side, assembly, factorization, first solve (and,
+  // in FP64 mode, the whole wave); nothing here waits on the host
+  auto stage1 = [&](size_t w) -> int {
+    hipStream_t s = (pipe && (w & 1)) ? ctx->pipe : caller;
     const Wave& wv = waves[w];
     const int nj = wv.e - wv.b;
     const int npad_max = jobs[wv.b].npad;
@@ -758,17 +816,12 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     int32_t* jinfo = job_info + wv.b;
     double* jnorm = norms + 8 * (size_t)wv.b;
     int32_t* jdone = done + wv.b;
-    char* p = wbase;
-    void* abuf = p;
-    p += wave_sizes[5 * w];
-    double2* m64 = (double2*)p;
-    p += wave_sizes[5 * w + 1];
-    double2* xbuf = (double2*)p;
-    p += wave_sizes[5 * w + 2];
-    double2* rbuf = (double2*)p;
-    p += wave_sizes[5 * w + 3];
-    int32_t* piv = (int32_t*)p;
-
+    const WaveBufs wb = bufs_of(w);
+    void* abuf = wb.abuf;
+    double2* m64 = wb.m64;
+    double2* xbuf = wb.xbuf;
+    int32_t* piv = wb.piv;
+    int rc;
     GemmProfiler* prof = nullptr;
     if (ctx->profiling) {
       ctx->n_true.resize(nj);
@@ -792,6 +845,30 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
       if (sym) launch_zero_pivot_to_fallback(nj, jinfo, s);
       launch_zero_i32(jdone, nj, s);
       launch_zero(jnorm, 8 * (int64_t)nj, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return LSMS_OK;
+  };
+  // stage 2 of a split-mode wave: refinement (host reads of its own stream only), FP64
+  // fallback, tau blocks and status
+  auto stage2 = [&](size_t w) -> int {
+    if (precision == LSMS_FP64) return LSMS_OK;
+    hipStream_t s = (pipe && (w & 1)) ? ctx->pipe : caller;
+    const Wave& wv = waves[w];
+    const int nj = wv.e - wv.b;
+    const int npad_max = jobs[wv.b].npad;
+    const JobDesc* jd = jobs_dev + wv.b;
+    int32_t* jinfo = job_info + wv.b;
+    double* jnorm = norms + 8 * (size_t)wv.b;
+    int32_t* jdone = done + wv.b;
+    const WaveBufs wb = bufs_of(w);
+    void* abuf = wb.abuf;
+    double2* m64 = wb.m64;
+    double2* xbuf = wb.xbuf;
+    double2* rbuf = wb.rbuf;
+    int32_t* piv = wb.piv;
+    int rc;
+    {
       int left = nj;
       for (int it = 0; it <= max_refine; ++it) {
         const int last = it == max_refine;
@@ -813,7 +890,8 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
         // those that met a zero pivot) are recomputed in FP64: the FP64 copy of the matrix
         // is factored in place with partial pivoting and solved directly.
         std::vector<int32_t> hinfo(nj);
-        HIP_TRY(hipMemcpy(hinfo.data(), jinfo, nj * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpyAsync(hinfo.data(), jinfo, nj * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
         std::vector<JobDesc> fb;
         for (int j = 0; j < nj; ++j)
           if (hinfo[j] == LSMS_INFO_NOCONV) {
@@ -828,7 +906,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           if (rc) return rc;
           JobDesc* fjd = (JobDesc*)ctx->fallback.p;
           int32_t* finfo = (int32_t*)((char*)ctx->fallback.p + align_up(fb.size() * sizeof(JobDesc), 256));
-          HIP_TRY(hipMemcpy(fjd, fb.data(), fb.size() * sizeof(JobDesc), hipMemcpyHostToDevice));
+          HIP_TRY(hipMemcpyAsync(fjd, fb.data(), fb.size() * sizeof(JobDesc), hipMemcpyHostToDevice, s));
           launch_zero_i32(finfo, nf, s);
           const int fpad = fb[0].npad;
           launch_init_rhs(fjd, nf, fpad, liz_atom, rhs_t, xbuf, s);
@@ -838,12 +916,37 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s, nullptr, fts);
           lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, s);
           launch_fallback_status(nf, fjd, finfo, jinfo, s);
+          // the fallback's job list is context scratch: done before another wave reuses it
+          HIP_TRY(hipStreamSynchronize(s));
         }
       }
       launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, spm, liz_atom, s);
       launch_write_status(jd, nj, jinfo, jnorm, info, berr, mirror, s);
     }
     HIP_TRY(hipGetLastError());
+    return LSMS_OK;
+  };
+  if (!pipe) {
+    for (size_t w = 0; w < waves.size(); ++w) {
+      rc = stage1(w);
+      if (rc) return rc;
+      rc = stage2(w);
+      if (rc) return rc;
+    }
+  } else {
+    rc = stage1(0);
+    if (rc) return rc;
+    for (size_t w = 0; w < waves.size(); ++w) {
+      if (w + 1 < waves.size()) {
+        rc = stage1(w + 1);
+        if (rc) return rc;
+      }
+      rc = stage2(w);
+      if (rc) return rc;
+    }
+    // the caller's stream continues after the second stream's last wave
+    HIP_TRY(hipEventRecord(ctx->pipe_end, ctx->pipe));
+    HIP_TRY(hipStreamWaitEvent(caller, ctx->pipe_end, 0));
   }
   if (keep) {
     fac->jobs = jobs;
@@ -921,9 +1024,10 @@ extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
     ctx->tslu_chunk = value;
     return LSMS_OK;
   }
-  if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY) {
+  if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY || knob == LSMS_TUNE_PIPELINE) {
     if (value != 0 && value != 1) return fail(LSMS_E_ARG, "knob %d takes 0 or 1 (got %d)", knob, value);
-    (knob == LSMS_TUNE_GRAPHS ? ctx->graphs : ctx->conj_symmetry) = value == 1;
+    (knob == LSMS_TUNE_GRAPHS ? ctx->graphs : knob == LSMS_TUNE_PIPELINE ? ctx->pipeline : ctx->conj_symmetry) =
+        value == 1;
     return LSMS_OK;
   }
   if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);
@@ -943,8 +1047,10 @@ extern "C" int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value) {
     *value = (knob == LSMS_TUNE_LOOKAHEAD ? ctx->lookahead : ctx->symmetric) ? 1 : 0;
     return LSMS_OK;
   }
-  if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY) {
-    *value = (knob == LSMS_TUNE_GRAPHS ? ctx->graphs : ctx->conj_symmetry) ? 1 : 0;
+  if (knob == LSMS_TUNE_GRAPHS || knob == LSMS_TUNE_CONJ_SYMMETRY || knob == LSMS_TUNE_PIPELINE) {
+    *value = (knob == LSMS_TUNE_GRAPHS ? ctx->graphs : knob == LSMS_TUNE_PIPELINE ? ctx->pipeline : ctx->conj_symmetry)
+                 ? 1
+                 : 0;
     return LSMS_OK;
   }
   if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);

@@ -579,6 +579,9 @@ def test_lookahead_matches_single_stream(lctx, name, precision, chunk):
     liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
     la, lp, phase, species, J = _device_inputs(w, liz)
     lctx.set_tslu_chunk(chunk)
+    # the look-ahead stream turns wave pipelining off; keep it off in both runs so the waves
+    # group the (uneven) systems alike (it is off by default too)
+    lctx.set_pipeline(False)
     try:
         lctx.set_lookahead(False)
         a = lctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
@@ -850,3 +853,43 @@ def test_graph_replay_symmetric(lctx):
     finally:
         lctx.set_graphs(False)
         lctx.set_symmetric(False)
+
+
+@pytest.mark.parametrize("precision", ["split", "fp64"])
+def test_pipelined_waves_bitwise(lctx, precision):
+    """Waves alternating between two streams (LSMS_TUNE_PIPELINE) give bitwise
+    the results of one stream and of a single wave when all systems share one padded size:
+    a 4 GiB workspace cuts bcc250 into many waves.  Also with captured graphs replayed on
+    both streams."""
+    import paper_2311_12134_amd as P
+    w = synthetic.workload("bcc250")
+    eta = w["etas"][0]
+    print("[gpu] pipelined waves bcc250 %s" % precision, flush=True)
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    la, lp, phase, species, J = _device_inputs(w, liz)
+
+    def solve(ctx):
+        tp, tm, info, berr = ctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
+        sig, _, _ = ctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"])
+        torch.cuda.synchronize()
+        return [a.cpu().numpy() for a in (tp, tm, info, berr, sig)]
+
+    one = solve(lctx)  # the whole batch is one wave in the default workspace
+    small = P.Context(0, workspace_limit=4 << 30)
+    try:
+        assert not small.pipeline()
+        small.set_pipeline(True)
+        got = solve(small)
+        small.set_graphs(True)
+        replays = [solve(small) for _ in range(2)]
+        small.set_graphs(False)
+        small.set_pipeline(False)
+        ref = solve(small)
+    finally:
+        small.close()
+    assert (one[2] == 0).all()
+    for i, (a, b, c) in enumerate(zip(got, ref, one)):
+        assert np.array_equal(a, b) and np.array_equal(a, c), i
+    for r in replays:
+        for i, (a, b) in enumerate(zip(got, r)):
+            assert np.array_equal(a, b), i
