@@ -114,6 +114,7 @@ struct lsms_ctx {
   int32_t* pinned_flag = nullptr;  // host-visible counter read back between refinement sweeps
   DevBuf fallback;                 // job list of the FP64 fallback
   bool pipeline = false;           // alternate waves between two streams (see lsms_tau_solve)
+  int cu_count = 1;                // compute units of the device (wave sizes are trimmed to multiples)
   hipStream_t pipe = nullptr;      // the second stream (non-blocking, default priority)
   hipEvent_t pipe_start = nullptr, pipe_end = nullptr;
 };
@@ -279,6 +280,11 @@ extern "C" int lsms_create(int hip_device, int lmax, size_t workspace_limit, lsm
     workspace_limit = (size_t)(0.6 * (double)fr);
   }
   c->workspace_limit = workspace_limit;
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+      c->cu_count = cus;
+  }
   int rc = build_gaunt(c->gaunt);
   if (rc) return rc;
   HIP_TRY(upload_gaunt(c->gaunt));
@@ -499,21 +505,35 @@ struct Wave {
   int64_t bytes;
 };
 
-static std::vector<Wave> make_waves(std::vector<JobDesc>& jobs, int precision, int64_t limit, bool single) {
+// Jobs (sorted by size) grouped into waves of at most `limit` bytes.  A wave that the limit
+// cuts is trimmed to a multiple of `round` jobs (the compute units: the panel, inverse and
+// diagonal-solve launches run one workgroup per job, one per compute unit at a time), so no
+// wave but the last ends in a nearly empty round of those latency-bound launches.
+static std::vector<Wave> make_waves(std::vector<JobDesc>& jobs, int precision, int64_t limit, bool single,
+                                    int round = 1) {
   std::vector<Wave> waves;
+  const int n = (int)jobs.size();
+  std::vector<int64_t> need(n);
+  for (int j = 0; j < n; ++j) {
+    JobBytes jb = job_bytes(jobs[j].npad, precision);
+    need[j] = jb.a + jb.m + jb.x + jb.r + jb.piv;
+  }
   int b = 0;
   int64_t acc = 0;
-  for (int j = 0; j < (int)jobs.size(); ++j) {
-    JobBytes jb = job_bytes(jobs[j].npad, precision);
-    int64_t need = jb.a + jb.m + jb.x + jb.r + jb.piv;
-    if (!single && j > b && (acc + need > limit || j - b >= 8192)) {
-      waves.push_back({b, j, acc});
-      b = j;
+  for (int j = 0; j < n; ++j) {
+    if (!single && j > b && (acc + need[j] > limit || j - b >= 8192)) {
+      int e = j;
+      if (round > 1 && j - b > round) e = b + (j - b) / round * round;
+      int64_t bytes = 0;
+      for (int q = b; q < e; ++q) bytes += need[q];
+      waves.push_back({b, e, bytes});
+      b = e;
       acc = 0;
+      for (int q = b; q < j; ++q) acc += need[q];
     }
-    acc += need;
+    acc += need[j];
   }
-  waves.push_back({b, (int)jobs.size(), acc});
+  waves.push_back({b, n, acc});
   return waves;
 }
 
@@ -698,12 +718,12 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
               jobs[0].npad <= 2 * std::max(ctx->tslu_chunk, NB);
   std::vector<Wave> waves;
   if (pipe) {
-    waves = make_waves(jobs, precision, limit / 2, false);
+    waves = make_waves(jobs, precision, limit / 2, false, ctx->cu_count);
     int64_t mw = 0;
     for (auto& w : waves) mw = std::max(mw, w.bytes);
     if (waves.size() < 2 || mw > limit / 2) pipe = false;
   }
-  if (!pipe) waves = make_waves(jobs, precision, limit, keep != nullptr);
+  if (!pipe) waves = make_waves(jobs, precision, limit, keep != nullptr, ctx->cu_count);
   int64_t max_wave = 0;
   for (auto& w : waves) max_wave = std::max(max_wave, w.bytes);
   max_wave = align_up(max_wave, 256);

@@ -190,9 +190,10 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   __shared__ int s_pos[PERM_MAX], s_org[PERM_MAX];
   __shared__ int s_lpos[2 * IB], s_lorg[2 * IB], s_lcnt;
   __shared__ T s_held[2 * IB][2 * NB - IB];
-  // The next leaf stays on chip for 16-wide FP32 leaves of at most half of the registers
-  // (the other shapes run out of registers or occupancy with it).
-  constexpr bool KEEP_NEXT = sizeof(T) == sizeof(float2) && IB == 16 && S * IB * 2 <= 128;
+  // The next leaf stays on chip for 16-wide FP32 leaves of at most half of the registers and
+  // for the 256-thread kernels' 8-wide FP32 leaves of one or two row slots (the other shapes
+  // run out of registers or occupancy with it).
+  constexpr bool KEEP_NEXT = sizeof(T) == sizeof(float2) && (IB == 16 || (PT == 256 && S <= 2)) && S * IB * 2 <= 128;
   __shared__ T s_X[KEEP_NEXT ? PT : 1][IB + 1];  // next leaf, MFMA layout -> one row per thread (wave-private rows)
 
   // the leaf in registers in the storage precision (its updates too; pivot keys in FP64)
@@ -435,8 +436,8 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       constexpr int CBM = (NB - IB + 15) / 16;          // 16-column blocks, at most
       constexpr int VRB = CBM * 4 * (int)sizeof(T) / 4;  // registers per block's old values
       // with the next leaf kept on chip its registers stay live through the update, so the
-      // groups are two blocks (one with four row slots)
-      constexpr int RBP = KEEP_NEXT ? (S >= 4 ? 1 : 2) : (VRB * 4 <= 96 ? 4 : (VRB * 2 <= 96 ? 2 : 1));
+      // groups are two blocks (one with four row slots or 256 threads)
+      constexpr int RBP = KEEP_NEXT ? (S >= 4 || PT == 256 ? 1 : 2) : (VRB * 4 <= 96 ? 4 : (VRB * 2 <= 96 ? 2 : 1));
       typedef StripMma<T, 1, IB> Mma;
       const int ii = lane & 15, kq = lane >> 4;
 #pragma unroll 1
