@@ -258,12 +258,12 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * knob LSMS_TUNE_GEMM_F32 selects the tiling, 0 .. LSMS_GEMM_F32_VARIANTS - 1, or -1 for
  * the library's default (0: 64 x 64 tiles; 1, 2: 64 x 64 pipelined through two LDS stages,
  * 2 with an XCD-aware workgroup order; 3 - 6: 128-row / 128-column tiles; 7: as 2 with the C
- * tile prefetched early; 8: as 2 with K chunks of 32); every tiling computes the same update (results may differ in
- * FP32 rounding order only).  Host-side setting of the context, no device work; returns
+ * tile prefetched early; 8: as 2 with K chunks of 32; 9: as 2 on FP32 MFMA 32x32x2); every
+ * tiling computes the same update (results may differ in FP32 rounding order only).  Host-side setting of the context, no device work; returns
  * LSMS_E_ARG for an unknown knob or value.  lsms_get_tuning reports the tiling in effect.
  */
 #define LSMS_TUNE_GEMM_F32 0
-#define LSMS_GEMM_F32_VARIANTS 9
+#define LSMS_GEMM_F32_VARIANTS 10
 /*
  * knob LSMS_TUNE_GRAPHS (0 or 1, default 0): with 1, lsms_tau_solve captures each wave's
  * factorization and first solve (a fixed sequence of a few hundred launches) into a HIP

@@ -249,7 +249,7 @@ class Context:
         """Time every split-mode tiling for systems of padded size npad on a synthetic batch
         and adopt the fastest; returns (best tiling, [ms per tiling])."""
         best = ctypes.c_int(-1)
-        ms = (ctypes.c_float * 9)()
+        ms = (ctypes.c_float * 10)()
         check(lib().lsms_autotune(self._h, int(npad), int(batch), ctypes.byref(best), ms, _stream()))
         return best.value, [float(x) for x in ms]
 

@@ -170,13 +170,16 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, i
 // share L21 and U12 panels, run on the same XCD (workgroups are dealt to the eight XCDs
 // round-robin) and hit the same L2.
 // ------------------------------------------------------------------------------------
-template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false>
+template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false, bool M32 = false>
 __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, int tiles_x, int tiles_y, int k, int kd,
                                                          int r_begin, int c_begin, int c_end, float2* work) {
   // KC: K chunk per LDS stage.  PFC: the wave's C elements are loaded two chunks before
   // the end, so their latency overlaps the last chunks' MFMAs instead of the epilogue.
   // TRI: only the tiles on and below the diagonal of the (square) updated block, numbered
   // row by row (tile row y holds y + 1 tiles) -- the symmetric factorization's update.
+  // M32: each wave's 32 x 32 block on FP32 MFMA 32x32x2 (three 32 x 32 real products, two
+  // k per step; A lane l -> (row l%32, k l/32), B lane l -> (k l/32, column l%32), D lane l,
+  // register r -> (row 8(r/4) + 4(l/32) + r%4, column l%32)): half the MFMA instructions.
   constexpr int WAVES_N = TN / WN;
   static_assert((TM / WM) * (TN / WN) == 4, "four waves per workgroup");
   constexpr int BM = WM / 16, BN = WN / 16;
@@ -273,15 +276,22 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
     }
   };
 
-  f4 t1[BM][BN], t2[BM][BN], t3[BM][BN];
+  static_assert(!M32 || (WM == 32 && WN == 32 && !PFC), "32x32x2 form: one 32 x 32 block per wave");
+  typedef float f16v __attribute__((ext_vector_type(16)));
+  constexpr int BM_ = M32 ? 1 : BM, BN_ = M32 ? 1 : BN;
+  f4 t1[BM_][BN_], t2[BM_][BN_], t3[BM_][BN_];
+  f16v u1, u2, u3;  // the 32x32x2 form's accumulators
 #pragma unroll
-  for (int i = 0; i < BM; ++i)
+  for (int i = 0; i < BM_; ++i)
 #pragma unroll
-    for (int j = 0; j < BN; ++j) {
+    for (int j = 0; j < BN_; ++j) {
       t1[i][j] = f4{0, 0, 0, 0};
       t2[i][j] = f4{0, 0, 0, 0};
       t3[i][j] = f4{0, 0, 0, 0};
     }
+  u1 = f16v{};
+  u2 = f16v{};
+  u3 = f16v{};
   const int ii = lane & 15, kq = lane >> 4;
 
   load(0);
@@ -306,6 +316,17 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
     const bool more = kc + KC < kd;
     if (more) load(kc + KC);
     if (PFC && kc == (kd > 2 * KC ? kd - 2 * KC : 0)) load_c();
+    if constexpr (M32) {
+#pragma unroll
+      for (int k2 = 0; k2 < KC; k2 += 2) {
+        const int kk = k2 + (lane >> 5), i32 = lane & 31;
+        const float2 a = sA[cur][kk][(wm * WM + i32) ^ aswz(kk)];
+        const float2 b = sB[cur][kk][wn * WN + i32];
+        u1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, u1, 0, 0, 0);
+        u2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, u2, 0, 0, 0);
+        u3 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x + a.y, b.x + b.y, u3, 0, 0, 0);
+      }
+    } else
 #pragma unroll
     for (int k4 = 0; k4 < KC; k4 += 4) {
       float2 a[BM], b[BN];
@@ -334,6 +355,23 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
     cur ^= 1;
   }
   if (!active) return;
+  if constexpr (M32) {
+    const int rbase = row0 + wm * WM, cbase = col0 + wn * WN + (lane & 31);
+    if (cbase < cmax) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = rbase + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row < npad) {
+          float2* cp = A + (int64_t)row * ld + cbase;
+          float2 cv = *cp;
+          cv.x -= u1[r] - u2[r];
+          cv.y -= u3[r] - u1[r] - u2[r];
+          *cp = cv;
+        }
+      }
+    }
+    return;
+  }
   // D lane l, register r -> (row 4(l/16) + r, col l%16) of each 16 x 16 block
 #pragma unroll
   for (int i = 0; i < BM; ++i)
@@ -359,13 +397,13 @@ void launch_gemm_f64(const JobDesc* jobs, int njobs, int rows, int cols, int k, 
   gemm_f64_kernel<<<grid, 256, 0, s>>>(jobs, k, kd, r_begin, c_begin, c_end, work);
 }
 
-template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false>
+template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false, bool M32 = false>
 static void launch_tiled(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                          int c_begin, int c_end, float2* work, hipStream_t s) {
   const int tx = (cols + TN - 1) / TN, ty = (rows + TM - 1) / TM;
   const int64_t n = TRI ? (int64_t)ty * (ty + 1) / 2 * njobs : (int64_t)tx * ty * njobs;
-  gemm_f32_3m_tiled<TM, TN, WM, WN, XCD, KC, PFC, TRI><<<(unsigned)n, 256, 0, s>>>(jobs, tx, ty, k, kd, r_begin,
-                                                                                   c_begin, c_end, work);
+  gemm_f32_3m_tiled<TM, TN, WM, WN, XCD, KC, PFC, TRI, M32><<<(unsigned)n, 256, 0, s>>>(jobs, tx, ty, k, kd, r_begin,
+                                                                                        c_begin, c_end, work);
 }
 
 // Lower-triangle tiles only (rows and columns start together): the update
@@ -375,7 +413,7 @@ void launch_gemm_f32_lower(const JobDesc* jobs, int njobs, int rows, int k, int 
   launch_tiled<64, 64, 32, 32, true, 16, false, true>(jobs, njobs, rows, rows, k, kd, rc_begin, rc_begin, 0, work, s);
 }
 
-int gemm_f32_variants() { return 9; }
+int gemm_f32_variants() { return 10; }
 
 void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                      int c_begin, int c_end, float2* work, hipStream_t s) {
@@ -388,6 +426,7 @@ void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int 
     case 6: launch_tiled<128, 128, 64, 64, false>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
     case 7: launch_tiled<64, 64, 32, 32, true, 16, true>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
     case 8: launch_tiled<64, 64, 32, 32, true, 32, false>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
+    case 9: launch_tiled<64, 64, 32, 32, true, 16, false, false, true>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s); break;
     default: {
       dim3 grid(cols / 64, rows / 64, njobs);
       gemm_f32_3m_kernel<<<grid, 256, 0, s>>>(jobs, k, kd, r_begin, c_begin, c_end, work);
