@@ -767,10 +767,12 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   const int row0 = k + wave * 16;  // this wavefront's 16 panel rows
   if (SECOND) {
     // s_X -= L[k.., k-NB..k) U[k-NB.., col0..]: wave w owns rows 16w .. 16w+16
+    T la[NB / 4];
+#pragma unroll
+    for (int s4 = 0; s4 < NB / 4; ++s4) la[s4] = A[(int64_t)(row0 + ii) * ld + (k - NB) + 4 * s4 + (lane >> 4)];
     StripMma<T, 4> d;
     d.zero();
-    d.run([&](int i, int kk) { return A[(int64_t)(row0 + i) * ld + (k - NB) + kk]; },
-          [&](int kk, int c) { return A[(int64_t)(k - NB + kk) * ld + col0 + c]; }, lane);
+    d.run_regs(la, [&](int kk, int c) { return A[(int64_t)(k - NB + kk) * ld + col0 + c]; }, lane);
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -779,19 +781,22 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
         st2(xp, csub(ld2(xp), d.value(cb, r)));
       }
   }
-  __syncthreads();
   // U12 = L11^-1 A12 straight from the accumulators to the panel rows (the inverse is
-  // stored below the diagonal; its unit diagonal and zero upper part are implied)
+  // stored below the diagonal; its unit diagonal and zero upper part are implied).  The
+  // lane's sixteen inverse entries are loaded before the barrier, in one batch.
+  T li[NB / 4];
+  {
+    const int q = wave * 16 + ii;
+#pragma unroll
+    for (int s4 = 0; s4 < NB / 4; ++s4) {
+      const int kk = 4 * s4 + (lane >> 4);
+      li[s4] = kk < q ? A[(int64_t)(k + q) * ld + k + kk] : T{kk == q ? 1.0f : 0.0f, 0.0f};
+    }
+  }
+  __syncthreads();
   StripMma<T, 4> u;
   u.zero();
-  u.run(
-      [&](int i, int kk) {
-        const int q = wave * 16 + i;
-        T l = A[(int64_t)(k + q) * ld + k + kk];
-        if (kk >= q) l = T{kk == q ? 1.0f : 0.0f, 0.0f};
-        return l;
-      },
-      [&](int kk, int c) { return s_X[kk][c]; }, lane);
+  u.run_regs(li, [&](int kk, int c) { return s_X[kk][c]; }, lane);
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
