@@ -50,36 +50,72 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, eta, n_sample, n_single=3):
-    """The oracle as it stands on a few atoms of the same workload (host cores), and on a
-    smaller sample with its BLAS held to one thread."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, etas, n_sample, n_single=3):
+    """The oracle as it stands on a seeded sample of atoms of the same workload (host cores),
+    split evenly over the broadenings the timed region cycles through, and a smaller sample
+    with its BLAS held to one thread.  The oracle builds its own LIZ for the sampled centres
+    (outside the timer, as the library's LIZ build is outside the GPU's timed region); its
+    per-atom Kubo sums are returned for the error report."""
     from oracle import kubo
+    from oracle import liz as oliz
     try:
         from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         threadpool_limits = None
         threads = os.cpu_count()
-    import paper_2311_12134_amd as P
-    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    rng = np.random.default_rng(2311012134 + 30)
+    sample = rng.choice(len(w["pos"]), n_sample, replace=False)
+    groups = {eta: sorted(int(a) for a in sample[k::len(etas)]) for k, eta in enumerate(etas)}
+    lists = oliz.build_liz(w["pos"], w["cell"], w["r_liz"], centres=sorted(int(a) for a in sample))
 
-    def run(atoms):
+    def run(atoms, eta):
         t0 = time.perf_counter()
-        kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
-                   atoms=atoms, liz_lists=(liz.ptr, liz.atom, liz.pos))
-        return time.perf_counter() - t0
+        r = kubo.sigma(w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta,
+                       atoms=atoms, liz_lists=lists)
+        return time.perf_counter() - t0, r
 
-    dt = run(list(range(n_sample)))
-    what = "of the %s workload at eta=%g (both energies, assembly + LU + both tau blocks + Kubo traces)" % (
-        w["name"], eta)
+    dt = 0.0
+    per_atom = {}
+    for eta, atoms in groups.items():
+        d, r = run(atoms, eta)
+        dt += d
+        per_atom[eta] = r["per_atom"]
+    what = "of the %s workload, %s atoms at eta %s Ry (both energies, assembly + LU + both tau blocks + Kubo " \
+           "traces)" % (w["name"], "/".join(str(len(a)) for a in groups.values()), "/".join("%g" % e for e in etas))
     res = {"value": n_sample / dt, "unit": "atoms/s", "cores": int(threads), "kind": "oracle",
-           "sample": "%d atoms %s, %.1f s" % (n_sample, what, dt)}
+           "sample": "%d atoms %s, %.1f s" % (n_sample, what, dt), "cpu_model": cpu_model()}
     if threadpool_limits is not None and n_single > 0:
+        atoms1 = groups[etas[0]][:n_single]
         with threadpool_limits(limits=1):
-            d1 = run(list(range(n_single)))
-        res["single_thread"] = {"value": n_single / d1, "unit": "atoms/s", "cores": 1,
-                                "sample": "%d atoms %s, %.1f s" % (n_single, what, d1)}
-    return res
+            d1, _ = run(atoms1, etas[0])
+        res["single_thread"] = {"value": len(atoms1) / d1, "unit": "atoms/s", "cores": 1,
+                                "sample": "%d atoms of the same sample at eta %g, %.1f s" % (len(atoms1), etas[0], d1)}
+    return res, lists, groups, per_atom
+
+
+def oracle_errors(groups, oracle_pa, gpu_pa):
+    """Largest relative error of the GPU's per-atom Kubo sums (all 4 x 3 entries) against the
+    oracle's, per broadening, over the sampled atoms."""
+    out = {}
+    for eta, atoms in groups.items():
+        if eta not in gpu_pa:
+            continue
+        errs = [float(np.abs(gpu_pa[eta][a] - oracle_pa[eta][a]).max() / np.abs(oracle_pa[eta][a]).max())
+                for a in atoms]
+        out[eta] = max(errs)
+    return out
 
 
 def adjoint_leg(P, torch, ctx):
@@ -175,6 +211,29 @@ def paper_scale_leg(P, torch, ctx, n_sample, precision, ldlt=False):
     return res
 
 
+def gemm_roofline(ctx, precision, workload, tiling, timed_in):
+    """The wide trailing update's roofline entry from the launches recorded while profiling."""
+    gemm_ms, launches, flops, alg_bytes = ctx.kernel_stats(kind=1)
+    if not launches:
+        return None
+    avg_s = gemm_ms / launches / 1e3
+    achieved = flops / launches / avg_s
+    peak = PEAK_FP32_MFMA if precision == "split" else PEAK_FP64_MFMA
+    if precision == "split":
+        kname = "gemm_f32_3m_tiled" if tiling > 0 else "gemm_f32_3m_kernel"
+    else:
+        kname = "gemm_f64_kernel"
+    with open(GEMM_SOURCE, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    rec = TRAFFIC.get((precision, workload, tiling if precision == "split" else -1))
+    same_shape = rec is not None and abs(alg_bytes / launches / rec["alg_bytes_per_launch"] - 1) < 1e-3
+    traffic = rec["bytes_per_launch"] if rec is not None and rec["sha256"] == digest and same_shape else None
+    return {"kernel": kname, "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "timed_in": timed_in, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "launches": launches, "avg_launch_ms": 1e3 * avg_s, "alg_flops_per_launch": flops / launches,
+            "alg_bytes_per_launch": alg_bytes / launches}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,9 +247,10 @@ def main():
     ap.add_argument("--gemm-tiling", type=int, default=-1,
                     help="tiling of the split-mode trailing update (-1: autotune, unless --no-autotune)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tiling")
-    ap.add_argument("--graphs", action="store_true",
-                    help="replay factorization + solve from HIP graphs (the roofline then comes from one extra "
-                         "eager step after the timed region)")
+    ap.add_argument("--graphs", action=argparse.BooleanOptionalAction, default=True,
+                    help="time the steps with each wave's factorization + first solve replayed from HIP graphs "
+                         "(default); the trailing update's launch times then come from a second, eager timed "
+                         "region over the same steps, which is reported too")
     ap.add_argument("--no-conj-leg", action="store_true",
                     help="skip the separately reported run that solves z+ only and derives tau(z-)")
     ap.add_argument("--paper-scale-atoms", type=int, default=26,
@@ -238,6 +298,21 @@ def main():
     phase = torch.from_numpy(np.ascontiguousarray(w["phase"])).to(dev)
     species = torch.from_numpy(w["species"].astype(np.int32)).to(dev)
     J = torch.from_numpy(np.ascontiguousarray(w["J"])).to(dev)
+    n_atoms = liz.n_atoms
+    tp = torch.empty((liz.total, 16, 16), dtype=torch.complex128, device=dev)
+    tm = torch.empty_like(tp)
+
+    def outputs():
+        # one set per broadening, so every eta's status and sums survive the timed region
+        return {eta: {"info": torch.empty((n_atoms, 2), dtype=torch.int32, device=dev),
+                      "berr": torch.empty((n_atoms, 2), dtype=torch.float64, device=dev),
+                      "sig": torch.empty(3, dtype=torch.float64, device=dev),
+                      "st": torch.empty((4, 3), dtype=torch.complex128, device=dev),
+                      "pa": torch.empty((n_atoms, 4, 3), dtype=torch.complex128, device=dev)} for eta in etas}
+
+    main_out = outputs()
+    fp64_out = outputs() if (not args.no_fp64_compare and args.precision == "split") else None
+    side_out = outputs()
     ws = int(args.workspace_frac * torch.cuda.mem_get_info()[0]) if args.workspace_frac > 0 else 0
     ctx = P.Context(0, workspace_limit=ws)
     ctx.set_pipeline(args.pipeline)
@@ -248,21 +323,22 @@ def main():
         best, ms = ctx.autotune(npad_max, batch=256)
         tune = {"npad": npad_max, "batch": 256, "best": best, "ms_per_tiling": [round(m, 3) for m in ms]}
         log("autotuned tiling %d for npad %d: %s ms" % (best, npad_max, tune["ms_per_tiling"]))
-    ctx.set_graphs(args.graphs)
-    n_atoms = liz.n_atoms
-    tp = torch.empty((liz.total, 16, 16), dtype=torch.complex128, device=dev)
-    tm = torch.empty_like(tp)
-    info = torch.empty((n_atoms, 2), dtype=torch.int32, device=dev)
-    berr = torch.empty((n_atoms, 2), dtype=torch.float64, device=dev)
-    sig = torch.empty(3, dtype=torch.float64, device=dev)
-    st = torch.empty((4, 3), dtype=torch.complex128, device=dev)
 
-    def step(i, precision, keep_sigma=None):
+    def step(i, precision, out):
         eta = etas[i % len(etas)]
-        ctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision, out=(tp, tm, info, berr))
-        ctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], out=(sig, st, None))
-        if keep_sigma is not None:
-            keep_sigma[eta] = sig.clone()
+        b = out[eta]
+        ctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision, out=(tp, tm, b["info"], b["berr"]))
+        ctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], out=(b["sig"], b["st"], b["pa"]))
+
+    def timed(precision, out, steps, graphs, profile):
+        ctx.set_graphs(graphs)
+        ctx.set_profiling(profile)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(i, precision, out)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
@@ -273,37 +349,36 @@ def main():
         log("copy calibration: %d bytes read, %d bytes written" % (src.numel() * 4, dst.numel() * 4))
         del src, dst
 
-    sig_main = {}
+    ctx.set_graphs(args.graphs)
     for i in range(args.warmup):
-        step(i, args.precision, sig_main)
+        step(i, args.precision, main_out)
         torch.cuda.synchronize()
         log("warmup step %d done" % i)
-    # The trailing update's launches are timed with HIP events inside the timed region.  The
-    # library replays no graph while it profiles, so with --graphs the timed region runs
-    # unprofiled and one more (eager, profiled) step supplies the roofline figures.
-    ctx.set_profiling(not args.graphs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i, args.precision, sig_main)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    # The trailing update's launches are timed with HIP events on the stream they run on.  The
+    # library records no events inside replayed graphs, so with graphs the headline region runs
+    # unprofiled and a second, eager region over the same steps supplies the launch times.
+    elapsed = timed(args.precision, main_out, args.steps, args.graphs, not args.graphs)
+    eager = None
     if args.graphs:
-        ctx.set_profiling(True)
-        step(0, args.precision)
-        torch.cuda.synchronize()
-    gemm_ms, gemm_launches, gemm_flops, gemm_bytes = ctx.kernel_stats(kind=1)
-    narrow_ms, narrow_launches, narrow_flops, _ = ctx.kernel_stats(kind=0)
+        el_e = timed(args.precision, main_out, args.steps, False, True)
+        eager = {"value": n_atoms * args.steps / el_e, "unit": "atoms/s", "ms_per_step": 1e3 * el_e / args.steps,
+                 "what": "the same steps with every launch issued eagerly (trailing-update launches timed)"}
+        log("eager region: %.1f ms/step" % (1e3 * el_e / args.steps))
     tiling = ctx.gemm_tiling()
+    roof = gemm_roofline(ctx, args.precision, args.workload, tiling,
+                         "the eager timed region" if args.graphs else "the timed region")
+    narrow_ms, narrow_launches, narrow_flops, _ = ctx.kernel_stats(kind=0)
     ctx.set_profiling(False)
-    info_np = info.cpu().numpy()
+    ctx.set_graphs(False)
     ms_per_step = 1e3 * elapsed / args.steps
     value = n_atoms * args.steps / elapsed
-    log("timed %d steps: %.1f ms/step, %.1f atoms/s" % (args.steps, ms_per_step, value))
+    log("timed %d steps: %.1f ms/step, %.1f atoms/s%s" % (args.steps, ms_per_step, value,
+                                                         " (graph replay)" if args.graphs else ""))
 
     n_true = 16 * np.diff(liz.ptr).astype(np.float64)
     alg_flops_step = float(np.sum(2.0 * ((8.0 / 3.0) * n_true**3 + 128.0 * n_true**2)))
     peak = PEAK_FP32_MFMA if args.precision == "split" else PEAK_FP64_MFMA
+    timed_etas = sorted({etas[i % len(etas)] for i in range(max(args.steps, 1))}, reverse=True)
     out = {"metric": METRIC, "value": value, "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None,
@@ -312,83 +387,74 @@ def main():
            "config": {"workload": "%s: %s, %d atoms, LIZ %d-%d atoms, lmax 3, eF %.2f Ry, eta cycling %s Ry"
                       % (w["name"], w["lattice"], n_atoms, int(n_true.min() / 16), int(n_true.max() / 16),
                          w["e_fermi"], etas),
-                      "precision": args.precision, "gemm_tiling": ctx.gemm_tiling(), "graphs": args.graphs,
+                      "precision": args.precision, "gemm_tiling": tiling, "graphs": args.graphs,
                       "pipeline": args.pipeline, "workspace_frac": args.workspace_frac or 0.6,
                       "parallelism": "single GPU, all atoms batched"},
            "path_tflops_alg": alg_flops_step * args.steps / elapsed / 1e12,
-           "path_frac_of_peak": alg_flops_step * args.steps / elapsed / peak,
-           "info_nonzero": int((info_np != 0).sum())}
+           "path_frac_of_peak": alg_flops_step * args.steps / elapsed / peak}
+    if eager is not None:
+        eager["path_frac_of_peak"] = alg_flops_step * args.steps / (1e-3 * eager["ms_per_step"] * args.steps) / peak
+        out["eager"] = eager
     if tune is not None:
         out["autotune"] = tune
-    if gemm_launches:
-        avg_s = gemm_ms / gemm_launches / 1e3
-        achieved = gemm_flops / gemm_launches / avg_s
-        if args.precision == "split":
-            kname = "gemm_f32_3m_tiled" if tiling > 0 else "gemm_f32_3m_kernel"
-        else:
-            kname = "gemm_f64_kernel"
-        with open(GEMM_SOURCE, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
-        rec = TRAFFIC.get((args.precision, args.workload, tiling if args.precision == "split" else -1))
-        same_shape = rec is not None and abs(gemm_bytes / max(gemm_launches, 1) / rec["alg_bytes_per_launch"] - 1) < 1e-3
-        traffic = rec["bytes_per_launch"] if rec is not None and rec["sha256"] == digest and same_shape else None
-        out["roofline"] = {"kernel": kname, "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                           "timed_in": "an extra eager step after the timed region" if args.graphs
-                           else "the timed region",
-                           "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                           "launches": gemm_launches, "avg_launch_ms": 1e3 * avg_s,
-                           "alg_flops_per_launch": gemm_flops / gemm_launches,
-                           "alg_bytes_per_launch": gemm_bytes / gemm_launches}
+    if roof is not None:
+        out["roofline"] = roof
     if narrow_launches:
         out["narrow_update"] = {"launches": narrow_launches, "avg_launch_ms": narrow_ms / narrow_launches,
                                 "achieved_tflops": narrow_flops / (narrow_ms / 1e3) / 1e12}
-    if not args.no_fp64_compare and args.precision == "split":
-        sig64 = {}
-        step(0, "fp64", sig64)  # warm-up of the FP64 path (workspace layout differs)
+    per_eta = {}
+    for eta in timed_etas:
+        b = main_out[eta]
+        info_np, berr_np = b["info"].cpu().numpy(), b["berr"].cpu().numpy()
+        per_eta[eta] = {"eta": eta, "info_nonzero": int((info_np != 0).sum()), "berr_max": float(berr_np.max()),
+                        "sigma": b["sig"].cpu().numpy().tolist()}
+    out["info_nonzero"] = sum(v["info_nonzero"] for v in per_eta.values())
+    if fp64_out is not None:
+        # the plain FP64 GPU path, one step per broadening after one warm-up step, its wide
+        # trailing update timed like the split mode's
+        step(0, "fp64", fp64_out)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        step(0, "fp64", sig64)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t1
-        eta0 = etas[0]
-        s_split = sig_main[eta0].cpu().numpy()
-        s_64 = sig64[eta0].cpu().numpy()
-        out["fp64_ms_per_step"] = 1e3 * t64
-        out["fp64_atoms_per_s"] = n_atoms / t64
-        out["split_speedup_vs_fp64"] = (n_atoms / t64) and value / (n_atoms / t64)
-        out["sigma_rel_err_split_vs_fp64"] = float(np.abs(s_split - s_64).max() / np.abs(s_64).max())
-        log("fp64 step %.1f ms; sigma split %s fp64 %s" % (1e3 * t64, s_split, s_64))
+        t64 = timed("fp64", fp64_out, len(etas), False, True)
+        roof64 = gemm_roofline(ctx, "fp64", args.workload, -1, "the FP64 steps")
+        ctx.set_profiling(False)
+        fp64_ms = 1e3 * t64 / len(etas)
+        out["fp64_ms_per_step"] = fp64_ms
+        out["fp64_atoms_per_s"] = n_atoms / (1e-3 * fp64_ms)
+        out["split_speedup_vs_fp64"] = value / out["fp64_atoms_per_s"]
+        if roof64 is not None:
+            out["fp64_roofline"] = roof64
+        errs = []
+        for eta in timed_etas:
+            s64 = fp64_out[eta]["sig"].cpu().numpy()
+            e = float(np.abs(np.array(per_eta[eta]["sigma"]) - s64).max() / np.abs(s64).max())
+            per_eta[eta]["sigma_fp64"] = s64.tolist()
+            per_eta[eta]["sigma_rel_err_split_vs_fp64"] = e
+            per_eta[eta]["fp64_info_nonzero"] = int((fp64_out[eta]["info"].cpu().numpy() != 0).sum())
+            errs.append(e)
+        out["sigma_rel_err_split_vs_fp64"] = max(errs)
+        log("fp64 step %.1f ms; max sigma rel err split vs fp64 %.2e" % (fp64_ms, max(errs)))
     if not args.no_conj_leg:
         # Algorithmic saving, reported apart from the like-for-like value above: solve z+ only
         # and write tau(z-) = P conj tau(z+) P (exact for real phase shifts).
         ctx.set_conj_symmetry(True)
-        sig_c = {}
-        step(0, args.precision, sig_c)
+        step(0, args.precision, side_out)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for i in range(args.steps):
-            step(i, args.precision, sig_c)
-        torch.cuda.synchronize()
-        tc = time.perf_counter() - t1
+        tc = timed(args.precision, side_out, args.steps, False, False)
+        errs = [float(np.abs(side_out[e]["sig"].cpu().numpy() - main_out[e]["sig"].cpu().numpy()).max()
+                      / np.abs(main_out[e]["sig"].cpu().numpy()).max()) for e in timed_etas]
         combined = None
         if not args.no_ldlt_leg and args.precision == "split":
             # both savings together: z+ only, factored through the symmetric form
             ctx.set_symmetric(True)
-            step(0, args.precision, {})
+            step(0, args.precision, side_out)
             torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            for i in range(args.steps):
-                step(i, args.precision, {})
-            torch.cuda.synchronize()
-            combined = n_atoms * args.steps / (time.perf_counter() - t2)
+            combined = n_atoms * args.steps / timed(args.precision, side_out, args.steps, False, False)
             ctx.set_symmetric(False)
         ctx.set_conj_symmetry(False)
-        errs = [float(np.abs(sig_c[e].cpu().numpy() - sig_main[e].cpu().numpy()).max()
-                      / np.abs(sig_main[e].cpu().numpy()).max()) for e in sig_c if e in sig_main]
         out["conj_symmetry"] = {"value": n_atoms * args.steps / tc, "unit": "atoms/s",
                                 "ms_per_step": 1e3 * tc / args.steps,
                                 "speedup_vs_full_solve": (n_atoms * args.steps / tc) / value,
-                                "sigma_rel_err_vs_full_solve": max(errs) if errs else None,
+                                "sigma_rel_err_vs_full_solve": max(errs),
                                 "what": "z+ systems only; tau(z-)_{LL'} = (-1)^(l+l') conj tau(z+)_{LL'}",
                                 "with_symmetric_ldlt": combined}
         log("conj-symmetry leg: %.1f ms/step, %.1f atoms/s" % (1e3 * tc / args.steps, n_atoms * args.steps / tc))
@@ -396,23 +462,18 @@ def main():
         # Algorithmic saving, reported apart: the complex-symmetric form 1 - T^1/2 g T^1/2 factored
         # by L D L^T without pivoting (half the trailing-update work), FP64 refinement as before.
         ctx.set_symmetric(True)
-        sig_l = {}
-        step(0, args.precision, sig_l)
+        step(0, args.precision, side_out)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for i in range(args.steps):
-            step(i, args.precision, sig_l)
-        torch.cuda.synchronize()
-        tl = time.perf_counter() - t1
+        tl = timed(args.precision, side_out, args.steps, False, False)
         ctx.set_symmetric(False)
-        errs = [float(np.abs(sig_l[e].cpu().numpy() - sig_main[e].cpu().numpy()).max()
-                      / np.abs(sig_main[e].cpu().numpy()).max()) for e in sig_l if e in sig_main]
-        info_l = info.cpu().numpy()
+        errs = [float(np.abs(side_out[e]["sig"].cpu().numpy() - main_out[e]["sig"].cpu().numpy()).max()
+                      / np.abs(main_out[e]["sig"].cpu().numpy()).max()) for e in timed_etas]
         out["symmetric_ldlt"] = {"value": n_atoms * args.steps / tl, "unit": "atoms/s",
                                  "ms_per_step": 1e3 * tl / args.steps,
                                  "speedup_vs_lu": (n_atoms * args.steps / tl) / value,
-                                 "sigma_rel_err_vs_lu": max(errs) if errs else None,
-                                 "info_nonzero": int((info_l != 0).sum()),
+                                 "sigma_rel_err_vs_lu": max(errs),
+                                 "info_nonzero": sum(int((side_out[e]["info"].cpu().numpy() != 0).sum())
+                                                     for e in timed_etas),
                                  "what": "S = 1 - T^1/2 g T^1/2, unpivoted L D L^T in FP32 (lower-triangle updates), "
                                          "FP64 refinement and fallback; not the paper's LU"}
         log("symmetric L D L^T leg: %.1f ms/step, %.1f atoms/s" % (1e3 * tl / args.steps, n_atoms * args.steps / tl))
@@ -421,9 +482,19 @@ def main():
                                                  ldlt=not args.no_ldlt_leg)
     if not args.no_adjoint_leg:
         out["adjoint"] = adjoint_leg(P, torch, ctx)
+    main_pa = {e: main_out[e]["pa"].cpu().numpy() for e in timed_etas}
+    fp64_pa = {e: fp64_out[e]["pa"].cpu().numpy() for e in timed_etas} if fp64_out is not None else None
     ctx.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, etas[0], args.cpu_sample)
+        cb, _, groups, oracle_pa = cpu_baseline(w, timed_etas, args.cpu_sample)
+        out["cpu_baseline"] = cb
+        for eta, e in oracle_errors(groups, oracle_pa, main_pa).items():
+            per_eta[eta]["kubo_per_atom_rel_err_vs_oracle"] = e
+            per_eta[eta]["oracle_atoms"] = groups[eta]
+        if fp64_pa is not None:
+            for eta, e in oracle_errors(groups, oracle_pa, fp64_pa).items():
+                per_eta[eta]["kubo_per_atom_rel_err_vs_oracle_fp64"] = e
+    out["per_eta"] = [per_eta[e] for e in timed_etas]
     print(json.dumps(out), flush=True)
 
 

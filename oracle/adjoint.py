@@ -18,9 +18,13 @@ import numpy as np
 from . import kkr, kubo, liz
 
 
-def dsigma_dphase(pos, cell, r_liz, species, phase, J, e_fermi, eta, dsigma, volume=None, liz_lists=None):
+def dsigma_dphase(pos, cell, r_liz, species, phase, J, e_fermi, eta, dsigma, volume=None, liz_lists=None,
+                  pairs=None):
     """Gradient of L = sum_mu dsigma[mu] * sigma_mu with respect to phase[N, 4].
 
+    ``pairs`` (None: all) restricts the result to the listed (site, l) entries: only the
+    atoms whose LIZ holds an image of a listed site contribute to them, so only those LIZ are
+    inverted; every other entry of the result is left zero.
     Returns complex [N, 4]; the imaginary part vanishes analytically.
     """
     pos = np.asarray(pos, dtype=np.float64)
@@ -44,9 +48,16 @@ def dsigma_dphase(pos, cell, r_liz, species, phase, J, e_fermi, eta, dsigma, vol
         w[c] = dsigma * 0.25 * kubo.SIGNS[c] * (-1.0 / (np.pi * volume))
     lshell = np.array([0, 1, 1, 1, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3])
     grad = np.zeros((N, 4), dtype=np.complex128)
+    wanted = None
+    if pairs is not None:
+        wanted = {}
+        for k, l in pairs:
+            wanted.setdefault(int(k), set()).add(int(l))
     for i in range(N):
         mem = latom[ptr[i]:ptr[i + 1]]
         nm = len(mem)
+        if nm == 0 or (wanted is not None and not any(int(k) in wanted for k in mem)):
+            continue
         P = lpos[ptr[i]:ptr[i + 1]]
         Wd, col, row = {}, {}, {}
         for tag, t, k in (("+", tp[mem], kp), ("-", tm[mem], km)):
@@ -63,6 +74,8 @@ def dsigma_dphase(pos, cell, r_liz, species, phase, J, e_fermi, eta, dsigma, vol
             W4 = Wd[e]
             for b in range(nm):
                 for l in range(4):
+                    if wanted is not None and l not in wanted.get(int(mem[b]), ()):
+                        continue
                     chans = np.nonzero(lshell == l)[0]
                     # d tau^{a0} and d tau^{0a} for unit dt at (b, l), energy e
                     Wab = W4[:, :, b, chans]          # [a, L1, p]

@@ -99,7 +99,7 @@ def sigma(pos, cell, r_liz, species, phase, J, e_fermi, eta, volume=None, atoms=
     if volume is None:
         volume = supercell_volume(cell)
     if liz_lists is None:
-        liz_lists = liz.build_liz(pos, cell, r_liz)
+        liz_lists = liz.build_liz(pos, cell, r_liz, centres=atoms)
     ptr, latom, lpos = liz_lists
     zp, zm, kp, km = kkr.energies(e_fermi, eta)
     tp, tm = kkr.t_matrix(phase, kp)

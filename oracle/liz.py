@@ -35,11 +35,14 @@ def image_range(cell, r_liz):
     return K
 
 
-def build_liz(pos, cell, r_liz):
-    """LIZ lists for every atom.
+def build_liz(pos, cell, r_liz, centres=None):
+    """LIZ lists for every atom (or only for the listed centres).
 
-    pos  : [N, 3] atom positions (bohr)
-    cell : [3, 3] lattice vectors as rows, or None for an open cluster
+    pos     : [N, 3] atom positions (bohr)
+    cell    : [3, 3] lattice vectors as rows, or None for an open cluster
+    centres : None (every atom) or an iterable of atom indices; every other atom
+              gets an empty LIZ (liz_ptr[m + 1] == liz_ptr[m]), the members of a
+              listed centre's LIZ are the same as in the full build
     Returns (liz_ptr [N+1] int64, liz_atom [S] int32, liz_pos [S, 3] float64)
     where liz_pos holds displacements (R_j + T) - R_m.
     """
@@ -56,10 +59,14 @@ def build_liz(pos, cell, r_liz):
         shifts = g[:, 0:1] * c[0] + g[:, 1:2] * c[1]
         shifts = shifts + g[:, 2:3] * c[2]
     ptr = [0]
-    atoms = []
-    disps = []
+    atoms = [np.zeros(0, dtype=np.int32)]
+    disps = [np.zeros((0, 3))]
     r2max = r_liz * r_liz
+    wanted = None if centres is None else set(int(c) for c in centres)
     for m in range(N):
+        if wanted is not None and m not in wanted:
+            ptr.append(ptr[-1])
+            continue
         img = pos[None, :, :] + shifts[:, None, :]  # [nshift, N, 3]
         d = img - pos[m]
         d2 = d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]

@@ -207,3 +207,17 @@ def workload(name):
     w["phase"] = w["phase_species"][w["species"]]
     w["volume"] = abs(float(np.linalg.det(w["cell"])))
     return w
+
+
+def fingerprint(w, keys=("pos", "cell", "species", "phase", "J", "r_liz", "e_fermi", "etas")):
+    """sha256 over a workload's input arrays, so a stored expected value can tell whether it
+    still belongs to the inputs these generators produce."""
+    import hashlib
+    h = hashlib.sha256()
+    for k in keys:
+        v = np.ascontiguousarray(np.asarray(w[k]))
+        h.update(k.encode())
+        h.update(str(v.dtype).encode())
+        h.update(str(v.shape).encode())
+        h.update(v.tobytes())
+    return h.hexdigest()

@@ -61,11 +61,35 @@ def test_liz_fcc4000_sizes():
     assert (np.diff(L.ptr) == 135).all()
 
 
-def test_liz_open_cluster():
+def _same_lists(L, o, centres):
+    for i in centres:
+        a, b, c, d = int(L.ptr[i]), int(L.ptr[i + 1]), int(o[0][i]), int(o[0][i + 1])
+        assert b - a == d - c
+        assert np.array_equal(L.atom[a:b], o[1][c:d]) and np.array_equal(L.pos[a:b], o[2][c:d]), i
+
+
+@pytest.mark.parametrize("name,full", [("fcc4000", True), ("fcc4000", False), ("bcc16000", False)])
+def test_liz_matches_oracle_on_sampled_centres(name, full):
+    """The large workloads' LIZ (full build and the centre-subset build) against the oracle's
+    own construction for seeded centres, bitwise."""
     import paper_2311_12134_amd as P
-    pos = np.array([[0, 0, 0], [3.0, 0, 0], [0, 4.0, 0], [10.0, 0, 0]])
-    L = P.build_liz(pos, None, 5.5)
-    o = oliz.build_liz(pos, None, 5.5)
+    w = synthetic.workload(name)
+    n = len(w["pos"])
+    centres = sorted(set([0, n - 1, n // 2 + 7] + list(np.random.default_rng(5).choice(n, 12, replace=False))))
+    L = P.build_liz(w["pos"], w["cell"], w["r_liz"], centres=None if full else centres)
+    o = oliz.build_liz(w["pos"], w["cell"], w["r_liz"], centres=centres)
+    _same_lists(L, o, centres)
+    assert all(int(o[0][i + 1] - o[0][i]) == 0 for i in range(n) if i not in set(centres))
+
+
+@pytest.mark.parametrize("pos,r", [
+    (np.array([[0, 0, 0], [3.0, 0, 0], [0, 4.0, 0], [10.0, 0, 0]]), 5.5),
+    (np.array([[0.0, 0.0, 0.0], [4.2, 0.3, 0.1], [0.4, 4.1, -0.3], [40.0, 0.0, 0.0], [47.0, 1.0, 0.0]]), 7.5),
+    (np.array([[0.0, 0.0, 0.0], [4.2, 0.3, 0.1], [0.4, 4.1, -0.3], [40.0, 0.0, 0.0], [47.0, 1.0, 0.0]]), 5.0)])
+def test_liz_open_cluster(pos, r):
+    import paper_2311_12134_amd as P
+    L = P.build_liz(pos, None, r)
+    o = oliz.build_liz(pos, None, r)
     assert np.array_equal(L.ptr, o[0]) and np.array_equal(L.atom, o[1]) and np.array_equal(L.pos, o[2])
 
 

@@ -33,3 +33,21 @@ def test_gradient_matches_central_differences():
     assert np.allclose(g.real, fd, rtol=0, atol=1e-7 * np.abs(fd).max())
     # the site outside everyone else's LIZ still contributes through its own LIZ
     assert np.abs(fd[5]).max() > 0
+
+
+def test_restricted_gradient_equals_full_gradient_entries():
+    """The (site, l) restriction used for the large gradient workload skips only LIZ that hold
+    no listed site: the listed entries equal those of the unrestricted gradient."""
+    w = synthetic.workload("bcc16")
+    eta = w["etas"][0]
+    dsig = np.array([1.0, 0.0, 0.0])
+    args = (w["pos"], w["cell"], w["r_liz"], w["species"], w["phase"], w["J"], w["e_fermi"], eta, dsig)
+    full = adjoint.dsigma_dphase(*args)
+    pairs = [(3, 0), (3, 2), (9, 1), (14, 3)]
+    part = adjoint.dsigma_dphase(*args, pairs=pairs)
+    for k, l in pairs:
+        assert part[k, l] == full[k, l]
+    mask = np.ones((16, 4), dtype=bool)
+    for k, l in pairs:
+        mask[k, l] = False
+    assert not part[mask].any()
