@@ -184,6 +184,30 @@ int lsms_kubo_sigma(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, cons
                     void* hip_stream);
 
 /*
+ * Allocation-free variant of lsms_kubo_sigma, for callers that cannot allocate device or
+ * pinned memory while they run (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same sums, the same kernels and the same fixed reduction
+ * order, so the outputs equal lsms_kubo_sigma's bitwise.  The call allocates nothing and
+ * never waits for the device: no hipMalloc / hipFree / hipHostMalloc, no host staging.
+ *   liz_ptr   DEVICE [n_atoms + 1] int64 CSR offsets (the host array of lsms_build_liz,
+ *             copied to the device by the caller; read by the kernels, not validated on
+ *             the host, so it must be consistent with liz_atom and the tau arrays)
+ *   n_atoms   1 .. LSMS_NOALLOC_MAX_ATOMS, else LSMS_E_ARG
+ *   other arguments as for lsms_kubo_sigma (per_atom may be NULL)
+ * With per_atom == NULL the per-atom partial sums go to a fixed scratch array of the
+ * library (LSMS_NOALLOC_MAX_ATOMS x 4 x 3 complex = 6 MiB per GPU, held from the first
+ * lsms_create on that GPU until the process ends).  Every call on one GPU shares that
+ * array and leaves its partial sums there; each call writes all n_atoms entries before it
+ * reads them, so nothing needs clearing, but calls that overlap on one GPU (two streams,
+ * two threads, two contexts) race on it and must be ordered by the caller.
+ */
+#define LSMS_NOALLOC_MAX_ATOMS 32768
+int lsms_kubo_sigma_noalloc(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr, const int32_t* liz_atom,
+                            const void* tau_plus, const void* tau_minus, const int32_t* species, int32_t n_species,
+                            const void* J, double volume, double* sigma, void* sigma_tilde, void* per_atom,
+                            void* hip_stream);
+
+/*
  * Full conductivity tensor: Eq. (10) for every pair of Cartesian directions, with mu
  * on the centre atom's current J^{m mu}(z2,z1) and nu on the member's J^{n nu}(z1,z2),
  * then Eq. (7) for each (mu, nu):

@@ -41,6 +41,8 @@ _PROTOS = {
                                c_double, c_int, c_void_p, c_void_p, c_void_p, c_void_p, P(c_void_p), c_void_p]),
     "lsms_kubo_sigma": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                 c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "lsms_kubo_sigma_noalloc": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_int32, c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lsms_kubo_sigma_tensor": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                        c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lsms_kubo_sigma_grad": (c_int, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

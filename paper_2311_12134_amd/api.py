@@ -166,6 +166,19 @@ class Context:
                                     float(volume), _ptr(sig), _ptr(st), _ptr(pa), _stream()))
         return sig, st, pa
 
+    def kubo_sigma_noalloc(self, liz_ptr_dev, liz_atom_dev, tau_plus, tau_minus, species, J, volume, sigma,
+                           sigma_tilde, per_atom=None):
+        """lsms_kubo_sigma_noalloc: the caller passes every array (liz_ptr on the device,
+        int64 [N+1]); the library allocates nothing and uses its fixed per-GPU scratch for the
+        per-atom sums when per_atom is None."""
+        n = liz_ptr_dev.numel() - 1
+        assert liz_ptr_dev.is_cuda and liz_ptr_dev.dtype == torch.int64
+        assert species.dtype == torch.int32 and J.dtype == torch.complex128 and J.is_contiguous()
+        check(lib().lsms_kubo_sigma_noalloc(self._h, n, _ptr(liz_ptr_dev), _ptr(liz_atom_dev), _ptr(tau_plus),
+                                            _ptr(tau_minus), _ptr(species), J.shape[0], _ptr(J), float(volume),
+                                            _ptr(sigma), _ptr(sigma_tilde), _ptr(per_atom), _stream()))
+        return sigma, sigma_tilde, per_atom
+
     def kubo_sigma_tensor(self, liz, liz_atom_dev, tau_plus, tau_minus, species, J, volume, per_atom=False,
                           out=None):
         """sigma [3,3] (float64, row mu, column nu), sigma_tilde [4,3,3] (complex128), per-atom sums [N,4,3,3]."""

@@ -21,6 +21,8 @@
 
 using namespace lsms;
 
+static_assert(LSMS_NOALLOC_MAX_ATOMS == lsms::NOALLOC_MAX_ATOMS, "fixed Kubo scratch size");
+
 
 // ---------------------------------------------------------------------------------
 // errors
@@ -288,6 +290,7 @@ extern "C" int lsms_create(int hip_device, int lmax, size_t workspace_limit, lsm
   int rc = build_gaunt(c->gaunt);
   if (rc) return rc;
   HIP_TRY(upload_gaunt(c->gaunt));
+  HIP_TRY(noalloc_scratch_init(hip_device));
   HIP_TRY(hipHostMalloc((void**)&c->pinned_flag, 256, hipHostMallocDefault));
   *out = c.release();
   return LSMS_OK;
@@ -1029,6 +1032,34 @@ extern "C" int lsms_kubo_sigma_tensor(lsms_ctx* ctx, int32_t n_atoms, const int6
                                       double* sigma, void* sigma_tilde, void* per_atom, void* hip_stream) {
   return kubo_sigma_common(ctx, n_atoms, liz_ptr, liz_atom, tau_plus, tau_minus, species, n_species, J, volume,
                            sigma, sigma_tilde, per_atom, true, hip_stream);
+}
+
+extern "C" int lsms_kubo_sigma_noalloc(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz_ptr,
+                                       const int32_t* liz_atom, const void* tau_plus, const void* tau_minus,
+                                       const int32_t* species, int32_t n_species, const void* J, double volume,
+                                       double* sigma, void* sigma_tilde, void* per_atom, void* hip_stream) {
+  if (!ctx) return fail(LSMS_E_ARG, "ctx is NULL");
+  if (n_atoms < 1 || n_atoms > LSMS_NOALLOC_MAX_ATOMS)
+    return fail(LSMS_E_ARG, "n_atoms %d outside [1, %d] (the fixed scratch holds %d atoms)", n_atoms,
+                LSMS_NOALLOC_MAX_ATOMS, LSMS_NOALLOC_MAX_ATOMS);
+  if (!liz_ptr || !liz_atom || !tau_plus || !tau_minus || !species || !J || !sigma || !sigma_tilde)
+    return fail(LSMS_E_ARG, "NULL device pointer");
+  if (n_species <= 0) return fail(LSMS_E_ARG, "n_species must be positive");
+  if (!(volume > 0.0) || !std::isfinite(volume)) return fail(LSMS_E_ARG, "volume must be positive");
+  HIP_TRY(hipSetDevice(ctx->device));
+  double2* pa = (double2*)per_atom;
+  if (!pa) {
+    pa = noalloc_scratch(ctx->device);
+    if (!pa) return fail(LSMS_E_STATE, "no scratch address for device %d", ctx->device);
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  // every atom's 12 partial sums are written before the reduction reads them, so the scratch
+  // needs no clearing between calls
+  launch_kubo_trace(n_atoms, liz_ptr, liz_atom, (const double2*)tau_plus, (const double2*)tau_minus, species,
+                    n_species, (const double2*)J, pa, false, s);
+  launch_kubo_reduce(n_atoms, pa, volume, sigma, (double2*)sigma_tilde, false, s);
+  HIP_TRY(hipGetLastError());
+  return LSMS_OK;
 }
 
 extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {

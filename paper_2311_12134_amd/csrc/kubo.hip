@@ -11,6 +11,8 @@
 // diagonal mu = nu (three sums) or the full tensor (nine pairings), and reduces over the
 // lanes at the end.  The sum over atoms then runs in a fixed order in a single
 // workgroup, so sigma is reproducible.
+#include <mutex>
+
 #include "lsms_internal.h"
 #include "strip_mma.h"
 
@@ -165,6 +167,43 @@ void launch_kubo_reduce(int n_atoms, const double2* per_atom, double volume, dou
     kubo_reduce_kernel<36><<<1, 256, 0, s>>>(n_atoms, per_atom, volume, sigma, sigma_tilde);
   else
     kubo_reduce_kernel<12><<<1, 256, 0, s>>>(n_atoms, per_atom, volume, sigma, sigma_tilde);
+}
+
+// ------------------------------------------------------------------------------------
+// Fixed scratch of the allocation-free Kubo sum: the per-atom partial sums [atom][4][3]
+// (complex) for up to NOALLOC_MAX_ATOMS atoms, one copy per GPU for the life of the
+// process.  Host code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): noalloc_scratch_init looks up its device address once per
+// device, with that device current, and everything else uses that address.
+// ------------------------------------------------------------------------------------
+static __device__ __align__(256) double2 scratch[(size_t)NOALLOC_MAX_ATOMS * 12];
+static constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int prev = 0;
+  hipError_t e = hipGetDevice(&prev);
+  if (e != hipSuccess) return e;
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return e;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  const hipError_t e2 = hipSetDevice(prev);
+  if (e != hipSuccess) return e;
+  if (e2 != hipSuccess) return e2;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+double2* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (double2*)g_scratch_ptr[device];
 }
 
 }  // namespace lsms

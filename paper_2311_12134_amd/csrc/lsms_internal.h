@@ -203,6 +203,10 @@ void launch_check_inputs(const JobDesc* jobs, int njobs, const double* liz_pos, 
 void launch_kubo_trace(int n_atoms, const int64_t* liz_ptr_dev, const int32_t* liz_atom, const double2* tau_plus,
                        const double2* tau_minus, const int32_t* species, int n_species, const double2* J,
                        double2* per_atom, bool tensor, hipStream_t s);
+// allocation-free Kubo sum: fixed per-device scratch of per-atom partial sums (kubo.hip)
+constexpr int NOALLOC_MAX_ATOMS = 32768;
+hipError_t noalloc_scratch_init(int device);  // once per device, at context creation
+double2* noalloc_scratch(int device);         // its device address (nullptr before init)
 void launch_kubo_reduce(int n_atoms, const double2* per_atom, double volume, double* sigma, double2* sigma_tilde,
                         bool tensor, hipStream_t s);
 
