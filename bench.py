@@ -211,6 +211,39 @@ def paper_scale_leg(P, torch, ctx, n_sample, precision, ldlt=False):
     return res
 
 
+F32_TILINGS = {0: "gemm_f32_3m_kernel", 1: "gemm_f32_3m_tiled<64,64,32,32>", 2: "gemm_f32_3m_tiled<64,64,32,32,xcd>",
+               3: "gemm_f32_3m_tiled<128,64,32,64,xcd>", 4: "gemm_f32_3m_tiled<64,128,64,32,xcd>",
+               5: "gemm_f32_3m_tiled<128,128,64,64,xcd>", 6: "gemm_f32_3m_tiled<128,128,64,64>",
+               7: "gemm_f32_3m_tiled<64,64,32,32,xcd,C prefetch>", 8: "gemm_f32_3m_tiled<64,64,32,32,xcd,K32>",
+               9: "gemm_f32_3m_tiled<64,64,32,32,xcd,32x32x2>"}
+F64_TILINGS = {0: "gemm_f64_kernel", 1: "gemm_f64_tiled<64,64,32,32,xcd,K8>", 2: "gemm_f64_tiled<32,64,16,32,xcd,K8>",
+               3: "gemm_f64_tiled<128,64,64,32,xcd,K8>", 4: "gemm_f64_tiled<64,128,32,64,xcd,K8>",
+               5: "gemm_f64_tiled<64,64,32,32,K8>"}
+
+
+def tune_all(ctx, npads, batch=256):
+    """The autotuner over every kernel choice of the LU for each padded-size bucket the workload
+    has (the largest npad of the bucket), and the split-mode panel threshold; the context keeps
+    the fastest per bucket.  Returns the per-bucket record for the JSON line."""
+    buckets = {}
+    for n in npads:
+        b = (n - 1) // 256
+        buckets[b] = max(buckets.get(b, 0), n)
+    rec = []
+    for b, n in sorted(buckets.items()):
+        entry = {"bucket": b, "npad_range": [256 * b + 1, 256 * (b + 1)], "tuned_at_npad": n}
+        for what in ("f32_wide", "f32_narrow", "f64_wide", "f64_narrow"):
+            best, ms = ctx.autotune_kernel(what, n, batch=batch)
+            entry[what] = {"best": best, "ms": [round(m, 3) for m in ms]}
+        rec.append(entry)
+        log("autotuned bucket %d (npad %d): %s" % (b, n, {k: entry[k]["best"] for k in
+                                                         ("f32_wide", "f32_narrow", "f64_wide", "f64_narrow")}))
+    thr, ms = ctx.autotune_kernel("f32_panel", batch=batch)
+    log("autotuned split-mode panel threshold: %d rows %s" % (thr, [round(m, 3) for m in ms]))
+    return {"batch": batch, "buckets": rec,
+            "panel_small_rows": {"best": thr, "ms_256_512_768_small_large": [round(m, 3) for m in ms]}}
+
+
 def gemm_roofline(ctx, precision, workload, tiling, timed_in):
     """The wide trailing update's roofline entry from the launches recorded while profiling."""
     gemm_ms, launches, flops, alg_bytes = ctx.kernel_stats(kind=1)
@@ -219,13 +252,10 @@ def gemm_roofline(ctx, precision, workload, tiling, timed_in):
     avg_s = gemm_ms / launches / 1e3
     achieved = flops / launches / avg_s
     peak = PEAK_FP32_MFMA if precision == "split" else PEAK_FP64_MFMA
-    if precision == "split":
-        kname = "gemm_f32_3m_tiled" if tiling > 0 else "gemm_f32_3m_kernel"
-    else:
-        kname = "gemm_f64_kernel"
+    kname = (F32_TILINGS if precision == "split" else F64_TILINGS).get(tiling, "tiling %d" % tiling)
     with open(GEMM_SOURCE, "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
-    rec = TRAFFIC.get((precision, workload, tiling if precision == "split" else -1))
+    rec = TRAFFIC.get((precision, workload, tiling))
     same_shape = rec is not None and abs(alg_bytes / launches / rec["alg_bytes_per_launch"] - 1) < 1e-3
     traffic = rec["bytes_per_launch"] if rec is not None and rec["sha256"] == digest and same_shape else None
     return {"kernel": kname, "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
@@ -245,8 +275,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gemm-tiling", type=int, default=-1,
-                    help="tiling of the split-mode trailing update (-1: autotune, unless --no-autotune)")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tiling")
+                    help="explicit tiling of the split-mode wide trailing update (-1: the autotuned one)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default kernel choices")
     ap.add_argument("--graphs", action=argparse.BooleanOptionalAction, default=True,
                     help="time the steps with each wave's factorization + first solve replayed from HIP graphs "
                          "(default); the trailing update's launch times then come from a second, eager timed "
@@ -318,11 +348,17 @@ def main():
     ctx.set_pipeline(args.pipeline)
     ctx.set_gemm_tiling(args.gemm_tiling)
     tune = None
-    if args.gemm_tiling < 0 and not args.no_autotune and args.precision == "split":
-        npad_max = int(-(-16 * int(np.diff(liz.ptr).max()) // 64) * 64)
-        best, ms = ctx.autotune(npad_max, batch=256)
-        tune = {"npad": npad_max, "batch": 256, "best": best, "ms_per_tiling": [round(m, 3) for m in ms]}
-        log("autotuned tiling %d for npad %d: %s ms" % (best, npad_max, tune["ms_per_tiling"]))
+    npads = sorted({int(-(-16 * int(m) // 64) * 64) for m in np.diff(liz.ptr) if m > 0})
+    if not args.no_autotune:
+        tune = tune_all(ctx, npads)
+
+    def tiling_in_effect(precision):
+        """The wide-update tiling the library picks for the workload's largest systems."""
+        if precision == "split" and args.gemm_tiling >= 0:
+            return args.gemm_tiling
+        b = (npads[-1] - 1) // 256
+        t = int(ctx.tuning_table("f32_wide" if precision == "split" else "f64_wide")[b])
+        return t if t >= 0 else (2 if precision == "split" else 1)
 
     def step(i, precision, out):
         eta = etas[i % len(etas)]
@@ -364,7 +400,7 @@ def main():
         eager = {"value": n_atoms * args.steps / el_e, "unit": "atoms/s", "ms_per_step": 1e3 * el_e / args.steps,
                  "what": "the same steps with every launch issued eagerly (trailing-update launches timed)"}
         log("eager region: %.1f ms/step" % (1e3 * el_e / args.steps))
-    tiling = ctx.gemm_tiling()
+    tiling = tiling_in_effect(args.precision)
     roof = gemm_roofline(ctx, args.precision, args.workload, tiling,
                          "the eager timed region" if args.graphs else "the timed region")
     narrow_ms, narrow_launches, narrow_flops, _ = ctx.kernel_stats(kind=0)
@@ -415,7 +451,7 @@ def main():
         step(0, "fp64", fp64_out)
         torch.cuda.synchronize()
         t64 = timed("fp64", fp64_out, len(etas), False, True)
-        roof64 = gemm_roofline(ctx, "fp64", args.workload, -1, "the FP64 steps")
+        roof64 = gemm_roofline(ctx, "fp64", args.workload, tiling_in_effect("fp64"), "the FP64 steps")
         ctx.set_profiling(False)
         fp64_ms = 1e3 * t64 / len(etas)
         out["fp64_ms_per_step"] = fp64_ms

@@ -355,8 +355,67 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * the waves costs about what the overlap gains.
  */
 #define LSMS_TUNE_PIPELINE 6
+/*
+ * knobs LSMS_TUNE_GEMM_F32_NARROW (split mode, 0 .. LSMS_GEMM_F32_VARIANTS - 1),
+ * LSMS_TUNE_GEMM_F64 and LSMS_TUNE_GEMM_F64_NARROW (FP64 mode, 0 .. LSMS_GEMM_F64_VARIANTS - 1:
+ * 0 the single-buffered 64 x 64 kernel; 1 64 x 64 with two LDS stages of K = 8 and the XCD
+ * order; 2 32 x 64; 3 128 x 64; 4 64 x 128; 5 as 1 without the XCD order): the
+ * tilings of the narrow (K = 64, a pair's second panel) and wide (K = 128) trailing updates.
+ * knob LSMS_TUNE_PANEL_SMALL_ROWS (0 .. 768): split-mode panels of at most this many rows run
+ * in 256-thread workgroups with 8-wide leaves, taller ones in 512-thread workgroups.
+ * For every such choice (and LSMS_TUNE_GEMM_F32), -1 (the initial value) means: the
+ * autotuned choice for the wave's padded size (lsms_autotune_kernel), else the library
+ * default.  lsms_get_tuning reports the explicit setting (-1 if none), except for
+ * LSMS_TUNE_GEMM_F32, where it reports the explicit setting or the default.
+ */
+#define LSMS_TUNE_GEMM_F32_NARROW 7
+#define LSMS_TUNE_GEMM_F64 8
+#define LSMS_TUNE_GEMM_F64_NARROW 9
+#define LSMS_TUNE_PANEL_SMALL_ROWS 10
+#define LSMS_GEMM_F64_VARIANTS 6
 int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
 int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
+
+/*
+ * Autotuner over the kernels of the blocked LU (the inverse of Eq. (3), the dominant cost of
+ * the method, Sec. II.A).  `what` selects the target:
+ *   LSMS_AUTOTUNE_F32_WIDE / LSMS_AUTOTUNE_F64_WIDE: every tiling of the split-mode / FP64
+ *     wide trailing update (K = 128 over the trailing (npad - 128)^2 block of an LU of size npad);
+ *   LSMS_AUTOTUNE_F32_NARROW / LSMS_AUTOTUNE_F64_NARROW: every tiling of the narrow update
+ *     (K = 64 over (npad - 64) rows x 64 columns);
+ *   LSMS_AUTOTUNE_F32_PANEL: the two split-mode panel variants at heights 256, 512 and 768
+ *     (npad ignored); ms[2 h + v] receives variant v (0: 256 threads, 8-wide leaves; 1: 512
+ *     threads) at height h, and the context's panel threshold becomes the largest height at
+ *     which variant 0 was faster (0: none), which *best receives.
+ * For the updates the fastest tiling becomes the context's choice for every wave whose
+ * largest padded size falls in npad's bucket (npad in (256 b, 256 (b + 1)]), *best receives
+ * it and ms (NULL, or host [ms_len >= number of tilings]) the best-of-three launch time of
+ * each tiling.  Each call allocates and frees a synthetic batch of `batch` systems (bounded
+ * pseudo-random values) and is synchronous on hip_stream.  npad: a multiple of 64 in
+ * (128, 16384]; batch in [1, 65535].  LSMS_E_ARG for bad sizes or target, LSMS_E_NOMEM if the
+ * batch cannot be allocated.  Explicit lsms_set_tuning choices take precedence over these.
+ */
+#define LSMS_AUTOTUNE_F32_WIDE 0
+#define LSMS_AUTOTUNE_F32_NARROW 1
+#define LSMS_AUTOTUNE_F64_WIDE 2
+#define LSMS_AUTOTUNE_F64_NARROW 3
+#define LSMS_AUTOTUNE_F32_PANEL 4
+#define LSMS_TUNE_BUCKETS 64
+int lsms_autotune_kernel(lsms_ctx* ctx, int what, int npad, int batch, int* best, float* ms, int ms_len,
+                         void* hip_stream);
+/* The autotuned choices of a target: out host [LSMS_TUNE_BUCKETS], the tiling of each npad
+ * bucket (-1: none); for LSMS_AUTOTUNE_F32_PANEL out[0] = the panel threshold (-1: none). */
+int lsms_tuning_table(lsms_ctx* ctx, int what, int* out);
+/*
+ * Tuning cache: lsms_tuning_save writes every autotuned choice of the context to a text file
+ * (first line "lsms-tune 1 <architecture>/<compute units>"), lsms_tuning_load replaces the
+ * context's autotuned choices by a file's (LSMS_E_STATE if it was written on another kind of
+ * device, LSMS_E_ARG if it cannot be read or parsed; the context is unchanged on error).
+ * lsms_create loads the file named by the environment variable LSMS_TUNE_CACHE when it
+ * exists and was written on this kind of device.  Host-side, no device work.
+ */
+int lsms_tuning_save(lsms_ctx* ctx, const char* path);
+int lsms_tuning_load(lsms_ctx* ctx, const char* path);
 
 /*
  * Autotuner for the split-mode trailing update: times every tiling on the widest update
@@ -371,6 +430,17 @@ int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
 int lsms_autotune(lsms_ctx* ctx, int npad, int batch, int* best, float* ms, void* hip_stream);
 int lsms_kernel_stats(lsms_ctx* ctx, int kind, double* total_ms, int64_t* launches, double* alg_flops,
                       double* alg_bytes);
+
+/*
+ * Peak-rate probes of the context's device, the ceilings against which the measured kernel
+ * rates can be read: `what` 0 FP64 matrix cores (v_mfma_f64_16x16x4), 1 FP32 matrix cores
+ * (16x16x4), 2 FP32 matrix cores (32x32x2), all in TFLOP/s of independent instruction
+ * streams filling every compute unit; 3 FP64 vector FMA (TFLOP/s); 4 a 1 GiB device-to-device
+ * copy (GB/s, bytes read plus written).  *value receives the best of three timed launches.
+ * Allocates and frees its buffers (2 GiB for the copy); synchronous on hip_stream.
+ * LSMS_E_ARG for an unknown probe, LSMS_E_DEVICE on a HIP error.
+ */
+int lsms_peak_probe(lsms_ctx* ctx, int what, double* value, void* hip_stream);
 
 /*
  * Host-only query of the library's Gaunt table (Sec. II.A: g is built from these

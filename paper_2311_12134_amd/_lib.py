@@ -50,6 +50,11 @@ _PROTOS = {
     "lsms_factors_free": (c_int, [c_void_p]),
     "lsms_batched_lu_solve": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_int, c_void_p,
                                       c_void_p]),
+    "lsms_autotune_kernel": (c_int, [c_void_p, c_int, c_int, c_int, P(c_int), c_void_p, c_int, c_void_p]),
+    "lsms_tuning_table": (c_int, [c_void_p, c_int, c_void_p]),
+    "lsms_tuning_save": (c_int, [c_void_p, ctypes.c_char_p]),
+    "lsms_tuning_load": (c_int, [c_void_p, ctypes.c_char_p]),
+    "lsms_peak_probe": (c_int, [c_void_p, c_int, P(c_double), c_void_p]),
     "lsms_gaunt_table": (c_int, [c_void_p]),
     "lsms_set_profiling": (c_int, [c_void_p, c_int]),
     "lsms_set_tuning": (c_int, [c_void_p, c_int, c_int]),

@@ -266,6 +266,51 @@ class Context:
         check(lib().lsms_autotune(self._h, int(npad), int(batch), ctypes.byref(best), ms, _stream()))
         return best.value, [float(x) for x in ms]
 
+    AUTOTUNE_TARGETS = {"f32_wide": 0, "f32_narrow": 1, "f64_wide": 2, "f64_narrow": 3, "f32_panel": 4}
+    KNOBS = {"f32_wide": 0, "f32_narrow": 7, "f64_wide": 8, "f64_narrow": 9, "panel_small_rows": 10}
+
+    def autotune_kernel(self, what, npad=0, batch=256):
+        """lsms_autotune_kernel: time every variant of one LU kernel (see AUTOTUNE_TARGETS) and
+        record the fastest for npad's bucket (the panel target: the small-panel threshold).
+        Returns (best, [ms per variant])."""
+        best = ctypes.c_int(-1)
+        ms = (ctypes.c_float * 16)()
+        check(lib().lsms_autotune_kernel(self._h, self.AUTOTUNE_TARGETS[what], int(npad), int(batch),
+                                         ctypes.byref(best), ms, 16, _stream()))
+        n = {"f32_wide": 10, "f32_narrow": 10, "f64_wide": 6, "f64_narrow": 6, "f32_panel": 6}[what]
+        return best.value, [float(x) for x in ms[:n]]
+
+    PROBES = {"mfma_f64": 0, "mfma_f32": 1, "mfma_f32_32x32x2": 2, "fma_f64": 3, "copy": 4}
+
+    def peak_probe(self, what):
+        """lsms_peak_probe: the device's sustained rate for one instruction stream (TFLOP/s) or
+        a 1 GiB copy (GB/s)."""
+        v = ctypes.c_double(0)
+        check(lib().lsms_peak_probe(self._h, self.PROBES[what], ctypes.byref(v), _stream()))
+        return v.value
+
+    def tuning_table(self, what):
+        """The autotuned choice per npad bucket (bucket b: npad in (256 b, 256 (b + 1)]), -1 if
+        none; for "f32_panel" the panel threshold."""
+        out = np.full(64, -1, dtype=np.int32)
+        check(lib().lsms_tuning_table(self._h, self.AUTOTUNE_TARGETS[what], out.ctypes.data_as(ctypes.c_void_p)))
+        return int(out[0]) if what == "f32_panel" else out
+
+    def tuning_save(self, path):
+        check(lib().lsms_tuning_save(self._h, str(path).encode()))
+
+    def tuning_load(self, path):
+        check(lib().lsms_tuning_load(self._h, str(path).encode()))
+
+    def set_knob(self, name, value):
+        """Explicit kernel choice (see KNOBS); -1 returns to the autotuned choice or the default."""
+        check(lib().lsms_set_tuning(self._h, self.KNOBS[name], int(value)))
+
+    def knob(self, name):
+        v = ctypes.c_int(0)
+        check(lib().lsms_get_tuning(self._h, self.KNOBS[name], ctypes.byref(v)))
+        return v.value
+
     def gemm_tiling(self):
         v = ctypes.c_int(0)
         check(lib().lsms_get_tuning(self._h, 0, ctypes.byref(v)))

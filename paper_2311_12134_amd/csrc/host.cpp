@@ -8,6 +8,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -91,10 +92,23 @@ struct EventProf : GemmProfiler {
   }
 };
 
+// Autotuned kernel choices are kept per bucket of padded system size: bucket b holds
+// npad in (256 b, 256 (b + 1)].
+static inline int tune_bucket(int npad) { return std::min(std::max((npad - 1) / 256, 0), LSMS_TUNE_BUCKETS - 1); }
+
 struct lsms_ctx {
   int device = 0;
   bool profiling = false;
-  int gemm_f32 = -1;  // tiling of the split-mode trailing update, -1: library default
+  // explicit kernel choices (lsms_set_tuning); -1: the autotuned table, else the default
+  int gemm_f32 = -1;  // tiling of the split-mode wide trailing update
+  int gemm_f32_narrow = -1;
+  int gemm_f64 = -1;
+  int gemm_f64_narrow = -1;
+  int panel_small_rows = -1;
+  // autotuned choices: tuned[precision][kind][bucket] (kind 0 narrow, 1 wide), -1 unset;
+  // tuned_panel_rows: split-mode panels up to this height take the small variant
+  int8_t tuned[2][2][LSMS_TUNE_BUCKETS];
+  int tuned_panel_rows = -1;
   bool graphs = false;  // replay each wave's factorization + first solve from a HIP graph
   bool conj_symmetry = false;  // solve z+ only and derive z- (tau(z-) = P conj tau(z+) P)
   int tslu_chunk = 2048;       // rows per chunk of the tall-panel tournament
@@ -121,8 +135,34 @@ struct lsms_ctx {
   hipEvent_t pipe_start = nullptr, pipe_end = nullptr;
 };
 
-// Tiling of the split-mode trailing update in effect for a context.
-static int gemm_f32_variant(const lsms_ctx* ctx) { return ctx->gemm_f32 >= 0 ? ctx->gemm_f32 : 2; }
+// Library defaults where neither an explicit choice nor an autotuned one exists.
+static constexpr int kDefaultF32Wide = 2, kDefaultF32Narrow = 2, kDefaultF64Wide = 1, kDefaultF64Narrow = 1;
+
+// Tiling of the split-mode trailing update in effect for a context (explicit or default).
+static int gemm_f32_variant(const lsms_ctx* ctx) { return ctx->gemm_f32 >= 0 ? ctx->gemm_f32 : kDefaultF32Wide; }
+
+// Kernel choices for a wave whose largest system has padded size npad: an explicit setting,
+// else the autotuned choice of npad's bucket, else the default.
+static Tiling pick_tiling(const lsms_ctx* c, int precision, int npad) {
+  const int b = tune_bucket(npad);
+  const int p = precision == LSMS_SPLIT ? 1 : 0;
+  auto choose = [&](int expl, int kind, int def) {
+    if (expl >= 0) return expl;
+    return c->tuned[p][kind][b] >= 0 ? (int)c->tuned[p][kind][b] : def;
+  };
+  Tiling t;
+  if (p == 1) {
+    t.wide = choose(c->gemm_f32, 1, kDefaultF32Wide);
+    t.narrow = choose(c->gemm_f32_narrow, 0, kDefaultF32Narrow);
+  } else {
+    t.wide = choose(c->gemm_f64, 1, kDefaultF64Wide);
+    t.narrow = choose(c->gemm_f64_narrow, 0, kDefaultF64Narrow);
+  }
+  t.panel_small_rows = c->panel_small_rows >= 0 ? c->panel_small_rows
+                       : c->tuned_panel_rows >= 0 ? c->tuned_panel_rows
+                                                  : PANEL_SMALL_ROWS;
+  return t;
+}
 
 struct lsms_factors {
   lsms_ctx* ctx = nullptr;
@@ -276,6 +316,7 @@ extern "C" int lsms_create(int hip_device, int lmax, size_t workspace_limit, lsm
   std::unique_ptr<lsms_ctx> c(new (std::nothrow) lsms_ctx());
   if (!c) return fail(LSMS_E_NOMEM, "host allocation failed");
   c->device = hip_device;
+  std::memset(c->tuned, -1, sizeof(c->tuned));
   if (workspace_limit == 0) {
     size_t fr = 0, tot = 0;
     HIP_TRY(hipMemGetInfo(&fr, &tot));
@@ -291,6 +332,15 @@ extern "C" int lsms_create(int hip_device, int lmax, size_t workspace_limit, lsm
   if (rc) return rc;
   HIP_TRY(upload_gaunt(c->gaunt));
   HIP_TRY(noalloc_scratch_init(hip_device));
+  // a tuning cache named by the environment is read when it exists (and fits this device)
+  if (const char* path = std::getenv("LSMS_TUNE_CACHE")) {
+    FILE* f = std::fopen(path, "r");
+    if (f) {
+      std::fclose(f);
+      rc = lsms_tuning_load(c.get(), path);
+      if (rc != LSMS_OK && rc != LSMS_E_STATE) return rc;
+    }
+  }
   HIP_TRY(hipHostMalloc((void**)&c->pinned_flag, 256, hipHostMallocDefault));
   *out = c.release();
   return LSMS_OK;
@@ -604,7 +654,8 @@ static int side_stream(lsms_ctx* ctx, const SideStream** out) {
 static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int nj, int npad_max, void* abuf,
                             int32_t* piv, int32_t* jinfo, double2* xbuf, GemmProfiler* prof, hipStream_t s,
                             bool sym = false) {
-  const int variant = gemm_f32_variant(ctx);
+  const Tiling tiling = pick_tiling(ctx, precision, npad_max);
+  const int variant = tiling.wide;
   TallScratch ts;
   int rc = tall_scratch(ctx, nj, npad_max, &ts, s);
   if (rc) return rc;
@@ -620,13 +671,13 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
   }
   auto issue = [&](hipStream_t q, GemmProfiler* pr) {
     if (precision == LSMS_FP64) {
-      lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, q, pr, ts, side);
+      lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, q, pr, tiling, ts, side);
       lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, q);
     } else {
       if (sym)
         ldlt_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, NB, ctx->ldlt.p);
       else
-        lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, ts, side);
+        lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, tiling, ts, side);
       // the first solve in FP32 on a rounded copy of the right-hand side (refined below)
       launch_x32(jd, nj, npad_max, 0, xbuf, xbuf, nullptr, q);
       lu_solve_f32_single(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, nullptr, q);
@@ -638,7 +689,8 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
     HIP_TRY(hipGetLastError());
     return LSMS_OK;
   }
-  const std::vector<intptr_t> key = {precision, nj, npad_max, variant, (intptr_t)jd, (intptr_t)abuf,
+  const std::vector<intptr_t> key = {precision, nj, npad_max, variant, tiling.narrow, tiling.panel_small_rows,
+                                     (intptr_t)jd, (intptr_t)abuf,
                                      (intptr_t)piv, (intptr_t)jinfo, (intptr_t)xbuf, ts.chunk,
                                      (intptr_t)ts.base, sym ? 1 : 0, (intptr_t)ctx->ldlt.p};
   auto it = ctx->graph_cache.find(key);
@@ -936,7 +988,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           TallScratch fts;
           rc = tall_scratch(ctx, nf, fpad, &fts, s);
           if (rc) return rc;
-          lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s, nullptr, fts);
+          lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s, nullptr, pick_tiling(ctx, LSMS_FP64, fpad), fts);
           lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, s);
           launch_fallback_status(nf, fjd, finfo, jinfo, s);
           // the fallback's job list is context scratch: done before another wave reuses it
@@ -1081,6 +1133,20 @@ extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
         value == 1;
     return LSMS_OK;
   }
+  if (knob == LSMS_TUNE_GEMM_F32_NARROW || knob == LSMS_TUNE_GEMM_F64 || knob == LSMS_TUNE_GEMM_F64_NARROW) {
+    const int nv = knob == LSMS_TUNE_GEMM_F32_NARROW ? gemm_f32_variants() : gemm_f64_variants();
+    if (value < -1 || value >= nv) return fail(LSMS_E_ARG, "tiling %d outside [-1, %d) for knob %d", value, nv, knob);
+    (knob == LSMS_TUNE_GEMM_F32_NARROW ? ctx->gemm_f32_narrow
+     : knob == LSMS_TUNE_GEMM_F64      ? ctx->gemm_f64
+                                       : ctx->gemm_f64_narrow) = value;
+    return LSMS_OK;
+  }
+  if (knob == LSMS_TUNE_PANEL_SMALL_ROWS) {
+    if (value < -1 || value > PANEL_SMALL_ROWS)
+      return fail(LSMS_E_ARG, "panel height %d outside [-1, %d]", value, PANEL_SMALL_ROWS);
+    ctx->panel_small_rows = value;
+    return LSMS_OK;
+  }
   if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);
   if (value < -1 || value >= gemm_f32_variants())
     return fail(LSMS_E_ARG, "gemm_f32 tiling %d outside [-1, %d)", value, gemm_f32_variants());
@@ -1104,6 +1170,14 @@ extern "C" int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value) {
                  : 0;
     return LSMS_OK;
   }
+  if (knob == LSMS_TUNE_GEMM_F32_NARROW || knob == LSMS_TUNE_GEMM_F64 || knob == LSMS_TUNE_GEMM_F64_NARROW ||
+      knob == LSMS_TUNE_PANEL_SMALL_ROWS) {
+    *value = knob == LSMS_TUNE_GEMM_F32_NARROW ? ctx->gemm_f32_narrow
+             : knob == LSMS_TUNE_GEMM_F64      ? ctx->gemm_f64
+             : knob == LSMS_TUNE_GEMM_F64_NARROW ? ctx->gemm_f64_narrow
+                                                 : ctx->panel_small_rows;
+    return LSMS_OK;
+  }
   if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);
   *value = gemm_f32_variant(ctx);
   return LSMS_OK;
@@ -1120,9 +1194,146 @@ extern "C" int lsms_autotune(lsms_ctx* ctx, int npad, int batch, int* best, floa
   if (gemm_f32_autotune(npad, batch, (hipStream_t)hip_stream, t, &b) != 0 || b < 0)
     return fail(LSMS_E_NOMEM, "autotuning batch of %d systems of size %d could not run", batch, npad);
   ctx->gemm_f32 = b;
+  ctx->tuned[1][1][tune_bucket(npad)] = (int8_t)b;
   *best = b;
   if (ms)
     for (int v = 0; v < LSMS_GEMM_F32_VARIANTS; ++v) ms[v] = t[v];
+  return LSMS_OK;
+}
+
+extern "C" int lsms_autotune_kernel(lsms_ctx* ctx, int what, int npad, int batch, int* best, float* ms,
+                                    int ms_len, void* hip_stream) {
+  if (!ctx || !best) return fail(LSMS_E_ARG, "NULL argument");
+  if (batch < 1 || batch > 65535) return fail(LSMS_E_ARG, "batch %d outside [1, 65535]", batch);
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (what == LSMS_AUTOTUNE_F32_PANEL) {
+    // both variants at the heights the small one can take; the threshold is the largest
+    // height at which the small workgroups won (0: never)
+    const int heights[3] = {256, 512, PANEL_SMALL_ROWS};
+    if (ms && ms_len < 6) return fail(LSMS_E_ARG, "ms needs 6 entries for the panel autotuner");
+    int thr = 0;
+    for (int h = 0; h < 3; ++h) {
+      float t2[2];
+      if (panel_autotune(heights[h], batch, s, t2) != 0)
+        return fail(LSMS_E_NOMEM, "panel autotuning batch of %d systems of height %d could not run", batch,
+                    heights[h]);
+      if (t2[0] <= t2[1]) thr = heights[h];
+      if (ms) {
+        ms[2 * h] = t2[0];
+        ms[2 * h + 1] = t2[1];
+      }
+    }
+    ctx->tuned_panel_rows = thr;
+    *best = thr;
+    return LSMS_OK;
+  }
+  if (what < LSMS_AUTOTUNE_F32_WIDE || what > LSMS_AUTOTUNE_F64_NARROW)
+    return fail(LSMS_E_ARG, "unknown autotuner target %d", what);
+  const int precision = (what == LSMS_AUTOTUNE_F32_WIDE || what == LSMS_AUTOTUNE_F32_NARROW) ? 1 : 0;
+  const int kind = (what == LSMS_AUTOTUNE_F32_WIDE || what == LSMS_AUTOTUNE_F64_WIDE) ? 1 : 0;
+  if (npad % PAD != 0 || npad <= 2 * NB || npad > NL * LSMS_MAX_LIZ)
+    return fail(LSMS_E_ARG, "npad %d must be a multiple of %d in (%d, %d]", npad, PAD, 2 * NB, NL * LSMS_MAX_LIZ);
+  const int nv = precision ? gemm_f32_variants() : gemm_f64_variants();
+  if (ms && ms_len < nv) return fail(LSMS_E_ARG, "ms needs %d entries for this autotuner target", nv);
+  std::vector<float> t(nv);
+  int b = -1;
+  if (update_autotune(precision, kind, npad, batch, s, t.data(), &b) != 0 || b < 0)
+    return fail(LSMS_E_NOMEM, "autotuning batch of %d systems of size %d could not run", batch, npad);
+  ctx->tuned[precision][kind][tune_bucket(npad)] = (int8_t)b;
+  *best = b;
+  if (ms)
+    for (int v = 0; v < nv; ++v) ms[v] = t[v];
+  return LSMS_OK;
+}
+
+extern "C" int lsms_peak_probe(lsms_ctx* ctx, int what, double* value, void* hip_stream) {
+  if (!ctx || !value) return fail(LSMS_E_ARG, "NULL argument");
+  if (what < 0 || what > 4) return fail(LSMS_E_ARG, "unknown probe %d", what);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (peak_probe(what, ctx->cu_count, (hipStream_t)hip_stream, value) != 0)
+    return fail(LSMS_E_DEVICE, "probe %d failed: %s", what, hipGetErrorString(hipGetLastError()));
+  return LSMS_OK;
+}
+
+extern "C" int lsms_tuning_table(lsms_ctx* ctx, int what, int* out) {
+  if (!ctx || !out) return fail(LSMS_E_ARG, "NULL argument");
+  if (what == LSMS_AUTOTUNE_F32_PANEL) {
+    out[0] = ctx->tuned_panel_rows;
+    return LSMS_OK;
+  }
+  if (what < LSMS_AUTOTUNE_F32_WIDE || what > LSMS_AUTOTUNE_F64_NARROW)
+    return fail(LSMS_E_ARG, "unknown autotuner target %d", what);
+  const int precision = (what == LSMS_AUTOTUNE_F32_WIDE || what == LSMS_AUTOTUNE_F32_NARROW) ? 1 : 0;
+  const int kind = (what == LSMS_AUTOTUNE_F32_WIDE || what == LSMS_AUTOTUNE_F64_WIDE) ? 1 : 0;
+  for (int b = 0; b < LSMS_TUNE_BUCKETS; ++b) out[b] = ctx->tuned[precision][kind][b];
+  return LSMS_OK;
+}
+
+// The cache identifies the device by its architecture name and compute-unit count.
+static int device_tag(int device, char* tag, size_t len) {
+  hipDeviceProp_t p;
+  HIP_TRY(hipGetDeviceProperties(&p, device));
+  std::snprintf(tag, len, "%s/%d", p.gcnArchName, p.multiProcessorCount);
+  for (char* q = tag; *q; ++q)
+    if (*q == ' ') *q = '_';
+  return LSMS_OK;
+}
+
+extern "C" int lsms_tuning_save(lsms_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(LSMS_E_ARG, "NULL argument");
+  char tag[256];
+  int rc = device_tag(ctx->device, tag, sizeof(tag));
+  if (rc) return rc;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(LSMS_E_ARG, "cannot write %s", path);
+  std::fprintf(f, "lsms-tune 1 %s\n", tag);
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < 2; ++k)
+      for (int b = 0; b < LSMS_TUNE_BUCKETS; ++b)
+        if (ctx->tuned[p][k][b] >= 0) std::fprintf(f, "update %d %d %d %d\n", p, k, b, (int)ctx->tuned[p][k][b]);
+  if (ctx->tuned_panel_rows >= 0) std::fprintf(f, "panel %d\n", ctx->tuned_panel_rows);
+  const bool ok = std::ferror(f) == 0;
+  std::fclose(f);
+  return ok ? LSMS_OK : fail(LSMS_E_ARG, "writing %s failed", path);
+}
+
+extern "C" int lsms_tuning_load(lsms_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(LSMS_E_ARG, "NULL argument");
+  char tag[256], ftag[256];
+  int rc = device_tag(ctx->device, tag, sizeof(tag));
+  if (rc) return rc;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(LSMS_E_ARG, "cannot read %s", path);
+  int version = 0;
+  if (std::fscanf(f, "lsms-tune %d %255s", &version, ftag) != 2 || version != 1) {
+    std::fclose(f);
+    return fail(LSMS_E_ARG, "%s is not a tuning cache", path);
+  }
+  if (std::strcmp(tag, ftag) != 0) {
+    std::fclose(f);
+    return fail(LSMS_E_STATE, "%s was tuned on %s, this device is %s", path, ftag, tag);
+  }
+  int8_t tuned[2][2][LSMS_TUNE_BUCKETS];
+  std::memset(tuned, -1, sizeof(tuned));
+  int panel = -1;
+  char word[32];
+  while (std::fscanf(f, "%31s", word) == 1) {
+    int p, k, b, v;
+    if (std::strcmp(word, "update") == 0 && std::fscanf(f, "%d %d %d %d", &p, &k, &b, &v) == 4 && p >= 0 && p < 2 &&
+        k >= 0 && k < 2 && b >= 0 && b < LSMS_TUNE_BUCKETS && v >= 0 &&
+        v < (p ? gemm_f32_variants() : gemm_f64_variants())) {
+      tuned[p][k][b] = (int8_t)v;
+    } else if (std::strcmp(word, "panel") == 0 && std::fscanf(f, "%d", &v) == 1 && v >= 0 && v <= PANEL_SMALL_ROWS) {
+      panel = v;
+    } else {
+      std::fclose(f);
+      return fail(LSMS_E_ARG, "malformed entry in %s", path);
+    }
+  }
+  std::fclose(f);
+  std::memcpy(ctx->tuned, tuned, sizeof(tuned));
+  ctx->tuned_panel_rows = panel;
   return LSMS_OK;
 }
 
@@ -1265,10 +1476,10 @@ extern "C" int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t
   launch_zero_i32(info, batch, s);
   launch_load_user(jd, batch, npad_max, aptr, bptr, nrhs, prec, abuf, xbuf, s);
   if (prec == LSMS_FP64) {
-    lu_factor_f64(jd, batch, npad_max, (double2*)abuf, piv, info, s, nullptr, ts);
+    lu_factor_f64(jd, batch, npad_max, (double2*)abuf, piv, info, s, nullptr, pick_tiling(ctx, prec, npad_max), ts);
     lu_solve_f64(jd, batch, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
   } else {
-    lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s, nullptr, gemm_f32_variant(ctx), ts);
+    lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s, nullptr, pick_tiling(ctx, prec, npad_max), ts);
     lu_solve_f32(jd, batch, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
   }
   launch_store_user(jd, batch, npad_max, bptr, nrhs, xbuf, s);

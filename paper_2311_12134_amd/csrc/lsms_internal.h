@@ -133,6 +133,29 @@ struct GemmProfiler {
 // The FP32 update comes in several tilings (variant 0 .. gemm_f32_variants() - 1).
 void launch_gemm_f64(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin, int c_begin,
                      int c_end, double2* work, hipStream_t s);
+// The FP64 update's tilings (gemm64.hip): variant 0 .. gemm_f64_variants() - 1, 0 = the plain kernel above.
+int gemm_f64_variants();
+void launch_gemm_f64_variant(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd,
+                             int r_begin, int c_begin, int c_end, double2* work, hipStream_t s);
+// Split-mode panels of at most this many rows use 256-thread workgroups with 8-wide leaves.
+constexpr int PANEL_SMALL_ROWS = 3 * 256;
+// Kernel choices of one LU: the tilings of the wide (K = 2 NB) and narrow (K = NB) trailing
+// updates, and the height up to which split-mode panels take the small-workgroup variant.
+struct Tiling {
+  int wide = 0;
+  int narrow = 0;
+  int panel_small_rows = PANEL_SMALL_ROWS;
+};
+// The split-mode panel at k = 0 in one of its two variants (autotuner; lu.hip).
+void launch_panel_f32_variant(int variant, const JobDesc* jobs, int njobs, int rows, float2* work, int32_t* piv,
+                              int32_t* info, hipStream_t s);
+// Autotuner (tune.hip): precision 0 FP64, 1 split; kind 1 wide, 0 narrow.  ms[variant] gets
+// the best of three launches, *best the fastest; panel_autotune times the two split-mode
+// panel variants at one height (ms[2]).  Return 0 or -1 (allocation or launch failure).
+int update_autotune(int precision, int kind, int npad, int batch, hipStream_t s, float* ms, int* best);
+int panel_autotune(int rows, int batch, hipStream_t s, float* ms);
+// Peak-rate probes (probe.hip); what as in lsms_peak_probe.  Returns 0 or -1.
+int peak_probe(int what, int cu_count, hipStream_t s, double* value);
 int gemm_f32_variants();
 // Times every FP32 tiling on a synthetic batch (batch systems of size npad, widest update);
 // ms[variant] receives the best of three launches, *best the fastest.  Returns 0 or -1.
@@ -160,9 +183,10 @@ struct SideStream {
 };
 
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof, const TallScratch& tall, const SideStream* side = nullptr);
+                   hipStream_t s, GemmProfiler* prof, Tiling tiling, const TallScratch& tall,
+                   const SideStream* side = nullptr);
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall,
+                   hipStream_t s, GemmProfiler* prof, Tiling tiling, const TallScratch& tall,
                    const SideStream* side = nullptr);
 // Symmetric factorization S = L D L^T of complex-symmetric systems (no pivoting), stored as
 // an LU with U = D L^T so the LU solves apply.  Panels taller than tall_rows take the

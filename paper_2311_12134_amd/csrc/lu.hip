@@ -1048,14 +1048,15 @@ __global__ __launch_bounds__(256) void tslu_l21_kernel(const JobDesc* jobs, int 
 // panel's memory traffic).  Past 2560 rows the leaf is halved to stay in registers.
 template <typename T>
 static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int rows, T* work, int32_t* piv,
-                         int32_t* info, hipStream_t s, int nopiv = 0) {
+                         int32_t* info, hipStream_t s, int nopiv = 0, int small_rows = PANEL_SMALL_ROWS) {
   constexpr int PT = 512;
   constexpr int IBW = sizeof(T) == sizeof(float2) ? 16 : 8;
   if constexpr (sizeof(T) == sizeof(float2)) {
-    if (rows <= 3 * 256) {
-      // FP32 storage up to 768 rows: 256-thread workgroups with 8-wide leaves fit two jobs
-      // per CU, which hides more of the short panels' barrier and shuffle latency (past
-      // that the wider leaves of the 512-thread kernel win)
+    if (rows <= std::min(small_rows, 3 * 256)) {
+      // FP32 storage up to small_rows (at most 768) rows: 256-thread workgroups with 8-wide
+      // leaves fit two jobs per CU, which hides more of the short panels' barrier and shuffle
+      // latency (past some height the wider leaves of the 512-thread kernel win; the
+      // autotuner finds where)
       const int S2 = (rows + 255) / 256;
       switch (S2) {
         case 1: panel_kernel<T, 256, 1, 8><<<njobs, 256, 0, s>>>(jobs, k, left, work, piv, info, nopiv); return;
@@ -1077,11 +1078,18 @@ static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int ro
   }
 }
 
+// The split-mode panel at k = 0 of systems of `rows` rows, for the autotuner: variant 0 the
+// 256-thread workgroups with 8-wide leaves (rows <= 768), 1 the 512-thread ones.
+void launch_panel_f32_variant(int variant, const JobDesc* jobs, int njobs, int rows, float2* work, int32_t* piv,
+                              int32_t* info, hipStream_t s) {
+  launch_panel<float2>(jobs, njobs, 0, 0, rows, work, piv, info, s, 0, variant == 0 ? 3 * 256 : 0);
+}
+
 // One panel (and the inverses of its diagonal triangles): the register-resident panel
 // kernel, or the tournament for panels taller than 2 chunk rows.
 template <typename T>
 static void panel_step(const JobDesc* jobs, int njobs, int npad_max, int k, int left, T* work, int32_t* piv,
-                       int32_t* info, const TallScratch& ts, hipStream_t s) {
+                       int32_t* info, const TallScratch& ts, hipStream_t s, int small_rows) {
   const int rows = npad_max - k;
   if (ts.chunk > 0 && rows > 2 * ts.chunk && ts.base) {
     const TallLayout L = tall_layout(ts.njobs, ts.npad_max, ts.chunk);
@@ -1108,7 +1116,7 @@ static void panel_step(const JobDesc* jobs, int njobs, int npad_max, int k, int 
     if (rows > NB) tslu_l21_kernel<T><<<dim3((rows - NB + 63) / 64, njobs), 256, 0, s>>>(jobs, k, work);
     return;
   }
-  launch_panel<T>(jobs, njobs, k, left, rows, work, piv, info, s);
+  launch_panel<T>(jobs, njobs, k, left, rows, work, piv, info, s, 0, small_rows);
   launch_linv<T>(jobs, njobs, k, work, s);
 }
 
@@ -1148,7 +1156,7 @@ static void update_cost(const GemmProfiler* prof, int njobs, int kd, int r_begin
 template <typename T, typename Gemm>
 static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work, int32_t* piv, int32_t* info,
                           hipStream_t s, GemmProfiler* prof, const TallScratch& tall, const SideStream* side,
-                          Gemm gemm) {
+                          int small_rows, Gemm gemm) {
   auto timed_gemm = [&](int k, int kd, int r_begin, int c_begin, int c_end) {
     const int rows = npad_max - r_begin;
     const int cols = (c_end > 0 ? std::min(c_end, npad_max) : npad_max) - c_begin;
@@ -1166,13 +1174,13 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
     if (ahead)
       (void)hipStreamWaitEvent(s, side->panel_done, 0);
     else
-      panel_step<T>(jobs, njobs, npad_max, k, 0, work, piv, info, tall, s);
+      panel_step<T>(jobs, njobs, npad_max, k, 0, work, piv, info, tall, s, small_rows);
     ahead = false;
     const int rest = npad_max - k - NB;
     if (rest <= 0) break;
     swap_trsm_kernel<T, false><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, piv);
     timed_gemm(k, NB, k + NB, k + NB, k + 2 * NB);  // the second panel's columns
-    panel_step<T>(jobs, njobs, npad_max, k + NB, NB, work, piv, info, tall, s);
+    panel_step<T>(jobs, njobs, npad_max, k + NB, NB, work, piv, info, tall, s, small_rows);
     const int rest2 = npad_max - k - 2 * NB;
     if (rest2 <= 0) break;
     swap_trsm_kernel<T, true><<<dim3(rest2 / 64, njobs), 256, 0, s>>>(jobs, k + NB, work, piv);
@@ -1180,7 +1188,7 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
       timed_gemm(k, 2 * NB, k + 2 * NB, k + 2 * NB, k + 3 * NB);  // the next first panel's columns
       (void)hipEventRecord(side->update_done, s);
       (void)hipStreamWaitEvent(side->stream, side->update_done, 0);
-      panel_step<T>(jobs, njobs, npad_max, k + 2 * NB, 0, work, piv, info, tall, side->stream);
+      panel_step<T>(jobs, njobs, npad_max, k + 2 * NB, 0, work, piv, info, tall, side->stream, small_rows);
       (void)hipEventRecord(side->panel_done, side->stream);
       ahead = true;
       timed_gemm(k, 2 * NB, k + 2 * NB, k + 3 * NB, 0);
@@ -1330,23 +1338,23 @@ void ldlt_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work,
   }
 }
 
+// The narrow update of a pair's second panel (64 columns, K = NB) takes the narrow tiling; the
+// K = 2 NB updates (split or not at the look-ahead panel) take the wide one, so every element
+// sums in the same order with and without the look-ahead stream.
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof, const TallScratch& tall, const SideStream* side) {
-  lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall, side,
+                   hipStream_t s, GemmProfiler* prof, Tiling tiling, const TallScratch& tall, const SideStream* side) {
+  lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall, side, tiling.panel_small_rows,
                          [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
-                           launch_gemm_f64(jobs, njobs, rows, cols, k, kd, rb, cb, ce, work, s);
+                           launch_gemm_f64_variant(kd == NB ? tiling.narrow : tiling.wide, jobs, njobs, rows, cols,
+                                                   k, kd, rb, cb, ce, work, s);
                          });
 }
 
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
-                   hipStream_t s, GemmProfiler* prof, int gemm_variant, const TallScratch& tall,
-                   const SideStream* side) {
-  lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall, side,
+                   hipStream_t s, GemmProfiler* prof, Tiling tiling, const TallScratch& tall, const SideStream* side) {
+  lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall, side, tiling.panel_small_rows,
                         [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
-                          // the narrow update of a pair's second panel (64 columns, K = NB) keeps the
-                          // 64 x 64 tiling; the K = 2 NB updates (split or not at the look-ahead panel)
-                          // use the chosen tiling, so every element sums in the same order either way
-                          launch_gemm_f32(ce > 0 && kd == NB ? 0 : gemm_variant, jobs, njobs, rows, cols, k, kd, rb,
+                          launch_gemm_f32(kd == NB ? tiling.narrow : tiling.wide, jobs, njobs, rows, cols, k, kd, rb,
                                           cb, ce, work, s);
                         });
 }

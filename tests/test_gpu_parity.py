@@ -217,6 +217,121 @@ def test_split_lu_every_gemm_tiling(lctx, tiling):
         assert err <= 2e-5, (tiling, sizes[k], err)
 
 
+def _random_systems(seed, sizes, scale_diag=2.0):
+    rng = np.random.default_rng(seed)
+    dev = torch.device("cuda", 0)
+    mats, rhs, refs = [], [], []
+    for n in sizes:
+        A = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) / np.sqrt(n) + scale_diag * np.eye(n)
+        B = rng.normal(size=(n, 3)) + 1j * rng.normal(size=(n, 3))
+        refs.append(np.linalg.solve(A, B))
+        mats.append(torch.from_numpy(A).to(dev))
+        rhs.append(torch.from_numpy(B).to(dev))
+    return mats, rhs, refs
+
+
+@pytest.mark.parametrize("knob,nv", [("f64_wide", 6), ("f64_narrow", 6), ("f32_narrow", 10)])
+def test_lu_every_update_tiling(lctx, knob, nv):
+    """Every tiling of the FP64 wide and narrow trailing updates (FP64 solve to 1e-10) and of
+    the split-mode narrow update (FP32 factors without refinement, to FP32 rounding) on an
+    uneven batch whose trailing blocks end on 64-row halves of the 128-wide tiles."""
+    sizes = [1000, 700, 450, 129, 1]
+    precision = "split" if knob.startswith("f32") else "fp64"
+    tol = 2e-5 if precision == "split" else 1e-10
+    print("[gpu] every tiling of %s" % knob, flush=True)
+    for v in range(nv):
+        mats, rhs, refs = _random_systems(13 + v, sizes)
+        lctx.set_knob(knob, v)
+        try:
+            assert lctx.knob(knob) == v
+            info = lctx.batched_lu_solve(mats, rhs, precision=precision).cpu().numpy()
+        finally:
+            lctx.set_knob(knob, -1)
+        torch.cuda.synchronize()
+        for k, ref in enumerate(refs):
+            assert info[k] == 0
+            err = np.abs(rhs[k].cpu().numpy() - ref).max() / np.abs(ref).max()
+            assert err <= tol, (knob, v, sizes[k], err)
+
+
+@pytest.mark.parametrize("rows", [0, 256, 512, 768])
+def test_split_panel_variant_threshold(lctx, rows):
+    """The split-mode panel's small-workgroup variant used up to 0, 256, 512 or 768 rows: the
+    same solves to FP32 rounding."""
+    mats, rhs, refs = _random_systems(17, [1000, 700, 450, 300, 129])
+    lctx.set_knob("panel_small_rows", rows)
+    try:
+        info = lctx.batched_lu_solve(mats, rhs, precision="split").cpu().numpy()
+    finally:
+        lctx.set_knob("panel_small_rows", -1)
+    torch.cuda.synchronize()
+    for k, ref in enumerate(refs):
+        assert info[k] == 0
+        assert np.abs(rhs[k].cpu().numpy() - ref).max() <= 2e-5 * np.abs(ref).max(), (rows, k)
+
+
+def test_autotuned_choices_per_bucket_at_parity(tmp_path):
+    """The autotuner on the disordered 1940-atom bcc workload's two npad buckets (LIZ of
+    74-94 sites: padded sizes 1216-1536) for every target; the waves then take each bucket's
+    choices, and sampled atoms of every size in both precisions match the oracle.  The table
+    survives a save / load round trip through the tuning cache, and a fresh context reads it
+    from LSMS_TUNE_CACHE."""
+    import os
+    import paper_2311_12134_amd as P
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = P.Context(0)
+    try:
+        w = synthetic.workload("bcc1940")
+        eta = w["etas"][0]
+        liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+        npads = sorted({int(-(-16 * n // 64) * 64) for n in np.diff(liz.ptr)})
+        buckets = sorted({(n - 1) // 256 for n in npads})
+        assert len(buckets) == 2
+        print("[gpu] autotune bcc1940 buckets %s" % buckets, flush=True)
+        for b in buckets:
+            npad = max(n for n in npads if (n - 1) // 256 == b)
+            for what in ("f32_wide", "f32_narrow", "f64_wide", "f64_narrow"):
+                best, ms = ctx.autotune_kernel(what, npad, batch=64)
+                assert ms[best] == min(ms) and ctx.tuning_table(what)[b] == best
+        thr, ms = ctx.autotune_kernel("f32_panel", batch=64)
+        assert thr in (0, 256, 512, 768) and ctx.tuning_table("f32_panel") == thr
+        la, lp, phase, species, J = _device_inputs(w, liz)
+        sizes = np.diff(liz.ptr)
+        atoms = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 1000,
+                        int(np.nonzero(sizes == np.median(sizes))[0][0])})
+        o = _oracle_atoms(w, eta, atoms, liz)
+        for precision, tol in (("split", TOL_SPLIT), ("fp64", TOL64)):
+            tp, tm, info, _ = ctx.tau_solve(liz, la, lp, phase, w["e_fermi"], eta, precision=precision)
+            _, _, pa = ctx.kubo_sigma(liz, la, tp, tm, species, J, w["volume"], per_atom=True)
+            torch.cuda.synchronize()
+            assert (info.cpu().numpy() == 0).all()
+            pa = pa.cpu().numpy()
+            for i in atoms:
+                sl = slice(int(liz.ptr[i]), int(liz.ptr[i + 1]))
+                for tag, t in (("+", tp), ("-", tm)):
+                    ref = o["tau"][i]["col" + tag]
+                    err = np.linalg.norm(t[sl].cpu().numpy() - ref) / np.linalg.norm(ref)
+                    assert err <= tol, (precision, i, tag, err)
+                assert np.abs(pa[i] - o["per_atom"][i]).max() <= tol * np.abs(o["per_atom"][i]).max()
+        path = tmp_path / "tune.txt"
+        ctx.tuning_save(path)
+        tables = {what: ctx.tuning_table(what) for what in ("f32_wide", "f32_narrow", "f64_wide", "f64_narrow")}
+        os.environ["LSMS_TUNE_CACHE"] = str(path)
+        try:
+            ctx2 = P.Context(0)
+        finally:
+            del os.environ["LSMS_TUNE_CACHE"]
+        try:
+            for what, tab in tables.items():
+                assert np.array_equal(ctx2.tuning_table(what), tab), what
+            assert ctx2.tuning_table("f32_panel") == thr
+        finally:
+            ctx2.close()
+    finally:
+        ctx.close()
+
+
 def _grad_setup(w):
     import paper_2311_12134_amd as P
     dev = torch.device("cuda", 0)
