@@ -215,7 +215,8 @@ F32_TILINGS = {0: "gemm_f32_3m_kernel", 1: "gemm_f32_3m_tiled<64,64,32,32>", 2: 
                3: "gemm_f32_3m_tiled<128,64,32,64,xcd>", 4: "gemm_f32_3m_tiled<64,128,64,32,xcd>",
                5: "gemm_f32_3m_tiled<128,128,64,64,xcd>", 6: "gemm_f32_3m_tiled<128,128,64,64>",
                7: "gemm_f32_3m_tiled<64,64,32,32,xcd,C prefetch>", 8: "gemm_f32_3m_tiled<64,64,32,32,xcd,K32>",
-               9: "gemm_f32_3m_tiled<64,64,32,32,xcd,32x32x2>"}
+               9: "gemm_f32_3m_tiled<64,64,32,32,xcd,32x32x2>", 10: "gemm_f32_3m_persist<64,64,32,32,xcd>",
+               11: "gemm_f32_3m_persist<64,64,32,32,xcd,C prefetch>"}
 F64_TILINGS = {0: "gemm_f64_kernel", 1: "gemm_f64_tiled<64,64,32,32,xcd,K8>", 2: "gemm_f64_tiled<32,64,16,32,xcd,K8>",
                3: "gemm_f64_tiled<128,64,64,32,xcd,K8>", 4: "gemm_f64_tiled<64,128,32,64,xcd,K8>",
                5: "gemm_f64_tiled<64,64,32,32,K8>"}

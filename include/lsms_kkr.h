@@ -141,7 +141,9 @@ int lsms_build_liz_subset(lsms_ctx* ctx, int32_t n_atoms, const double* pos, con
  *             the symmetric form, met a zero pivot) and the system was recomputed by the
  *             FP64 LU (tau valid); k > 0 for an exact zero pivot of the FP64 LU (tau not
  *             valid); LSMS_INFO_BADINPUT
- *   berr      device [n_atoms][2] double (out): final backward error (split mode),
+ *   berr      device [n_atoms][2] double (out): final backward error of the refined solution
+ *             (split mode); -1 for a system recomputed by the FP64 LU (info = LSMS_INFO_NOCONV
+ *             or a zero pivot after it), whose solution no split-mode residual describes;
  *             0 in FP64 mode
  *   keep      NULL, or receives a library-owned handle that keeps every LU factor
  *             alive for lsms_kubo_sigma_grad (free with lsms_factors_free)
@@ -282,12 +284,14 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * knob LSMS_TUNE_GEMM_F32 selects the tiling, 0 .. LSMS_GEMM_F32_VARIANTS - 1, or -1 for
  * the library's default (0: 64 x 64 tiles; 1, 2: 64 x 64 pipelined through two LDS stages,
  * 2 with an XCD-aware workgroup order; 3 - 6: 128-row / 128-column tiles; 7: as 2 with the C
- * tile prefetched early; 8: as 2 with K chunks of 32; 9: as 2 on FP32 MFMA 32x32x2); every
+ * tile prefetched early; 8: as 2 with K chunks of 32; 9: as 2 on FP32 MFMA 32x32x2; 10: as 2 in a
+ * persistent grid of resident workgroups that loops over the tiles; 11: as 10 with the C tile
+ * prefetched early); every
  * tiling computes the same update (results may differ in FP32 rounding order only).  Host-side setting of the context, no device work; returns
  * LSMS_E_ARG for an unknown knob or value.  lsms_get_tuning reports the tiling in effect.
  */
 #define LSMS_TUNE_GEMM_F32 0
-#define LSMS_GEMM_F32_VARIANTS 10
+#define LSMS_GEMM_F32_VARIANTS 12
 /*
  * knob LSMS_TUNE_GRAPHS (0 or 1, default 0): with 1, lsms_tau_solve captures each wave's
  * factorization and first solve (a fixed sequence of a few hundred launches) into a HIP

@@ -627,7 +627,8 @@ void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double to
                         int32_t* job_info, int32_t* pending, hipStream_t s);
 void launch_zero_i32(int32_t* p, int n, hipStream_t s);
 void launch_zero_pivot_to_fallback(int njobs, int32_t* job_info, hipStream_t s);
-void launch_fallback_status(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info, hipStream_t s);
+void launch_fallback_status(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info, double* norms,
+                            hipStream_t s);
 }  // namespace lsms
 
 // ---------------------------------------------------------------------------------
@@ -990,7 +991,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           if (rc) return rc;
           lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s, nullptr, pick_tiling(ctx, LSMS_FP64, fpad), fts);
           lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, s);
-          launch_fallback_status(nf, fjd, finfo, jinfo, s);
+          launch_fallback_status(nf, fjd, finfo, jinfo, jnorm, s);
           // the fallback's job list is context scratch: done before another wave reuses it
           HIP_TRY(hipStreamSynchronize(s));
         }
@@ -1134,7 +1135,7 @@ extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
     return LSMS_OK;
   }
   if (knob == LSMS_TUNE_GEMM_F32_NARROW || knob == LSMS_TUNE_GEMM_F64 || knob == LSMS_TUNE_GEMM_F64_NARROW) {
-    const int nv = knob == LSMS_TUNE_GEMM_F32_NARROW ? gemm_f32_variants() : gemm_f64_variants();
+    const int nv = knob == LSMS_TUNE_GEMM_F32_NARROW ? gemm_f32_variants_all() : gemm_f64_variants();
     if (value < -1 || value >= nv) return fail(LSMS_E_ARG, "tiling %d outside [-1, %d) for knob %d", value, nv, knob);
     (knob == LSMS_TUNE_GEMM_F32_NARROW ? ctx->gemm_f32_narrow
      : knob == LSMS_TUNE_GEMM_F64      ? ctx->gemm_f64
@@ -1148,8 +1149,8 @@ extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
     return LSMS_OK;
   }
   if (knob != LSMS_TUNE_GEMM_F32) return fail(LSMS_E_ARG, "unknown tuning knob %d", knob);
-  if (value < -1 || value >= gemm_f32_variants())
-    return fail(LSMS_E_ARG, "gemm_f32 tiling %d outside [-1, %d)", value, gemm_f32_variants());
+  if (value < -1 || value >= gemm_f32_variants_all())
+    return fail(LSMS_E_ARG, "gemm_f32 tiling %d outside [-1, %d)", value, gemm_f32_variants_all());
   ctx->gemm_f32 = value;
   return LSMS_OK;
 }
@@ -1234,7 +1235,7 @@ extern "C" int lsms_autotune_kernel(lsms_ctx* ctx, int what, int npad, int batch
   const int kind = (what == LSMS_AUTOTUNE_F32_WIDE || what == LSMS_AUTOTUNE_F64_WIDE) ? 1 : 0;
   if (npad % PAD != 0 || npad <= 2 * NB || npad > NL * LSMS_MAX_LIZ)
     return fail(LSMS_E_ARG, "npad %d must be a multiple of %d in (%d, %d]", npad, PAD, 2 * NB, NL * LSMS_MAX_LIZ);
-  const int nv = precision ? gemm_f32_variants() : gemm_f64_variants();
+  const int nv = precision ? gemm_f32_variants_all() : gemm_f64_variants();
   if (ms && ms_len < nv) return fail(LSMS_E_ARG, "ms needs %d entries for this autotuner target", nv);
   std::vector<float> t(nv);
   int b = -1;
@@ -1322,7 +1323,7 @@ extern "C" int lsms_tuning_load(lsms_ctx* ctx, const char* path) {
     int p, k, b, v;
     if (std::strcmp(word, "update") == 0 && std::fscanf(f, "%d %d %d %d", &p, &k, &b, &v) == 4 && p >= 0 && p < 2 &&
         k >= 0 && k < 2 && b >= 0 && b < LSMS_TUNE_BUCKETS && v >= 0 &&
-        v < (p ? gemm_f32_variants() : gemm_f64_variants())) {
+        v < (p ? gemm_f32_variants_all() : gemm_f64_variants())) {
       tuned[p][k][b] = (int8_t)v;
     } else if (std::strcmp(word, "panel") == 0 && std::fscanf(f, "%d", &v) == 1 && v >= 0 && v <= PANEL_SMALL_ROWS) {
       panel = v;

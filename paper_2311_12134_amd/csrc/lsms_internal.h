@@ -157,6 +157,10 @@ int panel_autotune(int rows, int batch, hipStream_t s, float* ms);
 // Peak-rate probes (probe.hip); what as in lsms_peak_probe.  Returns 0 or -1.
 int peak_probe(int what, int cu_count, hipStream_t s, double* value);
 int gemm_f32_variants();
+// All FP32 tilings: those of gemm.hip and the persistent forms (gemm_persist.hip).
+int gemm_f32_variants_all();
+void launch_gemm_f32_any(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
+                         int c_begin, int c_end, float2* work, hipStream_t s);
 // Times every FP32 tiling on a synthetic batch (batch systems of size npad, widest update);
 // ms[variant] receives the best of three launches, *best the fastest.  Returns 0 or -1.
 int gemm_f32_autotune(int npad, int batch, hipStream_t s, float* ms, int* best);

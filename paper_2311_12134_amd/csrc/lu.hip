@@ -1354,8 +1354,8 @@ void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, i
                    hipStream_t s, GemmProfiler* prof, Tiling tiling, const TallScratch& tall, const SideStream* side) {
   lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall, side, tiling.panel_small_rows,
                         [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
-                          launch_gemm_f32(kd == NB ? tiling.narrow : tiling.wide, jobs, njobs, rows, cols, k, kd, rb,
-                                          cb, ce, work, s);
+                          launch_gemm_f32_any(kd == NB ? tiling.narrow : tiling.wide, jobs, njobs, rows, cols, k, kd,
+                                              rb, cb, ce, work, s);
                         });
 }
 

@@ -2,8 +2,8 @@
 // the diagnostic batched-solve entry point.
 //
 // Classical mixed-precision iterative refinement (Wilkinson; Moler 1967): with FP32
-// factors of M, repeat  r = B - M X (FP64, M kept in FP64),  d = U^-1 L^-1 P r (FP32
-// factors, FP64 arithmetic),  X += d,  until the normwise backward error
+// factors of M, repeat  r = B - M X (FP64, M kept in FP64),  d = U^-1 L^-1 P r (an FP32 solve
+// with the FP32 factors on a rounded copy of r),  X += d (FP64),  until the normwise backward error
 //   berr = ||r||_inf / (||M||_inf ||X||_inf + ||B||_inf)
 // reaches the requested tolerance.  B = E0 t_centre is regenerated from the t-matrix.
 // Per-job norms live in norms[job][8]: 0 ||M||, 1 ||r||, 2 ||X||, 3 berr, 4 ||B||.
@@ -154,14 +154,21 @@ void launch_zero_pivot_to_fallback(int njobs, int32_t* job_info, hipStream_t s) 
   zero_pivot_to_fallback_kernel<<<(njobs + 255) / 256, 256, 0, s>>>(njobs, job_info);
 }
 
-// After the FP64 fallback: a zero pivot of the partial-pivoting LU marks the system singular.
-__global__ void fallback_status_kernel(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info) {
+// After the FP64 fallback: a zero pivot of the partial-pivoting LU marks the system singular,
+// and the backward error of the discarded split-mode solution no longer describes the
+// returned one, so it is replaced by the sentinel -1.
+__global__ void fallback_status_kernel(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info,
+                                       double* norms) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f < nf && finfo[f] > 0) job_info[fjobs[f].info] = finfo[f];
+  if (f >= nf) return;
+  const int j = fjobs[f].info;
+  if (finfo[f] > 0) job_info[j] = finfo[f];
+  norms[j * 8 + 3] = -1.0;
 }
 
-void launch_fallback_status(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info, hipStream_t s) {
-  fallback_status_kernel<<<(nf + 255) / 256, 256, 0, s>>>(nf, fjobs, finfo, job_info);
+void launch_fallback_status(int nf, const JobDesc* fjobs, const int32_t* finfo, int32_t* job_info, double* norms,
+                            hipStream_t s) {
+  fallback_status_kernel<<<(nf + 255) / 256, 256, 0, s>>>(nf, fjobs, finfo, job_info, norms);
 }
 
 void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double tol, int32_t* done, int last,

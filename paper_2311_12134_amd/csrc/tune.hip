@@ -95,7 +95,7 @@ int update_autotune(int precision, int kind, int npad, int batch, hipStream_t s,
     tune_fill_kernel<float2><<<(unsigned)((n + 255) / 256), 256, 0, s>>>((float2*)tb.a, n, 1.0f / (float)npad);
   const int kd = kind == 1 ? 2 * NB : NB;
   const int rows = npad - kd, cols = kind == 1 ? rows : NB, c_end = kind == 1 ? 0 : 2 * NB;
-  const int nv = f64 ? gemm_f64_variants() : gemm_f32_variants();
+  const int nv = f64 ? gemm_f64_variants() : gemm_f32_variants_all();
   *best = -1;
   for (int v = 0; v < nv; ++v) {
     const float t = tb.time(
@@ -103,7 +103,7 @@ int update_autotune(int precision, int kind, int npad, int batch, hipStream_t s,
           if (f64)
             launch_gemm_f64_variant(v, tb.jd, batch, rows, cols, 0, kd, kd, kd, c_end, (double2*)tb.a, s);
           else
-            launch_gemm_f32(v, tb.jd, batch, rows, cols, 0, kd, kd, kd, c_end, (float2*)tb.a, s);
+            launch_gemm_f32_any(v, tb.jd, batch, rows, cols, 0, kd, kd, kd, c_end, (float2*)tb.a, s);
         },
         s);
     if (t < 0.f) return -1;
