@@ -239,7 +239,8 @@ def tune_all(ctx, npads, batch=256):
         rec.append(entry)
         log("autotuned bucket %d (npad %d): %s" % (b, n, {k: entry[k]["best"] for k in
                                                          ("f32_wide", "f32_narrow", "f64_wide", "f64_narrow")}))
-    thr, ms = ctx.autotune_kernel("f32_panel", batch=batch)
+    # the panel runs one workgroup per system, so its batch must fill the chip several times over
+    thr, ms = ctx.autotune_kernel("f32_panel", batch=8 * batch)
     log("autotuned split-mode panel threshold: %d rows %s" % (thr, [round(m, 3) for m in ms]))
     return {"batch": batch, "buckets": rec,
             "panel_small_rows": {"best": thr, "ms_256_512_768_small_large": [round(m, 3) for m in ms]}}
@@ -277,7 +278,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gemm-tiling", type=int, default=-1,
                     help="explicit tiling of the split-mode wide trailing update (-1: the autotuned one)")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default kernel choices")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="no autotuning: the library's defaults, or the tuning cache named by LSMS_TUNE_CACHE")
+    ap.add_argument("--save-tuning", default=None,
+                    help="write the autotuned kernel choices to this tuning cache (lsms_tuning_save)")
     ap.add_argument("--graphs", action=argparse.BooleanOptionalAction, default=True,
                     help="time the steps with each wave's factorization + first solve replayed from HIP graphs "
                          "(default); the trailing update's launch times then come from a second, eager timed "
@@ -298,6 +302,9 @@ def main():
     ap.add_argument("--workspace-frac", type=float, default=0.8,
                     help="wave workspace as a fraction of free HBM after the inputs are allocated "
                          "(the library's own default is 0.6, which leaves more room for the caller)")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="print the device's sustained MFMA, FP64 FMA and HBM rates (lsms_peak_probe) as one "
+                         "JSON line and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device copy before the timed region (scale for HBM counters)")
     args = ap.parse_args()
@@ -309,6 +316,15 @@ def main():
     import torch
     import paper_2311_12134_amd as P
     import synthetic
+
+    if args.peak_probe:
+        ctx = P.Context(0)
+        units = {"mfma_f64": "TFLOP/s", "mfma_f32": "TFLOP/s", "mfma_f32_32x32x2": "TFLOP/s", "fma_f64": "TFLOP/s",
+                 "copy": "GB/s (read + written)", "write": "GB/s", "read": "GB/s"}
+        res = {k: {"value": ctx.peak_probe(k), "unit": u} for k, u in units.items()}
+        ctx.close()
+        print(json.dumps(res), flush=True)
+        return
 
     if args.paper_scale_only:
         ctx = P.Context(0)
@@ -352,6 +368,8 @@ def main():
     npads = sorted({int(-(-16 * int(m) // 64) * 64) for m in np.diff(liz.ptr) if m > 0})
     if not args.no_autotune:
         tune = tune_all(ctx, npads)
+        if args.save_tuning:
+            ctx.tuning_save(args.save_tuning)
 
     def tiling_in_effect(precision):
         """The wide-update tiling the library picks for the workload's largest systems."""

@@ -440,8 +440,9 @@ int lsms_kernel_stats(lsms_ctx* ctx, int kind, double* total_ms, int64_t* launch
  * rates can be read: `what` 0 FP64 matrix cores (v_mfma_f64_16x16x4), 1 FP32 matrix cores
  * (16x16x4), 2 FP32 matrix cores (32x32x2), all in TFLOP/s of independent instruction
  * streams filling every compute unit; 3 FP64 vector FMA (TFLOP/s); 4 a 1 GiB device-to-device
- * copy (GB/s, bytes read plus written).  *value receives the best of three timed launches.
- * Allocates and frees its buffers (2 GiB for the copy); synchronous on hip_stream.
+ * copy (GB/s, bytes read plus written); 5 writes of 1 GiB; 6 reads of 1 GiB (GB/s).  *value
+ * receives the best of three timed launches.  Allocates and frees its buffers (2 GiB for the
+ * bandwidth probes); synchronous on hip_stream.
  * LSMS_E_ARG for an unknown probe, LSMS_E_DEVICE on a HIP error.
  */
 int lsms_peak_probe(lsms_ctx* ctx, int what, double* value, void* hip_stream);

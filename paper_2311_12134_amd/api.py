@@ -280,7 +280,7 @@ class Context:
         n = {"f32_wide": 12, "f32_narrow": 12, "f64_wide": 6, "f64_narrow": 6, "f32_panel": 6}[what]
         return best.value, [float(x) for x in ms[:n]]
 
-    PROBES = {"mfma_f64": 0, "mfma_f32": 1, "mfma_f32_32x32x2": 2, "fma_f64": 3, "copy": 4}
+    PROBES = {"mfma_f64": 0, "mfma_f32": 1, "mfma_f32_32x32x2": 2, "fma_f64": 3, "copy": 4, "write": 5, "read": 6}
 
     def peak_probe(self, what):
         """lsms_peak_probe: the device's sustained rate for one instruction stream (TFLOP/s) or

@@ -1250,7 +1250,7 @@ extern "C" int lsms_autotune_kernel(lsms_ctx* ctx, int what, int npad, int batch
 
 extern "C" int lsms_peak_probe(lsms_ctx* ctx, int what, double* value, void* hip_stream) {
   if (!ctx || !value) return fail(LSMS_E_ARG, "NULL argument");
-  if (what < 0 || what > 4) return fail(LSMS_E_ARG, "unknown probe %d", what);
+  if (what < 0 || what > 6) return fail(LSMS_E_ARG, "unknown probe %d", what);
   HIP_TRY(hipSetDevice(ctx->device));
   if (peak_probe(what, ctx->cu_count, (hipStream_t)hip_stream, value) != 0)
     return fail(LSMS_E_DEVICE, "probe %d failed: %s", what, hipGetErrorString(hipGetLastError()));

@@ -88,8 +88,23 @@ __global__ __launch_bounds__(256) void probe_copy_kernel(const float4* __restric
     dst[i] = src[i];
 }
 
+__global__ __launch_bounds__(256) void probe_fill_kernel(float4* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = make_float4((float)i, 0.f, 0.f, 1.f);
+}
+
+__global__ __launch_bounds__(256) void probe_read_kernel(const float4* __restrict__ src, int64_t n, float* out) {
+  float s = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 v = src[i];
+    s += v.x + v.y + v.z + v.w;
+  }
+  if (s == 12345.678f) out[0] = s;  // keeps the loads; never true for the filled values
+}
+
 // what: 0 FP64 MFMA 16x16x4, 1 FP32 MFMA 16x16x4, 2 FP32 MFMA 32x32x2 (TFLOP/s), 3 FP64
-// vector FMA (TFLOP/s), 4 device-to-device copy of 1 GiB (GB/s, bytes read + written).
+// vector FMA (TFLOP/s), 4 device-to-device copy of 1 GiB (GB/s, bytes read + written),
+// 5 writes of 1 GiB, 6 reads of 1 GiB (GB/s).
 // Best of three timed launches after one warm-up; returns 0, or -1 on a HIP error.
 int peak_probe(int what, int cu_count, hipStream_t s, double* value) {
   const int blocks = cu_count * 4;
@@ -99,7 +114,7 @@ int peak_probe(int what, int cu_count, hipStream_t s, double* value) {
   int rc = -1;
   const int64_t copy_elems = (1ll << 30) / 16;
   if (hipMalloc((void**)&out, (size_t)blocks * 256 * sizeof(double)) != hipSuccess) return -1;
-  if (what == 4 && hipMalloc((void**)&buf, (size_t)copy_elems * 2 * 16) != hipSuccess) {
+  if (what >= 4 && hipMalloc((void**)&buf, (size_t)copy_elems * 2 * 16) != hipSuccess) {
     hipFree(out);
     return -1;
   }
@@ -111,7 +126,9 @@ int peak_probe(int what, int cu_count, hipStream_t s, double* value) {
         case 1: probe_mfma_f32_kernel<<<blocks, 256, 0, s>>>(iters, out); break;
         case 2: probe_mfma_f32_32_kernel<<<blocks, 256, 0, s>>>(iters, out); break;
         case 3: probe_fma_f64_kernel<<<blocks, 256, 0, s>>>(iters, out); break;
-        default: probe_copy_kernel<<<cu_count * 16, 256, 0, s>>>(buf, buf + copy_elems, copy_elems);
+        case 4: probe_copy_kernel<<<cu_count * 16, 256, 0, s>>>(buf, buf + copy_elems, copy_elems); break;
+        case 5: probe_fill_kernel<<<cu_count * 16, 256, 0, s>>>(buf, copy_elems); break;
+        default: probe_read_kernel<<<cu_count * 16, 256, 0, s>>>(buf, copy_elems, (float*)out);
       }
     };
     // work per launch: waves x iterations x instructions x flops per instruction
@@ -122,8 +139,10 @@ int peak_probe(int what, int cu_count, hipStream_t s, double* value) {
       case 1: work = waves * iters * PROBE_CHAINS * (2.0 * 16 * 16 * 4); break;
       case 2: work = waves * iters * 4 * (2.0 * 32 * 32 * 2); break;
       case 3: work = waves * 64.0 * iters * PROBE_CHAINS * 2.0; break;
-      default: work = 2.0 * 16.0 * (double)copy_elems;
+      case 4: work = 2.0 * 16.0 * (double)copy_elems; break;
+      default: work = 16.0 * (double)copy_elems;
     }
+    if (what == 6) probe_fill_kernel<<<cu_count * 16, 256, 0, s>>>(buf, copy_elems);
     launch();
     float best = 1e30f;
     bool ok = hipGetLastError() == hipSuccess;
@@ -136,7 +155,7 @@ int peak_probe(int what, int cu_count, hipStream_t s, double* value) {
       best = std::min(best, ms);
     }
     if (ok) {
-      *value = work / (best * 1e-3) / (what == 4 ? 1e9 : 1e12);
+      *value = work / (best * 1e-3) / (what >= 4 ? 1e9 : 1e12);
       rc = 0;
     }
   }
