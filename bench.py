@@ -216,7 +216,10 @@ F32_TILINGS = {0: "gemm_f32_3m_kernel", 1: "gemm_f32_3m_tiled<64,64,32,32>", 2: 
                5: "gemm_f32_3m_tiled<128,128,64,64,xcd>", 6: "gemm_f32_3m_tiled<128,128,64,64>",
                7: "gemm_f32_3m_tiled<64,64,32,32,xcd,C prefetch>", 8: "gemm_f32_3m_tiled<64,64,32,32,xcd,K32>",
                9: "gemm_f32_3m_tiled<64,64,32,32,xcd,32x32x2>", 10: "gemm_f32_3m_persist<64,64,32,32,xcd>",
-               11: "gemm_f32_3m_persist<64,64,32,32,xcd,C prefetch>"}
+               11: "gemm_f32_3m_persist<64,64,32,32,xcd,C prefetch>", 12: "gemm_f32_3m_big<128,64>",
+               13: "gemm_f32_3m_big<64,128>", 14: "gemm_f32_3m_big<128,128>",
+               15: "gemm_f32_3m_big<64,64,prefetch 2>", 16: "gemm_f32_3m_big<64,128,prefetch 2>",
+               17: "gemm_f32_3m_stream", 18: "gemm_f32_3m_stream<C prefetch>"}
 F64_TILINGS = {0: "gemm_f64_kernel", 1: "gemm_f64_tiled<64,64,32,32,xcd,K8>", 2: "gemm_f64_tiled<32,64,16,32,xcd,K8>",
                3: "gemm_f64_tiled<128,64,64,32,xcd,K8>", 4: "gemm_f64_tiled<64,128,32,64,xcd,K8>",
                5: "gemm_f64_tiled<64,64,32,32,K8>"}
@@ -278,6 +281,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gemm-tiling", type=int, default=-1,
                     help="explicit tiling of the split-mode wide trailing update (-1: the autotuned one)")
+    ap.add_argument("--group-f32", type=int, default=-1,
+                    help="panels per group of the split-mode LU, 2 .. 4 (-1: the library default or the tuning cache's)")
+    ap.add_argument("--group-f64", type=int, default=-1,
+                    help="panels per group of the FP64 LU, 2 .. 4 (-1: the library default or the tuning cache's)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="no autotuning: the library's defaults, or the tuning cache named by LSMS_TUNE_CACHE")
     ap.add_argument("--save-tuning", default=None,
@@ -364,6 +371,10 @@ def main():
     ctx = P.Context(0, workspace_limit=ws)
     ctx.set_pipeline(args.pipeline)
     ctx.set_gemm_tiling(args.gemm_tiling)
+    if args.group_f32 > 0:
+        ctx.set_knob("group_f32", args.group_f32)
+    if args.group_f64 > 0:
+        ctx.set_knob("group_f64", args.group_f64)
     tune = None
     npads = sorted({int(-(-16 * int(m) // 64) * 64) for m in np.diff(liz.ptr) if m > 0})
     if not args.no_autotune:
@@ -377,7 +388,7 @@ def main():
             return args.gemm_tiling
         b = (npads[-1] - 1) // 256
         t = int(ctx.tuning_table("f32_wide" if precision == "split" else "f64_wide")[b])
-        return t if t >= 0 else (2 if precision == "split" else 1)
+        return t if t >= 0 else 1  # the library's default for both precisions
 
     def step(i, precision, out):
         eta = etas[i % len(etas)]
@@ -443,6 +454,7 @@ def main():
                       % (w["name"], w["lattice"], n_atoms, int(n_true.min() / 16), int(n_true.max() / 16),
                          w["e_fermi"], etas),
                       "precision": args.precision, "gemm_tiling": tiling, "graphs": args.graphs,
+                      "panels_per_group": ctx.knob("group_f32" if args.precision == "split" else "group_f64"),
                       "pipeline": args.pipeline, "workspace_frac": args.workspace_frac or 0.6,
                       "parallelism": "single GPU, all atoms batched"},
            "path_tflops_alg": alg_flops_step * args.steps / elapsed / 1e12,

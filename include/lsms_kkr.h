@@ -270,8 +270,9 @@ int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t* n, void* 
  * the caller's stream (0 switches recording off).  lsms_kernel_stats waits for the
  * recorded events and returns, over the launches of the given kind, the summed launch
  * time (ms), the number of launches, their algorithmic flops and their algorithmic bytes.
- * kind 1 selects the wide updates (K = 128, the trailing matrix below a pair of panels),
- * kind 0 the narrow updates of a pair's second panel (K = 64), -1 both.  A launch updates,
+ * kind 1 selects the wide updates (K = 64 G, the trailing matrix past a group of G panels,
+ * LSMS_TUNE_GROUP_F32 / _F64), kind 0 the narrow updates of a panel's columns within its
+ * group (K = 64, 128, .. 64 (G - 1)), -1 both.  A launch updates,
  * in every system, the unpadded block of m rows and c columns: 8 m c K flops (the
  * standard complex count; the split mode executes 3/4 of it on the matrix cores) and
  * es (m K + K c + 2 m c) bytes, es = 8 (split) or 16 (FP64).  All outputs are host
@@ -281,17 +282,20 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
 
 /*
  * Tuning of the split-mode trailing update (the FP32 matrix-core part of the LU of Eq. (3)).
- * knob LSMS_TUNE_GEMM_F32 selects the tiling, 0 .. LSMS_GEMM_F32_VARIANTS - 1, or -1 for
- * the library's default (0: 64 x 64 tiles; 1, 2: 64 x 64 pipelined through two LDS stages,
+ * knob LSMS_TUNE_GEMM_F32 selects the tiling of the wide update, 0 .. LSMS_GEMM_F32_VARIANTS - 1,
+ * or -1 for the autotuned choice or the library's default, 1 (0: 64 x 64 tiles; 1, 2: 64 x 64 pipelined through two LDS stages,
  * 2 with an XCD-aware workgroup order; 3 - 6: 128-row / 128-column tiles; 7: as 2 with the C
  * tile prefetched early; 8: as 2 with K chunks of 32; 9: as 2 on FP32 MFMA 32x32x2; 10: as 2 in a
  * persistent grid of resident workgroups that loops over the tiles; 11: as 10 with the C tile
- * prefetched early); every
+ * prefetched early; 12, 13, 14: 128 x 64, 64 x 128 and 128 x 128 tiles of 8, 8 and 16 waves of
+ * 32 x 32; 15, 16: 64 x 64 and 64 x 128 tiles with the K chunks prefetched two ahead; 17, 18:
+ * the streaming persistent form, whose next tile's first K chunk is loaded during the current
+ * tile's last one, without and with the C tile loaded early); every
  * tiling computes the same update (results may differ in FP32 rounding order only).  Host-side setting of the context, no device work; returns
  * LSMS_E_ARG for an unknown knob or value.  lsms_get_tuning reports the tiling in effect.
  */
 #define LSMS_TUNE_GEMM_F32 0
-#define LSMS_GEMM_F32_VARIANTS 12
+#define LSMS_GEMM_F32_VARIANTS 19
 /*
  * knob LSMS_TUNE_GRAPHS (0 or 1, default 0): with 1, lsms_tau_solve captures each wave's
  * factorization and first solve (a fixed sequence of a few hundred launches) into a HIP
@@ -322,7 +326,7 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
 #define LSMS_TUNE_TSLU_CHUNK 3
 /*
  * knob LSMS_TUNE_LOOKAHEAD (0 or 1, default 0): with 1, lsms_tau_solve factors the first
- * panel of the next pair on a second stream of the context (default priority) while the
+ * panel of the next group on a second stream of the context (default priority) while the
  * rest of the current trailing update runs on the caller's stream; events order them and
  * the call's work is complete on the caller's stream when its last launch is.  Results
  * are bitwise those of 0.  Not used inside captured graphs (LSMS_TUNE_GRAPHS).
@@ -364,7 +368,8 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * LSMS_TUNE_GEMM_F64 and LSMS_TUNE_GEMM_F64_NARROW (FP64 mode, 0 .. LSMS_GEMM_F64_VARIANTS - 1:
  * 0 the single-buffered 64 x 64 kernel; 1 64 x 64 with two LDS stages of K = 8 and the XCD
  * order; 2 32 x 64; 3 128 x 64; 4 64 x 128; 5 as 1 without the XCD order): the
- * tilings of the narrow (K = 64, a pair's second panel) and wide (K = 128) trailing updates.
+ * tilings of the narrow (a panel's 64 columns within its group, K < 64 x group) and wide
+ * (K = 64 x group) trailing updates.
  * knob LSMS_TUNE_PANEL_SMALL_ROWS (0 .. 768): split-mode panels of at most this many rows run
  * in 256-thread workgroups with 8-wide leaves, taller ones in 512-thread workgroups.
  * For every such choice (and LSMS_TUNE_GEMM_F32), -1 (the initial value) means: the
@@ -376,6 +381,14 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
 #define LSMS_TUNE_GEMM_F64 8
 #define LSMS_TUNE_GEMM_F64_NARROW 9
 #define LSMS_TUNE_PANEL_SMALL_ROWS 10
+/* knobs LSMS_TUNE_GROUP_F32 (split mode) and LSMS_TUNE_GROUP_F64 (FP64 mode): panels per
+ * group of the blocked LU, 2 .. 4, or -1 for the default (4).  The trailing matrix is updated
+ * once per group with K = 64 x group (the wide update), the panels inside a group left-looking
+ * (the narrow updates, K < 64 x group); larger groups move work from the wide update, whose
+ * efficiency grows with K, to the narrow updates and the interchange kernel.  The autotuner
+ * times the shapes of the group in effect when it runs. */
+#define LSMS_TUNE_GROUP_F32 11
+#define LSMS_TUNE_GROUP_F64 12
 #define LSMS_GEMM_F64_VARIANTS 6
 int lsms_set_tuning(lsms_ctx* ctx, int knob, int value);
 int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
@@ -384,9 +397,10 @@ int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
  * Autotuner over the kernels of the blocked LU (the inverse of Eq. (3), the dominant cost of
  * the method, Sec. II.A).  `what` selects the target:
  *   LSMS_AUTOTUNE_F32_WIDE / LSMS_AUTOTUNE_F64_WIDE: every tiling of the split-mode / FP64
- *     wide trailing update (K = 128 over the trailing (npad - 128)^2 block of an LU of size npad);
+ *     wide trailing update (K = 64 G over the trailing (npad - 64 G)^2 block of an LU of size
+ *     npad, G the precision's panels per group in effect);
  *   LSMS_AUTOTUNE_F32_NARROW / LSMS_AUTOTUNE_F64_NARROW: every tiling of the narrow update
- *     (K = 64 over (npad - 64) rows x 64 columns);
+ *     of a group's last panel (K = 64 (G - 1) over (npad - 64 (G - 1)) rows x 64 columns);
  *   LSMS_AUTOTUNE_F32_PANEL: the two split-mode panel variants at heights 256, 512 and 768
  *     (npad ignored); ms[2 h + v] receives variant v (0: 256 threads, 8-wide leaves; 1: 512
  *     threads) at height h, and the context's panel threshold becomes the largest height at
@@ -396,7 +410,7 @@ int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
  * it and ms (NULL, or host [ms_len >= number of tilings]) the best-of-three launch time of
  * each tiling.  Each call allocates and frees a synthetic batch of `batch` systems (bounded
  * pseudo-random values) and is synchronous on hip_stream.  npad: a multiple of 64 in
- * (128, 16384]; batch in [1, 65535].  LSMS_E_ARG for bad sizes or target, LSMS_E_NOMEM if the
+ * (64 G, 16384]; batch in [1, 65535].  LSMS_E_ARG for bad sizes or target, LSMS_E_NOMEM if the
  * batch cannot be allocated.  Explicit lsms_set_tuning choices take precedence over these.
  */
 #define LSMS_AUTOTUNE_F32_WIDE 0
@@ -412,8 +426,10 @@ int lsms_autotune_kernel(lsms_ctx* ctx, int what, int npad, int batch, int* best
 int lsms_tuning_table(lsms_ctx* ctx, int what, int* out);
 /*
  * Tuning cache: lsms_tuning_save writes every autotuned choice of the context to a text file
- * (first line "lsms-tune 1 <architecture>/<compute units>"), lsms_tuning_load replaces the
- * context's autotuned choices by a file's (LSMS_E_STATE if it was written on another kind of
+ * (first line "lsms-tune 1 <architecture>/<compute units>"), with the explicit panels-per-group
+ * settings (LSMS_TUNE_GROUP_F32 / _F64) the tilings were timed with; lsms_tuning_load replaces
+ * the context's autotuned choices by a file's and applies its group settings (LSMS_E_STATE if
+ * it was written on another kind of
  * device, LSMS_E_ARG if it cannot be read or parsed; the context is unchanged on error).
  * lsms_create loads the file named by the environment variable LSMS_TUNE_CACHE when it
  * exists and was written on this kind of device.  Host-side, no device work.
@@ -423,11 +439,12 @@ int lsms_tuning_load(lsms_ctx* ctx, const char* path);
 
 /*
  * Autotuner for the split-mode trailing update: times every tiling on the widest update
- * of an LU of size npad (K = 128 over the trailing (npad - 128)^2 block) for a synthetic
+ * of an LU of size npad (K = 64 G over the trailing (npad - 64 G)^2 block, G the split
+ * mode's panels per group) for a synthetic
  * batch of `batch` systems (bounded random FP32 values, allocated and freed by the call,
  * npad^2 * 8 * batch bytes), then makes the fastest the context's tiling (as
  * lsms_set_tuning would).  *best receives it; ms (NULL, or host [LSMS_GEMM_F32_VARIANTS])
- * the best-of-three launch time of each tiling.  npad: a multiple of 64 in (128, 4096];
+ * the best-of-three launch time of each tiling.  npad: a multiple of 64 in (64 G, 4096];
  * batch in [1, 65535].  Synchronous on hip_stream; LSMS_E_ARG for bad sizes,
  * LSMS_E_NOMEM if the batch cannot be allocated.
  */

@@ -262,22 +262,23 @@ class Context:
         """Time every split-mode tiling for systems of padded size npad on a synthetic batch
         and adopt the fastest; returns (best tiling, [ms per tiling])."""
         best = ctypes.c_int(-1)
-        ms = (ctypes.c_float * 12)()
+        ms = (ctypes.c_float * 19)()
         check(lib().lsms_autotune(self._h, int(npad), int(batch), ctypes.byref(best), ms, _stream()))
         return best.value, [float(x) for x in ms]
 
     AUTOTUNE_TARGETS = {"f32_wide": 0, "f32_narrow": 1, "f64_wide": 2, "f64_narrow": 3, "f32_panel": 4}
-    KNOBS = {"f32_wide": 0, "f32_narrow": 7, "f64_wide": 8, "f64_narrow": 9, "panel_small_rows": 10}
+    KNOBS = {"f32_wide": 0, "f32_narrow": 7, "f64_wide": 8, "f64_narrow": 9, "panel_small_rows": 10,
+             "group_f32": 11, "group_f64": 12}
 
     def autotune_kernel(self, what, npad=0, batch=256):
         """lsms_autotune_kernel: time every variant of one LU kernel (see AUTOTUNE_TARGETS) and
         record the fastest for npad's bucket (the panel target: the small-panel threshold).
         Returns (best, [ms per variant])."""
         best = ctypes.c_int(-1)
-        ms = (ctypes.c_float * 16)()
+        ms = (ctypes.c_float * 19)()
         check(lib().lsms_autotune_kernel(self._h, self.AUTOTUNE_TARGETS[what], int(npad), int(batch),
-                                         ctypes.byref(best), ms, 16, _stream()))
-        n = {"f32_wide": 12, "f32_narrow": 12, "f64_wide": 6, "f64_narrow": 6, "f32_panel": 6}[what]
+                                         ctypes.byref(best), ms, 19, _stream()))
+        n = {"f32_wide": 19, "f32_narrow": 19, "f64_wide": 6, "f64_narrow": 6, "f32_panel": 6}[what]
         return best.value, [float(x) for x in ms[:n]]
 
     PROBES = {"mfma_f64": 0, "mfma_f32": 1, "mfma_f32_32x32x2": 2, "fma_f64": 3, "copy": 4, "write": 5, "read": 6}

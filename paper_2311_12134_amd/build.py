@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "liblsms_kkr.so")
 OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-DEVICE_SOURCES = ["assemble.hip", "lu.hip", "gemm.hip", "gemm64.hip", "gemm_persist.hip", "tune.hip", "probe.hip", "solve.hip", "refine.hip", "kubo.hip", "adjoint.hip"]
+DEVICE_SOURCES = ["assemble.hip", "lu.hip", "gemm.hip", "gemm64.hip", "gemm_persist.hip", "gemm_wide.hip", "tune.hip", "probe.hip", "solve.hip", "refine.hip", "kubo.hip", "adjoint.hip"]
 HOST_SOURCES = ["host.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-I" + os.path.join(HERE, "..", "include"),

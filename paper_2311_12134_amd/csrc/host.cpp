@@ -105,6 +105,8 @@ struct lsms_ctx {
   int gemm_f64 = -1;
   int gemm_f64_narrow = -1;
   int panel_small_rows = -1;
+  int group_f32 = -1;  // panels per group of the split-mode LU (-1: the default)
+  int group_f64 = -1;  // the same for the FP64 LU
   // autotuned choices: tuned[precision][kind][bucket] (kind 0 narrow, 1 wide), -1 unset;
   // tuned_panel_rows: split-mode panels up to this height take the small variant
   int8_t tuned[2][2][LSMS_TUNE_BUCKETS];
@@ -136,7 +138,8 @@ struct lsms_ctx {
 };
 
 // Library defaults where neither an explicit choice nor an autotuned one exists.
-static constexpr int kDefaultF32Wide = 2, kDefaultF32Narrow = 2, kDefaultF64Wide = 1, kDefaultF64Narrow = 1;
+static constexpr int kDefaultF32Wide = 1, kDefaultF32Narrow = 7, kDefaultF64Wide = 1, kDefaultF64Narrow = 1;
+static constexpr int kDefaultGroupF32 = 4, kDefaultGroupF64 = 4;
 
 // Tiling of the split-mode trailing update in effect for a context (explicit or default).
 static int gemm_f32_variant(const lsms_ctx* ctx) { return ctx->gemm_f32 >= 0 ? ctx->gemm_f32 : kDefaultF32Wide; }
@@ -161,6 +164,8 @@ static Tiling pick_tiling(const lsms_ctx* c, int precision, int npad) {
   t.panel_small_rows = c->panel_small_rows >= 0 ? c->panel_small_rows
                        : c->tuned_panel_rows >= 0 ? c->tuned_panel_rows
                                                   : PANEL_SMALL_ROWS;
+  t.group = p == 1 ? (c->group_f32 > 0 ? c->group_f32 : kDefaultGroupF32)
+                   : (c->group_f64 > 0 ? c->group_f64 : kDefaultGroupF64);
   return t;
 }
 
@@ -177,6 +182,7 @@ struct lsms_factors {
   double2 kp{0, 0}, km{0, 0};
   const int32_t* liz_atom = nullptr;     // the forward call's arrays, for a consistency check
   int64_t total_members = 0;
+  int group = 2;  // panels per group of the factorization (the solves must match)
 };
 
 static int ensure_dev(DevBuf& b, size_t bytes, hipStream_t s) {
@@ -673,7 +679,7 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
   auto issue = [&](hipStream_t q, GemmProfiler* pr) {
     if (precision == LSMS_FP64) {
       lu_factor_f64(jd, nj, npad_max, (double2*)abuf, piv, jinfo, q, pr, tiling, ts, side);
-      lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, q);
+      lu_solve_f64(jd, nj, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, tiling.group, q);
     } else {
       if (sym)
         ldlt_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, variant, NB, ctx->ldlt.p);
@@ -681,7 +687,7 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
         lu_factor_f32(jd, nj, npad_max, (float2*)abuf, piv, jinfo, q, pr, tiling, ts, side);
       // the first solve in FP32 on a rounded copy of the right-hand side (refined below)
       launch_x32(jd, nj, npad_max, 0, xbuf, xbuf, nullptr, q);
-      lu_solve_f32_single(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, nullptr, q);
+      lu_solve_f32_single(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, nullptr, tiling.group, q);
       launch_x32(jd, nj, npad_max, 1, nullptr, xbuf, nullptr, q);
     }
   };
@@ -691,6 +697,7 @@ static int factor_and_solve(lsms_ctx* ctx, int precision, const JobDesc* jd, int
     return LSMS_OK;
   }
   const std::vector<intptr_t> key = {precision, nj, npad_max, variant, tiling.narrow, tiling.panel_small_rows,
+                                     tiling.group,
                                      (intptr_t)jd, (intptr_t)abuf,
                                      (intptr_t)piv, (intptr_t)jinfo, (intptr_t)xbuf, ts.chunk,
                                      (intptr_t)ts.base, sym ? 1 : 0, (intptr_t)ctx->ldlt.p};
@@ -817,6 +824,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     fac.reset(new lsms_factors());
     fac->ctx = ctx;
     fac->precision = precision;
+    fac->group = pick_tiling(ctx, precision, 0).group;
     fac->n_atoms = n_atoms;
     fac->kp = kp;
     fac->km = km;
@@ -958,7 +966,8 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
         if (last || left == 0) break;
         // correction: FP32 solve on the rounded residual, added to the FP64 solution
         launch_x32(jd, nj, npad_max, 0, rbuf, xbuf, jdone, s);
-        lu_solve_f32_single(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, jdone, s);
+        lu_solve_f32_single(jd, nj, npad_max, (const float2*)abuf, piv, xbuf, jdone,
+                            pick_tiling(ctx, LSMS_SPLIT, npad_max).group, s);
         launch_x32(jd, nj, npad_max, 2, nullptr, xbuf, jdone, s);
       }
       if (left > 0 || sym) {
@@ -989,8 +998,9 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
           TallScratch fts;
           rc = tall_scratch(ctx, nf, fpad, &fts, s);
           if (rc) return rc;
-          lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s, nullptr, pick_tiling(ctx, LSMS_FP64, fpad), fts);
-          lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, s);
+          const Tiling ft = pick_tiling(ctx, LSMS_FP64, fpad);
+          lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s, nullptr, ft, fts);
+          lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, ft.group, s);
           launch_fallback_status(nf, fjd, finfo, jinfo, jnorm, s);
           // the fallback's job list is context scratch: done before another wave reuses it
           HIP_TRY(hipStreamSynchronize(s));
@@ -1142,6 +1152,12 @@ extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
                                        : ctx->gemm_f64_narrow) = value;
     return LSMS_OK;
   }
+  if (knob == LSMS_TUNE_GROUP_F32 || knob == LSMS_TUNE_GROUP_F64) {
+    if (value != -1 && (value < 2 || value > GROUP_MAX))
+      return fail(LSMS_E_ARG, "panels per group %d outside [2, %d] (or -1)", value, GROUP_MAX);
+    (knob == LSMS_TUNE_GROUP_F32 ? ctx->group_f32 : ctx->group_f64) = value;
+    return LSMS_OK;
+  }
   if (knob == LSMS_TUNE_PANEL_SMALL_ROWS) {
     if (value < -1 || value > PANEL_SMALL_ROWS)
       return fail(LSMS_E_ARG, "panel height %d outside [-1, %d]", value, PANEL_SMALL_ROWS);
@@ -1171,6 +1187,11 @@ extern "C" int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value) {
                  : 0;
     return LSMS_OK;
   }
+  if (knob == LSMS_TUNE_GROUP_F32 || knob == LSMS_TUNE_GROUP_F64) {
+    const int v = knob == LSMS_TUNE_GROUP_F32 ? ctx->group_f32 : ctx->group_f64;
+    *value = v > 0 ? v : (knob == LSMS_TUNE_GROUP_F32 ? kDefaultGroupF32 : kDefaultGroupF64);
+    return LSMS_OK;
+  }
   if (knob == LSMS_TUNE_GEMM_F32_NARROW || knob == LSMS_TUNE_GEMM_F64 || knob == LSMS_TUNE_GEMM_F64_NARROW ||
       knob == LSMS_TUNE_PANEL_SMALL_ROWS) {
     *value = knob == LSMS_TUNE_GEMM_F32_NARROW ? ctx->gemm_f32_narrow
@@ -1192,7 +1213,11 @@ extern "C" int lsms_autotune(lsms_ctx* ctx, int npad, int batch, int* best, floa
   HIP_TRY(hipSetDevice(ctx->device));
   float t[LSMS_GEMM_F32_VARIANTS];
   int b = -1;
-  if (gemm_f32_autotune(npad, batch, (hipStream_t)hip_stream, t, &b) != 0 || b < 0)
+  const int group = pick_tiling(ctx, LSMS_SPLIT, npad).group;
+  if (npad <= group * NB)
+    return fail(LSMS_E_ARG, "npad %d has no wide update with %d panels per group (needs > %d)", npad, group,
+                group * NB);
+  if (update_autotune(1, 1, npad, batch, group, (hipStream_t)hip_stream, t, &b) != 0 || b < 0)
     return fail(LSMS_E_NOMEM, "autotuning batch of %d systems of size %d could not run", batch, npad);
   ctx->gemm_f32 = b;
   ctx->tuned[1][1][tune_bucket(npad)] = (int8_t)b;
@@ -1239,7 +1264,11 @@ extern "C" int lsms_autotune_kernel(lsms_ctx* ctx, int what, int npad, int batch
   if (ms && ms_len < nv) return fail(LSMS_E_ARG, "ms needs %d entries for this autotuner target", nv);
   std::vector<float> t(nv);
   int b = -1;
-  if (update_autotune(precision, kind, npad, batch, s, t.data(), &b) != 0 || b < 0)
+  const int group = pick_tiling(ctx, precision ? LSMS_SPLIT : LSMS_FP64, npad).group;
+  if (npad <= group * NB)
+    return fail(LSMS_E_ARG, "npad %d has no %s update with %d panels per group (needs > %d)", npad,
+                kind ? "wide" : "narrow", group, group * NB);
+  if (update_autotune(precision, kind, npad, batch, group, s, t.data(), &b) != 0 || b < 0)
     return fail(LSMS_E_NOMEM, "autotuning batch of %d systems of size %d could not run", batch, npad);
   ctx->tuned[precision][kind][tune_bucket(npad)] = (int8_t)b;
   *best = b;
@@ -1294,6 +1323,9 @@ extern "C" int lsms_tuning_save(lsms_ctx* ctx, const char* path) {
       for (int b = 0; b < LSMS_TUNE_BUCKETS; ++b)
         if (ctx->tuned[p][k][b] >= 0) std::fprintf(f, "update %d %d %d %d\n", p, k, b, (int)ctx->tuned[p][k][b]);
   if (ctx->tuned_panel_rows >= 0) std::fprintf(f, "panel %d\n", ctx->tuned_panel_rows);
+  // the panels per group the tilings were timed with (explicit settings only)
+  if (ctx->group_f64 > 0) std::fprintf(f, "group 0 %d\n", ctx->group_f64);
+  if (ctx->group_f32 > 0) std::fprintf(f, "group 1 %d\n", ctx->group_f32);
   const bool ok = std::ferror(f) == 0;
   std::fclose(f);
   return ok ? LSMS_OK : fail(LSMS_E_ARG, "writing %s failed", path);
@@ -1317,7 +1349,7 @@ extern "C" int lsms_tuning_load(lsms_ctx* ctx, const char* path) {
   }
   int8_t tuned[2][2][LSMS_TUNE_BUCKETS];
   std::memset(tuned, -1, sizeof(tuned));
-  int panel = -1;
+  int panel = -1, group[2] = {-1, -1};
   char word[32];
   while (std::fscanf(f, "%31s", word) == 1) {
     int p, k, b, v;
@@ -1327,6 +1359,9 @@ extern "C" int lsms_tuning_load(lsms_ctx* ctx, const char* path) {
       tuned[p][k][b] = (int8_t)v;
     } else if (std::strcmp(word, "panel") == 0 && std::fscanf(f, "%d", &v) == 1 && v >= 0 && v <= PANEL_SMALL_ROWS) {
       panel = v;
+    } else if (std::strcmp(word, "group") == 0 && std::fscanf(f, "%d %d", &p, &v) == 2 && p >= 0 && p < 2 &&
+               v >= 2 && v <= GROUP_MAX) {
+      group[p] = v;
     } else {
       std::fclose(f);
       return fail(LSMS_E_ARG, "malformed entry in %s", path);
@@ -1335,6 +1370,8 @@ extern "C" int lsms_tuning_load(lsms_ctx* ctx, const char* path) {
   std::fclose(f);
   std::memcpy(ctx->tuned, tuned, sizeof(tuned));
   ctx->tuned_panel_rows = panel;
+  if (group[0] > 0) ctx->group_f64 = group[0];
+  if (group[1] > 0) ctx->group_f32 = group[1];
   return LSMS_OK;
 }
 
@@ -1407,7 +1444,7 @@ extern "C" int lsms_kubo_sigma_grad(lsms_ctx* ctx, const lsms_factors* factors, 
   launch_zero(dphase, (int64_t)n_atoms * 4, s);
   launch_adjoint_rhs(factors->jobs_dev, nj, factors->npad_max, liz_atom, (const double2*)tau_plus,
                      (const double2*)tau_minus, species, n_species, (const double2*)J, dsigma, volume, xbuf, s);
-  lu_solve_f64(factors->jobs_dev, nj, factors->npad_max, abuf, piv, xbuf, 0, 32, 1, s);
+  lu_solve_f64(factors->jobs_dev, nj, factors->npad_max, abuf, piv, xbuf, 0, 32, 1, factors->group, s);
   launch_adjoint_contract(factors->jobs_dev, nj, factors->npad_max, liz_atom, phase, factors->kp, xbuf, dphase, s);
   HIP_TRY(hipGetLastError());
   return LSMS_OK;
@@ -1477,11 +1514,13 @@ extern "C" int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t
   launch_zero_i32(info, batch, s);
   launch_load_user(jd, batch, npad_max, aptr, bptr, nrhs, prec, abuf, xbuf, s);
   if (prec == LSMS_FP64) {
-    lu_factor_f64(jd, batch, npad_max, (double2*)abuf, piv, info, s, nullptr, pick_tiling(ctx, prec, npad_max), ts);
-    lu_solve_f64(jd, batch, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, s);
+    const Tiling tl = pick_tiling(ctx, prec, npad_max);
+    lu_factor_f64(jd, batch, npad_max, (double2*)abuf, piv, info, s, nullptr, tl, ts);
+    lu_solve_f64(jd, batch, npad_max, (const double2*)abuf, piv, xbuf, 0, 16, 0, tl.group, s);
   } else {
-    lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s, nullptr, pick_tiling(ctx, prec, npad_max), ts);
-    lu_solve_f32(jd, batch, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, s);
+    const Tiling tl = pick_tiling(ctx, prec, npad_max);
+    lu_factor_f32(jd, batch, npad_max, (float2*)abuf, piv, info, s, nullptr, tl, ts);
+    lu_solve_f32(jd, batch, npad_max, (const float2*)abuf, piv, xbuf, 0, 16, 0, tl.group, s);
   }
   launch_store_user(jd, batch, npad_max, bptr, nrhs, xbuf, s);
   HIP_TRY(hipGetLastError());

@@ -123,7 +123,8 @@ void launch_init_rhs(const JobDesc* jobs, int njobs, int npad_max, const int32_t
 struct GemmProfiler {
   const int* n_true = nullptr;
   virtual void before(hipStream_t s) = 0;
-  // kind 0: narrow update of a pair's second panel (K = NB); 1: wide update (K = 2 NB)
+  // kind 0: narrow update of a panel's columns within its group (K < G NB); 1: wide update
+  // (K = G NB, G panels per group)
   virtual void after(hipStream_t s, double alg_flops, double alg_bytes, int kind) = 0;
   virtual ~GemmProfiler() {}
 };
@@ -139,20 +140,26 @@ void launch_gemm_f64_variant(int variant, const JobDesc* jobs, int njobs, int ro
                              int r_begin, int c_begin, int c_end, double2* work, hipStream_t s);
 // Split-mode panels of at most this many rows use 256-thread workgroups with 8-wide leaves.
 constexpr int PANEL_SMALL_ROWS = 3 * 256;
-// Kernel choices of one LU: the tilings of the wide (K = 2 NB) and narrow (K = NB) trailing
-// updates, and the height up to which split-mode panels take the small-workgroup variant.
+// Panels per group of the blocked LU: 2 .. GROUP_MAX.
+constexpr int GROUP_MAX = 4;
+// Kernel choices of one LU: the panels per group (the big trailing update has K = group NB),
+// the tilings of the wide (K = group NB) and narrow (a panel's columns within its group,
+// K < group NB) trailing updates, and the height up to which split-mode panels take the
+// small-workgroup variant.
 struct Tiling {
   int wide = 0;
   int narrow = 0;
   int panel_small_rows = PANEL_SMALL_ROWS;
+  int group = 2;
 };
 // The split-mode panel at k = 0 in one of its two variants (autotuner; lu.hip).
 void launch_panel_f32_variant(int variant, const JobDesc* jobs, int njobs, int rows, float2* work, int32_t* piv,
                               int32_t* info, hipStream_t s);
-// Autotuner (tune.hip): precision 0 FP64, 1 split; kind 1 wide, 0 narrow.  ms[variant] gets
-// the best of three launches, *best the fastest; panel_autotune times the two split-mode
-// panel variants at one height (ms[2]).  Return 0 or -1 (allocation or launch failure).
-int update_autotune(int precision, int kind, int npad, int batch, hipStream_t s, float* ms, int* best);
+// Autotuner (tune.hip): precision 0 FP64, 1 split; kind 1 wide (K = group NB), 0 narrow
+// (64 columns, K = (group - 1) NB).  ms[variant] gets the best of three launches, *best the
+// fastest; panel_autotune times the two split-mode panel variants at one height (ms[2]).
+// Return 0 or -1 (allocation or launch failure).
+int update_autotune(int precision, int kind, int npad, int batch, int group, hipStream_t s, float* ms, int* best);
 int panel_autotune(int rows, int batch, hipStream_t s, float* ms);
 // Peak-rate probes (probe.hip); what as in lsms_peak_probe.  Returns 0 or -1.
 int peak_probe(int what, int cu_count, hipStream_t s, double* value);
@@ -161,9 +168,6 @@ int gemm_f32_variants();
 int gemm_f32_variants_all();
 void launch_gemm_f32_any(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                          int c_begin, int c_end, float2* work, hipStream_t s);
-// Times every FP32 tiling on a synthetic batch (batch systems of size npad, widest update);
-// ms[variant] receives the best of three launches, *best the fastest.  Returns 0 or -1.
-int gemm_f32_autotune(int npad, int batch, hipStream_t s, float* ms, int* best);
 void launch_gemm_f32(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                      int c_begin, int c_end, float2* work, hipStream_t s);
 void launch_gemm_f32_lower(const JobDesc* jobs, int njobs, int rows, int k, int kd, int rc_begin, float2* work,
@@ -198,16 +202,17 @@ void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, i
 size_t ldlt_scratch_bytes(int njobs);
 void ldlt_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
                      hipStream_t s, GemmProfiler* prof, int gemm_variant, int tall_rows, void* scratch);
-// Solve with the factors: trans = 0 solves M X = B, trans = 1 solves M^T X = B (in place on X).
+// Solve with the factors: trans = 0 solves M X = B, trans = 1 solves M^T X = B (in place on X);
+// group = the panels per group the factorization used.
 void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
-                  double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);
+                  double2* x, int64_t x_col_off, int nrhs, int trans, int group, hipStream_t s);
 void lu_solve_f32(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
-                  double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s);
+                  double2* x, int64_t x_col_off, int nrhs, int trans, int group, hipStream_t s);
 // The split-mode refinement's solves (16 columns) in FP32 on the FP32 copy of the right-hand
 // side in columns 16 .. 23 of each solution row (launch_x32 fills and drains it); jobs
 // flagged in skip[] (may be null) are left alone.
 void lu_solve_f32_single(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
-                         double2* x, const int32_t* skip, hipStream_t s);
+                         double2* x, const int32_t* skip, int group, hipStream_t s);
 // mode 0: FP32 copy <- src columns 0 .. 15 (rounded); 1: x columns 0 .. 15 <- the copy;
 // 2: x columns 0 .. 15 += the copy (src used by mode 0 only; jobs flagged in done skipped)
 void launch_x32(const JobDesc* jobs, int njobs, int npad_max, int mode, const double2* src, double2* x,

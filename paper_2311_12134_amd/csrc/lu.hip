@@ -1,8 +1,9 @@
 // Batched complex LU with partial pivoting (the tau inverse of Eq. (3) is the dominant
-// cost of the method, Sec. II.A), right-looking and blocked with panel width NB.
+// cost of the method, Sec. II.A), blocked with panel width NB: right-looking over groups of
+// 2 to 4 panels, left-looking within a group (see lu_factor_any).
 //
 // All jobs of a wave advance through the same panel steps; every panel is a few
-// launches over the whole batch (panels come in look-ahead pairs, see lu_factor_any):
+// launches over the whole batch:
 //   panel_kernel      one workgroup per job factors rows [k, n) x cols [k, k+NB) with
 //                     partial pivoting (pivot = largest |re|+|im|, first on ties, keys
 //                     compared in FP64): IB-wide leaves live in registers (rows distributed
@@ -15,9 +16,9 @@
 //                     FP64 MFMA 16x16x4 with the four real products of a complex product,
 //                     or (split mode) FP32 MFMA 16x16x4 with three real products
 //                     (Ar Br, Ai Bi, (Ar+Ai)(Br+Bi)).
-// Interchanges are applied only to the right of each panel (and, for the second panel
-// of a pair, to the first panel's columns); the solves apply them panel by panel in the
-// same order, so older columns never need swapping.
+// Interchanges are applied only to the right of each panel (and to the L columns of the
+// earlier panels of its group); the solves apply them panel by panel in the same order,
+// so the columns of earlier groups never need swapping.
 // Matrices are row-major with leading dimension npad (a multiple of 64); the padding
 // is an identity block that no pivot ever selects.
 #include <algorithm>
@@ -336,8 +337,9 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
     }
     __syncthreads();
     // the leaf's interchanges on the other columns of the panel (whole panel rows), and on
-    // the `left` columns before it (the first panel of a pair, see lu_factor), applied as
-    // one gather: at most 2 IB rows change, listed as (position, original row) pairs
+    // the `left` columns before it (the earlier panels of its group, see lu_factor_any),
+    // applied as one gather: at most 2 IB rows change, listed as (position, original row)
+    // pairs, moved through LDS in chunks of 2 NB - IB columns
     if (t == 0) {
       int cnt = IB;
       for (int i = 0; i < IB; ++i) {
@@ -367,17 +369,22 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
     }
     __syncthreads();
     {
+      constexpr int CH = 2 * NB - IB;
       const int ncols = left + NB - IB, cnt = s_lcnt;
-      for (int idx = t; idx < cnt * ncols; idx += PT) {
-        const int e = idx / ncols, cc = idx - e * ncols, cr = cc - left;
-        const int colx = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
-        s_held[e][cc] = A[s_lorg[e] * ld + colx];
-      }
-      __syncthreads();
-      for (int idx = t; idx < cnt * ncols; idx += PT) {
-        const int e = idx / ncols, cc = idx - e * ncols, cr = cc - left;
-        const int colx = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
-        A[s_lpos[e] * ld + colx] = s_held[e][cc];
+      for (int c0 = 0; c0 < ncols; c0 += CH) {
+        const int nc = min(CH, ncols - c0);
+        if (c0 > 0) __syncthreads();  // the previous chunk is written back
+        for (int idx = t; idx < cnt * nc; idx += PT) {
+          const int e = idx / nc, ch = idx - e * nc, cc = c0 + ch, cr = cc - left;
+          const int colx = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
+          s_held[e][ch] = A[s_lorg[e] * ld + colx];
+        }
+        __syncthreads();
+        for (int idx = t; idx < cnt * nc; idx += PT) {
+          const int e = idx / nc, ch = idx - e * nc, cc = c0 + ch, cr = cc - left;
+          const int colx = cc < left ? k - left + cc : k + (cr < c * IB ? cr : cr + IB);
+          A[s_lpos[e] * ld + colx] = s_held[e][ch];
+        }
       }
     }
     __syncthreads();
@@ -716,11 +723,13 @@ static void launch_linv(const JobDesc* jobs, int njobs, int k, T* work, hipStrea
 // permuted rows are written back directly), then U12 = L11^-1 A12 is one 64 x 64 x 64
 // product on the matrix cores with the inverse stored by the inverse kernel (FP32 three-product
 // MFMA for FP32 storage, FP64 MFMA otherwise).
-// SECOND: k is the second panel of a pair whose first panel starts at k - NB.  Its
-// trailing columns have not yet received the first panel's update, so after the gather
-// the panel rows get  A12 -= L[k.., k-NB..k) U12_first  (same product) before U12.
+// SECOND: k is panel nprev >= 1 of a group whose first panel starts at k - nprev NB.  Its
+// trailing columns have not yet received the updates of the group's earlier panels, so
+// after the gather the panel rows get  A12 -= L[k.., k - nprev NB .. k) U12_earlier  (the
+// same 64 x 64 products, one per earlier panel, in panel order) before U12.
 template <typename T, bool SECOND>
-__global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int k, T* work, const int32_t* piv) {
+__global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int k, int nprev, T* work,
+                                                        const int32_t* piv) {
   const JobDesc jd = jobs[blockIdx.y];
   const int col0 = k + NB + blockIdx.x * 64;
   if (k >= jd.npad || col0 >= jd.npad) return;  // uniform
@@ -766,13 +775,17 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   const int ii = lane & 15;
   const int row0 = k + wave * 16;  // this wavefront's 16 panel rows
   if (SECOND) {
-    // s_X -= L[k.., k-NB..k) U[k-NB.., col0..]: wave w owns rows 16w .. 16w+16
-    T la[NB / 4];
-#pragma unroll
-    for (int s4 = 0; s4 < NB / 4; ++s4) la[s4] = A[(int64_t)(row0 + ii) * ld + (k - NB) + 4 * s4 + (lane >> 4)];
+    // s_X -= L[k.., kl..k) U[kl.., col0..], kl = k - nprev NB: wave w owns rows 16w .. 16w+16
     StripMma<T, 4> d;
     d.zero();
-    d.run_regs(la, [&](int kk, int c) { return A[(int64_t)(k - NB + kk) * ld + col0 + c]; }, lane);
+#pragma unroll 1
+    for (int q = 0; q < nprev; ++q) {
+      const int kq = k - (nprev - q) * NB;  // the earlier panel's first column
+      T la[NB / 4];
+#pragma unroll
+      for (int s4 = 0; s4 < NB / 4; ++s4) la[s4] = A[(int64_t)(row0 + ii) * ld + kq + 4 * s4 + (lane >> 4)];
+      d.run_regs(la, [&](int kk, int c) { return A[(int64_t)(kq + kk) * ld + col0 + c]; }, lane);
+    }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -1139,24 +1152,28 @@ static void update_cost(const GemmProfiler* prof, int njobs, int kd, int r_begin
   *bytes = b;
 }
 
-// Blocked right-looking LU with look-ahead over pairs of panels: panels start at every
-// multiple of 2 NB (first) and NB past it (second).  For a pair (k, k + NB):
-//   panel(k) -> interchanges + U12 on all trailing columns -> update of the second
-//   panel's columns only (K = NB) -> panel(k + NB), whose interchanges also permute the
-//   first panel's L rows -> interchanges + delayed first-panel update + U12 of the second
-//   panel on the columns beyond -> one trailing update with K = 2 NB.
-// The big update therefore streams the trailing matrix once per 2 NB columns.  The solves
-// apply the second panel's permutation right after the first panel's triangle.
-// With a side stream, the trailing update is split at the next pair's first panel: its
+// Blocked LU over groups of G panels (G = group, 2 .. GROUP_MAX): groups start at every
+// multiple of G NB, and the big trailing update runs once per group with K = G NB, so the
+// trailing matrix is streamed once per G NB columns.  Within a group the panels are
+// left-looking: for panel j of the group (first column kj = k + j NB)
+//   update of panel j's columns by the group's earlier panels (K = j NB, rows from kj) ->
+//   panel(kj), whose interchanges also permute the earlier panels' L columns (j NB of them)
+//   -> interchanges + delayed update by the earlier panels + U12 on every column past the
+//   panel (swap_trsm_kernel).
+// Then one trailing update A22 -= L21 U12 with K = G NB over the rows and columns past the
+// group.  Every element thus receives the same updates as in the right-looking order, in
+// a different association.  The solves apply each panel's permutation right after the
+// earlier panels of its group (see solve.hip).
+// With a side stream, the trailing update is split at the next group's first panel: its
 // NB columns are updated first, then that panel (and its inverses) is factored on the
 // side stream while the rest of the update runs on the main one.  The two touch disjoint
 // data (the panel reads and writes only its own columns and the diagonal block; the
-// update reads the L and U12 rows of this pair and writes columns past the panel), and the
-// next pair's interchanges wait for both.
+// update reads the L and U12 rows of this group and writes columns past the panel), and
+// the next group's interchanges wait for both.
 template <typename T, typename Gemm>
 static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work, int32_t* piv, int32_t* info,
                           hipStream_t s, GemmProfiler* prof, const TallScratch& tall, const SideStream* side,
-                          int small_rows, Gemm gemm) {
+                          int small_rows, int group, Gemm gemm) {
   auto timed_gemm = [&](int k, int kd, int r_begin, int c_begin, int c_end) {
     const int rows = npad_max - r_begin;
     const int cols = (c_end > 0 ? std::min(c_end, npad_max) : npad_max) - c_begin;
@@ -1169,31 +1186,35 @@ static void lu_factor_any(const JobDesc* jobs, int njobs, int npad_max, T* work,
       prof->after(s, f, b, c_end > 0 ? 0 : 1);
     }
   };
-  bool ahead = false;  // this pair's first panel was factored on the side stream
-  for (int k = 0; k < npad_max; k += 2 * NB) {
-    if (ahead)
-      (void)hipStreamWaitEvent(s, side->panel_done, 0);
-    else
-      panel_step<T>(jobs, njobs, npad_max, k, 0, work, piv, info, tall, s, small_rows);
+  const int GW = group * NB;
+  bool ahead = false;  // this group's first panel was factored on the side stream
+  for (int k = 0; k < npad_max; k += GW) {
+    for (int j = 0; j < group; ++j) {
+      const int kj = k + j * NB;
+      if (j > 0) timed_gemm(k, j * NB, kj, kj, kj + NB);  // panel j's columns, K = j NB
+      if (j == 0 && ahead)
+        (void)hipStreamWaitEvent(s, side->panel_done, 0);
+      else
+        panel_step<T>(jobs, njobs, npad_max, kj, j * NB, work, piv, info, tall, s, small_rows);
+      const int rest = npad_max - kj - NB;
+      if (rest <= 0) return;
+      if (j == 0)
+        swap_trsm_kernel<T, false><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, kj, 0, work, piv);
+      else
+        swap_trsm_kernel<T, true><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, kj, j, work, piv);
+    }
     ahead = false;
-    const int rest = npad_max - k - NB;
-    if (rest <= 0) break;
-    swap_trsm_kernel<T, false><<<dim3(rest / 64, njobs), 256, 0, s>>>(jobs, k, work, piv);
-    timed_gemm(k, NB, k + NB, k + NB, k + 2 * NB);  // the second panel's columns
-    panel_step<T>(jobs, njobs, npad_max, k + NB, NB, work, piv, info, tall, s, small_rows);
-    const int rest2 = npad_max - k - 2 * NB;
-    if (rest2 <= 0) break;
-    swap_trsm_kernel<T, true><<<dim3(rest2 / 64, njobs), 256, 0, s>>>(jobs, k + NB, work, piv);
-    if (side && rest2 > NB) {
-      timed_gemm(k, 2 * NB, k + 2 * NB, k + 2 * NB, k + 3 * NB);  // the next first panel's columns
+    const int rest = npad_max - k - GW;  // > 0: the group's last panel had columns past it
+    if (side && rest > NB) {
+      timed_gemm(k, GW, k + GW, k + GW, k + GW + NB);  // the next first panel's columns
       (void)hipEventRecord(side->update_done, s);
       (void)hipStreamWaitEvent(side->stream, side->update_done, 0);
-      panel_step<T>(jobs, njobs, npad_max, k + 2 * NB, 0, work, piv, info, tall, side->stream, small_rows);
+      panel_step<T>(jobs, njobs, npad_max, k + GW, 0, work, piv, info, tall, side->stream, small_rows);
       (void)hipEventRecord(side->panel_done, side->stream);
       ahead = true;
-      timed_gemm(k, 2 * NB, k + 2 * NB, k + 3 * NB, 0);
+      timed_gemm(k, GW, k + GW, k + GW + NB, 0);
     } else {
-      timed_gemm(k, 2 * NB, k + 2 * NB, k + 2 * NB, 0);
+      timed_gemm(k, GW, k + GW, k + GW, 0);
     }
   }
 }
@@ -1338,24 +1359,24 @@ void ldlt_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work,
   }
 }
 
-// The narrow update of a pair's second panel (64 columns, K = NB) takes the narrow tiling; the
-// K = 2 NB updates (split or not at the look-ahead panel) take the wide one, so every element
-// sums in the same order with and without the look-ahead stream.
+// The updates of a panel's columns within its group (64 columns, K < G NB) take the narrow
+// tiling; the K = G NB updates (split or not at the look-ahead panel) take the wide one, so
+// every element sums in the same order with and without the look-ahead stream.
 void lu_factor_f64(const JobDesc* jobs, int njobs, int npad_max, double2* work, int32_t* piv, int32_t* info,
                    hipStream_t s, GemmProfiler* prof, Tiling tiling, const TallScratch& tall, const SideStream* side) {
   lu_factor_any<double2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall, side, tiling.panel_small_rows,
-                         [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
-                           launch_gemm_f64_variant(kd == NB ? tiling.narrow : tiling.wide, jobs, njobs, rows, cols,
-                                                   k, kd, rb, cb, ce, work, s);
+                         tiling.group, [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
+                           launch_gemm_f64_variant(kd < tiling.group * NB ? tiling.narrow : tiling.wide, jobs, njobs,
+                                                   rows, cols, k, kd, rb, cb, ce, work, s);
                          });
 }
 
 void lu_factor_f32(const JobDesc* jobs, int njobs, int npad_max, float2* work, int32_t* piv, int32_t* info,
                    hipStream_t s, GemmProfiler* prof, Tiling tiling, const TallScratch& tall, const SideStream* side) {
   lu_factor_any<float2>(jobs, njobs, npad_max, work, piv, info, s, prof, tall, side, tiling.panel_small_rows,
-                        [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
-                          launch_gemm_f32_any(kd == NB ? tiling.narrow : tiling.wide, jobs, njobs, rows, cols, k, kd,
-                                              rb, cb, ce, work, s);
+                        tiling.group, [&](int rows, int cols, int k, int kd, int rb, int cb, int ce) {
+                          launch_gemm_f32_any(kd < tiling.group * NB ? tiling.narrow : tiling.wide, jobs, njobs,
+                                              rows, cols, k, kd, rb, cb, ce, work, s);
                         });
 }
 

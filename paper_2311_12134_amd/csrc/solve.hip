@@ -7,20 +7,22 @@
 // lower and the upper diagonal triangles in each diagonal block).  Hence
 //   M X = B   :  X = U^-1 L_K^-1 P_K ... L_1^-1 P_1 B          (trans = 0)
 //   M^T X = B :  X = P_1^T L_1^-T ... P_K^T L_K^-T U^-T B      (trans = 1)
-// Panels come in pairs (k, k + NB) and every pair costs two launches over the whole batch:
-//   solve_pair_diag_kernel    one workgroup per job: the pair's permutations (gathers of at
-//                             most 2 NB rows), both NB x NB diagonal steps as products with
-//                             the stored inverses (or their transposes) and the coupling block
-//                             between the two panels, on FP64 MFMA;
-//   solve_pair_update_kernel  one workgroup per (64-row strip, job): the strip against the
-//                             pair's 2 NB solved rows (K = 128) on FP64 MFMA 16x16x4 (four real
-//                             products per complex product), operands read straight from the
-//                             factors (FP32 factors widened in registers) and the solution, so
-//                             the factors stream from HBM once per solve and the solution rows
-//                             are read and written once per pair.
+// Panels come in groups of G (2 .. 4, as the factorization had them: the L rows of a
+// panel are stored after the permutations of the later panels of its group) and every group
+// costs two launches over the whole batch:
+//   solve_group_diag_kernel    one workgroup per job: panel by panel, the permutation (a
+//                              gather of at most 2 NB rows), the coupling blocks with the
+//                              group's panels solved before it, and the NB x NB diagonal step
+//                              as a product with the stored inverse (or its transpose);
+//   solve_group_update_kernel  one workgroup per (64-row strip, job): the strip against the
+//                              group's G NB solved rows (K = G NB) on the matrix cores,
+//                              operands read straight from the factors (FP32 factors widened in
+//                              registers for FP64 solves) and the solution, so the factors
+//                              stream from HBM once per solve and the solution rows are read
+//                              and written once per group.
 // The update is column-oriented (rows below for L and U^T, rows above for U) except for
-// L^T, whose pair rows need a sum over all rows below: there every strip adds its partial
-// product to the pair rows with FP64 atomics.  Arithmetic is FP64 for both storage types of
+// L^T, whose group rows need a sum over all rows below: there every strip adds its partial
+// product to the group rows with FP64 atomics.  Arithmetic is FP64 for both storage types of
 // the factors, except in the split-mode refinement: its forward solves (L and U) with the
 // FP32 factors run in FP32 (three-product FP32 MFMA) on an FP32 copy of the right-hand side,
 // since a solve with FP32 factors is no more accurate than FP32 however it is summed; the
@@ -99,12 +101,12 @@ __device__ inline void apply_perm(const int32_t* lst, bool inverse, XT* X, int* 
 }
 
 // ------------------------------------------------------------------------------------
-// pair solves: the panels of the factorization come in pairs (k, k + NB), k a multiple of
-// 2 NB (see lu_factor).  One launch per pair solves both diagonal blocks and the coupling
-// block between them; one launch per pair updates every other 64-row strip with K = 2 NB
-// (NB when the job's matrix ends after the first panel).  MFMA operands are read straight
-// from the factors and the solution rows (through the caches); no LDS stage, no barriers
-// in the update.
+// group solves: the panels of the factorization come in groups (k, k + NB, ..), k a
+// multiple of G NB (see lu_factor_any).  One launch per group solves its diagonal blocks and
+// the coupling blocks between them; one launch per group updates every other 64-row strip
+// with K = G NB (less when the job's matrix ends inside the group).  MFMA operands of the
+// update are read straight from the factors and the solution rows (through the caches); no
+// LDS stage, no barriers in the update.
 // ------------------------------------------------------------------------------------
 
 // Element (q, p) of an operator on a panel's rows at kp, from the stored diagonal block:
@@ -133,9 +135,9 @@ __device__ inline void panel_product(OP op, const XT (*xin)[NRHS], PUT put, int 
 }
 
 template <typename T, typename XT, int NRHS, int MODE>
-__global__ __launch_bounds__(256) void solve_pair_diag_kernel(const JobDesc* jobs, int k, const T* work,
-                                                              const int32_t* piv, double2* xbuf, int64_t col_off,
-                                                              const int32_t* skip) {
+__global__ __launch_bounds__(256) void solve_group_diag_kernel(const JobDesc* jobs, int k, int group, const T* work,
+                                                               const int32_t* piv, double2* xbuf, int64_t col_off,
+                                                               const int32_t* skip) {
   const int job = blockIdx.x;
   if (skip && skip[job]) return;
   const JobDesc jd = jobs[job];
@@ -145,8 +147,8 @@ __global__ __launch_bounds__(256) void solve_pair_diag_kernel(const JobDesc* job
   const int32_t* pv = piv + jd.piv_off;
   XT* X = XView<XT>::base(xbuf, jd, col_off);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const bool second = k + NB < jd.npad;
-  const int k2 = k + NB;
+  const int np = min(group, (jd.npad - k) / NB);  // panels of the group inside this job
+  auto kp = [&](int j) { return k + j * NB; };
   __shared__ XT s_a[NB][NRHS];
   __shared__ XT s_b[NB][NRHS];
   __shared__ int s_dst[PERM_MAX], s_src[PERM_MAX];
@@ -154,94 +156,82 @@ __global__ __launch_bounds__(256) void solve_pair_diag_kernel(const JobDesc* job
   auto load = [&](XT (*dst)[NRHS], int r0) {
     for (int idx = t; idx < NB * NRHS; idx += 256) dst[idx / NRHS][idx % NRHS] = xrow(r0 + idx / NRHS)[idx % NRHS];
   };
-  auto to_x = [&](int r0, bool keep) {  // result rows to the solution (and to s_b)
-    return [=](int row, int c, double2 v) {
-      xput(xrow(r0 + row)[c], v);
-      if (keep) xput(s_b[row][c], v);
-    };
+  auto to_x = [&](int r0) {  // result rows to the solution
+    return [=](int row, int c, double2 v) { xput(xrow(r0 + row)[c], v); };
   };
   // rows of s_a minus a product: each wave updates only its own rows, after its product
   auto minus_into_a = [&](int row, int c, double2 v) { s_a[row][c] = xminus(s_a[row][c], v); };
+  // s_a -= op (64 x 64) times the solved rows of panel i, staged through s_b
+  auto couple = [&](int i, auto op) {
+    __syncthreads();
+    load(s_b, kp(i));
+    __syncthreads();
+    panel_product<NRHS, XT>(op, s_b, minus_into_a, wave, lane);
+  };
   if (MODE == MODE_L) {
-    // P1, L1^-1, P2 (the first panel's L rows are stored after it), L21 coupling, L2^-1
-    apply_perm<NRHS, XT>(pv + perm_off(jd.npad, k), false, X, s_dst, s_src, t);
-    load(s_a, k);
-    __syncthreads();
-    panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, k, q, p); }, s_a, to_x(k, true), wave, lane);
-    if (!second) return;
-    __syncthreads();
-    apply_perm<NRHS, XT>(pv + perm_off(jd.npad, k2), false, X, s_dst, s_src, t);
-    load(s_a, k2);
-    __syncthreads();
-    panel_product<NRHS, XT>([&](int q, int p) { return fac<XT>(A + (int64_t)(k2 + q) * ld + k + p); }, s_b, minus_into_a,
-                        wave, lane);
-    __syncthreads();
-    panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, k2, q, p); }, s_a, to_x(k2, false), wave, lane);
+    // panel by panel: P_j (the earlier panels' L rows are stored after it), the couplings
+    // L[j, i] with the earlier panels of the group, L_j^-1
+    for (int j = 0; j < np; ++j) {
+      if (j > 0) __syncthreads();
+      apply_perm<NRHS, XT>(pv + perm_off(jd.npad, kp(j)), false, X, s_dst, s_src, t);
+      load(s_a, kp(j));
+      for (int i = 0; i < j; ++i)
+        couple(i, [&](int q, int p) { return fac<XT>(A + (int64_t)(kp(j) + q) * ld + kp(i) + p); });
+      __syncthreads();
+      panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, kp(j), q, p); }, s_a, to_x(kp(j)),
+                              wave, lane);
+    }
   } else if (MODE == MODE_U) {
-    // U2^-1, U12 coupling, U1^-1
-    if (second) {
-      load(s_a, k2);
+    // last panel first: the couplings U[j, i] with the later panels, U_j^-1
+    for (int j = np - 1; j >= 0; --j) {
       __syncthreads();
-      panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, k2, q, p); }, s_a, to_x(k2, true), wave,
-                          lane);
+      load(s_a, kp(j));
+      for (int i = j + 1; i < np; ++i)
+        couple(i, [&](int q, int p) { return fac<XT>(A + (int64_t)(kp(j) + q) * ld + kp(i) + p); });
       __syncthreads();
-      load(s_a, k);
-      __syncthreads();
-      panel_product<NRHS, XT>([&](int q, int p) { return fac<XT>(A + (int64_t)(k + q) * ld + k2 + p); }, s_b,
-                          minus_into_a, wave, lane);
-    } else {
-      load(s_a, k);
+      panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, kp(j), q, p); }, s_a, to_x(kp(j)),
+                              wave, lane);
     }
-    __syncthreads();
-    panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, k, q, p); }, s_a, to_x(k, false), wave, lane);
   } else if (MODE == MODE_UT) {
-    // U1^-T, U12^T coupling, U2^-T
-    load(s_a, k);
-    __syncthreads();
-    panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, k, p, q); }, s_a, to_x(k, true), wave, lane);
-    if (!second) return;
-    __syncthreads();
-    load(s_a, k2);
-    __syncthreads();
-    panel_product<NRHS, XT>([&](int q, int p) { return fac<XT>(A + (int64_t)(k + p) * ld + k2 + q); }, s_b, minus_into_a,
-                        wave, lane);
-    __syncthreads();
-    panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, k2, p, q); }, s_a, to_x(k2, false), wave,
-                        lane);
+    // first panel first: the couplings U[i, j]^T with the earlier panels, U_j^-T
+    for (int j = 0; j < np; ++j) {
+      __syncthreads();
+      load(s_a, kp(j));
+      for (int i = 0; i < j; ++i)
+        couple(i, [&](int q, int p) { return fac<XT>(A + (int64_t)(kp(i) + p) * ld + kp(j) + q); });
+      __syncthreads();
+      panel_product<NRHS, XT>([&](int q, int p) { return upper_inv<XT>(A, ld, kp(j), p, q); }, s_a, to_x(kp(j)),
+                              wave, lane);
+    }
   } else {
-    // MODE_LT: L2^-T, L21^T coupling, L1^-T, then P2^-1 and P1^-1
-    if (second) {
-      load(s_a, k2);
+    // MODE_LT, last panel first: the couplings L[i, j]^T with the later panels, L_j^-T; then
+    // the group's permutations inverted, last panel's first
+    for (int j = np - 1; j >= 0; --j) {
       __syncthreads();
-      panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, k2, p, q); }, s_a, to_x(k2, true), wave,
-                          lane);
+      load(s_a, kp(j));
+      for (int i = j + 1; i < np; ++i)
+        couple(i, [&](int q, int p) { return fac<XT>(A + (int64_t)(kp(i) + p) * ld + kp(j) + q); });
       __syncthreads();
-      load(s_a, k);
-      __syncthreads();
-      panel_product<NRHS, XT>([&](int q, int p) { return fac<XT>(A + (int64_t)(k2 + p) * ld + k + q); }, s_b,
-                          minus_into_a, wave, lane);
-    } else {
-      load(s_a, k);
+      panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, kp(j), p, q); }, s_a, to_x(kp(j)),
+                              wave, lane);
     }
     __syncthreads();
-    panel_product<NRHS, XT>([&](int q, int p) { return lower_inv<XT>(A, ld, k, p, q); }, s_a, to_x(k, false), wave, lane);
-    __syncthreads();
-    if (second) apply_perm<NRHS, XT>(pv + perm_off(jd.npad, k2), true, X, s_dst, s_src, t);
-    apply_perm<NRHS, XT>(pv + perm_off(jd.npad, k), true, X, s_dst, s_src, t);
+    for (int j = np - 1; j >= 0; --j) apply_perm<NRHS, XT>(pv + perm_off(jd.npad, kp(j)), true, X, s_dst, s_src, t);
   }
 }
 
-// One 64-row strip s against the pair's K = 2 NB rows (NB if the job ends after the first
-// panel):  MODE_L   X[s] -= L[s, pair] X[pair]      (s below the pair)
-//          MODE_U   X[s] -= U[s, pair] X[pair]      (s above)
-//          MODE_UT  X[s] -= U[pair, s]^T X[pair]    (s below)
-//          MODE_LT  X[pair] -= L[s, pair]^T X[s]    (s below; FP64 atomics into the pair rows)
+// One 64-row strip s against the group's K = KD rows (KD = G NB, or fewer where the job's
+// matrix ends inside the group):
+//          MODE_L   X[s] -= L[s, group] X[group]      (s below the group)
+//          MODE_U   X[s] -= U[s, group] X[group]      (s above)
+//          MODE_UT  X[s] -= U[group, s]^T X[group]    (s below)
+//          MODE_LT  X[group] -= L[s, group]^T X[s]    (s below; FP64 atomics into the group rows)
 template <typename T, typename XT, int NRHS, int MODE, int KD>
-__device__ inline void pair_update(const T* A, int64_t ld, XT* X, int k, int s0, int wave, int lane) {
+__device__ inline void group_update(const T* A, int64_t ld, XT* X, int k, int s0, int wave, int lane) {
   auto xrow = [&](int r) { return X + (int64_t)r * XView<XT>::LD; };
   const int ii = lane & 15;
   if constexpr (MODE == MODE_LT) {
-    // out rows = the pair's KD rows (KD / 16 blocks, dealt to the four waves), K = 64 strip rows
+    // out rows = the group's KD rows (KD / 16 blocks, dealt to the four waves), K = 64 strip rows
     for (int rb = wave; rb < KD / 16; rb += 4) {
       StripMma<double2, NRHS / 16> y;
       y.zero();
@@ -278,57 +268,63 @@ __device__ inline void pair_update(const T* A, int64_t ld, XT* X, int k, int s0,
 }
 
 template <typename T, typename XT, int NRHS, int MODE>
-__global__ __launch_bounds__(256) void solve_pair_update_kernel(const JobDesc* jobs, int k, const T* work,
-                                                                double2* xbuf, int64_t col_off, const int32_t* skip) {
+__global__ __launch_bounds__(256) void solve_group_update_kernel(const JobDesc* jobs, int k, int group, const T* work,
+                                                                 double2* xbuf, int64_t col_off, const int32_t* skip) {
   const int job = blockIdx.y;
   if (skip && skip[job]) return;
   const JobDesc jd = jobs[job];
   if (k >= jd.npad) return;
-  const int s0 = (MODE == MODE_U) ? blockIdx.x * 64 : k + 2 * NB + blockIdx.x * 64;
+  const int s0 = (MODE == MODE_U) ? blockIdx.x * 64 : k + group * NB + blockIdx.x * 64;
   if (MODE == MODE_U ? (s0 >= k) : (s0 >= jd.npad)) return;  // uniform
   const T* A = work + jd.a_off;
   const int64_t ld = jd.npad;
   XT* X = XView<XT>::base(xbuf, jd, col_off);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (MODE == MODE_U && k + NB >= jd.npad)
-    pair_update<T, XT, NRHS, MODE, NB>(A, ld, X, k, s0, wave, lane);
-  else
-    pair_update<T, XT, NRHS, MODE, 2 * NB>(A, ld, X, k, s0, wave, lane);
+  // strips below the group exist only when the whole group lies inside the job
+  const int kd = min(group * NB, jd.npad - k);
+  switch (kd / NB) {
+    case 1: group_update<T, XT, NRHS, MODE, NB>(A, ld, X, k, s0, wave, lane); break;
+    case 2: group_update<T, XT, NRHS, MODE, 2 * NB>(A, ld, X, k, s0, wave, lane); break;
+    case 3: group_update<T, XT, NRHS, MODE, 3 * NB>(A, ld, X, k, s0, wave, lane); break;
+    default: group_update<T, XT, NRHS, MODE, 4 * NB>(A, ld, X, k, s0, wave, lane); break;
+  }
 }
 
 template <typename T, typename XT, int NRHS>
 static void solve_all(const JobDesc* jobs, int njobs, int npad_max, const T* work, const int32_t* piv, double2* x,
-                      int64_t col_off, int trans, const int32_t* skip, hipStream_t s) {
-  const int last = ((npad_max - 1) / (2 * NB)) * (2 * NB);  // start of the last pair
+                      int64_t col_off, int trans, int group, const int32_t* skip, hipStream_t s) {
+  const int GW = group * NB;
+  const int last = ((npad_max - 1) / GW) * GW;  // start of the last group
   auto diag = [&](auto mode_tag, int k) {
     constexpr int MODE = decltype(mode_tag)::value;
-    solve_pair_diag_kernel<T, XT, NRHS, MODE><<<njobs, 256, 0, s>>>(jobs, k, work, piv, x, col_off, skip);
+    solve_group_diag_kernel<T, XT, NRHS, MODE><<<njobs, 256, 0, s>>>(jobs, k, group, work, piv, x, col_off, skip);
   };
   auto update = [&](auto mode_tag, int k, int strips) {
     constexpr int MODE = decltype(mode_tag)::value;
     if (strips <= 0) return;
-    solve_pair_update_kernel<T, XT, NRHS, MODE><<<dim3(strips, njobs), 256, 0, s>>>(jobs, k, work, x, col_off, skip);
+    solve_group_update_kernel<T, XT, NRHS, MODE>
+        <<<dim3(strips, njobs), 256, 0, s>>>(jobs, k, group, work, x, col_off, skip);
   };
   using L = std::integral_constant<int, MODE_L>;
   using U = std::integral_constant<int, MODE_U>;
   using UT = std::integral_constant<int, MODE_UT>;
   using LT = std::integral_constant<int, MODE_LT>;
   if (!trans) {
-    for (int k = 0; k < npad_max; k += 2 * NB) {
+    for (int k = 0; k < npad_max; k += GW) {
       diag(L{}, k);
-      update(L{}, k, (npad_max - k - 2 * NB) / 64);
+      update(L{}, k, (npad_max - k - GW) / 64);
     }
-    for (int k = last; k >= 0; k -= 2 * NB) {
+    for (int k = last; k >= 0; k -= GW) {
       diag(U{}, k);
       update(U{}, k, k / 64);
     }
   } else if constexpr (std::is_same<XT, double2>::value) {  // transposed solves: FP64 only
-    for (int k = 0; k < npad_max; k += 2 * NB) {
+    for (int k = 0; k < npad_max; k += GW) {
       diag(UT{}, k);
-      update(UT{}, k, (npad_max - k - 2 * NB) / 64);
+      update(UT{}, k, (npad_max - k - GW) / 64);
     }
-    for (int k = last; k >= 0; k -= 2 * NB) {
-      update(LT{}, k, (npad_max - k - 2 * NB) / 64);
+    for (int k = last; k >= 0; k -= GW) {
+      update(LT{}, k, (npad_max - k - GW) / 64);
       diag(LT{}, k);
     }
   }
@@ -336,26 +332,27 @@ static void solve_all(const JobDesc* jobs, int njobs, int npad_max, const T* wor
 
 template <typename T>
 static void solve_dispatch(const JobDesc* jobs, int njobs, int npad_max, const T* work, const int32_t* piv,
-                           double2* x, int64_t col_off, int nrhs, int trans, const int32_t* skip, hipStream_t s) {
+                           double2* x, int64_t col_off, int nrhs, int trans, int group, const int32_t* skip,
+                           hipStream_t s) {
   if (nrhs == 16)
-    solve_all<T, double2, 16>(jobs, njobs, npad_max, work, piv, x, col_off, trans, skip, s);
+    solve_all<T, double2, 16>(jobs, njobs, npad_max, work, piv, x, col_off, trans, group, skip, s);
   else
-    solve_all<T, double2, 32>(jobs, njobs, npad_max, work, piv, x, col_off, trans, skip, s);
+    solve_all<T, double2, 32>(jobs, njobs, npad_max, work, piv, x, col_off, trans, group, skip, s);
 }
 
 void lu_solve_f64(const JobDesc* jobs, int njobs, int npad_max, const double2* work, const int32_t* piv,
-                  double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s) {
-  solve_dispatch<double2>(jobs, njobs, npad_max, work, piv, x, x_col_off, nrhs, trans, nullptr, s);
+                  double2* x, int64_t x_col_off, int nrhs, int trans, int group, hipStream_t s) {
+  solve_dispatch<double2>(jobs, njobs, npad_max, work, piv, x, x_col_off, nrhs, trans, group, nullptr, s);
 }
 
 void lu_solve_f32(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
-                  double2* x, int64_t x_col_off, int nrhs, int trans, hipStream_t s) {
-  solve_dispatch<float2>(jobs, njobs, npad_max, work, piv, x, x_col_off, nrhs, trans, nullptr, s);
+                  double2* x, int64_t x_col_off, int nrhs, int trans, int group, hipStream_t s) {
+  solve_dispatch<float2>(jobs, njobs, npad_max, work, piv, x, x_col_off, nrhs, trans, group, nullptr, s);
 }
 
 void lu_solve_f32_single(const JobDesc* jobs, int njobs, int npad_max, const float2* work, const int32_t* piv,
-                         double2* x, const int32_t* skip, hipStream_t s) {
-  solve_all<float2, float2, 16>(jobs, njobs, npad_max, work, piv, x, 0, 0, skip, s);
+                         double2* x, const int32_t* skip, int group, hipStream_t s) {
+  solve_all<float2, float2, 16>(jobs, njobs, npad_max, work, piv, x, 0, 0, group, skip, s);
 }
 
 }  // namespace lsms

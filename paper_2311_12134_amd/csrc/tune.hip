@@ -1,8 +1,10 @@
 // Autotuning of the blocked LU of Eq. (3) (whose inverse dominates the cost, Sec. II.A):
 // every tiling of a trailing update, or both variants of a split-mode panel, is timed on a
 // synthetic batch of the shape it will meet, and the caller keeps the fastest.
-//   kind 1 (wide): the widest update of an LU, K = 2 NB over the trailing (npad - 2 NB)^2 block;
-//   kind 0 (narrow): a pair's second-panel update, K = NB over (npad - NB) rows x NB columns;
+//   kind 1 (wide): the widest update of an LU with G panels per group, K = G NB over the
+//   trailing (npad - G NB)^2 block;
+//   kind 0 (narrow): the update of a group's last panel, K = (G - 1) NB over
+//   (npad - (G - 1) NB) rows x NB columns;
 //   panels: the split-mode panel of a given height with 256-thread workgroups and 8-wide
 //   leaves against 512-thread workgroups and 16-wide leaves.
 // Values are bounded pseudo-random numbers (an integer hash), so repeated updates stay finite.
@@ -84,7 +86,7 @@ struct TuneBatch {
 };
 }  // namespace
 
-int update_autotune(int precision, int kind, int npad, int batch, hipStream_t s, float* ms, int* best) {
+int update_autotune(int precision, int kind, int npad, int batch, int group, hipStream_t s, float* ms, int* best) {
   const bool f64 = precision == 0;
   TuneBatch tb(npad, batch, f64 ? sizeof(double2) : sizeof(float2), s);
   if (!tb.ok) return -1;
@@ -93,8 +95,8 @@ int update_autotune(int precision, int kind, int npad, int batch, hipStream_t s,
     tune_fill_kernel<double2><<<(unsigned)((n + 255) / 256), 256, 0, s>>>((double2*)tb.a, n, 1.0f / (float)npad);
   else
     tune_fill_kernel<float2><<<(unsigned)((n + 255) / 256), 256, 0, s>>>((float2*)tb.a, n, 1.0f / (float)npad);
-  const int kd = kind == 1 ? 2 * NB : NB;
-  const int rows = npad - kd, cols = kind == 1 ? rows : NB, c_end = kind == 1 ? 0 : 2 * NB;
+  const int kd = kind == 1 ? group * NB : (group - 1) * NB;
+  const int rows = npad - kd, cols = kind == 1 ? rows : NB, c_end = kind == 1 ? 0 : kd + NB;
   const int nv = f64 ? gemm_f64_variants() : gemm_f32_variants_all();
   *best = -1;
   for (int v = 0; v < nv; ++v) {
@@ -111,10 +113,6 @@ int update_autotune(int precision, int kind, int npad, int batch, hipStream_t s,
     if (*best < 0 || t < ms[*best]) *best = v;
   }
   return hipStreamSynchronize(s) == hipSuccess ? 0 : -1;
-}
-
-int gemm_f32_autotune(int npad, int batch, hipStream_t s, float* ms, int* best) {
-  return update_autotune(1, 1, npad, batch, s, ms, best);
 }
 
 int panel_autotune(int rows, int batch, hipStream_t s, float* ms) {

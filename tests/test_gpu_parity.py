@@ -188,7 +188,7 @@ def test_batched_lu_solve_random_and_singular(lctx):
     assert info[-1] > 0
 
 
-@pytest.mark.parametrize("tiling", list(range(12)))
+@pytest.mark.parametrize("tiling", list(range(19)))
 def test_split_lu_every_gemm_tiling(lctx, tiling):
     """FP32 factors without refinement, uneven batch whose trailing blocks end on 64-row and
     64-column halves of the 128-wide tiles: every tiling of the split-mode update must give
@@ -230,7 +230,7 @@ def _random_systems(seed, sizes, scale_diag=2.0):
     return mats, rhs, refs
 
 
-@pytest.mark.parametrize("knob,nv", [("f64_wide", 6), ("f64_narrow", 6), ("f32_narrow", 12)])
+@pytest.mark.parametrize("knob,nv", [("f64_wide", 6), ("f64_narrow", 6), ("f32_narrow", 19)])
 def test_lu_every_update_tiling(lctx, knob, nv):
     """Every tiling of the FP64 wide and narrow trailing updates (FP64 solve to 1e-10) and of
     the split-mode narrow update (FP32 factors without refinement, to FP32 rounding) on an
@@ -252,6 +252,74 @@ def test_lu_every_update_tiling(lctx, knob, nv):
             assert info[k] == 0
             err = np.abs(rhs[k].cpu().numpy() - ref).max() / np.abs(ref).max()
             assert err <= tol, (knob, v, sizes[k], err)
+
+
+class _groups:
+    """Panels per group of both LUs set for a block (restored to the defaults after)."""
+
+    def __init__(self, lctx, group):
+        self.lctx, self.group = lctx, group
+
+    def __enter__(self):
+        self.lctx.set_knob("group_f32", self.group)
+        self.lctx.set_knob("group_f64", self.group)
+        assert self.lctx.knob("group_f32") == self.group and self.lctx.knob("group_f64") == self.group
+
+    def __exit__(self, *exc):
+        self.lctx.set_knob("group_f32", -1)
+        self.lctx.set_knob("group_f64", -1)
+
+
+@pytest.mark.parametrize("group", [2, 3, 4])
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_lu_groups_random_systems(lctx, precision, group):
+    """Two, three and four panels per group on one uneven batch whose matrices end on every
+    panel of a last group (1024, 960, 896, 832 rows and sizes off the 64 grid), against numpy:
+    FP64 to 1e-10, FP32 factors without refinement to FP32 rounding; and a singular system
+    (zero column 200) reported at its column."""
+    sizes = [1024, 960, 896, 832, 700, 450, 129, 1]
+    tol = 2e-5 if precision == "split" else 1e-10
+    print("[gpu] groups of %d panels, %s" % (group, precision), flush=True)
+    mats, rhs, refs = _random_systems(23 + group, sizes)
+    S = np.random.default_rng(5).normal(size=(300, 300)) + 0j
+    S[:, 200] = 0.0
+    mats.append(torch.from_numpy(S).to("cuda"))
+    rhs.append(torch.from_numpy(np.ones((300, 3), dtype=complex)).to("cuda"))
+    with _groups(lctx, group):
+        info = lctx.batched_lu_solve(mats, rhs, precision=precision).cpu().numpy()
+    torch.cuda.synchronize()
+    for k, ref in enumerate(refs):
+        assert info[k] == 0
+        err = np.abs(rhs[k].cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err <= tol, (precision, group, sizes[k], err)
+    assert info[-1] == 201
+
+
+@pytest.mark.parametrize("case", ["bcc16_split", "fcc32_fp64", "bcc1940_split", "tournament_bcc250_split",
+                                  "tournament_bcc1940_split", "adjoint_bcc16", "lookahead_bcc250_split",
+                                  "graph_fcc32_split", "ldlt_bcc250", "conj_fcc32_split"])
+@pytest.mark.parametrize("group", [3, 4])
+def test_groups_end_to_end(lctx, group, case):
+    """The end-to-end parity tests against the oracle (and the bitwise schedule tests) with
+    three and four panels per group in both LUs: tau solves, tournament panels (whose left
+    columns then span up to three panels), the adjoint's transposed solves, the look-ahead
+    stream, graph replay, the symmetric form and the z+/z- symmetry."""
+    print("[gpu] groups of %d panels: %s" % (group, case), flush=True)
+    run = {
+        "bcc16_split": lambda: test_bcc16_split_full(lctx),
+        "fcc32_fp64": lambda: test_fcc32_fp64_full(lctx),
+        "bcc1940_split": lambda: test_bcc1940_uneven_sampled(lctx),
+        "tournament_bcc250_split": lambda: test_tournament_panels_vs_oracle(lctx, "bcc250", "split", 128, TOL_SPLIT),
+        "tournament_bcc1940_split": lambda: test_tournament_panels_vs_oracle(lctx, "bcc1940", "split", 192,
+                                                                             TOL_SPLIT),
+        "adjoint_bcc16": lambda: test_adjoint_bcc16_vs_oracle_and_fd(lctx),
+        "lookahead_bcc250_split": lambda: test_lookahead_matches_single_stream(lctx, "bcc250", "split", 2048),
+        "graph_fcc32_split": lambda: test_graph_replay_matches_eager(lctx, "fcc32", "split"),
+        "ldlt_bcc250": lambda: test_symmetric_ldlt_vs_oracle(lctx, "bcc250", 2048),
+        "conj_fcc32_split": lambda: test_conj_symmetry_mode(lctx, "fcc32", "split", TOL_SPLIT),
+    }[case]
+    with _groups(lctx, group):
+        run()
 
 
 @pytest.mark.parametrize("rows", [0, 256, 512, 768])
@@ -466,7 +534,7 @@ def test_graph_replay_matches_eager(lctx, name, precision):
 
 def test_autotune_picks_fastest_tiling(lctx):
     best, ms = lctx.autotune(npad=448, batch=32)
-    assert 0 <= best < 12 and len(ms) == 12
+    assert 0 <= best < 19 and len(ms) == 19
     assert all(np.isfinite(m) and m > 0 for m in ms)
     assert ms[best] == min(ms)
     try:
@@ -941,7 +1009,8 @@ def test_argument_errors_are_reported(lctx):
     la, lp, phase, species, J = _device_inputs(w, liz)
     print("[gpu] argument errors", flush=True)
     for knob_call in (lambda: lctx.set_tslu_chunk(100), lambda: lctx.set_tslu_chunk(4096),
-                      lambda: lctx.set_gemm_tiling(99)):
+                      lambda: lctx.set_gemm_tiling(99), lambda: lctx.set_knob("group_f32", 5),
+                      lambda: lctx.set_knob("group_f64", 1)):
         with pytest.raises(LsmsError):
             knob_call()
     with pytest.raises(LsmsError):
