@@ -267,6 +267,59 @@ __device__ inline void group_update(const T* A, int64_t ld, XT* X, int k, int s0
     }
 }
 
+// MODE_L and MODE_U with the strip's factor rows staged through LDS: the 64 x KD block
+// A[s0 .., k ..] streams from HBM in chunks of 256 bytes per row (32 FP32 or 16 FP64
+// complex columns), each thread moving 16-byte pieces of whole rows (coalesced), through two
+// buffers (35 KB, four workgroups per compute unit) with the next chunk's loads issued before
+// the current chunk's products; each wave then takes its 16 rows' operands from LDS.  Same
+// products, same order as group_update.
+template <typename T, typename XT, int NRHS, int KD>
+__device__ inline void group_update_staged(const T* A, int64_t ld, XT* X, int k, int s0, int t, int wave, int lane,
+                                           float4 (*sL)[64][17]) {
+  constexpr int KCH = 256 / (int)sizeof(T);  // complex columns per chunk
+  constexpr int NCH = KD / KCH;
+  constexpr int Q = 64 * 16 / 256;            // 16-byte pieces per thread and chunk
+  auto xrow = [&](int r) { return X + (int64_t)r * XView<XT>::LD; };
+  float4 held[Q];
+  auto load = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int idx = t + 256 * q, row = idx >> 4, p4 = idx & 15;
+      held[q] = ((const float4*)(A + (int64_t)(s0 + row) * ld + k + c * KCH))[p4];
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int idx = t + 256 * q;
+      sL[buf][idx >> 4][idx & 15] = held[q];
+    }
+  };
+  StripMma<XT, NRHS / 16, KCH> y;
+  y.zero();
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int c = 0; c < NCH; ++c) {
+    const int cur = c & 1;
+    if (c + 1 < NCH) load(c + 1);
+    const T* rows = (const T*)&sL[cur][wave * 16][0];
+    y.run([&](int i, int kk) { return fac<XT>(rows + (int64_t)i * (17 * 16 / sizeof(T)) + kk); },
+          [&](int kk, int cc) { return xrow(k + c * KCH + kk)[cc]; }, lane);
+    if (c + 1 < NCH) store(cur ^ 1);
+    __syncthreads();
+  }
+  const int ii = lane & 15;
+  const int r0 = s0 + wave * 16;
+#pragma unroll
+  for (int cb = 0; cb < NRHS / 16; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      XT* xp = xrow(r0 + y.row(r, lane)) + cb * 16 + ii;
+      *xp = xminus(*xp, y.value(cb, r));
+    }
+}
+
 template <typename T, typename XT, int NRHS, int MODE>
 __global__ __launch_bounds__(256) void solve_group_update_kernel(const JobDesc* jobs, int k, int group, const T* work,
                                                                  double2* xbuf, int64_t col_off, const int32_t* skip) {
@@ -282,6 +335,17 @@ __global__ __launch_bounds__(256) void solve_group_update_kernel(const JobDesc* 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // strips below the group exist only when the whole group lies inside the job
   const int kd = min(group * NB, jd.npad - k);
+  if constexpr (MODE == MODE_L || MODE == MODE_U) {
+    __shared__ float4 sL[2][64][17];
+    const int t = threadIdx.x;
+    switch (kd / NB) {
+      case 1: group_update_staged<T, XT, NRHS, NB>(A, ld, X, k, s0, t, wave, lane, sL); break;
+      case 2: group_update_staged<T, XT, NRHS, 2 * NB>(A, ld, X, k, s0, t, wave, lane, sL); break;
+      case 3: group_update_staged<T, XT, NRHS, 3 * NB>(A, ld, X, k, s0, t, wave, lane, sL); break;
+      default: group_update_staged<T, XT, NRHS, 4 * NB>(A, ld, X, k, s0, t, wave, lane, sL); break;
+    }
+    return;
+  }
   switch (kd / NB) {
     case 1: group_update<T, XT, NRHS, MODE, NB>(A, ld, X, k, s0, wave, lane); break;
     case 2: group_update<T, XT, NRHS, MODE, 2 * NB>(A, ld, X, k, s0, wave, lane); break;
