@@ -626,9 +626,10 @@ static void energies(double e_fermi, double eta, double2& kp, double2& km) {
 
 // Refinement state per job: norms[j][0] = ||M||_inf, [1] = ||r||_inf, [2] = ||X||_inf, [3] = berr.
 namespace lsms {
+// first: the first pass of a refinement, which also forms ||M||_inf (kept by later passes)
 void launch_residual_norms(const JobDesc* jobs, int njobs, int npad_max, const double2* m64, const double2* x,
                            double2* r, const double2* tpm, const int32_t* liz_atom, double* norms,
-                           const int32_t* done, hipStream_t s);
+                           const int32_t* done, int first, hipStream_t s);
 void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double tol, int32_t* done, int last,
                         int32_t* job_info, int32_t* pending, hipStream_t s);
 void launch_zero_i32(int32_t* p, int n, hipStream_t s);
@@ -956,7 +957,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
       int left = nj;
       for (int it = 0; it <= max_refine; ++it) {
         const int last = it == max_refine;
-        launch_residual_norms(jd, nj, npad_max, m64, xbuf, rbuf, rhs_t, liz_atom, jnorm, jdone, s);
+        launch_residual_norms(jd, nj, npad_max, m64, xbuf, rbuf, rhs_t, liz_atom, jnorm, jdone, it == 0, s);
         launch_zero_i32(pending, 1, s);
         launch_refine_step(jd, nj, jnorm, refine_tol, jdone, last, jinfo, pending, s);
         // read back how many jobs still miss the tolerance: stop as soon as none does

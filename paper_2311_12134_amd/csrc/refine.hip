@@ -20,7 +20,14 @@ __device__ inline void atomic_max_nonneg(double* addr, double v) {
 
 __device__ inline double cabs2(double2 v) { return sqrt(v.x * v.x + v.y * v.y); }
 
-// r = B - M X for 64 rows x 16 columns per workgroup; M X on FP64 MFMA (4 real products).
+// r = B - M X for 64 rows x 16 columns per workgroup; M X on FP64 MFMA with three real
+// products per complex product (Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)): the kernel streams the FP64
+// copy of M once per pass, and three products keep the matrix cores under that stream.
+// MNORM: also ||M||_inf (the first pass of a refinement; M does not change between passes,
+// so the later passes skip the modulus of every element).  The moduli are taken in FP32 (a
+// relative error of about 1e-7 in a norm that only scales the backward error) and summed
+// in FP64; entries of M = 1 - t g are far below the FP32 range.
+template <bool MNORM>
 __global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, const double2* m64, const double2* x,
                                                        double2* r, const double2* tpm, const int32_t* liz_atom,
                                                        double* norms, const int32_t* done) {
@@ -37,7 +44,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, cons
   __shared__ double2 sM[64][16 + 1];
   __shared__ double2 sX[16][16 + 1];
   __shared__ double s_max[3][4];
-  d4 are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+  d4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
   double rowabs = 0.0;
   for (int kc = 0; kc < npad; kc += 16) {
     {
@@ -47,7 +54,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, cons
       for (int u = 0; u < 4; ++u) {
         const double2 v = src[u];
         sM[i][k4 + u] = v;
-        rowabs += cabs2(v);
+        if (MNORM) rowabs += (double)__builtin_sqrtf((float)(v.x * v.x + v.y * v.y));
       }
       const int kk = t >> 4, c = t & 15;
       sX[kk][c] = X[(int64_t)(kc + kk) * NRHS_MAX + c];
@@ -57,10 +64,9 @@ __global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, cons
     for (int k4 = 0; k4 < 16; k4 += 4) {
       const double2 a = sM[wave * 16 + (lane & 15)][k4 + (lane >> 4)];
       const double2 b = sX[k4 + (lane >> 4)][lane & 15];
-      are = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, are, 0, 0, 0);
-      are = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, are, 0, 0, 0);
-      aim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, aim, 0, 0, 0);
-      aim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, aim, 0, 0, 0);
+      t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, t1, 0, 0, 0);
+      t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, t2, 0, 0, 0);
+      t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, t3, 0, 0, 0);
     }
     __syncthreads();
   }
@@ -78,7 +84,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, cons
   for (int q = 0; q < 4; ++q) {
     const int row = row0 + wave * 16 + (lane >> 4) + 4 * q;
     double2 b = (row == col) ? tc : make_double2(0.0, 0.0);
-    double2 rv = make_double2(b.x - are[q], b.y - aim[q]);
+    double2 rv = make_double2(b.x - (t1[q] - t2[q]), b.y - (t3[q] - t1[q] - t2[q]));
     R[(int64_t)row * NRHS_MAX + col] = rv;
     double a = cabs2(rv);
 #pragma unroll
@@ -104,7 +110,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, cons
     s_max[2][wave] = xmax;
   }
   __syncthreads();
-  if (t < 3) {
+  if (t < 3 && (MNORM || t > 0)) {
     double v = fmax(fmax(s_max[t][0], s_max[t][1]), fmax(s_max[t][2], s_max[t][3]));
     atomic_max_nonneg(norms + job * 8 + t, v);
   }
@@ -117,9 +123,12 @@ __global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, cons
 
 void launch_residual_norms(const JobDesc* jobs, int njobs, int npad_max, const double2* m64, const double2* x,
                            double2* r, const double2* tpm, const int32_t* liz_atom, double* norms,
-                           const int32_t* done, hipStream_t s) {
+                           const int32_t* done, int first, hipStream_t s) {
   dim3 grid(npad_max / 64, njobs);
-  residual_kernel<<<grid, 256, 0, s>>>(jobs, m64, x, r, tpm, liz_atom, norms, done);
+  if (first)
+    residual_kernel<true><<<grid, 256, 0, s>>>(jobs, m64, x, r, tpm, liz_atom, norms, done);
+  else
+    residual_kernel<false><<<grid, 256, 0, s>>>(jobs, m64, x, r, tpm, liz_atom, norms, done);
 }
 
 // Backward error of every pending job; jobs that reach tol are marked done, the others
@@ -138,8 +147,7 @@ __global__ void refine_step_kernel(int njobs, double* norms, double tol, int32_t
     atomicAdd(pending, 1);
     if (last) job_info[j] = -1;
   }
-  nm[0] = 0.0;
-  nm[1] = 0.0;
+  nm[1] = 0.0;  // ||M|| (nm[0]) is kept for the next pass
   nm[2] = 0.0;
 }
 
