@@ -775,24 +775,59 @@ __global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int
   const int ii = lane & 15;
   const int row0 = k + wave * 16;  // this wavefront's 16 panel rows
   if (SECOND) {
-    // s_X -= L[k.., kl..k) U[kl.., col0..], kl = k - nprev NB: wave w owns rows 16w .. 16w+16
+    // s_X -= L[k.., kl..k) U[kl.., col0..], kl = k - nprev NB: wave w owns rows 16w .. 16w+16.
     StripMma<T, 4> d;
     d.zero();
+    if constexpr (sizeof(T) == sizeof(float2)) {
+      // FP32 storage: the wave's gathered rows move to registers (accumulator layout), so that
+      // s_X can stage each earlier panel's 64 x 64 block of U rows, loaded once per workgroup
+      // 16 bytes of a row per access instead of once per wave through the cache
+      S xs[4][4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xs[cb][r] = s_X[wave * 16 + d.row(r, lane)][cb * 16 + ii];
+      constexpr int P4 = 64 * (int)sizeof(T) / 16;  // 16-byte pieces per row of the block
 #pragma unroll 1
-    for (int q = 0; q < nprev; ++q) {
-      const int kq = k - (nprev - q) * NB;  // the earlier panel's first column
-      T la[NB / 4];
+      for (int q = 0; q < nprev; ++q) {
+        const int kq = k - (nprev - q) * NB;  // the earlier panel's first column
+        __syncthreads();                      // s_X is free (copied out, or the last products done)
+        for (int idx = t; idx < NB * P4; idx += 256) {
+          const int row = idx / P4, p4 = idx - row * P4;
+          ((float4*)&s_X[row][0])[p4] = ((const float4*)(A + (int64_t)(kq + row) * ld + col0))[p4];
+        }
+        T la[NB / 4];
 #pragma unroll
-      for (int s4 = 0; s4 < NB / 4; ++s4) la[s4] = A[(int64_t)(row0 + ii) * ld + kq + 4 * s4 + (lane >> 4)];
-      d.run_regs(la, [&](int kk, int c) { return A[(int64_t)(kq + kk) * ld + col0 + c]; }, lane);
-    }
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        S* xp = &s_X[wave * 16 + d.row(r, lane)][cb * 16 + ii];
-        st2(xp, csub(ld2(xp), d.value(cb, r)));
+        for (int s4 = 0; s4 < NB / 4; ++s4) la[s4] = A[(int64_t)(row0 + ii) * ld + kq + 4 * s4 + (lane >> 4)];
+        __syncthreads();
+        d.run_regs(la, [&](int kk, int c) { return s_X[kk][c]; }, lane);
       }
+      __syncthreads();  // every wave's products read s_X before it takes the updated rows
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          S* xp = &s_X[wave * 16 + d.row(r, lane)][cb * 16 + ii];
+          st2(xp, csub(wide(xs[cb][r]), d.value(cb, r)));
+        }
+    } else {
+      // FP64 storage (half the occupancy already): operands through the cache
+#pragma unroll 1
+      for (int q = 0; q < nprev; ++q) {
+        const int kq = k - (nprev - q) * NB;
+        T la[NB / 4];
+#pragma unroll
+        for (int s4 = 0; s4 < NB / 4; ++s4) la[s4] = A[(int64_t)(row0 + ii) * ld + kq + 4 * s4 + (lane >> 4)];
+        d.run_regs(la, [&](int kk, int c) { return A[(int64_t)(kq + kk) * ld + col0 + c]; }, lane);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          S* xp = &s_X[wave * 16 + d.row(r, lane)][cb * 16 + ii];
+          st2(xp, csub(ld2(xp), d.value(cb, r)));
+        }
+    }
   }
   // U12 = L11^-1 A12 straight from the accumulators to the panel rows (the inverse is
   // stored below the diagonal; its unit diagonal and zero upper part are implied).  The
