@@ -31,13 +31,22 @@ import numpy as np  # noqa: E402
 METRIC = "atoms/sec through LIZ τ-solve + Kubo trace; % MFMA peak; split vs FP64 at 1e-8"
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64_MFMA = 78.6e12
-GEMM_SOURCE = os.path.join(ROOT, "paper_2311_12134_amd", "csrc", "gemm.hip")
+CSRC = os.path.join(ROOT, "paper_2311_12134_amd", "csrc")
+
+
+def gemm_source(precision, tiling):
+    """The source file that holds a trailing-update tiling's kernel."""
+    if precision == "split":
+        name = "gemm.hip" if tiling < 10 else ("gemm_wide.hip" if 12 <= tiling <= 16 else "gemm_persist.hip")
+    else:
+        name = "gemm.hip" if tiling == 0 else "gemm64.hip"
+    return os.path.join(CSRC, name)
 
 # HBM bytes per launch of the trailing-update kernel on this workload, from two rocprofv3
 # counter runs (FETCH_SIZE, WRITE_SIZE) over one step, each scaled by what the same counter
 # read for a 1 GiB device-to-device copy in the same run (--copy-calibration).  Keyed by
-# (precision, workload, tiling) and tied to the sha256 of the kernel source the counters were
-# taken on and to the launches' algorithmic bytes (the wave size, which follows the free HBM):
+# (precision, workload, tiling) and tied to the sha256 of the kernel's source file (gemm_source)
+# when the counters were taken and to the launches' algorithmic bytes (the wave size, which follows the free HBM):
 # any later change to that source, or launches of another shape, make the figure stale and
 # it is reported as null.
 TRAFFIC = {
@@ -258,7 +267,7 @@ def gemm_roofline(ctx, precision, workload, tiling, timed_in):
     achieved = flops / launches / avg_s
     peak = PEAK_FP32_MFMA if precision == "split" else PEAK_FP64_MFMA
     kname = (F32_TILINGS if precision == "split" else F64_TILINGS).get(tiling, "tiling %d" % tiling)
-    with open(GEMM_SOURCE, "rb") as f:
+    with open(gemm_source(precision, tiling), "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
     rec = TRAFFIC.get((precision, workload, tiling))
     same_shape = rec is not None and abs(alg_bytes / launches / rec["alg_bytes_per_launch"] - 1) < 1e-3

@@ -17,15 +17,17 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.stdout == ""
 
 
-def test_traffic_record_belongs_to_the_current_trailing_update_source():
-    """bench.py reports roofline.traffic only while the kernel source matches the one its
-    counters were taken on; the committed record must be for the committed source."""
+def test_traffic_records_belong_to_the_current_trailing_update_sources():
+    """bench.py reports roofline.traffic only while the kernel's source file matches the one
+    its counters were taken on; every committed record must be for the committed source."""
     import bench
-    with open(bench.GEMM_SOURCE, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    rec = bench.TRAFFIC[("split", "fcc4000", 2)]
-    assert rec["sha256"] == digest, ("the trailing-update source changed after its FETCH_SIZE / WRITE_SIZE "
-                                     "counters were taken: re-take them and update the record")
-    # measured HBM bytes cannot fall below the algorithmic minimum, and wasted re-reads show
-    # up as a large ratio
-    assert 1.0 <= rec["bytes_per_launch"] / rec["alg_bytes_per_launch"] < 1.5
+    assert bench.TRAFFIC
+    for (precision, workload, tiling), rec in bench.TRAFFIC.items():
+        with open(bench.gemm_source(precision, tiling), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+        assert rec["sha256"] == digest, ("the source of %s tiling %d changed after its FETCH_SIZE / WRITE_SIZE "
+                                         "counters were taken: re-take them and update the record"
+                                         % (precision, tiling))
+        # measured HBM bytes cannot fall below the algorithmic minimum, and wasted re-reads
+        # show up as a large ratio
+        assert 1.0 <= rec["bytes_per_launch"] / rec["alg_bytes_per_launch"] < 1.5
