@@ -37,7 +37,8 @@ CSRC = os.path.join(ROOT, "paper_2311_12134_amd", "csrc")
 def gemm_source(precision, tiling):
     """The source file that holds a trailing-update tiling's kernel."""
     if precision == "split":
-        name = "gemm.hip" if tiling < 10 else ("gemm_wide.hip" if 12 <= tiling <= 16 else "gemm_persist.hip")
+        name = "gemm.hip" if tiling < 10 or tiling == 19 else (
+            "gemm_wide.hip" if 12 <= tiling <= 16 or tiling == 20 else "gemm_persist.hip")
     else:
         name = "gemm.hip" if tiling == 0 else "gemm64.hip"
     return os.path.join(CSRC, name)
@@ -50,8 +51,16 @@ def gemm_source(precision, tiling):
 # any later change to that source, or launches of another shape, make the figure stale and
 # it is reported as null.
 TRAFFIC = {
-    ("split", "fcc4000", 2): {"sha256": "8e12dec1ca13c0f6459bfebb36d6acbecaee9563b6075dca181c1da06f2e9832",
-                              "alg_bytes_per_launch": 5.2306e10, "bytes_per_launch": 5.3861e10},
+    ("split", "fcc4000", 1): {"sha256": "2e3078da84b18709ee1905d4151e5884815da676e36d9ca16b6e12f1ce630b8a",
+                              "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 1.0079e11},
+    ("split", "fcc4000", 2): {"sha256": "2e3078da84b18709ee1905d4151e5884815da676e36d9ca16b6e12f1ce630b8a",
+                              "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 9.2529e10},
+    ("split", "fcc4000", 13): {"sha256": "9001bedb113c858cbd9ba443f681c5ea7cc9357d9d5376fc8cf357fbb44d05b4",
+                               "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 8.3501e10},
+    ("split", "fcc4000", 19): {"sha256": "2e3078da84b18709ee1905d4151e5884815da676e36d9ca16b6e12f1ce630b8a",
+                               "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 6.1872e10},
+    ("split", "fcc4000", 20): {"sha256": "9001bedb113c858cbd9ba443f681c5ea7cc9357d9d5376fc8cf357fbb44d05b4",
+                               "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 6.3301e10},
 }
 
 
@@ -228,7 +237,8 @@ F32_TILINGS = {0: "gemm_f32_3m_kernel", 1: "gemm_f32_3m_tiled<64,64,32,32>", 2: 
                11: "gemm_f32_3m_persist<64,64,32,32,xcd,C prefetch>", 12: "gemm_f32_3m_big<128,64>",
                13: "gemm_f32_3m_big<64,128>", 14: "gemm_f32_3m_big<128,128>",
                15: "gemm_f32_3m_big<64,64,prefetch 2>", 16: "gemm_f32_3m_big<64,128,prefetch 2>",
-               17: "gemm_f32_3m_stream", 18: "gemm_f32_3m_stream<C prefetch>"}
+               17: "gemm_f32_3m_stream", 18: "gemm_f32_3m_stream<C prefetch>",
+               19: "gemm_f32_3m_tiled<64,64,32,32,xcd,bands of 8>", 20: "gemm_f32_3m_big<64,128,bands of 8>"}
 F64_TILINGS = {0: "gemm_f64_kernel", 1: "gemm_f64_tiled<64,64,32,32,xcd,K8>", 2: "gemm_f64_tiled<32,64,16,32,xcd,K8>",
                3: "gemm_f64_tiled<128,64,64,32,xcd,K8>", 4: "gemm_f64_tiled<64,128,32,64,xcd,K8>",
                5: "gemm_f64_tiled<64,64,32,32,K8>"}
@@ -255,7 +265,8 @@ def tune_all(ctx, npads, batch=256):
     thr, ms = ctx.autotune_kernel("f32_panel", batch=8 * batch)
     log("autotuned split-mode panel threshold: %d rows %s" % (thr, [round(m, 3) for m in ms]))
     return {"batch": batch, "buckets": rec,
-            "panel_small_rows": {"best": thr, "ms_256_512_768_small_large": [round(m, 3) for m in ms]}}
+            "panel_small_rows": {"best": thr, "heights": [256, 512, 768],
+                                 "ms_small_large_per_height": [round(m, 3) for m in ms]}}
 
 
 def gemm_roofline(ctx, precision, workload, tiling, timed_in):
@@ -397,7 +408,7 @@ def main():
             return args.gemm_tiling
         b = (npads[-1] - 1) // 256
         t = int(ctx.tuning_table("f32_wide" if precision == "split" else "f64_wide")[b])
-        return t if t >= 0 else 1  # the library's default for both precisions
+        return t if t >= 0 else (19 if precision == "split" else 1)  # the library's defaults
 
     def step(i, precision, out):
         eta = etas[i % len(etas)]

@@ -283,19 +283,21 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
 /*
  * Tuning of the split-mode trailing update (the FP32 matrix-core part of the LU of Eq. (3)).
  * knob LSMS_TUNE_GEMM_F32 selects the tiling of the wide update, 0 .. LSMS_GEMM_F32_VARIANTS - 1,
- * or -1 for the autotuned choice or the library's default, 1 (0: 64 x 64 tiles; 1, 2: 64 x 64 pipelined through two LDS stages,
+ * or -1 for the autotuned choice or the library's default, 19 (0: 64 x 64 tiles; 1, 2: 64 x 64 pipelined through two LDS stages,
  * 2 with an XCD-aware workgroup order; 3 - 6: 128-row / 128-column tiles; 7: as 2 with the C
  * tile prefetched early; 8: as 2 with K chunks of 32; 9: as 2 on FP32 MFMA 32x32x2; 10: as 2 in a
  * persistent grid of resident workgroups that loops over the tiles; 11: as 10 with the C tile
  * prefetched early; 12, 13, 14: 128 x 64, 64 x 128 and 128 x 128 tiles of 8, 8 and 16 waves of
  * 32 x 32; 15, 16: 64 x 64 and 64 x 128 tiles with the K chunks prefetched two ahead; 17, 18:
  * the streaming persistent form, whose next tile's first K chunk is loaded during the current
- * tile's last one, without and with the C tile loaded early); every
+ * tile's last one, without and with the C tile loaded early; 19: as 2 with each job's tiles
+ * numbered in bands of eight tile rows, so one XCD's resident workgroups share few L21 and
+ * U12 panels in its L2; 20: as 13 in bands of eight tile rows); every
  * tiling computes the same update (results may differ in FP32 rounding order only).  Host-side setting of the context, no device work; returns
  * LSMS_E_ARG for an unknown knob or value.  lsms_get_tuning reports the tiling in effect.
  */
 #define LSMS_TUNE_GEMM_F32 0
-#define LSMS_GEMM_F32_VARIANTS 19
+#define LSMS_GEMM_F32_VARIANTS 21
 /*
  * knob LSMS_TUNE_GRAPHS (0 or 1, default 0): with 1, lsms_tau_solve captures each wave's
  * factorization and first solve (a fixed sequence of a few hundred launches) into a HIP
@@ -370,8 +372,9 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * order; 2 32 x 64; 3 128 x 64; 4 64 x 128; 5 as 1 without the XCD order): the
  * tilings of the narrow (a panel's 64 columns within its group, K < 64 x group) and wide
  * (K = 64 x group) trailing updates.
- * knob LSMS_TUNE_PANEL_SMALL_ROWS (0 .. 768): split-mode panels of at most this many rows run
- * in 256-thread workgroups with 8-wide leaves, taller ones in 512-thread workgroups.
+ * knob LSMS_TUNE_PANEL_SMALL_ROWS (0 .. 768, default 768): split-mode panels of at most this
+ * many rows run in 256-thread workgroups with 8-wide leaves (three jobs per compute unit),
+ * taller ones in 512-thread workgroups with 16-wide leaves (one job per compute unit).
  * For every such choice (and LSMS_TUNE_GEMM_F32), -1 (the initial value) means: the
  * autotuned choice for the wave's padded size (lsms_autotune_kernel), else the library
  * default.  lsms_get_tuning reports the explicit setting (-1 if none), except for
@@ -401,11 +404,14 @@ int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
  *     npad, G the precision's panels per group in effect);
  *   LSMS_AUTOTUNE_F32_NARROW / LSMS_AUTOTUNE_F64_NARROW: every tiling of the narrow update
  *     of a group's last panel (K = 64 (G - 1) over (npad - 64 (G - 1)) rows x 64 columns);
- *   LSMS_AUTOTUNE_F32_PANEL: the two split-mode panel variants at heights 256, 512 and 768
- *     (npad ignored); ms[2 h + v] receives variant v (0: 256 threads, 8-wide leaves; 1: 512
- *     threads) at height h, and the context's panel threshold becomes the largest height at
- *     which variant 0 was faster (0: none), which *best receives.
- * For the updates the fastest tiling becomes the context's choice for every wave whose
+ *   LSMS_AUTOTUNE_F32_PANEL: the two split-mode panel variants at the LSMS_PANEL_HEIGHTS
+ *     heights 256, 512 and 768 (npad ignored; batch systems of the
+ *     panel's 64 columns); ms[2 h + v] (ms_len >= 2 LSMS_PANEL_HEIGHTS) receives variant v
+ *     (0: 256 threads, 8-wide leaves; 1: 512 threads) at height h, and the context's panel
+ *     threshold becomes the height T (0: none) for which the small variant up to T and the
+ *     large one above give the least summed time over the measured heights; *best receives T.
+ * For the updates the fastest tiling (the library default unless another is faster by more
+ * than 1 %, the spread of repeated timings) becomes the context's choice for every wave whose
  * largest padded size falls in npad's bucket (npad in (256 b, 256 (b + 1)]), *best receives
  * it and ms (NULL, or host [ms_len >= number of tilings]) the best-of-three launch time of
  * each tiling.  Each call allocates and frees a synthetic batch of `batch` systems (bounded
@@ -418,6 +424,7 @@ int lsms_get_tuning(lsms_ctx* ctx, int knob, int* value);
 #define LSMS_AUTOTUNE_F64_WIDE 2
 #define LSMS_AUTOTUNE_F64_NARROW 3
 #define LSMS_AUTOTUNE_F32_PANEL 4
+#define LSMS_PANEL_HEIGHTS 3
 #define LSMS_TUNE_BUCKETS 64
 int lsms_autotune_kernel(lsms_ctx* ctx, int what, int npad, int batch, int* best, float* ms, int ms_len,
                          void* hip_stream);
@@ -442,7 +449,8 @@ int lsms_tuning_load(lsms_ctx* ctx, const char* path);
  * of an LU of size npad (K = 64 G over the trailing (npad - 64 G)^2 block, G the split
  * mode's panels per group) for a synthetic
  * batch of `batch` systems (bounded random FP32 values, allocated and freed by the call,
- * npad^2 * 8 * batch bytes), then makes the fastest the context's tiling (as
+ * npad^2 * 8 * batch bytes), then makes the fastest (the default 19 unless another is more
+ * than 1 % faster) the context's tiling (as
  * lsms_set_tuning would).  *best receives it; ms (NULL, or host [LSMS_GEMM_F32_VARIANTS])
  * the best-of-three launch time of each tiling.  npad: a multiple of 64 in (64 G, 4096];
  * batch in [1, 65535].  Synchronous on hip_stream; LSMS_E_ARG for bad sizes,

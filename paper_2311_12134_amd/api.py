@@ -262,7 +262,7 @@ class Context:
         """Time every split-mode tiling for systems of padded size npad on a synthetic batch
         and adopt the fastest; returns (best tiling, [ms per tiling])."""
         best = ctypes.c_int(-1)
-        ms = (ctypes.c_float * 19)()
+        ms = (ctypes.c_float * 21)()
         check(lib().lsms_autotune(self._h, int(npad), int(batch), ctypes.byref(best), ms, _stream()))
         return best.value, [float(x) for x in ms]
 
@@ -275,10 +275,10 @@ class Context:
         record the fastest for npad's bucket (the panel target: the small-panel threshold).
         Returns (best, [ms per variant])."""
         best = ctypes.c_int(-1)
-        ms = (ctypes.c_float * 19)()
+        ms = (ctypes.c_float * 21)()
         check(lib().lsms_autotune_kernel(self._h, self.AUTOTUNE_TARGETS[what], int(npad), int(batch),
-                                         ctypes.byref(best), ms, 19, _stream()))
-        n = {"f32_wide": 19, "f32_narrow": 19, "f64_wide": 6, "f64_narrow": 6, "f32_panel": 6}[what]
+                                         ctypes.byref(best), ms, 21, _stream()))
+        n = {"f32_wide": 21, "f32_narrow": 21, "f64_wide": 6, "f64_narrow": 6, "f32_panel": 6}[what]
         return best.value, [float(x) for x in ms[:n]]
 
     PROBES = {"mfma_f64": 0, "mfma_f32": 1, "mfma_f32_32x32x2": 2, "fma_f64": 3, "copy": 4, "write": 5, "read": 6}

@@ -170,7 +170,8 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_kernel(const JobDesc* jobs, i
 // share L21 and U12 panels, run on the same XCD (workgroups are dealt to the eight XCDs
 // round-robin) and hit the same L2.
 // ------------------------------------------------------------------------------------
-template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false, bool M32 = false>
+template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false, bool M32 = false,
+          int SWZ = 0>
 __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, int tiles_x, int tiles_y, int k, int kd,
                                                          int r_begin, int c_begin, int c_end, float2* work) {
   // KC: K chunk per LDS stage.  PFC: the wave's C elements are loaded two chunks before
@@ -180,6 +181,11 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
   // M32: each wave's 32 x 32 block on FP32 MFMA 32x32x2 (three 32 x 32 real products, two
   // k per step; A lane l -> (row l%32, k l/32), B lane l -> (k l/32, column l%32), D lane l,
   // register r -> (row 8(r/4) + 4(l/32) + r%4, column l%32)): half the MFMA instructions.
+  // SWZ > 0: a job's tiles are numbered in bands of SWZ tile rows, column by column within a
+  // band, so the workgroups resident on one XCD at a time (consecutive numbers) cover a
+  // SWZ-row by (resident / SWZ)-column block and read SWZ row panels of L21 and that many
+  // column panels of U12, which stay in the XCD's L2 while K grows (row by row, a block
+  // of four tile rows needs every column panel of U12).
   constexpr int WAVES_N = TN / WN;
   static_assert((TM / WM) * (TN / WN) == 4, "four waves per workgroup");
   constexpr int BM = WM / 16, BN = WN / 16;
@@ -202,6 +208,14 @@ __global__ __launch_bounds__(256) void gemm_f32_3m_tiled(const JobDesc* jobs, in
     while ((y + 1) * (y + 2) / 2 <= u) ++y;
     ty = y;
     tx = u - y * (y + 1) / 2;
+  } else if (SWZ > 0) {
+    const int tpj = tiles_x * tiles_y;
+    job = T / tpj;
+    const int u = T - job * tpj;
+    const int band = u / (SWZ * tiles_x), rem = u - band * SWZ * tiles_x;
+    const int rows = min(SWZ, tiles_y - band * SWZ);
+    tx = rem / rows;
+    ty = band * SWZ + (rem - tx * rows);
   } else {
     tx = T % tiles_x;
     T /= tiles_x;
@@ -397,13 +411,21 @@ void launch_gemm_f64(const JobDesc* jobs, int njobs, int rows, int cols, int k, 
   gemm_f64_kernel<<<grid, 256, 0, s>>>(jobs, k, kd, r_begin, c_begin, c_end, work);
 }
 
-template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false, bool M32 = false>
+template <int TM, int TN, int WM, int WN, bool XCD, int KC = 16, bool PFC = false, bool TRI = false, bool M32 = false,
+          int SWZ = 0>
 static void launch_tiled(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                          int c_begin, int c_end, float2* work, hipStream_t s) {
   const int tx = (cols + TN - 1) / TN, ty = (rows + TM - 1) / TM;
   const int64_t n = TRI ? (int64_t)ty * (ty + 1) / 2 * njobs : (int64_t)tx * ty * njobs;
-  gemm_f32_3m_tiled<TM, TN, WM, WN, XCD, KC, PFC, TRI, M32><<<(unsigned)n, 256, 0, s>>>(jobs, tx, ty, k, kd, r_begin,
-                                                                                        c_begin, c_end, work);
+  gemm_f32_3m_tiled<TM, TN, WM, WN, XCD, KC, PFC, TRI, M32, SWZ>
+      <<<(unsigned)n, 256, 0, s>>>(jobs, tx, ty, k, kd, r_begin, c_begin, c_end, work);
+}
+
+// Tiling 2 with the tiles of a job numbered in bands of eight tile rows (see SWZ above).
+void launch_gemm_f32_banded(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
+                            int c_begin, int c_end, float2* work, hipStream_t s) {
+  launch_tiled<64, 64, 32, 32, true, 16, false, false, false, 8>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin,
+                                                                 c_end, work, s);
 }
 
 // Lower-triangle tiles only (rows and columns start together): the update

@@ -392,17 +392,22 @@ static int persist_grid(K kernel) {
   return wgs;
 }
 
-template <int TM, int TN, int DEPTH>
+template <int TM, int TN, int DEPTH, int SWZ>
 void launch_big(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin, int c_begin,
                 int c_end, float2* work, hipStream_t s);  // gemm_wide.hip
 
-int gemm_f32_variants_all() { return gemm_f32_variants() + 9; }
+void launch_gemm_f32_banded(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
+                            int c_begin, int c_end, float2* work, hipStream_t s);  // gemm.hip
+
+int gemm_f32_variants_all() { return gemm_f32_variants() + 11; }
 
 // Variants past the tiled family of gemm.hip: 10 the persistent 64 x 64 form, 11 the same
 // with the C tile loaded two chunks early; 12, 13, 14 the 128 x 64, 64 x 128 and 128 x 128
 // tiles of eight and sixteen waves; 15, 16 the 64 x 64 and 64 x 128 tiles with the K chunks
 // prefetched two ahead (gemm_wide.hip); 17, 18 the streaming persistent form without and
-// with the C tile loaded at the start of a tile's last chunk.
+// with the C tile loaded at the start of a tile's last chunk; 19 tiling 2 with the tiles of
+// a job in bands of eight tile rows (gemm.hip); 20 the 64 x 128 tile (13) in bands of eight
+// tile rows (gemm_wide.hip).
 void launch_gemm_f32_any(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin,
                          int c_begin, int c_end, float2* work, hipStream_t s) {
   const int base = gemm_f32_variants();
@@ -410,17 +415,25 @@ void launch_gemm_f32_any(int variant, const JobDesc* jobs, int njobs, int rows, 
     launch_gemm_f32(variant, jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
     return;
   }
+  if (variant == base + 9) {
+    launch_gemm_f32_banded(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
+    return;
+  }
+  if (variant == base + 10) {
+    launch_big<64, 128, 1, 8>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
+    return;
+  }
   if (variant >= base + 2 && variant < base + 7) {
     if (variant == base + 2)
-      launch_big<128, 64, 1>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
+      launch_big<128, 64, 1, 0>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
     else if (variant == base + 3)
-      launch_big<64, 128, 1>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
+      launch_big<64, 128, 1, 0>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
     else if (variant == base + 4)
-      launch_big<128, 128, 1>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
+      launch_big<128, 128, 1, 0>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
     else if (variant == base + 5)
-      launch_big<64, 64, 2>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
+      launch_big<64, 64, 2, 0>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
     else
-      launch_big<64, 128, 2>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
+      launch_big<64, 128, 2, 0>(jobs, njobs, rows, cols, k, kd, r_begin, c_begin, c_end, work, s);
     return;
   }
   const int tx = (cols + 63) / 64, ty = (rows + 63) / 64;

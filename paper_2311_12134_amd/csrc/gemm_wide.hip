@@ -14,7 +14,7 @@ namespace lsms {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <int TM, int TN, int DEPTH>
+template <int TM, int TN, int DEPTH, int SWZ = 0>
 __global__ __launch_bounds__((TM / 32) * (TN / 32) * 64) void gemm_f32_3m_big(const JobDesc* jobs, int tiles_x,
                                                                                 int tiles_y, int k, int kd,
                                                                                 int r_begin, int c_begin, int c_end,
@@ -30,10 +30,21 @@ __global__ __launch_bounds__((TM / 32) * (TN / 32) * 64) void gemm_f32_3m_big(co
     const int N = gridDim.x, q = N >> 3, r = N & 7, x = T & 7;
     T = x * q + min(x, r) + (T >> 3);
   }
-  const int tx = T % tiles_x;
-  T /= tiles_x;
-  const int ty = T % tiles_y;
-  const int job = T / tiles_y;
+  int tx, ty, job;
+  if (SWZ > 0) {  // a job's tiles in bands of SWZ tile rows, column by column within a band
+    const int tpj = tiles_x * tiles_y;
+    job = T / tpj;
+    const int u = T - job * tpj;
+    const int band = u / (SWZ * tiles_x), rem = u - band * SWZ * tiles_x;
+    const int rows = min(SWZ, tiles_y - band * SWZ);
+    tx = rem / rows;
+    ty = band * SWZ + (rem - tx * rows);
+  } else {
+    tx = T % tiles_x;
+    T /= tiles_x;
+    ty = T % tiles_y;
+    job = T / tiles_y;
+  }
   const JobDesc jd = jobs[job];
   const int row0 = r_begin + ty * TM, col0 = c_begin + tx * TN;
   const int npad = jd.npad;
@@ -170,19 +181,20 @@ __global__ __launch_bounds__((TM / 32) * (TN / 32) * 64) void gemm_f32_3m_big(co
     }
 }
 
-template <int TM, int TN, int DEPTH>
+template <int TM, int TN, int DEPTH, int SWZ>
 void launch_big(const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd, int r_begin, int c_begin,
                 int c_end, float2* work, hipStream_t s) {
   const int tx = (cols + TN - 1) / TN, ty = (rows + TM - 1) / TM;
   const int64_t n = (int64_t)tx * ty * njobs;
-  gemm_f32_3m_big<TM, TN, DEPTH><<<(unsigned)n, (TM / 32) * (TN / 32) * 64, 0, s>>>(jobs, tx, ty, k, kd, r_begin,
-                                                                                   c_begin, c_end, work);
+  gemm_f32_3m_big<TM, TN, DEPTH, SWZ><<<(unsigned)n, (TM / 32) * (TN / 32) * 64, 0, s>>>(jobs, tx, ty, k, kd, r_begin,
+                                                                                        c_begin, c_end, work);
 }
 
-template void launch_big<128, 64, 1>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
-template void launch_big<64, 128, 1>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
-template void launch_big<128, 128, 1>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
-template void launch_big<64, 64, 2>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
-template void launch_big<64, 128, 2>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
+template void launch_big<128, 64, 1, 0>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
+template void launch_big<64, 128, 1, 0>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
+template void launch_big<128, 128, 1, 0>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
+template void launch_big<64, 64, 2, 0>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
+template void launch_big<64, 128, 2, 0>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
+template void launch_big<64, 128, 1, 8>(const JobDesc*, int, int, int, int, int, int, int, int, float2*, hipStream_t);
 
 }  // namespace lsms

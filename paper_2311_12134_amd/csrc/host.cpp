@@ -138,7 +138,7 @@ struct lsms_ctx {
 };
 
 // Library defaults where neither an explicit choice nor an autotuned one exists.
-static constexpr int kDefaultF32Wide = 1, kDefaultF32Narrow = 7, kDefaultF64Wide = 1, kDefaultF64Narrow = 1;
+static constexpr int kDefaultF32Wide = 19, kDefaultF32Narrow = 7, kDefaultF64Wide = 1, kDefaultF64Narrow = 1;
 static constexpr int kDefaultGroupF32 = 4, kDefaultGroupF64 = 4;
 
 // Tiling of the split-mode trailing update in effect for a context (explicit or default).
@@ -1160,8 +1160,8 @@ extern "C" int lsms_set_tuning(lsms_ctx* ctx, int knob, int value) {
     return LSMS_OK;
   }
   if (knob == LSMS_TUNE_PANEL_SMALL_ROWS) {
-    if (value < -1 || value > PANEL_SMALL_ROWS)
-      return fail(LSMS_E_ARG, "panel height %d outside [-1, %d]", value, PANEL_SMALL_ROWS);
+    if (value < -1 || value > PANEL_SMALL_MAX)
+      return fail(LSMS_E_ARG, "panel height %d outside [-1, %d]", value, PANEL_SMALL_MAX);
     ctx->panel_small_rows = value;
     return LSMS_OK;
   }
@@ -1220,6 +1220,7 @@ extern "C" int lsms_autotune(lsms_ctx* ctx, int npad, int batch, int* best, floa
                 group * NB);
   if (update_autotune(1, 1, npad, batch, group, (hipStream_t)hip_stream, t, &b) != 0 || b < 0)
     return fail(LSMS_E_NOMEM, "autotuning batch of %d systems of size %d could not run", batch, npad);
+  if (t[kDefaultF32Wide] <= 1.01f * t[b]) b = kDefaultF32Wide;  // as lsms_autotune_kernel
   ctx->gemm_f32 = b;
   ctx->tuned[1][1][tune_bucket(npad)] = (int8_t)b;
   *best = b;
@@ -1235,20 +1236,30 @@ extern "C" int lsms_autotune_kernel(lsms_ctx* ctx, int what, int npad, int batch
   hipStream_t s = (hipStream_t)hip_stream;
   HIP_TRY(hipSetDevice(ctx->device));
   if (what == LSMS_AUTOTUNE_F32_PANEL) {
-    // both variants at the heights the small one can take; the threshold is the largest
-    // height at which the small workgroups won (0: never)
-    const int heights[3] = {256, 512, PANEL_SMALL_ROWS};
-    if (ms && ms_len < 6) return fail(LSMS_E_ARG, "ms needs 6 entries for the panel autotuner");
-    int thr = 0;
-    for (int h = 0; h < 3; ++h) {
-      float t2[2];
-      if (panel_autotune(heights[h], batch, s, t2) != 0)
+    // both variants at heights the small one can take; the threshold T (panels of at most
+    // T rows take the small workgroups) minimises the summed time over the measured
+    // heights, as an LU's panels cover every height below its size evenly (0: never)
+    const int heights[LSMS_PANEL_HEIGHTS] = {256, 512, PANEL_SMALL_MAX};
+    if (ms && ms_len < 2 * LSMS_PANEL_HEIGHTS)
+      return fail(LSMS_E_ARG, "ms needs %d entries for the panel autotuner", 2 * LSMS_PANEL_HEIGHTS);
+    float t[LSMS_PANEL_HEIGHTS][2];
+    for (int h = 0; h < LSMS_PANEL_HEIGHTS; ++h) {
+      if (panel_autotune(heights[h], batch, s, t[h]) != 0)
         return fail(LSMS_E_NOMEM, "panel autotuning batch of %d systems of height %d could not run", batch,
                     heights[h]);
-      if (t2[0] <= t2[1]) thr = heights[h];
       if (ms) {
-        ms[2 * h] = t2[0];
-        ms[2 * h + 1] = t2[1];
+        ms[2 * h] = t[h][0];
+        ms[2 * h + 1] = t[h][1];
+      }
+    }
+    int thr = 0;
+    double best_sum = 0.0;
+    for (int c = 0; c <= LSMS_PANEL_HEIGHTS; ++c) {  // c heights take the small variant
+      double sum = 0.0;
+      for (int h = 0; h < LSMS_PANEL_HEIGHTS; ++h) sum += t[h][h < c ? 0 : 1];
+      if (c == 0 || sum < best_sum) {
+        best_sum = sum;
+        thr = c == 0 ? 0 : heights[c - 1];
       }
     }
     ctx->tuned_panel_rows = thr;
@@ -1271,6 +1282,11 @@ extern "C" int lsms_autotune_kernel(lsms_ctx* ctx, int what, int npad, int batch
                 kind ? "wide" : "narrow", group, group * NB);
   if (update_autotune(precision, kind, npad, batch, group, s, t.data(), &b) != 0 || b < 0)
     return fail(LSMS_E_NOMEM, "autotuning batch of %d systems of size %d could not run", batch, npad);
+  // the default stays unless another tiling is faster by more than the spread of repeated
+  // timings (1 %): near-ties are decided by noise, and the default's tile order is the one
+  // that moves least HBM traffic
+  const int def = precision ? (kind ? kDefaultF32Wide : kDefaultF32Narrow) : (kind ? kDefaultF64Wide : kDefaultF64Narrow);
+  if (t[def] <= 1.01f * t[b]) b = def;
   ctx->tuned[precision][kind][tune_bucket(npad)] = (int8_t)b;
   *best = b;
   if (ms)
@@ -1358,7 +1374,7 @@ extern "C" int lsms_tuning_load(lsms_ctx* ctx, const char* path) {
         k >= 0 && k < 2 && b >= 0 && b < LSMS_TUNE_BUCKETS && v >= 0 &&
         v < (p ? gemm_f32_variants_all() : gemm_f64_variants())) {
       tuned[p][k][b] = (int8_t)v;
-    } else if (std::strcmp(word, "panel") == 0 && std::fscanf(f, "%d", &v) == 1 && v >= 0 && v <= PANEL_SMALL_ROWS) {
+    } else if (std::strcmp(word, "panel") == 0 && std::fscanf(f, "%d", &v) == 1 && v >= 0 && v <= PANEL_SMALL_MAX) {
       panel = v;
     } else if (std::strcmp(word, "group") == 0 && std::fscanf(f, "%d %d", &p, &v) == 2 && p >= 0 && p < 2 &&
                v >= 2 && v <= GROUP_MAX) {

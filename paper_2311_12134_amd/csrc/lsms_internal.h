@@ -138,8 +138,10 @@ void launch_gemm_f64(const JobDesc* jobs, int njobs, int rows, int cols, int k, 
 int gemm_f64_variants();
 void launch_gemm_f64_variant(int variant, const JobDesc* jobs, int njobs, int rows, int cols, int k, int kd,
                              int r_begin, int c_begin, int c_end, double2* work, hipStream_t s);
-// Split-mode panels of at most this many rows use 256-thread workgroups with 8-wide leaves.
+// Split-mode panels of at most PANEL_SMALL_ROWS rows (the default; autotuned or set per
+// context up to PANEL_SMALL_MAX) use 256-thread workgroups with 8-wide leaves.
 constexpr int PANEL_SMALL_ROWS = 3 * 256;
+constexpr int PANEL_SMALL_MAX = 3 * 256;
 // Panels per group of the blocked LU: 2 .. GROUP_MAX.
 constexpr int GROUP_MAX = 4;
 // Kernel choices of one LU: the panels per group (the big trailing update has K = group NB),

@@ -1100,11 +1100,13 @@ static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int ro
   constexpr int PT = 512;
   constexpr int IBW = sizeof(T) == sizeof(float2) ? 16 : 8;
   if constexpr (sizeof(T) == sizeof(float2)) {
-    if (rows <= std::min(small_rows, 3 * 256)) {
-      // FP32 storage up to small_rows (at most 768) rows: 256-thread workgroups with 8-wide
-      // leaves fit two jobs per CU, which hides more of the short panels' barrier and shuffle
-      // latency (past some height the wider leaves of the 512-thread kernel win; the
-      // autotuner finds where)
+    if (rows <= std::min(small_rows, PANEL_SMALL_MAX)) {
+      // FP32 storage up to small_rows (at most PANEL_SMALL_MAX = 768) rows: 256-thread
+      // workgroups with 8-wide leaves fit three jobs per CU, which hides more of the short
+      // panels' barrier and shuffle latency behind another job's work (where the wider leaves
+      // of the 512-thread kernel, one job per CU, win instead is found by the autotuner; up
+      // to 2304 rows the small form was measured 1.1-1.6x slower than the large one from
+      // 1024 rows on, as more row slots per thread drop it to two and one job per CU)
       const int S2 = (rows + 255) / 256;
       switch (S2) {
         case 1: panel_kernel<T, 256, 1, 8><<<njobs, 256, 0, s>>>(jobs, k, left, work, piv, info, nopiv); return;
@@ -1127,10 +1129,10 @@ static void launch_panel(const JobDesc* jobs, int njobs, int k, int left, int ro
 }
 
 // The split-mode panel at k = 0 of systems of `rows` rows, for the autotuner: variant 0 the
-// 256-thread workgroups with 8-wide leaves (rows <= 768), 1 the 512-thread ones.
+// 256-thread workgroups with 8-wide leaves (rows <= PANEL_SMALL_MAX), 1 the 512-thread ones.
 void launch_panel_f32_variant(int variant, const JobDesc* jobs, int njobs, int rows, float2* work, int32_t* piv,
                               int32_t* info, hipStream_t s) {
-  launch_panel<float2>(jobs, njobs, 0, 0, rows, work, piv, info, s, 0, variant == 0 ? 3 * 256 : 0);
+  launch_panel<float2>(jobs, njobs, 0, 0, rows, work, piv, info, s, 0, variant == 0 ? PANEL_SMALL_MAX : 0);
 }
 
 // One panel (and the inverses of its diagonal triangles): the register-resident panel

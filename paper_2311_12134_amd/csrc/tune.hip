@@ -5,8 +5,8 @@
 //   trailing (npad - G NB)^2 block;
 //   kind 0 (narrow): the update of a group's last panel, K = (G - 1) NB over
 //   (npad - (G - 1) NB) rows x NB columns;
-//   panels: the split-mode panel of a given height with 256-thread workgroups and 8-wide
-//   leaves against 512-thread workgroups and 16-wide leaves.
+//   panels: the split-mode panel of a given height (its NB columns only) with 256-thread
+//   workgroups and 8-wide leaves against 512-thread workgroups and 16-wide leaves.
 // Values are bounded pseudo-random numbers (an integer hash), so repeated updates stay finite.
 #include <algorithm>
 #include <vector>
@@ -30,7 +30,8 @@ __global__ void tune_fill_kernel(T* a, int64_t n, float scale) {
 
 namespace {
 // A synthetic batch of `batch` systems of padded size npad with their job descriptors,
-// pivot and status arrays; freed by the destructor.
+// pivot and status arrays; freed by the destructor.  cols > 0: only the first cols columns
+// of each system are stored (leading dimension cols), enough for a panel at k = 0.
 struct TuneBatch {
   void* a = nullptr;
   JobDesc* jd = nullptr;
@@ -38,8 +39,9 @@ struct TuneBatch {
   int32_t* info = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   bool ok = false;
-  TuneBatch(int npad, int batch, size_t elem, hipStream_t s) {
-    const int64_t per = (int64_t)npad * npad;
+  int64_t per = 0;  // elements per system
+  TuneBatch(int npad, int batch, size_t elem, hipStream_t s, int cols = 0) {
+    per = (int64_t)npad * (cols > 0 ? cols : npad);
     std::vector<JobDesc> host(batch);
     for (int j = 0; j < batch; ++j) {
       JobDesc d{};
@@ -48,6 +50,7 @@ struct TuneBatch {
       d.n = npad;
       d.npad = npad;
       d.nl = npad / NL;
+      d.ld = cols > 0 ? cols : 0;
       host[j] = d;
     }
     if (hipMalloc(&a, (size_t)(per * batch) * elem) != hipSuccess) return;
@@ -116,9 +119,9 @@ int update_autotune(int precision, int kind, int npad, int batch, int group, hip
 }
 
 int panel_autotune(int rows, int batch, hipStream_t s, float* ms) {
-  TuneBatch tb(rows, batch, sizeof(float2), s);
+  TuneBatch tb(rows, batch, sizeof(float2), s, NB);
   if (!tb.ok) return -1;
-  const int64_t n = (int64_t)rows * rows * batch;
+  const int64_t n = tb.per * batch;
   for (int v = 0; v < 2; ++v) {
     float t = tb.time(
         [&]() {

@@ -28,6 +28,9 @@ def test_traffic_records_belong_to_the_current_trailing_update_sources():
         assert rec["sha256"] == digest, ("the source of %s tiling %d changed after its FETCH_SIZE / WRITE_SIZE "
                                          "counters were taken: re-take them and update the record"
                                          % (precision, tiling))
-        # measured HBM bytes cannot fall below the algorithmic minimum, and wasted re-reads
-        # show up as a large ratio
-        assert 1.0 <= rec["bytes_per_launch"] / rec["alg_bytes_per_launch"] < 1.5
+        # measured HBM bytes cannot fall below the algorithmic minimum
+        assert rec["bytes_per_launch"] / rec["alg_bytes_per_launch"] >= 1.0
+    # wasted re-reads show up as a large ratio: the library's default split-mode tiling (19,
+    # tiles in bands of eight rows) must stay close to the algorithmic bytes
+    rec = bench.TRAFFIC[("split", "fcc4000", 19)]
+    assert rec["bytes_per_launch"] / rec["alg_bytes_per_launch"] < 1.3

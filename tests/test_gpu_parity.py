@@ -188,7 +188,7 @@ def test_batched_lu_solve_random_and_singular(lctx):
     assert info[-1] > 0
 
 
-@pytest.mark.parametrize("tiling", list(range(19)))
+@pytest.mark.parametrize("tiling", list(range(21)))
 def test_split_lu_every_gemm_tiling(lctx, tiling):
     """FP32 factors without refinement, uneven batch whose trailing blocks end on 64-row and
     64-column halves of the 128-wide tiles: every tiling of the split-mode update must give
@@ -230,7 +230,7 @@ def _random_systems(seed, sizes, scale_diag=2.0):
     return mats, rhs, refs
 
 
-@pytest.mark.parametrize("knob,nv", [("f64_wide", 6), ("f64_narrow", 6), ("f32_narrow", 19)])
+@pytest.mark.parametrize("knob,nv", [("f64_wide", 6), ("f64_narrow", 6), ("f32_narrow", 21)])
 def test_lu_every_update_tiling(lctx, knob, nv):
     """Every tiling of the FP64 wide and narrow trailing updates (FP64 solve to 1e-10) and of
     the split-mode narrow update (FP32 factors without refinement, to FP32 rounding) on an
@@ -324,9 +324,10 @@ def test_groups_end_to_end(lctx, group, case):
 
 @pytest.mark.parametrize("rows", [0, 256, 512, 768])
 def test_split_panel_variant_threshold(lctx, rows):
-    """The split-mode panel's small-workgroup variant used up to 0, 256, 512 or 768 rows: the
-    same solves to FP32 rounding."""
-    mats, rhs, refs = _random_systems(17, [1000, 700, 450, 300, 129])
+    """The split-mode panel's small-workgroup variant used up to 0, 256, 512 or 768 rows on a
+    batch of sizes up to 2300 (its panels run through every row-slot count of both variants):
+    the same solves to FP32 rounding."""
+    mats, rhs, refs = _random_systems(17, [2300, 1800, 1000, 450, 129])
     lctx.set_knob("panel_small_rows", rows)
     try:
         info = lctx.batched_lu_solve(mats, rhs, precision="split").cpu().numpy()
@@ -361,9 +362,11 @@ def test_autotuned_choices_per_bucket_at_parity(tmp_path):
             npad = max(n for n in npads if (n - 1) // 256 == b)
             for what in ("f32_wide", "f32_narrow", "f64_wide", "f64_narrow"):
                 best, ms = ctx.autotune_kernel(what, npad, batch=64)
-                assert ms[best] == min(ms) and ctx.tuning_table(what)[b] == best
+                # the fastest, or the default within 1 % of it
+                assert ms[best] <= 1.01 * min(ms) and ctx.tuning_table(what)[b] == best
         thr, ms = ctx.autotune_kernel("f32_panel", batch=64)
         assert thr in (0, 256, 512, 768) and ctx.tuning_table("f32_panel") == thr
+        assert len(ms) == 6 and all(m > 0 for m in ms)
         la, lp, phase, species, J = _device_inputs(w, liz)
         sizes = np.diff(liz.ptr)
         atoms = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 1000,
@@ -534,9 +537,9 @@ def test_graph_replay_matches_eager(lctx, name, precision):
 
 def test_autotune_picks_fastest_tiling(lctx):
     best, ms = lctx.autotune(npad=448, batch=32)
-    assert 0 <= best < 19 and len(ms) == 19
+    assert 0 <= best < 21 and len(ms) == 21
     assert all(np.isfinite(m) and m > 0 for m in ms)
-    assert ms[best] == min(ms)
+    assert ms[best] == min(ms) or (best == 19 and ms[19] <= 1.01 * min(ms))  # the default within 1 %
     try:
         assert lctx.gemm_tiling() == best
     finally:
