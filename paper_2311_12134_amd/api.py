@@ -219,7 +219,7 @@ class Context:
         check(lib().lsms_set_tuning(self._h, 1, 1 if on else 0))
 
     def set_lookahead(self, on=True):
-        """Factor the next pair's first panel on a second stream during the trailing update."""
+        """Factor the next group's first panel on a second stream during the trailing update."""
         check(lib().lsms_set_tuning(self._h, 4, 1 if on else 0))
 
     def set_symmetric(self, on=True):

@@ -115,7 +115,7 @@ struct lsms_ctx {
   bool conj_symmetry = false;  // solve z+ only and derive z- (tau(z-) = P conj tau(z+) P)
   int tslu_chunk = 2048;       // rows per chunk of the tall-panel tournament
   DevBuf tall;                 // tall-panel scratch
-  bool lookahead = false;      // factor the next pair's first panel on a side stream
+  bool lookahead = false;      // factor the next group's first panel on a side stream
   bool symmetric = false;      // split mode: symmetric form and L D L^T instead of LU
   DevBuf ldlt;                 // scratch of its tall panels
   SideStream side;             // created on first use
