@@ -256,11 +256,14 @@ def tune_all(ctx, npads, batch=256):
     for b, n in sorted(buckets.items()):
         entry = {"bucket": b, "npad_range": [256 * b + 1, 256 * (b + 1)], "tuned_at_npad": n}
         for what in ("f32_wide", "f32_narrow", "f64_wide", "f64_narrow"):
+            if n <= 64 * ctx.knob("group_f32" if what.startswith("f32") else "group_f64"):
+                continue  # matrices this small have no update of the autotuner's shapes
             best, ms = ctx.autotune_kernel(what, n, batch=batch)
             entry[what] = {"best": best, "ms": [round(m, 3) for m in ms]}
         rec.append(entry)
         log("autotuned bucket %d (npad %d): %s" % (b, n, {k: entry[k]["best"] for k in
-                                                         ("f32_wide", "f32_narrow", "f64_wide", "f64_narrow")}))
+                                                         ("f32_wide", "f32_narrow", "f64_wide", "f64_narrow")
+                                                         if k in entry}))
     # the panel runs one workgroup per system, so its batch must fill the chip several times over
     thr, ms = ctx.autotune_kernel("f32_panel", batch=8 * batch)
     log("autotuned split-mode panel threshold: %d rows %s" % (thr, [round(m, 3) for m in ms]))
