@@ -134,6 +134,32 @@ __device__ inline void ylm_column(int m, double x, double y, double z, double* Y
   }
 }
 
+// (-4 pi i kappa) i^l h_l(kappa d) for l = 0 .. 6 into H[0 .. 6]: h0 = -i e^{ix}/x,
+// h1 = -e^{ix}(x + i)/x^2 (x = kappa d), then the upward recurrence
+// h_{l+1} = (2l + 1)/x h_l - h_{l-1}.
+__device__ inline void hankel_terms(double2 kappa, double dist, double2* H) {
+  const double2 x = make_double2(kappa.x * dist, kappa.y * dist);
+  double sx, cx;
+  sincos(x.x, &sx, &cx);
+  const double ex = exp(-x.y);
+  const double2 eix = make_double2(ex * cx, ex * sx);
+  const double2 ix = cinv(x);
+  const double2 pre = make_double2(4.0 * M_PI * kappa.y, -4.0 * M_PI * kappa.x);  // -4 pi i kappa
+  double2 hm = cmul(make_double2(eix.y, -eix.x), ix);                             // h0
+  const double2 tq = cmul(eix, make_double2(x.x, x.y + 1.0));
+  double2 h = cmul(make_double2(-tq.x, -tq.y), cmul(ix, ix));                      // h1
+  H[0] = cmul(pre, hm);
+  double2 ph = make_double2(0.0, 1.0);  // i^l
+  H[1] = cmul(cmul(pre, ph), h);
+  for (int l = 1; l < 6; ++l) {
+    const double2 hn = csub(cmul(make_double2((2 * l + 1) * ix.x, (2 * l + 1) * ix.y), h), hm);
+    hm = h;
+    h = hn;
+    ph = make_double2(-ph.y, ph.x);
+    H[l + 1] = cmul(cmul(pre, ph), h);
+  }
+}
+
 // Pair p of the upper triangle a <= b < n of an n x n grid, numbered row by row (row a
 // starts at a n - a (a - 1) / 2); p past the end gives some a <= b, unused.
 __device__ inline void pair_of(int p, int n, int& a, int& b) {
@@ -156,10 +182,14 @@ __device__ inline void pair_of(int p, int n, int& a, int& b) {
 // slot-dealt Gaunt terms, applies i^{l - l'}, stages g^{ab} in LDS and writes the rows of
 // -t_a g^{ab} and of -t_b (g^{ab})^T.  Diagonal and padding blocks are the identity / zero.
 // spm != nullptr: the symmetric form, blocks -s_a g_ab s_b (s = t^{1/2}) instead of -t_a g_ab.
+// vtab != nullptr (split mode): also the FP64 contraction v^{ab} = i^{-(l - l')} g^{ab} of each
+// pair a < b, symmetric in (L, L') (the Gaunt coefficients are), packed as its upper triangle
+// (vblock_index), for the refinement's residual: 2176 bytes per pair instead of the 8 KB of
+// the two FP64 blocks of M.
 template <typename T>
 __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, const double* liz_pos,
                                                        const int32_t* liz_atom, const double2* tpm, double2 kp,
-                                                       double2 km, T* work, double2* m64, const double2* spm) {
+                                                       double2 km, T* work, double2* vtab, const double2* spm) {
   constexpr int BPW = 64;
   __shared__ double s_coef[4][64][GT];
   __shared__ uint16_t s_l3[4][64][GT];
@@ -191,28 +221,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
       double* Y = &s_Y[q][0];
       if (part == 3) {
         ylm_column(3, rx * inv, ry * inv, rz * inv, Y);
-        // h_l(x), x = kappa |R|: h0 = -i e^{ix}/x, h1 = -e^{ix}(x + i)/x^2, upward recurrence;
-        // stored times (-4 pi i kappa) i^l
-        const double2 x = make_double2(kappa.x * dist, kappa.y * dist);
-        double sx, cx;
-        sincos(x.x, &sx, &cx);
-        const double ex = exp(-x.y);
-        const double2 eix = make_double2(ex * cx, ex * sx);
-        const double2 ix = cinv(x);
-        const double2 pre = make_double2(4.0 * M_PI * kappa.y, -4.0 * M_PI * kappa.x);  // -4 pi i kappa
-        double2 hm = cmul(make_double2(eix.y, -eix.x), ix);                             // h0
-        const double2 tq = cmul(eix, make_double2(x.x, x.y + 1.0));
-        double2 h = cmul(make_double2(-tq.x, -tq.y), cmul(ix, ix));                      // h1
-        s_H[q][0] = cmul(pre, hm);
-        double2 ph = make_double2(0.0, 1.0);  // i^l
-        s_H[q][1] = cmul(cmul(pre, ph), h);
-        for (int l = 1; l < 6; ++l) {
-          const double2 hn = csub(cmul(make_double2((2 * l + 1) * ix.x, (2 * l + 1) * ix.y), h), hm);
-          hm = h;
-          h = hn;
-          ph = make_double2(-ph.y, ph.x);
-          s_H[q][l + 1] = cmul(cmul(pre, ph), h);
-        }
+        hankel_terms(kappa, dist, &s_H[q][0]);
       } else {
         ylm_column(part, rx * inv, ry * inv, rz * inv, Y);
         ylm_column(part + 4, rx * inv, ry * inv, rz * inv, Y);
@@ -240,6 +249,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
           g.x += cy * h.x;
           g.y += cy * h.y;
         }
+        if (vtab && L <= Lp) vtab[jd.v_off + (int64_t)pp * VBLOCK + vblock_index(L, Lp)] = g;
         // i^{l - l'}
         s_G[wave][L][Lp] = e == 0 ? g : e == 1 ? make_double2(-g.y, g.x) : e == 2 ? make_double2(-g.x, -g.y)
                                                                                     : make_double2(g.y, -g.x);
@@ -258,12 +268,10 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
         const double2 gab = s_G[wave][L][Lc];
         const double2 vab = spm ? cmul(cmul(sa[lidx(L)], gab), sb[lidx(Lc)]) : cmul(ta[lidx(L)], gab);
         st2(work + jd.a_off + base_ab + (int64_t)L * jd.npad + Lc, make_double2(-vab.x, -vab.y));
-        if (m64) m64[jd.m_off + base_ab + (int64_t)L * jd.npad + Lc] = make_double2(-vab.x, -vab.y);
         // block (b, a): g^{ba}_{L Lc} = g^{ab}_{Lc L}
         const double2 gba = s_G[wave][Lc][L];
         const double2 vba = spm ? cmul(cmul(sb[lidx(L)], gba), sa[lidx(Lc)]) : cmul(tb[lidx(L)], gba);
         st2(work + jd.a_off + base_ba + (int64_t)L * jd.npad + Lc, make_double2(-vba.x, -vba.y));
-        if (m64) m64[jd.m_off + base_ba + (int64_t)L * jd.npad + Lc] = make_double2(-vba.x, -vba.y);
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -273,11 +281,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
         const int L = Lr + 4 * r;
         const double2 v = make_double2((a == b && L == Lc) ? 1.0 : 0.0, 0.0);
         st2(work + jd.a_off + base_ab + (int64_t)L * jd.npad + Lc, v);
-        if (m64) m64[jd.m_off + base_ab + (int64_t)L * jd.npad + Lc] = v;
-        if (a != b) {
-          st2(work + jd.a_off + base_ba + (int64_t)L * jd.npad + Lc, v);
-          if (m64) m64[jd.m_off + base_ba + (int64_t)L * jd.npad + Lc] = v;
-        }
+        if (a != b) st2(work + jd.a_off + base_ba + (int64_t)L * jd.npad + Lc, v);
       }
     }
   }
@@ -285,18 +289,18 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
 
 void launch_assemble_f64(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
                          const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, double2* work,
-                         hipStream_t s) {
+                         const double2* spm, hipStream_t s) {
   const int nbp = npad_max / NL;
   dim3 grid((nbp * (nbp + 1) / 2 + 63) / 64, njobs);
-  assemble_kernel<double2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, nullptr, nullptr);
+  assemble_kernel<double2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, nullptr, spm);
 }
 
 void launch_assemble_split(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
                            const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, float2* work,
-                           double2* m64, const double2* spm, hipStream_t s) {
+                           double2* vtab, const double2* spm, hipStream_t s) {
   const int nbp = npad_max / NL;
   dim3 grid((nbp * (nbp + 1) / 2 + 63) / 64, njobs);
-  assemble_kernel<float2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, m64, spm);
+  assemble_kernel<float2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, vtab, spm);
 }
 
 // B = E0 t_centre: rows (0, L) carry t_l of the centre on the diagonal.

@@ -131,6 +131,7 @@ struct lsms_ctx {
   size_t pinned_bytes = 0;
   int32_t* pinned_flag = nullptr;  // host-visible counter read back between refinement sweeps
   DevBuf fallback;                 // job list of the FP64 fallback
+  DevBuf fallback_mat;             // its matrix when a wave's matrix area cannot hold one
   bool pipeline = false;           // alternate waves between two streams (see lsms_tau_solve)
   int cu_count = 1;                // compute units of the device (wave sizes are trimmed to multiples)
   hipStream_t pipe = nullptr;      // the second stream (non-blocking, default priority)
@@ -361,6 +362,7 @@ extern "C" int lsms_destroy(lsms_ctx* ctx) {
   if (ctx->pinned) hipHostFree(ctx->pinned);
   if (ctx->pinned_flag) hipHostFree(ctx->pinned_flag);
   if (ctx->fallback.p) hipFree(ctx->fallback.p);
+  if (ctx->fallback_mat.p) hipFree(ctx->fallback_mat.p);
   if (ctx->tall.p) hipFree(ctx->tall.p);
   if (ctx->ldlt.p) hipFree(ctx->ldlt.p);
   for (auto& kv : ctx->graph_cache) hipGraphExecDestroy(kv.second);
@@ -531,14 +533,15 @@ extern "C" int lsms_build_liz_subset(lsms_ctx* ctx, int32_t n_atoms, const doubl
 static inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct JobBytes {
-  int64_t a, m, x, r, piv;
+  int64_t a, v, x, r, piv;
 };
 
 static JobBytes job_bytes(int npad, int precision) {
   JobBytes b;
   const int64_t n2 = (int64_t)npad * npad;
   b.a = align_up(n2 * (precision == LSMS_SPLIT ? 8 : 16), 256);
-  b.m = precision == LSMS_SPLIT ? align_up(n2 * 16, 256) : 0;
+  const int64_t nb = npad / NL;
+  b.v = precision == LSMS_SPLIT ? align_up(nb * (nb + 1) / 2 * VBLOCK * 16, 256) : 0;
   b.x = align_up((int64_t)npad * NRHS_MAX * 16, 256);
   b.r = precision == LSMS_SPLIT ? b.x : 0;
   b.piv = align_up(piv_ints(npad) * 4, 256);
@@ -567,22 +570,25 @@ struct Wave {
 // Jobs (sorted by size) grouped into waves of at most `limit` bytes.  A wave that the limit
 // cuts is trimmed to a multiple of `round` jobs (the compute units: the panel, inverse and
 // diagonal-solve launches run one workgroup per job, one per compute unit at a time), so no
-// wave but the last ends in a nearly empty round of those latency-bound launches.
-static std::vector<Wave> make_waves(std::vector<JobDesc>& jobs, int precision, int64_t limit, bool single,
-                                    int round = 1) {
+// wave but the last ends in a nearly empty round of those latency-bound launches.  The waves
+// are then evened out: with w waves needed, each takes about 1/w of the jobs (rounded to the
+// same multiple), so that the last is not a small remainder whose launches fill the chip
+// poorly.
+static std::vector<Wave> make_waves_capped(std::vector<JobDesc>& jobs, int precision, int64_t limit, bool single,
+                                           int round, int cap) {
   std::vector<Wave> waves;
   const int n = (int)jobs.size();
   std::vector<int64_t> need(n);
   for (int j = 0; j < n; ++j) {
     JobBytes jb = job_bytes(jobs[j].npad, precision);
-    need[j] = jb.a + jb.m + jb.x + jb.r + jb.piv;
+    need[j] = jb.a + jb.v + jb.x + jb.r + jb.piv;
   }
   int b = 0;
   int64_t acc = 0;
   for (int j = 0; j < n; ++j) {
-    if (!single && j > b && (acc + need[j] > limit || j - b >= 8192)) {
+    if (!single && j > b && (acc + need[j] > limit || j - b >= cap)) {
       int e = j;
-      if (round > 1 && j - b > round) e = b + (j - b) / round * round;
+      if (round > 1 && j - b > round && j - b < cap) e = b + (j - b) / round * round;
       int64_t bytes = 0;
       for (int q = b; q < e; ++q) bytes += need[q];
       waves.push_back({b, e, bytes});
@@ -596,17 +602,31 @@ static std::vector<Wave> make_waves(std::vector<JobDesc>& jobs, int precision, i
   return waves;
 }
 
+static std::vector<Wave> make_waves(std::vector<JobDesc>& jobs, int precision, int64_t limit, bool single,
+                                    int round = 1) {
+  std::vector<Wave> waves = make_waves_capped(jobs, precision, limit, single, round, 8192);
+  const int nw = (int)waves.size();
+  if (single || nw < 2) return waves;
+  const int n = (int)jobs.size();
+  int cap = (n + nw - 1) / nw;
+  if (round > 1) cap = (cap + round - 1) / round * round;
+  std::vector<Wave> even = make_waves_capped(jobs, precision, limit, single, round, std::min(cap, 8192));
+  return even.size() <= waves.size() ? even : waves;
+}
+
 // Offsets (complex elements for matrices / blocks, int32 elements for pivots) of every
-// job of a wave inside one allocation: [matrices | m64 | x | r | piv].
+// job of a wave inside one allocation: [matrices | v | x | r | piv].  Split mode keeps no FP64
+// copy of the matrices, only the packed FP64 contractions v of every pair of members, from
+// which the refinement's residual forms M X.
 static void layout_wave(std::vector<JobDesc>& jobs, const Wave& w, int precision, int64_t& bytes_a,
-                        int64_t& bytes_m, int64_t& bytes_x, int64_t& bytes_r, int64_t& bytes_p) {
-  bytes_a = bytes_m = bytes_x = bytes_r = bytes_p = 0;
+                        int64_t& bytes_v, int64_t& bytes_x, int64_t& bytes_r, int64_t& bytes_p) {
+  bytes_a = bytes_v = bytes_x = bytes_r = bytes_p = 0;
   for (int j = w.b; j < w.e; ++j) {
     JobBytes jb = job_bytes(jobs[j].npad, precision);
     jobs[j].a_off = bytes_a / (precision == LSMS_SPLIT ? 8 : 16);
     bytes_a += jb.a;
-    jobs[j].m_off = precision == LSMS_SPLIT ? bytes_m / 16 : -1;
-    bytes_m += jb.m;
+    jobs[j].v_off = precision == LSMS_SPLIT ? bytes_v / 16 : -1;
+    bytes_v += jb.v;
     jobs[j].x_off = bytes_x / 16;
     bytes_x += jb.x;
     jobs[j].r_off = precision == LSMS_SPLIT ? bytes_r / 16 : -1;
@@ -626,10 +646,6 @@ static void energies(double e_fermi, double eta, double2& kp, double2& km) {
 
 // Refinement state per job: norms[j][0] = ||M||_inf, [1] = ||r||_inf, [2] = ||X||_inf, [3] = berr.
 namespace lsms {
-// first: the first pass of a refinement, which also forms ||M||_inf (kept by later passes)
-void launch_residual_norms(const JobDesc* jobs, int njobs, int npad_max, const double2* m64, const double2* x,
-                           double2* r, const double2* tpm, const int32_t* liz_atom, double* norms,
-                           const int32_t* done, int first, hipStream_t s);
 void launch_refine_step(const JobDesc* jobs, int njobs, double* norms, double tol, int32_t* done, int last,
                         int32_t* job_info, int32_t* pending, hipStream_t s);
 void launch_zero_i32(int32_t* p, int n, hipStream_t s);
@@ -873,7 +889,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
   hipStream_t const caller = s;
   struct WaveBufs {
     void* abuf;
-    double2 *m64, *xbuf, *rbuf;
+    double2 *vtab, *xbuf, *rbuf;
     int32_t* piv;
   };
   auto bufs_of = [&](size_t w) {
@@ -881,7 +897,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     WaveBufs b;
     b.abuf = p;
     p += wave_sizes[5 * w];
-    b.m64 = (double2*)p;
+    b.vtab = (double2*)p;
     p += wave_sizes[5 * w + 1];
     b.xbuf = (double2*)p;
     p += wave_sizes[5 * w + 2];
@@ -903,7 +919,6 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     int32_t* jdone = done + wv.b;
     const WaveBufs wb = bufs_of(w);
     void* abuf = wb.abuf;
-    double2* m64 = wb.m64;
     double2* xbuf = wb.xbuf;
     int32_t* piv = wb.piv;
     int rc;
@@ -917,14 +932,14 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     launch_check_inputs(jd, nj, liz_pos, liz_atom, phase, jinfo, s);
     launch_init_rhs(jd, nj, npad_max, liz_atom, rhs_t, xbuf, s);
     if (precision == LSMS_FP64) {
-      launch_assemble_f64(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (double2*)abuf, s);
+      launch_assemble_f64(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (double2*)abuf, nullptr, s);
       rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s);
       if (rc) return rc;
       launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, nullptr, liz_atom,
                       s);
       launch_write_status(jd, nj, jinfo, nullptr, info, berr, mirror, s);
     } else {
-      launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, m64, spm, s);
+      launch_assemble_split(jd, nj, npad_max, liz_pos, liz_atom, tpm, kp, km, (float2*)abuf, wb.vtab, spm, s);
       rc = factor_and_solve(ctx, precision, jd, nj, npad_max, abuf, piv, jinfo, xbuf, prof, s, sym);
       if (rc) return rc;
       if (sym) launch_zero_pivot_to_fallback(nj, jinfo, s);
@@ -948,7 +963,6 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
     int32_t* jdone = done + wv.b;
     const WaveBufs wb = bufs_of(w);
     void* abuf = wb.abuf;
-    double2* m64 = wb.m64;
     double2* xbuf = wb.xbuf;
     double2* rbuf = wb.rbuf;
     int32_t* piv = wb.piv;
@@ -957,7 +971,7 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
       int left = nj;
       for (int it = 0; it <= max_refine; ++it) {
         const int last = it == max_refine;
-        launch_residual_norms(jd, nj, npad_max, m64, xbuf, rbuf, rhs_t, liz_atom, jnorm, jdone, it == 0, s);
+        launch_residual(jd, nj, npad_max, wb.vtab, liz_atom, tpm, spm, xbuf, rbuf, jnorm, jdone, it == 0, s);
         launch_zero_i32(pending, 1, s);
         launch_refine_step(jd, nj, jnorm, refine_tol, jdone, last, jinfo, pending, s);
         // read back how many jobs still miss the tolerance: stop as soon as none does
@@ -973,8 +987,10 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
       }
       if (left > 0 || sym) {
         // Jobs whose refinement did not converge (info = NOCONV; in the symmetric form also
-        // those that met a zero pivot) are recomputed in FP64: the FP64 copy of the matrix
-        // is factored in place with partial pivoting and solved directly.
+        // those that met a zero pivot) are recomputed in FP64: the matrix is assembled again in
+        // FP64, factored with partial pivoting and solved directly.  The FP32 factors are done
+        // with, so the wave's matrix area holds these FP64 matrices, as many at a time as fit
+        // (a single job whose FP64 matrix does not fit there borrows a buffer of its own).
         std::vector<int32_t> hinfo(nj);
         HIP_TRY(hipMemcpyAsync(hinfo.data(), jinfo, nj * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -982,29 +998,44 @@ extern "C" int lsms_tau_solve(lsms_ctx* ctx, int32_t n_atoms, const int64_t* liz
         for (int j = 0; j < nj; ++j)
           if (hinfo[j] == LSMS_INFO_NOCONV) {
             JobDesc d = jobs[wv.b + j];
-            d.a_off = d.m_off;
             d.info = j;
             fb.push_back(d);
           }
         if (!fb.empty()) {
-          const int nf = (int)fb.size();
-          rc = ensure_dev(ctx->fallback, fb.size() * sizeof(JobDesc) + align_up(4 * (int64_t)nf, 256) + 256, s);
+          // jobs are sorted by size, largest first: every chunk's slots take the first job's size
+          const int64_t slot = align_up((int64_t)fb[0].npad * fb[0].npad * 16, 256);
+          int64_t cap = std::min<int64_t>(wave_sizes[5 * w] / slot, (int64_t)fb.size());
+          char* fmat = (char*)abuf;
+          if (cap < 1) {
+            rc = ensure_dev(ctx->fallback_mat, (size_t)slot, s);
+            if (rc) return rc;
+            fmat = (char*)ctx->fallback_mat.p;
+            cap = 1;
+          }
+          rc = ensure_dev(ctx->fallback, (size_t)(align_up(cap * (int64_t)sizeof(JobDesc), 256) + 4 * cap + 256), s);
           if (rc) return rc;
           JobDesc* fjd = (JobDesc*)ctx->fallback.p;
-          int32_t* finfo = (int32_t*)((char*)ctx->fallback.p + align_up(fb.size() * sizeof(JobDesc), 256));
-          HIP_TRY(hipMemcpyAsync(fjd, fb.data(), fb.size() * sizeof(JobDesc), hipMemcpyHostToDevice, s));
-          launch_zero_i32(finfo, nf, s);
-          const int fpad = fb[0].npad;
-          launch_init_rhs(fjd, nf, fpad, liz_atom, rhs_t, xbuf, s);
-          TallScratch fts;
-          rc = tall_scratch(ctx, nf, fpad, &fts, s);
-          if (rc) return rc;
-          const Tiling ft = pick_tiling(ctx, LSMS_FP64, fpad);
-          lu_factor_f64(fjd, nf, fpad, m64, piv, finfo, s, nullptr, ft, fts);
-          lu_solve_f64(fjd, nf, fpad, m64, piv, xbuf, 0, 16, 0, ft.group, s);
-          launch_fallback_status(nf, fjd, finfo, jinfo, jnorm, s);
-          // the fallback's job list is context scratch: done before another wave reuses it
-          HIP_TRY(hipStreamSynchronize(s));
+          int32_t* finfo = (int32_t*)((char*)ctx->fallback.p + align_up(cap * (int64_t)sizeof(JobDesc), 256));
+          for (size_t c0 = 0; c0 < fb.size(); c0 += (size_t)cap) {
+            const int nf = (int)std::min<int64_t>(cap, (int64_t)(fb.size() - c0));
+            std::vector<JobDesc> part(fb.begin() + c0, fb.begin() + c0 + nf);
+            for (int q = 0; q < nf; ++q) part[q].a_off = q * (slot / 16);
+            const int fpad = part[0].npad;
+            HIP_TRY(hipMemcpyAsync(fjd, part.data(), nf * sizeof(JobDesc), hipMemcpyHostToDevice, s));
+            launch_zero_i32(finfo, nf, s);
+            launch_init_rhs(fjd, nf, fpad, liz_atom, rhs_t, xbuf, s);
+            launch_assemble_f64(fjd, nf, fpad, liz_pos, liz_atom, tpm, kp, km, (double2*)fmat, spm, s);
+            TallScratch fts;
+            rc = tall_scratch(ctx, nf, fpad, &fts, s);
+            if (rc) return rc;
+            const Tiling ft = pick_tiling(ctx, LSMS_FP64, fpad);
+            lu_factor_f64(fjd, nf, fpad, (double2*)fmat, piv, finfo, s, nullptr, ft, fts);
+            lu_solve_f64(fjd, nf, fpad, (const double2*)fmat, piv, xbuf, 0, 16, 0, ft.group, s);
+            launch_fallback_status(nf, fjd, finfo, jinfo, jnorm, s);
+            // the job list (and a borrowed matrix buffer) are context scratch: done before the
+            // next chunk or another wave reuses them
+            HIP_TRY(hipStreamSynchronize(s));
+          }
         }
       }
       launch_copy_tau(jd, nj, npad_max, xbuf, (double2*)tau_plus, (double2*)tau_minus, mirror, spm, liz_atom, s);
@@ -1501,9 +1532,9 @@ extern "C" int lsms_batched_lu_solve(lsms_ctx* ctx, int32_t batch, const int32_t
     jobs[b] = j;
   }
   Wave w{0, batch, 0};
-  int64_t ba, bm, bx, br, bp;
+  int64_t ba, bv, bx, br, bp;
   const int prec = precision == LSMS_SPLIT ? LSMS_SPLIT : LSMS_FP64;
-  layout_wave(jobs, w, prec, ba, bm, bx, br, bp);
+  layout_wave(jobs, w, prec, ba, bv, bx, br, bp);  // no refinement here: the table (bv) is not allocated
   const int64_t ptr_bytes = align_up((int64_t)batch * 16, 256);
   const int64_t jd_bytes = align_up((int64_t)batch * sizeof(JobDesc), 256);
   const int64_t total = ba + bx + bp + jd_bytes + 2 * ptr_bytes;

@@ -64,7 +64,7 @@ template <> struct LdsOf<float2> { typedef float2 type; };
 // One (atom, energy) system.
 struct JobDesc {
   int64_t a_off;    // working matrix (npad x npad, row-major, ld = npad), in complex elements
-  int64_t m_off;    // FP64 copy of M (split mode), in complex elements; -1 if absent
+  int64_t v_off;    // packed FP64 structure-constant blocks (split mode), in complex elements; -1 if absent
   int64_t x_off;    // solution / right-hand-side block (npad x NRHS_MAX complex double)
   int64_t r_off;    // residual / correction block (split mode), same shape; -1 if absent
   int64_t piv_off;  // pivots (npad int32)
@@ -80,6 +80,18 @@ struct JobDesc {
 };
 
 constexpr int NRHS_MAX = 32;  // columns of the solution block (16 forward, 32 adjoint)
+
+// Split mode keeps, per pair of LIZ members a < b, the FP64 Gaunt contraction
+// v^{ab}_{LL'} = sum_{L''} C_{L L' L''} (-4 pi i kappa) i^{l''} h_{l''}(kappa |R|) Y_{L''}(R^), R = p_a - p_b,
+// so that g^{ab} = i^l v^{ab} i^{-l'}.  v is symmetric in (L, L') and is stored as its upper
+// triangle, row by row: VBLOCK complex entries per pair, the pair numbered like the upper
+// triangle of the member grid (pair_index).  For the reversed pair v^{ba} = (-1)^{l + l'} v^{ab}.
+constexpr int VBLOCK = NL * (NL + 1) / 2;
+__host__ __device__ inline int vblock_index(int L, int Lp) { return L * NL - L * (L - 1) / 2 + (Lp - L); }  // L <= Lp
+// pair a <= b of an nb x nb grid, numbered row by row
+__host__ __device__ inline int64_t pair_index(int a, int b, int nb) {
+  return (int64_t)a * nb - (int64_t)a * (a - 1) / 2 + (b - a);
+}
 
 // The NB interchanges of one panel permute at most 2 NB rows.  The panel kernel stores
 // that permutation once per panel as (destination row, source row) pairs so that the
@@ -106,13 +118,20 @@ void launch_tmatrix(const double* phase, int n_atoms, double2 kappa_plus, double
                     hipStream_t s);
 
 // M = 1 - T g over each job's LIZ (padded with identity), written to the working
-// matrix (double2 or float2) and, if m64 != nullptr, also to the FP64 copy.
+// matrix (double2 or float2); spm != nullptr: the symmetric form 1 - S g S, S = T^{1/2}.
+// Split mode also writes the packed FP64 contractions of every pair (vtab, at v_off).
 void launch_assemble_f64(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
                          const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, double2* work,
-                         hipStream_t s);
+                         const double2* spm, hipStream_t s);
 void launch_assemble_split(const JobDesc* jobs, int njobs, int npad_max, const double* liz_pos,
                            const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, float2* work,
-                           double2* m64, const double2* spm, hipStream_t s);
+                           double2* vtab, const double2* spm, hipStream_t s);
+// Residual r = B - M X of the split-mode refinement from the packed contractions (vtab) and
+// the t-matrices (spm != nullptr: the symmetric form); norms[job][0..4] as in the refinement
+// (first: also ||M||_inf); jobs with done[job] set are skipped.
+void launch_residual(const JobDesc* jobs, int njobs, int npad_max, const double2* vtab, const int32_t* liz_atom,
+                     const double2* tpm, const double2* spm, const double2* x, double2* r, double* norms,
+                     const int32_t* done, int first, hipStream_t s);
 // B = E0 t_centre in the solution block (first NL columns), zero elsewhere.
 void launch_init_rhs(const JobDesc* jobs, int njobs, int npad_max, const int32_t* liz_atom, const double2* tpm,
                      double2* x, hipStream_t s);

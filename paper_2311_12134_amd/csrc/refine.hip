@@ -2,8 +2,8 @@
 // the diagnostic batched-solve entry point.
 //
 // Classical mixed-precision iterative refinement (Wilkinson; Moler 1967): with FP32
-// factors of M, repeat  r = B - M X (FP64, M kept in FP64),  d = U^-1 L^-1 P r (an FP32 solve
-// with the FP32 factors on a rounded copy of r),  X += d (FP64),  until the normwise backward error
+// factors of M, repeat  r = B - M X (FP64),  d = U^-1 L^-1 P r (an FP32 solve with the FP32
+// factors on a rounded copy of r),  X += d (FP64),  until the normwise backward error
 //   berr = ||r||_inf / (||M||_inf ||X||_inf + ||B||_inf)
 // reaches the requested tolerance.  B = E0 t_centre is regenerated from the t-matrix.
 // Per-job norms live in norms[job][8]: 0 ||M||, 1 ||r||, 2 ||X||, 3 berr, 4 ||B||.
@@ -18,85 +18,191 @@ __device__ inline void atomic_max_nonneg(double* addr, double v) {
   atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
 }
 
-__device__ inline double cabs2(double2 v) { return sqrt(v.x * v.x + v.y * v.y); }
+__device__ inline double cabs_(double2 v) { return sqrt(v.x * v.x + v.y * v.y); }
+__device__ inline int lch(int L) { return L < 1 ? 0 : L < 4 ? 1 : L < 9 ? 2 : 3; }  // l of channel L
 
-// r = B - M X for 64 rows x 16 columns per workgroup; M X on FP64 MFMA with three real
-// products per complex product (Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)): the kernel streams the FP64
-// copy of M once per pass, and three products keep the matrix cores under that stream.
-// MNORM: also ||M||_inf (the first pass of a refinement; M does not change between passes,
-// so the later passes skip the modulus of every element).  The moduli are taken in FP32 (a
-// relative error of about 1e-7 in a norm that only scales the backward error) and summed
-// in FP64; entries of M = 1 - t g are far below the FP32 range.
-template <bool MNORM>
-__global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, const double2* m64, const double2* x,
-                                                       double2* r, const double2* tpm, const int32_t* liz_atom,
-                                                       double* norms, const int32_t* done) {
+// z i^e
+__device__ inline double2 ipow_mul(double2 z, int e) {
+  e &= 3;
+  return e == 0 ? z : e == 1 ? make_double2(-z.y, z.x) : e == 2 ? make_double2(-z.x, -z.y) : make_double2(z.y, -z.x);
+}
+
+// The residual uses M = 1 - D G E (G the structure constants, zero diagonal blocks and
+// padding; D = T, E = 1, or D = E = T^{1/2} in the symmetric form) through the packed
+// contractions v (g^{ab} = I v^{ab} I^{-1}, I = diag(i^l)):
+//   r_a = B_a - X_a + D_a I sum_{b != a} v^{ab} X'_b,   X'_b = I^{-1} E_b X_b.
+// rotate_x_kernel forms X' once per pass, in columns 16 .. 31 of the residual rows (their
+// columns 0 .. 15 receive the residual); zero on padding members.
+__global__ void rotate_x_kernel(const JobDesc* jobs, const int32_t* liz_atom, const double2* spm, const double2* x,
+                                double2* r, const int32_t* done) {
   const int job = blockIdx.y;
   if (done[job]) return;
   const JobDesc jd = jobs[job];
-  const int row0 = blockIdx.x * 64;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= jd.npad * NL) return;
+  const int row = idx / NL, c = idx % NL, site = row / NL, L = row % NL;
+  double2 v = make_double2(0.0, 0.0);
+  if (site < jd.nl) {
+    v = x[jd.x_off + (int64_t)row * NRHS_MAX + c];
+    if (spm) v = cmul(spm[liz_atom[jd.liz_off + site] * 8 + jd.energy * 4 + lch(L)], v);
+    v = ipow_mul(v, -lch(L));
+  }
+  r[jd.x_off + (int64_t)row * NRHS_MAX + NL + c] = v;
+}
+
+// r = B - M X for the 16 rows of one member per wavefront (four per workgroup): per member
+// b != a the 16 x 16 block v^{ab} is read from the packed table straight into the FP64 MFMA
+// operand layout (lane l, step s: entry (l % 16, 4 s + l / 16), the table's upper triangle by
+// symmetry; reversed pairs take the sign (-1)^{l + l'}), X'_b from the rotated rows, and
+// v X' accumulates with three real products per complex product (Ar Br, Ai Bi,
+// (Ar + Ai)(Br + Bi)); the next member's operands load while the current products run.
+// Reads 2176 bytes of table per block instead of the 4 KB of a stored FP64 block of M, and
+// each pair's block has two readers (rows a and b): the members are visited in the cyclic
+// order a + 1, a - 1, a + 2, a - 2, ... (mod nl), so both readers of pair (a, a + t) reach it
+// within one block of each other, and a job's workgroups are dealt to one XCD (workgroups
+// go to the eight XCDs round-robin), so the second read finds the block in that XCD's L2.
+// MNORM: also ||M||_inf (first pass of a refinement): per row 1 + |d_l| sum |v e|, the moduli
+// in FP32 (a relative error of about 1e-7 in a norm that only scales the backward error),
+// summed in FP64.
+constexpr int RDEPTH = 2;
+
+template <bool MNORM, bool SYM>
+__global__ __launch_bounds__(256, MNORM && SYM ? 2 : 3) void residual_kernel(const JobDesc* jobs, const double2* vtab,
+                                                       const int32_t* liz_atom, const double2* dtab,
+                                                       const double2* x, double2* r, double* norms,
+                                                       const int32_t* done, int tiles) {
+  int T = blockIdx.x;
+  {
+    const int N = gridDim.x, q = N >> 3, r = N & 7, x = T & 7;
+    T = x * q + min(x, r) + (T >> 3);
+  }
+  const int job = T / tiles;
+  if (done[job]) return;
+  const JobDesc jd = jobs[job];
+  const int row0 = (T - job * tiles) * 64;
   if (row0 >= jd.npad) return;
-  const double2* M = m64 + jd.m_off;
-  const double2* X = x + jd.x_off;
-  double2* R = r + jd.x_off;  // residual blocks mirror the solution blocks' offsets
-  const int npad = jd.npad;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  __shared__ double2 sM[64][16 + 1];
-  __shared__ double2 sX[16][16 + 1];
+  const int a = row0 / NL + wave;  // this wavefront's member (16 rows)
+  const int nl = jd.nl, nb = jd.npad / NL;
   __shared__ double s_max[3][4];
+  const double2* X = x + jd.x_off;
+  double2* R = r + jd.x_off;
+  const double2* Xr = R + NL;  // X'
+  const double2* V = vtab + jd.v_off;
+  const int eoff = jd.energy * 4;
   d4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
   double rowabs = 0.0;
-  for (int kc = 0; kc < npad; kc += 16) {
-    {
-      const int i = t >> 2, k4 = (t & 3) * 4;
-      const double2* src = M + (int64_t)(row0 + i) * npad + kc + k4;
+  if (a < nl) {  // uniform per wavefront
+    const int i = lane & 15;
+    int toff[4];
+    double sg[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double2 v = src[u];
-        sM[i][k4 + u] = v;
-        if (MNORM) rowabs += (double)__builtin_sqrtf((float)(v.x * v.x + v.y * v.y));
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + (lane >> 4);
+      toff[s] = i <= k ? vblock_index(i, k) : vblock_index(k, i);
+      sg[s] = ((lch(i) + lch(k)) & 1) ? -1.0 : 1.0;
+    }
+    const int xo = (lane >> 4) * NRHS_MAX + i;  // X' entry (row b NL + lane / 16 + 4 s)
+    // block k of the cyclic order: member a + (k / 2 + 1) for even k, a - (k / 2 + 1) for odd k
+    auto member = [&](int k) {
+      const int d = (k >> 1) + 1;
+      return (k & 1) ? (a - d + nl) % nl : (a + d) % nl;
+    };
+    const int nblk = nl - 1;
+    auto load_v = [&](int k, double2* av) {
+      if (k < nblk) {  // uniform
+        const int b = member(k);
+        const double2* blk = V + pair_index(min(a, b), max(a, b), nb) * VBLOCK;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) av[s] = blk[toff[s]];
       }
-      const int kk = t >> 4, c = t & 15;
-      sX[kk][c] = X[(int64_t)(kc + kk) * NRHS_MAX + c];
-    }
-    __syncthreads();
+    };
+    auto load_x = [&](int k, double2* xv) {
+      if (k < nblk) {  // uniform
+        const int b = member(k);
 #pragma unroll
-    for (int k4 = 0; k4 < 16; k4 += 4) {
-      const double2 a = sM[wave * 16 + (lane & 15)][k4 + (lane >> 4)];
-      const double2 b = sX[k4 + (lane >> 4)][lane & 15];
-      t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, t1, 0, 0, 0);
-      t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, t2, 0, 0, 0);
-      t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x + b.y, t3, 0, 0, 0);
+        for (int s = 0; s < 4; ++s) xv[s] = Xr[(int64_t)b * NL * NRHS_MAX + xo + 4 * s * NRHS_MAX];
+      }
+    };
+    auto mul = [&](int k, const double2* av, const double2* xv) {
+      const int b = member(k);
+      double2 A[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) A[s] = b < a ? make_double2(sg[s] * av[s].x, sg[s] * av[s].y) : av[s];
+      if (MNORM) {
+        double2 eb[4];
+        if (SYM) {
+          const double2* e = dtab + liz_atom[jd.liz_off + b] * 8 + eoff;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) eb[s] = e[lch(4 * s + (lane >> 4))];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          double m = (double)__builtin_sqrtf((float)(A[s].x * A[s].x + A[s].y * A[s].y));
+          if (SYM) m *= cabs_(eb[s]);
+          rowabs += m;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].x, xv[s].x, t1, 0, 0, 0);
+        t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].y, xv[s].y, t2, 0, 0, 0);
+        t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s].x + A[s].y, xv[s].x + xv[s].y, t3, 0, 0, 0);
+      }
+    };
+    // table blocks load RDEPTH blocks ahead (they come from HBM), X' one block ahead (it stays
+    // in L2); static register sets through unrolling
+    double2 av[RDEPTH][4], xv[2][4];
+#pragma unroll
+    for (int u = 0; u < RDEPTH; ++u) load_v(u, av[u]);
+    load_x(0, xv[0]);
+    for (int k = 0; k < nblk; k += RDEPTH) {
+#pragma unroll
+      for (int u = 0; u < RDEPTH; ++u) {
+        if (k + u < nblk) {  // uniform
+          load_x(k + u + 1, xv[(u + 1) & 1]);
+          mul(k + u, av[u], xv[u & 1]);
+          load_v(k + u + RDEPTH, av[u]);
+        }
+      }
     }
-    __syncthreads();
   }
-  // ||M||_inf over this tile's rows: four threads share a row
-  rowabs += __shfl_xor(rowabs, 1);
-  rowabs += __shfl_xor(rowabs, 2);
-  double mmax = rowabs;
-  // residual entries: lane l, register q -> row 16*wave + l/16 + 4q, column l%16
+  // ||M||_inf over the member's rows: lanes l, l + 16, l + 32, l + 48 hold parts of row l % 16
+  double mmax = 1.0;
+  if (MNORM) {
+    rowabs += __shfl_xor(rowabs, 16);
+    rowabs += __shfl_xor(rowabs, 32);
+    if (a < nl) mmax = 1.0 + cabs_(dtab[liz_atom[jd.liz_off + a] * 8 + eoff + lch(lane & 15)]) * rowabs;
+  }
+  // residual entries: lane l, register q -> row 16 a + l / 16 + 4 q, column l % 16
   const int col = lane & 15;
-  const double2 tc = (col < NL) ? tpm[liz_atom[jd.liz_off] * 8 + jd.energy * 4 +
-                                      (col == 0 ? 0 : (col < 4 ? 1 : (col < 9 ? 2 : 3)))]
-                                : make_double2(0, 0);
+  const double2 tc = dtab[liz_atom[jd.liz_off] * 8 + eoff + lch(col)];  // B = E0 t_centre (or s_centre)
+  const double2* da = a < nl ? dtab + liz_atom[jd.liz_off + a] * 8 + eoff : nullptr;
   double rmax = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int row = row0 + wave * 16 + (lane >> 4) + 4 * q;
-    double2 b = (row == col) ? tc : make_double2(0.0, 0.0);
-    double2 rv = make_double2(b.x - (t1[q] - t2[q]), b.y - (t3[q] - t1[q] - t2[q]));
+    const int i = (lane >> 4) + 4 * q, row = a * NL + i;
+    const double2 xv = X[(int64_t)row * NRHS_MAX + col];
+    double2 rv = (row == col) ? tc : make_double2(0.0, 0.0);
+    rv.x -= xv.x;
+    rv.y -= xv.y;
+    if (da) {  // + d_l i^l (v X')
+      const double2 dg = cmul(ipow_mul(da[lch(i)], lch(i)), make_double2(t1[q] - t2[q], t3[q] - t1[q] - t2[q]));
+      rv.x += dg.x;
+      rv.y += dg.y;
+    }
     R[(int64_t)row * NRHS_MAX + col] = rv;
-    double a = cabs2(rv);
+    double v = cabs_(rv);
 #pragma unroll
-    for (int o = 1; o < 16; o <<= 1) a += __shfl_xor(a, o);
-    rmax = fmax(rmax, a);
+    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+    rmax = fmax(rmax, v);
   }
-  // ||X||_inf over the tile's rows
+  // ||X||_inf over the workgroup's rows
   double xmax = 0.0;
   if (t < 64) {
-    double s = 0.0;
-    for (int c = 0; c < 16; ++c) s += cabs2(X[(int64_t)(row0 + t) * NRHS_MAX + c]);
-    xmax = s;
+    double v = 0.0;
+    for (int c = 0; c < 16; ++c) v += cabs_(X[(int64_t)(row0 + t) * NRHS_MAX + c]);
+    xmax = v;
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -111,24 +217,34 @@ __global__ __launch_bounds__(256) void residual_kernel(const JobDesc* jobs, cons
   }
   __syncthreads();
   if (t < 3 && (MNORM || t > 0)) {
-    double v = fmax(fmax(s_max[t][0], s_max[t][1]), fmax(s_max[t][2], s_max[t][3]));
+    const double v = fmax(fmax(s_max[t][0], s_max[t][1]), fmax(s_max[t][2], s_max[t][3]));
     atomic_max_nonneg(norms + job * 8 + t, v);
   }
   if (t == 3 && row0 == 0) {
     double b = 0.0;
-    for (int l = 0; l < 4; ++l) b = fmax(b, cabs2(tpm[liz_atom[jd.liz_off] * 8 + jd.energy * 4 + l]));
+    for (int l = 0; l < 4; ++l) b = fmax(b, cabs_(dtab[liz_atom[jd.liz_off] * 8 + eoff + l]));
     norms[job * 8 + 4] = b;
   }
 }
 
-void launch_residual_norms(const JobDesc* jobs, int njobs, int npad_max, const double2* m64, const double2* x,
-                           double2* r, const double2* tpm, const int32_t* liz_atom, double* norms,
-                           const int32_t* done, int first, hipStream_t s) {
-  dim3 grid(npad_max / 64, njobs);
-  if (first)
-    residual_kernel<true><<<grid, 256, 0, s>>>(jobs, m64, x, r, tpm, liz_atom, norms, done);
-  else
-    residual_kernel<false><<<grid, 256, 0, s>>>(jobs, m64, x, r, tpm, liz_atom, norms, done);
+void launch_residual(const JobDesc* jobs, int njobs, int npad_max, const double2* vtab, const int32_t* liz_atom,
+                     const double2* tpm, const double2* spm, const double2* x, double2* r, double* norms,
+                     const int32_t* done, int first, hipStream_t s) {
+  rotate_x_kernel<<<dim3((npad_max * NL + 255) / 256, njobs), 256, 0, s>>>(jobs, liz_atom, spm, x, r, done);
+  const int tiles = npad_max / 64;
+  const dim3 grid(tiles * njobs);
+  const double2* d = spm ? spm : tpm;
+  if (spm) {
+    if (first)
+      residual_kernel<true, true><<<grid, 256, 0, s>>>(jobs, vtab, liz_atom, d, x, r, norms, done, tiles);
+    else
+      residual_kernel<false, true><<<grid, 256, 0, s>>>(jobs, vtab, liz_atom, d, x, r, norms, done, tiles);
+  } else {
+    if (first)
+      residual_kernel<true, false><<<grid, 256, 0, s>>>(jobs, vtab, liz_atom, d, x, r, norms, done, tiles);
+    else
+      residual_kernel<false, false><<<grid, 256, 0, s>>>(jobs, vtab, liz_atom, d, x, r, norms, done, tiles);
+  }
 }
 
 // Backward error of every pending job; jobs that reach tol are marked done, the others

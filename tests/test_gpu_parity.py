@@ -496,6 +496,41 @@ def test_split_fallback_to_fp64_when_refinement_cannot_converge(lctx):
     _check_atoms(g, o, atoms, TOL64)
 
 
+def _split_job_bytes(npad):
+    """Workspace of one split-mode system (the wave layout: FP32 matrix, packed FP64
+    contractions of the member pairs, solution and residual blocks, pivots and their
+    per-panel interchange lists), each part rounded to 256 bytes."""
+    def al(v):
+        return (v + 255) // 256 * 256
+    nb = npad // 16
+    return (al(npad * npad * 8) + al(nb * (nb + 1) // 2 * 136 * 16) + 2 * al(npad * 32 * 16)
+            + al((npad + npad // 64 * 258) * 4))
+
+
+def test_split_fallback_in_one_job_waves():
+    """A workspace that holds one system per wave: the FP64 recomputation of a system whose
+    refinement cannot converge does not fit in the wave's FP32 matrix area and takes a buffer
+    of its own; FP64 parity as with the shared area."""
+    import paper_2311_12134_amd as P
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = synthetic.workload("bcc16")
+    eta = w["etas"][0]
+    liz = P.build_liz(w["pos"], w["cell"], w["r_liz"])
+    nl = np.diff(liz.ptr)
+    npad = int(((16 * nl.max() + 63) // 64) * 64)
+    small = P.Context(0, workspace_limit=int(1.5 * _split_job_bytes(npad)))
+    try:
+        g = _run(small, w, eta, precision="split", refine_tol=1e-300, max_refine=0)
+    finally:
+        small.close()
+    assert (g["info"] == -1).all()
+    assert (g["berr"] == -1.0).all()
+    atoms = list(range(16))
+    o = _oracle_atoms(w, eta, atoms, g["liz"])
+    _check_atoms(g, o, atoms, TOL64)
+
+
 def test_split_refinement_reaches_tolerance_quickly(lctx):
     w = synthetic.workload("bcc250")
     g = _run(lctx, w, w["etas"][0], precision="split", refine_tol=1e-14, max_refine=3, per_atom=False)
