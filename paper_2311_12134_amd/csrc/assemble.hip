@@ -30,6 +30,11 @@ struct GauntSlots {
 };
 __constant__ GauntSlots c_slots;
 
+// Terms per slot group of the lmax = 3 table (the upload checks them): the assembly keeps a
+// lane's coefficients in registers, unrolled to these counts.
+__host__ __device__ constexpr int slot_terms(int r) { return r == 0 ? 2 : r == 1 ? 3 : r == 2 ? 4 : 7; }
+constexpr int SLOT_TERMS_ALL = 16;
+
 static int lidx_h(int L) { return L == 0 ? 0 : (L < 4 ? 1 : (L < 9 ? 2 : 3)); }
 
 hipError_t upload_gaunt(const GauntTable& g) {
@@ -56,6 +61,8 @@ hipError_t upload_gaunt(const GauntTable& g) {
       sl.l3[r][lane][j] = (uint16_t)(l3 | ll << 8);
     }
   }
+  for (int r = 0; r < 4; ++r)
+    if (sl.nterm[r] > slot_terms(r)) return hipErrorInvalidValue;
   for (int l = 0; l <= 6; ++l)
     for (int m = 0; m <= l; ++m) sl.ynorm[l][m] = ylm_norm<6>(l, m);
   return hipMemcpyToSymbol(HIP_SYMBOL(c_slots), &sl, sizeof(GauntSlots));
@@ -101,18 +108,27 @@ void launch_tmatrix(const double* phase, int n_atoms, double2 kappa_plus, double
 
 __device__ inline int lidx(int L) { return L == 0 ? 0 : (L < 4 ? 1 : (L < 9 ? 2 : 3)); }
 
-// The harmonics Y_{l, +-m} of the unit vector (x, y, z) for one m and l = m .. 6 (see ylm.h).
-__device__ inline void ylm_column(int m, double x, double y, double z, double* Y) {
+// P_{l, +-m} = H_l Y_{l, +-m} for one m and l = m .. 6: the real harmonics of the unit vector
+// (x, y, z) (see ylm.h), (x + i y)^m and the associated Legendre recurrence in z, times the
+// Hankel term of each l.  The l loop runs over every l with the entries below m skipped, so H
+// is indexed statically.
+__device__ inline void ylm_column_times(int m, double x, double y, double z, const double2* H, double2* P) {
   double c = 1.0, s = 0.0;  // (x + i y)^m
-  for (int q = 0; q < m; ++q) {
-    const double cn = c * x - s * y;
-    s = c * y + s * x;
-    c = cn;
-  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    if (q < m) {
+      const double cn = c * x - s * y;
+      s = c * y + s * x;
+      c = cn;
+    }
   double qmm = 1.0;
-  for (int q = 1; q < 2 * m; q += 2) qmm *= q;  // (2m - 1)!!
+#pragma unroll
+  for (int q = 1; q < 12; q += 2)
+    if (q < 2 * m) qmm *= q;  // (2m - 1)!!
   double q2 = 0.0, q1 = qmm;
-  for (int l = m; l <= 6; ++l) {
+#pragma unroll
+  for (int l = 0; l <= 6; ++l) {
+    if (l < m) continue;
     double q;
     if (l == m)
       q = qmm;
@@ -126,10 +142,11 @@ __device__ inline void ylm_column(int m, double x, double y, double z, double* Y
     }
     const double nq = c_slots.ynorm[l][m] * q;
     if (m == 0) {
-      Y[l * l + l] = nq;
+      P[l * l + l] = make_double2(nq * H[l].x, nq * H[l].y);
     } else {
-      Y[l * l + l + m] = M_SQRT2 * nq * c;
-      Y[l * l + l - m] = M_SQRT2 * nq * s;
+      const double yc = M_SQRT2 * nq * c, ys = M_SQRT2 * nq * s;
+      P[l * l + l + m] = make_double2(yc * H[l].x, yc * H[l].y);
+      P[l * l + l - m] = make_double2(ys * H[l].x, ys * H[l].y);
     }
   }
 }
@@ -176,61 +193,68 @@ __device__ inline void pair_of(int p, int n, int& a, int& b) {
 // triangle of the padded block grid, row by row).  The structure constants are reciprocal,
 // g^{ba}_{LL'} = g^{ab}_{L'L} (R -> -R flips Y_{L''} by (-1)^{l''} = (-1)^{l+l'} on the Gaunt
 // terms, which cancels the i^{l-l'} phase change of the swap), so one evaluation per pair
-// gives both blocks.  Phase 1: four threads per pair evaluate the 49 real harmonics of
-// R^ = (p_a - p_b)/|R| (split by |m|) and (-4 pi i kappa) i^l h_l(kappa |R|), l <= 6 (the
-// fourth thread), into LDS.  Phase 2: each wavefront contracts its pairs against the
-// slot-dealt Gaunt terms, applies i^{l - l'}, stages g^{ab} in LDS and writes the rows of
-// -t_a g^{ab} and of -t_b (g^{ab})^T.  Diagonal and padding blocks are the identity / zero.
+// gives both blocks.  Phase 1: eight lanes per pair, lane m < 7 evaluates the Hankel terms
+// (-4 pi i kappa) i^l h_l(kappa |R|) and the harmonics Y_{l, +-m} of R^ = (p_a - p_b)/|R| and
+// writes P_{L''} = H_{l''} Y_{L''} for its channels to LDS.  Phase 2: each wavefront contracts
+// its pairs, every lane over its Gaunt slots (coefficients and P offsets in registers,
+// unrolled to the fixed term counts), applies i^{l - l'}, stages g^{ab} in LDS and writes the
+// rows of -t_a g^{ab} and of -t_b (g^{ab})^T.  Diagonal and padding blocks are the identity / zero.
 // spm != nullptr: the symmetric form, blocks -s_a g_ab s_b (s = t^{1/2}) instead of -t_a g_ab.
 // vtab != nullptr (split mode): also the FP64 contraction v^{ab} = i^{-(l - l')} g^{ab} of each
 // pair a < b, symmetric in (L, L') (the Gaunt coefficients are), packed as its upper triangle
 // (vblock_index), for the refinement's residual: 2176 bytes per pair instead of the 8 KB of
 // the two FP64 blocks of M.
+constexpr int ASM_PAIRS = 32;  // pairs per workgroup
+
 template <typename T>
-__global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, const double* liz_pos,
+__global__ __launch_bounds__(256, 3) void assemble_kernel(const JobDesc* jobs, const double* liz_pos,
                                                        const int32_t* liz_atom, const double2* tpm, double2 kp,
                                                        double2 km, T* work, double2* vtab, const double2* spm) {
-  constexpr int BPW = 64;
-  __shared__ double s_coef[4][64][GT];
-  __shared__ uint16_t s_l3[4][64][GT];
-  __shared__ uint16_t s_pair[4][64];
-  __shared__ double s_Y[BPW][NL3 + 1];
-  __shared__ double2 s_H[BPW][7];
+  __shared__ double2 s_P[ASM_PAIRS][NL3];
   __shared__ double2 s_G[4][NL][NL + 1];
   const JobDesc jd = jobs[blockIdx.y];
   const int nbp = jd.npad / NL;
   const int npairs = nbp * (nbp + 1) / 2;
-  const int p0 = blockIdx.x * BPW;
+  const int p0 = blockIdx.x * ASM_PAIRS;
   if (p0 >= npairs) return;  // uniform
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int i = t; i < 4 * 64 * GT; i += 256) {
-    (&s_coef[0][0][0])[i] = (&c_slots.coef[0][0][0])[i];
-    (&s_l3[0][0][0])[i] = (&c_slots.l3[0][0][0])[i];
-  }
-  (&s_pair[0][0])[t] = (&c_slots.pair[0][0])[t];
   const double2 kappa = jd.energy == 0 ? kp : km;
   {
-    const int q = t >> 2, part = t & 3, pp = p0 + q;
+    const int q = t >> 3, m = t & 7, pp = p0 + q;
     int a, b;
     pair_of(pp, nbp, a, b);
-    if (pp < npairs && a != b && b < jd.nl) {  // a < b < nl
+    if (m < 7 && pp < npairs && a != b && b < jd.nl) {  // a < b < nl
       const double* pa = liz_pos + (jd.liz_off + a) * 3;
       const double* pb = liz_pos + (jd.liz_off + b) * 3;
       const double rx = pa[0] - pb[0], ry = pa[1] - pb[1], rz = pa[2] - pb[2];
       const double dist = sqrt(rx * rx + ry * ry + rz * rz), inv = 1.0 / dist;
-      double* Y = &s_Y[q][0];
-      if (part == 3) {
-        ylm_column(3, rx * inv, ry * inv, rz * inv, Y);
-        hankel_terms(kappa, dist, &s_H[q][0]);
-      } else {
-        ylm_column(part, rx * inv, ry * inv, rz * inv, Y);
-        ylm_column(part + 4, rx * inv, ry * inv, rz * inv, Y);
+      double2 H[7];
+      hankel_terms(kappa, dist, H);
+      ylm_column_times(m, rx * inv, ry * inv, rz * inv, H, &s_P[q][0]);
+    }
+  }
+  // this lane's Gaunt slots
+  double coef[SLOT_TERMS_ALL];
+  int pof[SLOT_TERMS_ALL];
+  int Ls[4], Lps[4], es[4];
+  {
+    int k = 0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int pr = c_slots.pair[g][lane];
+      Ls[g] = pr & 15;
+      Lps[g] = (pr >> 4) & 15;
+      es[g] = pr >> 8;
+#pragma unroll
+      for (int j = 0; j < slot_terms(g); ++j, ++k) {
+        coef[k] = c_slots.coef[g][lane][j];
+        pof[k] = c_slots.l3[g][lane][j] & 0xff;
       }
     }
   }
   __syncthreads();
   const int Lr = lane >> 4, Lc = lane & 15;
-  for (int q = wave; q < BPW; q += 4) {
+  for (int q = wave; q < ASM_PAIRS; q += 4) {
     const int pp = p0 + q;
     if (pp >= npairs) break;  // uniform per wavefront
     int a, b;
@@ -238,21 +262,26 @@ __global__ __launch_bounds__(256) void assemble_kernel(const JobDesc* jobs, cons
     const int64_t base_ab = (int64_t)(a * NL) * jd.npad + b * NL;
     const int64_t base_ba = (int64_t)(b * NL) * jd.npad + a * NL;
     if (a != b && b < jd.nl) {
+      const double2* P = &s_P[q][0];
+      double2 p[SLOT_TERMS_ALL];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int pr = s_pair[r][lane], L = pr & 15, Lp = (pr >> 4) & 15, e = pr >> 8;
-        double2 g = make_double2(0.0, 0.0);
-        for (int j = 0; j < c_slots.nterm[r]; ++j) {
-          const int lt = s_l3[r][lane][j];
-          const double cy = s_coef[r][lane][j] * s_Y[q][lt & 0xff];
-          const double2 h = s_H[q][lt >> 8];
-          g.x += cy * h.x;
-          g.y += cy * h.y;
+      for (int k = 0; k < SLOT_TERMS_ALL; ++k) p[k] = P[pof[k]];
+      int k = 0;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < slot_terms(g); ++j, ++k) {
+          v.x += coef[k] * p[k].x;
+          v.y += coef[k] * p[k].y;
         }
-        if (vtab && L <= Lp) vtab[jd.v_off + (int64_t)pp * VBLOCK + vblock_index(L, Lp)] = g;
+        if (vtab && Ls[g] <= Lps[g]) vtab[jd.v_off + (int64_t)pp * VBLOCK + vblock_index(Ls[g], Lps[g])] = v;
         // i^{l - l'}
-        s_G[wave][L][Lp] = e == 0 ? g : e == 1 ? make_double2(-g.y, g.x) : e == 2 ? make_double2(-g.x, -g.y)
-                                                                                    : make_double2(g.y, -g.x);
+        const int e = es[g];
+        s_G[wave][Ls[g]][Lps[g]] = e == 0   ? v
+                                   : e == 1 ? make_double2(-v.y, v.x)
+                                   : e == 2 ? make_double2(-v.x, -v.y)
+                                            : make_double2(v.y, -v.x);
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -291,7 +320,7 @@ void launch_assemble_f64(const JobDesc* jobs, int njobs, int npad_max, const dou
                          const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, double2* work,
                          const double2* spm, hipStream_t s) {
   const int nbp = npad_max / NL;
-  dim3 grid((nbp * (nbp + 1) / 2 + 63) / 64, njobs);
+  dim3 grid((nbp * (nbp + 1) / 2 + ASM_PAIRS - 1) / ASM_PAIRS, njobs);
   assemble_kernel<double2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, nullptr, spm);
 }
 
@@ -299,7 +328,7 @@ void launch_assemble_split(const JobDesc* jobs, int njobs, int npad_max, const d
                            const int32_t* liz_atom, const double2* tpm, double2 kp, double2 km, float2* work,
                            double2* vtab, const double2* spm, hipStream_t s) {
   const int nbp = npad_max / NL;
-  dim3 grid((nbp * (nbp + 1) / 2 + 63) / 64, njobs);
+  dim3 grid((nbp * (nbp + 1) / 2 + ASM_PAIRS - 1) / ASM_PAIRS, njobs);
   assemble_kernel<float2><<<grid, 256, 0, s>>>(jobs, liz_pos, liz_atom, tpm, kp, km, work, vtab, spm);
 }
 
