@@ -52,15 +52,15 @@ def gemm_source(precision, tiling):
 # it is reported as null.
 TRAFFIC = {
     ("split", "fcc4000", 1): {"sha256": "2e3078da84b18709ee1905d4151e5884815da676e36d9ca16b6e12f1ce630b8a",
-                              "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 1.0079e11},
+                              "alg_bytes_per_launch": 6.9042e10, "bytes_per_launch": 1.3337e11},
     ("split", "fcc4000", 2): {"sha256": "2e3078da84b18709ee1905d4151e5884815da676e36d9ca16b6e12f1ce630b8a",
-                              "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 9.2529e10},
+                              "alg_bytes_per_launch": 6.9042e10, "bytes_per_launch": 1.2319e11},
     ("split", "fcc4000", 13): {"sha256": "9001bedb113c858cbd9ba443f681c5ea7cc9357d9d5376fc8cf357fbb44d05b4",
-                               "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 8.3501e10},
+                               "alg_bytes_per_launch": 6.9042e10, "bytes_per_launch": 1.1088e11},
     ("split", "fcc4000", 19): {"sha256": "2e3078da84b18709ee1905d4151e5884815da676e36d9ca16b6e12f1ce630b8a",
-                               "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 6.1872e10},
+                               "alg_bytes_per_launch": 6.9042e10, "bytes_per_launch": 8.2470e10},
     ("split", "fcc4000", 20): {"sha256": "9001bedb113c858cbd9ba443f681c5ea7cc9357d9d5376fc8cf357fbb44d05b4",
-                               "alg_bytes_per_launch": 5.1782e10, "bytes_per_launch": 6.3301e10},
+                               "alg_bytes_per_launch": 6.9042e10, "bytes_per_launch": 8.4043e10},
 }
 
 

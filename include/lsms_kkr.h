@@ -149,7 +149,13 @@ int lsms_build_liz_subset(lsms_ctx* ctx, int32_t n_atoms, const double* pos, con
  *             alive for lsms_kubo_sigma_grad (free with lsms_factors_free)
  *   hip_stream  hipStream_t (NULL = null stream)
  * Device memory used: the jobs are processed in waves that fit the workspace
- * limit (all at once when keep != NULL, else LSMS_E_NOMEM).
+ * limit (all at once when keep != NULL, else LSMS_E_NOMEM).  Per system: the working
+ * matrix (npad^2 complex, npad = n rounded up to 64; complex64 in split mode, complex128 in
+ * FP64 mode), in split mode the FP64 Gaunt contractions of every pair of LIZ members that the
+ * refinement's residual reads (2176 bytes per pair; no FP64 copy of M is kept), solution and
+ * residual blocks (npad x 32 complex128 each) and the pivots.  Systems recomputed in FP64 take
+ * the wave's matrix area once their FP32 factors are done with (a wave of one system borrows
+ * a buffer for its FP64 matrix).
  * An atom whose LIZ is empty (liz_ptr[a + 1] == liz_ptr[a]) is skipped: no system is
  * solved for it and its info and berr are 0 (not allowed with keep).  This lets a
  * caller solve a subset of a structure's atoms with the structure's phase array.
@@ -339,7 +345,8 @@ int lsms_set_profiling(lsms_ctx* ctx, int on);
  * the complex-symmetric form S = T^{1/2} M T^{-1/2} = 1 - T^{1/2} g T^{1/2} (g is symmetric by
  * reciprocity; T^{1/2} holds the principal square roots of the t_l, so no t is inverted):
  * S Y = T^{1/2} E0 is solved with an unpivoted L D L^T factorization in FP32 (half the
- * trailing-update work of the LU), refined in FP64 against an FP64 copy of S, and
+ * trailing-update work of the LU), refined in FP64 (residuals of S formed from the same FP64
+ * pair contractions as in the LU path), and
  * tau^{a0} = t_a^{1/2} Y_a.  Systems whose refinement does not converge (e.g. large
  * element growth without pivoting) fall back to the FP64 LU with partial pivoting of S, as
  * in the LU path.  With no pivots to choose, each panel factors only its diagonal block

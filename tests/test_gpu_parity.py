@@ -975,8 +975,8 @@ def test_graph_replay_with_tournament_panels(lctx):
 @pytest.mark.parametrize("name,chunk", [("fcc32", 2048), ("bcc250", 2048), ("bcc1940", 2048), ("bcc250", 256)])
 def test_symmetric_ldlt_vs_oracle(lctx, name, chunk):
     """Split mode on the symmetric form 1 - T^1/2 g T^1/2 with L D L^T (no pivoting), FP64
-    refinement against the FP64 copy of S: sampled atoms' tau and Kubo sums against the
-    oracle (which solves M X = T E0 by LU), and the backward error reached.  With 256-row
+    refinement of S (residuals from the FP64 pair contractions): sampled atoms' tau and Kubo
+    sums against the oracle (which solves M X = T E0 by LU), and the backward error reached.  With 256-row
     chunks the panels taller than 512 rows take the diagonal-block path of tall panels."""
     import paper_2311_12134_amd as P
     w = synthetic.workload(name)
