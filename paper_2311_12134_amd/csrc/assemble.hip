@@ -4,11 +4,13 @@
 // Structure constants for LIZ members a != b, R = p_a - p_b:
 //   g^{ab}_{LL'} = -4 pi i kappa  sum_{L''} i^{l - l' + l''} C_{L L' L''} h_{l''}(kappa |R|) Y_{L''}(R^)
 // with C the Gaunt integrals of three real harmonics and h_l = j_l + i y_l.
-// A workgroup produces 64 consecutive 16 x 16 blocks: the harmonics and Hankel functions of
-// each block are evaluated once (four threads per block), then each wavefront contracts its
-// blocks against the Gaunt terms (in LDS, dealt to lanes by term count) and writes
-// -t_a * g (row-scaled by the t-matrix of the row's member), or the identity on the
-// diagonal blocks and on the padding.
+// A workgroup produces 32 consecutive pairs of 16 x 16 blocks: the products of the harmonics
+// and Hankel functions of each pair are evaluated once (eight lanes per pair), then each
+// wavefront contracts its pairs against the Gaunt terms (dealt to lanes by term count, held
+// in registers) and writes -t_a * g (row-scaled by the t-matrix of the row's member) and its
+// transpose counterpart, or the identity on the diagonal blocks and on the padding; in split
+// mode also the packed FP64 contraction of every pair, from which the refinement's residual
+// forms M X.
 #include <algorithm>
 #include <cstring>
 
