@@ -55,12 +55,14 @@ __global__ void rotate_x_kernel(const JobDesc* jobs, const int32_t* liz_atom, co
 // operand layout (lane l, step s: entry (l % 16, 4 s + l / 16), the table's upper triangle by
 // symmetry; reversed pairs take the sign (-1)^{l + l'}), X'_b from the rotated rows, and
 // v X' accumulates with three real products per complex product (Ar Br, Ai Bi,
-// (Ar + Ai)(Br + Bi)); the next member's operands load while the current products run.
-// Reads 2176 bytes of table per block instead of the 4 KB of a stored FP64 block of M, and
-// each pair's block has two readers (rows a and b): the members are visited in the cyclic
+// (Ar + Ai)(Br + Bi)); table blocks load RDEPTH members ahead, X' one member ahead, while
+// the current products run.  Reads 2176 bytes of table per block instead of the 4 KB of a
+// stored FP64 block of M; the kernel is bound by its FP64 products, not by these reads.
+// Each pair's block has two readers (rows a and b): the members are visited in the cyclic
 // order a + 1, a - 1, a + 2, a - 2, ... (mod nl), so both readers of pair (a, a + t) reach it
 // within one block of each other, and a job's workgroups are dealt to one XCD (workgroups
-// go to the eight XCDs round-robin), so the second read finds the block in that XCD's L2.
+// go to the eight XCDs round-robin), so that the second read may find the block in that
+// XCD's L2 (the fetch counters show it mostly does not; the order costs nothing).
 // MNORM: also ||M||_inf (first pass of a refinement): per row 1 + |d_l| sum |v e|, the moduli
 // in FP32 (a relative error of about 1e-7 in a norm that only scales the backward error),
 // summed in FP64.
