@@ -728,7 +728,7 @@ static void launch_linv(const JobDesc* jobs, int njobs, int k, T* work, hipStrea
 // after the gather the panel rows get  A12 -= L[k.., k - nprev NB .. k) U12_earlier  (the
 // same 64 x 64 products, one per earlier panel, in panel order) before U12.
 template <typename T, bool SECOND>
-__global__ __launch_bounds__(256) void swap_trsm_kernel(const JobDesc* jobs, int k, int nprev, T* work,
+__global__ __launch_bounds__(256, sizeof(T) == sizeof(float2) ? 4 : 2) void swap_trsm_kernel(const JobDesc* jobs, int k, int nprev, T* work,
                                                         const int32_t* piv) {
   const JobDesc jd = jobs[blockIdx.y];
   const int col0 = k + NB + blockIdx.x * 64;
