@@ -21,9 +21,14 @@ namespace lsms {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Tiles of up to 64 x 64 are held to four waves per SIMD: left alone the compiler keeps the
+// accumulators in AGPRs and ends at three (104 VGPRs + 64 AGPRs); bounded, they fit 111 VGPRs
+// with no spills.
 template <int TM, int TN, int WM, int WN, bool XCD, int KC>
-__global__ __launch_bounds__(256) void gemm_f64_tiled(const JobDesc* jobs, int tiles_x, int tiles_y, int k, int kd,
-                                                      int r_begin, int c_begin, int c_end, double2* work) {
+__global__ __launch_bounds__(256, TM * TN <= 64 * 64 ? 4 : 1) void gemm_f64_tiled(const JobDesc* jobs, int tiles_x,
+                                                                                 int tiles_y, int k, int kd,
+                                                                                 int r_begin, int c_begin, int c_end,
+                                                                                 double2* work) {
   constexpr int WAVES_N = TN / WN;
   static_assert((TM / WM) * (TN / WN) == 4, "four waves per workgroup");
   constexpr int BM = WM / 16, BN = WN / 16;
