@@ -78,6 +78,17 @@ __device__ inline double2 pivot_inverse(double2 a, float2) {
 }
 __device__ inline double2 pivot_inverse(double2 a, double2) { return cinv(a); }
 
+// a - b c for the leaf's rank-1 updates: each component as two fused multiply-adds (two
+// roundings, where the product-then-difference form takes three operations and three roundings)
+__device__ inline float2 leaf_fms(float2 a, float2 b, float2 c) {
+  return make_float2(__builtin_fmaf(-b.x, c.x, __builtin_fmaf(b.y, c.y, a.x)),
+                     __builtin_fmaf(-b.x, c.y, __builtin_fmaf(-b.y, c.x, a.y)));
+}
+__device__ inline double2 leaf_fms(double2 a, double2 b, double2 c) {
+  return make_double2(__builtin_fma(-b.x, c.x, __builtin_fma(b.y, c.y, a.x)),
+                      __builtin_fma(-b.x, c.y, __builtin_fma(-b.y, c.x, a.y)));
+}
+
 __device__ inline double2 wide(double2 a) { return a; }
 __device__ inline double2 wide(float2 a) { return make_double2((double)a.x, (double)a.y); }
 __device__ inline void narrow_to(double2& d, double2 a) { d = a; }
@@ -185,7 +196,6 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   __shared__ T s_drow[2][IB];
   __shared__ int s_piv[IB];
   __shared__ double2 s_L11[IB][IB];
-  __shared__ double2 s_Li[IB][IB];
   __shared__ double2 s_U[IB][NB];
   __shared__ int s_pivall[NB];
   __shared__ int s_pos[PERM_MAX], s_org[PERM_MAX];
@@ -195,7 +205,14 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   // for the 256-thread kernels' 8-wide FP32 leaves of one or two row slots (the other shapes
   // run out of registers or occupancy with it).
   constexpr bool KEEP_NEXT = sizeof(T) == sizeof(float2) && (IB == 16 || (PT == 256 && S <= 2)) && S * IB * 2 <= 128;
-  __shared__ T s_X[KEEP_NEXT ? PT : 1][IB + 1];  // next leaf, MFMA layout -> one row per thread (wave-private rows)
+  // FP32 leaves move between memory and the row-per-thread registers through the wave's own
+  // rows of s_X: a row of IB FP32 complex values is IB / 2 16-byte chunks, so a wavefront's
+  // 16-byte access covers 64 / (IB / 2) whole rows (full 128- or 64-byte lines) instead of one
+  // chunk of 64 different rows, which costs one L2 request per lane and is the slow part of
+  // storing a leaf.  The same rows carry the next leaf out of the rank update.
+  constexpr bool STAGE = sizeof(T) == sizeof(float2);
+  constexpr int CPR = IB / 2, RPI = 64 / CPR;  // chunks per leaf row, rows per staged access
+  __shared__ T s_X[STAGE ? PT : 1][IB + 1];  // one row per thread (wave-private rows)
 
   // the leaf in registers in the storage precision (its updates too; pivot keys in FP64)
   T v[S][IB];
@@ -207,14 +224,45 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
   for (int c = 0; c < NB / IB; ++c) {
     const int cl = k + c * IB;
     if (c == 0 || !KEEP_NEXT) {  // otherwise the leaf came from the previous leaf's rank update
+      if constexpr (STAGE) {
+        const int ch = lane % CPR, rsub = lane / CPR;
+        int kb = k;
+        asm volatile("" : "+s"(kb));  // row addresses are formed here, not held across the leaves
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int r = k + t + s * PT;
-        if (r >= cl && r < nrows) {
-          load_row<IB>(A + r * ld + cl, v[s]);
-        } else {
+        for (int s = 0; s < S; ++s) {
+          const int rw = kb + s * PT + wave * 64;  // the wave's first row in this slot
+          if (rw >= nrows) {                      // uniform per wave
 #pragma unroll
-          for (int q = 0; q < IB; ++q) v[s][q] = T{0, 0};
+            for (int q = 0; q < IB; ++q) v[s][q] = T{0, 0};
+            continue;
+          }
+          float4 x[CPR];
+#pragma unroll
+          for (int u = 0; u < CPR; ++u) {
+            const int r = rw + u * RPI + rsub;
+            x[u] = (r >= cl && r < nrows) ? *(const float4*)(A + r * ld + cl + 2 * ch) : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+          for (int u = 0; u < CPR; ++u) {
+            T* d = s_X[wave * 64 + u * RPI + rsub] + 2 * ch;
+            d[0] = T{x[u].x, x[u].y};
+            d[1] = T{x[u].z, x[u].w};
+          }
+          wave_sync();
+#pragma unroll
+          for (int q = 0; q < IB; ++q) v[s][q] = s_X[t][q];
+          wave_sync();  // every lane has its row before the next slot rewrites them
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int r = k + t + s * PT;
+          if (r >= cl && r < nrows) {
+            load_row<IB>(A + r * ld + cl, v[s]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < IB; ++q) v[s][q] = T{0, 0};
+          }
         }
       }
     }
@@ -256,7 +304,12 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       }
       if (t == 0) s_key[(col + 1) % 3] = 0ull;
       __syncthreads();
-      const unsigned long long best = s_key[col % 3];
+      // every lane reads the same key: taking it as a scalar makes the pivot row, its slot and
+      // the row buffers uniform, so the interchange below branches per wavefront
+      const unsigned long long bk = s_key[col % 3];
+      const unsigned long long best =
+          ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(bk >> 32)) << 32) |
+          (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)bk);
       int p = best != 0ull ? k + pivot_row(best) : d;
       const bool from_cand = best != 0ull && p >= d && p < nrows;
       if (!from_cand) p = d;
@@ -308,7 +361,7 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
           if (q > j) {
             const T pq = prow[q];
 #pragma unroll
-            for (int s = 0; s < S; ++s) v[s][q] = cfms(v[s][q], l[s], pq);
+            for (int s = 0; s < S; ++s) v[s][q] = leaf_fms(v[s][q], l[s], pq);
           }
         }
       } else {
@@ -320,19 +373,46 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
             v[s][j] = l;
 #pragma unroll
             for (int q = 0; q < IB; ++q)
-              if (q > j) v[s][q] = cfms(v[s][q], l, prow[q]);
+              if (q > j) v[s][q] = leaf_fms(v[s][q], l, prow[q]);
           }
         }
       }
     }
-    // leaf back to memory, its diagonal block to LDS
+    // the leaf's diagonal block to LDS, then the leaf back to memory (the registers of a row
+    // slot are free once it is staged)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int r = k + t + s * PT;
-      if (r >= cl && r < nrows) store_row<IB>(A + r * ld + cl, v[s]);
       if (r >= cl && r < cl + IB) {
 #pragma unroll
         for (int q = 0; q < IB; ++q) s_L11[r - cl][q] = wide(v[s][q]);
+      }
+    }
+    if constexpr (STAGE) {
+      const int ch = lane % CPR, rsub = lane / CPR;
+      int kb = k;
+      asm volatile("" : "+s"(kb));  // row addresses are formed here, not held across the leaves
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int rw = kb + s * PT + wave * 64;
+        if (rw + 64 <= cl || rw >= nrows) continue;  // uniform per wave
+#pragma unroll
+        for (int q = 0; q < IB; ++q) s_X[t][q] = v[s][q];
+        wave_sync();
+#pragma unroll
+        for (int u = 0; u < CPR; ++u) {
+          const int r = rw + u * RPI + rsub;
+          const T* e = s_X[wave * 64 + u * RPI + rsub] + 2 * ch;
+          const T e0 = e[0], e1 = e[1];
+          if (r >= cl && r < nrows) *(float4*)(A + r * ld + cl + 2 * ch) = make_float4(e0.x, e0.y, e1.x, e1.y);
+        }
+        wave_sync();  // read before the next slot rewrites the rows
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int r = k + t + s * PT;
+        if (r >= cl && r < nrows) store_row<IB>(A + r * ld + cl, v[s]);
       }
     }
     __syncthreads();
@@ -390,44 +470,21 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
     __syncthreads();
     const int w = k + NB - cl - IB;  // panel columns right of the leaf
     if (w > 0) {
-      // U rows of the leaf, U = L11^-1 A[cl .. cl+IB, right of the leaf]: the first IB
-      // threads each form one column of the inverse of the leaf's unit lower triangle in
-      // registers, then every output is an independent dot product
-      for (int idx = t; idx < IB * w; idx += PT) {
-        const int q = idx / w, cc = idx - q * w;
-        s_U[q][cc] = ld2(A + (cl + q) * ld + cl + IB + cc);
-      }
-      if (t < IB) {  // column t of the inverse, row by row (each thread reads only its column)
-#pragma unroll 1
+      // U rows of the leaf, U = L11^-1 A[cl .. cl+IB, right of the leaf], by forward
+      // substitution in FP64: one thread per column (w < 64, one wavefront), the column's IB
+      // values in registers, the entries of the leaf's unit lower triangle read alike by all
+      if (t < w) {
+        double2 u[IB];
+#pragma unroll
+        for (int q = 0; q < IB; ++q) u[q] = ld2(A + (cl + q) * ld + cl + IB + t);
+#pragma unroll
+        for (int q = 1; q < IB; ++q)
+#pragma unroll
+          for (int pp = 0; pp < q; ++pp) u[q] = leaf_fms(u[q], s_L11[q][pp], u[pp]);
+#pragma unroll
         for (int q = 0; q < IB; ++q) {
-          double2 acc = make_double2(q == t ? 1.0 : 0.0, 0.0);
-#pragma unroll 4
-          for (int pp = t; pp < q; ++pp) acc = cfms(acc, s_L11[q][pp], s_Li[pp][t]);
-          s_Li[q][t] = acc;
-        }
-      }
-      __syncthreads();
-      {
-        constexpr int OPT = (IB * (NB - IB) + PT - 1) / PT;  // outputs per thread at most
-        double2 res[OPT];
-#pragma unroll
-        for (int o = 0; o < OPT; ++o) {
-          const int idx = t + o * PT, q = idx / w, cc = idx - q * w;
-          double2 acc = make_double2(0.0, 0.0);
-          if (idx < IB * w) {
-            acc = s_U[q][cc];
-#pragma unroll
-            for (int pp = 0; pp < IB; ++pp)
-              if (pp < q) acc = cfma(acc, s_Li[q][pp], s_U[pp][cc]);
-            st2(A + (cl + q) * ld + cl + IB + cc, acc);
-          }
-          res[o] = acc;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int o = 0; o < OPT; ++o) {
-          const int idx = t + o * PT, q = idx / w, cc = idx - q * w;
-          if (idx < IB * w) s_U[q][cc] = res[o];
+          st2(A + (cl + q) * ld + cl + IB + t, u[q]);
+          s_U[q][t] = u[q];
         }
       }
       __syncthreads();
