@@ -833,7 +833,7 @@ __global__ __launch_bounds__(256, sizeof(T) == sizeof(float2) ? 4 : 2) void swap
   const int row0 = k + wave * 16;  // this wavefront's 16 panel rows
   if (SECOND) {
     // s_X -= L[k.., kl..k) U[kl.., col0..], kl = k - nprev NB: wave w owns rows 16w .. 16w+16.
-    StripMma<T, 4> d;
+    StripMma<T, 4, sizeof(T) == sizeof(float2) ? NB / 2 : NB> d;
     d.zero();
     if constexpr (sizeof(T) == sizeof(float2)) {
       // FP32 storage: the wave's gathered rows move to registers (accumulator layout), so that
@@ -853,11 +853,17 @@ __global__ __launch_bounds__(256, sizeof(T) == sizeof(float2) ? 4 : 2) void swap
           const int row = idx / P4, p4 = idx - row * P4;
           ((float4*)&s_X[row][0])[p4] = ((const float4*)(A + (int64_t)(kq + row) * ld + col0))[p4];
         }
-        T la[NB / 4];
+        // the left operand in two halves of K (the same products in the same order), so that
+        // its registers fit beside the held rows and the accumulators
+        T la[NB / 8];
 #pragma unroll
-        for (int s4 = 0; s4 < NB / 4; ++s4) la[s4] = A[(int64_t)(row0 + ii) * ld + kq + 4 * s4 + (lane >> 4)];
+        for (int s4 = 0; s4 < NB / 8; ++s4) la[s4] = A[(int64_t)(row0 + ii) * ld + kq + 4 * s4 + (lane >> 4)];
         __syncthreads();
         d.run_regs(la, [&](int kk, int c) { return s_X[kk][c]; }, lane);
+#pragma unroll
+        for (int s4 = 0; s4 < NB / 8; ++s4)
+          la[s4] = A[(int64_t)(row0 + ii) * ld + kq + NB / 2 + 4 * s4 + (lane >> 4)];
+        d.run_regs(la, [&](int kk, int c) { return s_X[NB / 2 + kk][c]; }, lane);
       }
       __syncthreads();  // every wave's products read s_X before it takes the updated rows
 #pragma unroll
