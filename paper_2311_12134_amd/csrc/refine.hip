@@ -57,7 +57,8 @@ __global__ void rotate_x_kernel(const JobDesc* jobs, const int32_t* liz_atom, co
 // v X' accumulates with three real products per complex product (Ar Br, Ai Bi,
 // (Ar + Ai)(Br + Bi)); table blocks load RDEPTH members ahead, X' one member ahead, while
 // the current products run.  Reads 2176 bytes of table per block instead of the 4 KB of a
-// stored FP64 block of M; the kernel is bound by its FP64 products, not by these reads.
+// stored FP64 block of M; these reads do not bound the kernel (loading further ahead, or
+// keeping the loads ahead of the products, leaves its time unchanged).
 // Each pair's block has two readers (rows a and b): the members are visited in the cyclic
 // order a + 1, a - 1, a + 2, a - 2, ... (mod nl), so both readers of pair (a, a + t) reach it
 // within one block of each other, and a job's workgroups are dealt to one XCD (workgroups
@@ -67,6 +68,7 @@ __global__ void rotate_x_kernel(const JobDesc* jobs, const int32_t* liz_atom, co
 // in FP32 (a relative error of about 1e-7 in a norm that only scales the backward error),
 // summed in FP64.
 constexpr int RDEPTH = 2;
+static_assert(RDEPTH % 2 == 0, "the X' register sets alternate by block parity across the unrolled steps");
 
 template <bool MNORM, bool SYM>
 __global__ __launch_bounds__(256, MNORM && SYM ? 2 : 3) void residual_kernel(const JobDesc* jobs, const double2* vtab,
