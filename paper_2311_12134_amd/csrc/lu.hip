@@ -502,11 +502,28 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       // with the next leaf kept on chip its registers stay live through the update, so the
       // groups are two blocks (one with four row slots or 256 threads)
       constexpr int RBP = KEEP_NEXT ? (S >= 4 || PT == 256 ? 1 : 2) : (VRB * 4 <= 96 ? 4 : (VRB * 2 <= 96 ? 2 : 1));
+      // The 16-wide kept leaves take their L operand from LDS (12 % off the rank updates of a
+      // 2048-row panel); the leaves not kept on chip would pay for its registers in occupancy
+      // or spills, and the 256-thread kernels ran their rank updates 20-40 % slower with it.
+      constexpr bool LOP_LDS = KEEP_NEXT && IB == 16;
       typedef StripMma<T, 1, IB> Mma;
       const int ii = lane & 15, kq = lane >> 4;
 #pragma unroll 1
       for (int s = 0; s < S; ++s) {
         const int r0 = k + s * PT;
+        if constexpr (LOP_LDS) {
+          // the slab's leaf rows, the L operand of its products, into the wave's rows of s_X
+          // (read there instead of from memory; rows past the matrix hold zeros); a group's
+          // rows take the next leaf only after the group's own products have read them
+          wave_sync();
+#pragma unroll
+          for (int ss = 0; ss < S; ++ss)
+            if (ss == s) {
+#pragma unroll
+              for (int q = 0; q < IB; ++q) s_X[t][q] = v[ss][q];
+            }
+          wave_sync();
+        }
 #pragma unroll 1
         for (int g = 0; g < 4; g += RBP) {
           const int gbase = r0 + wave * 64 + g * 16;
@@ -516,8 +533,13 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
 #pragma unroll
           for (int b = 0; b < RBP; ++b) {
             const int rl = gbase + b * 16 + ii;
+            if constexpr (LOP_LDS) {
 #pragma unroll
-            for (int q = 0; q < IB / 4; ++q) lop[b][q] = rl < nrows ? A[rl * ld + cl + 4 * q + kq] : T{0, 0};
+              for (int q = 0; q < IB / 4; ++q) lop[b][q] = s_X[wave * 64 + (g + b) * 16 + ii][4 * q + kq];
+            } else {
+#pragma unroll
+              for (int q = 0; q < IB / 4; ++q) lop[b][q] = rl < nrows ? A[rl * ld + cl + 4 * q + kq] : T{0, 0};
+            }
 #pragma unroll
             for (int cb = 0; cb < CBM; ++cb)
 #pragma unroll
