@@ -502,9 +502,9 @@ __global__ __launch_bounds__(PT) void panel_kernel(const JobDesc* jobs, int k, i
       // with the next leaf kept on chip its registers stay live through the update, so the
       // groups are two blocks (one with four row slots or 256 threads)
       constexpr int RBP = KEEP_NEXT ? (S >= 4 || PT == 256 ? 1 : 2) : (VRB * 4 <= 96 ? 4 : (VRB * 2 <= 96 ? 2 : 1));
-      // The 16-wide kept leaves take their L operand from LDS (12 % off the rank updates of a
-      // 2048-row panel); the leaves not kept on chip would pay for its registers in occupancy
-      // or spills, and the 256-thread kernels ran their rank updates 20-40 % slower with it.
+      // The 16-wide kept leaves take their L operand from LDS, which shortens their rank
+      // updates; the leaves not kept on chip would pay for its registers in occupancy or
+      // spills, and the 256-thread kernels ran their rank updates slower with it.
       constexpr bool LOP_LDS = KEEP_NEXT && IB == 16;
       typedef StripMma<T, 1, IB> Mma;
       const int ii = lane & 15, kq = lane >> 4;
